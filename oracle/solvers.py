@@ -1,0 +1,100 @@
+"""Plain FP64 completion drivers built from the primitives in ``cp`` (oracle).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+"""
+import numpy as np
+
+from . import cp
+
+
+def als_sweep(idx, t, A, dims, lam):
+    """One least-squares ALS sweep (Section 2.2; Section 4 ALS listing):
+    modes in order 0..N-1 (block Gauss-Seidel, Appendix A); for mode n the
+    right-hand sides are M = MTTKRP_n(t) and the new rows solve
+    (G^(i) + lam I) x_i = M_i with G^(i) built from Omega-hat.  The current
+    rows of mode n are not used (Newton step from a zero initial guess).
+    Returns the new factor list and, per mode, (G, M, info) of that solve
+    (G without lam, for the fast-loss identity).
+    Pinned by: monotone objective decrease, vanishing gradient of the solved
+    mode, the fast-loss identity, and ridge regression by lstsq."""
+    A = [np.array(a, dtype=np.float64) for a in A]
+    aux = []
+    for n in range(len(A)):
+        M = cp.mttkrp(idx, t, A, n, dims[n])
+        G = cp.gram(idx, None, A, n, dims[n])
+        X, info = cp.solve_rows(G, M, lam)
+        A[n] = X
+        aux.append((G, M, info))
+    return A, aux
+
+
+def als_fast_loss(t, A_n, G, M):
+    """Least-squares loss after solving mode n, from that solve's left- and
+    right-hand sides (Section 2.2 identity):
+    sum t^2 + sum_i a_i^T G^(i) a_i - 2 sum_{i,r} a_ir M_ir."""
+    A_n = np.asarray(A_n, dtype=np.float64)
+    quad = float(np.einsum("ir,irs,is->", A_n, G, A_n))
+    lin = float(np.sum(A_n * M))
+    return float(np.sum(np.asarray(t, dtype=np.float64) ** 2)) + quad - 2.0 * lin
+
+
+def _dot(X, Y):
+    return float(sum(np.sum(np.asarray(x) * np.asarray(y)) for x, y in zip(X, Y)))
+
+
+def pcg(apply_H, apply_Pinv, B, tol, kmax):
+    """Preconditioned conjugate gradient on block vectors (lists of arrays),
+    from x0 = 0.  Stops when the unpreconditioned residual norm, relative to
+    the initial one, is at most ``tol`` or after ``kmax`` iterations
+    (Section 5.6 / 5.7 stopping rule).  Inner products run over the
+    concatenation of all blocks.  Returns (X, iterations, final rel. res.).
+    Pinned by: convergence to numpy.linalg.solve on small SPD systems."""
+    X = [np.zeros_like(b, dtype=np.float64) for b in B]
+    Rr = [np.array(b, dtype=np.float64) for b in B]
+    r0 = np.sqrt(_dot(Rr, Rr))
+    if r0 == 0.0:
+        return X, 0, 0.0
+    Z = apply_Pinv(Rr)
+    P = [z.copy() for z in Z]
+    rz = _dot(Rr, Z)
+    rel = 1.0
+    k = 0
+    while k < kmax:
+        HP = apply_H(P)
+        alpha = rz / _dot(P, HP)
+        X = [x + alpha * p for x, p in zip(X, P)]
+        Rr = [r - alpha * hp for r, hp in zip(Rr, HP)]
+        k += 1
+        rel = np.sqrt(_dot(Rr, Rr)) / r0
+        if rel <= tol:
+            break
+        Z = apply_Pinv(Rr)
+        rz_new = _dot(Rr, Z)
+        beta = rz_new / rz
+        rz = rz_new
+        P = [z + beta * p for z, p in zip(Z, P)]
+    return X, k, rel
+
+
+def gn_step(idx, t, A, dims, loss, lam, tol, kmax):
+    """One preconditioned Gauss-Newton iteration (Section 2.5 and its
+    implementation in Section 4): solve H dx = -grad f by PCG with the
+    implicit GN operator (weights phi'', diagonal shift 2 lam) and the
+    block-diagonal preconditioner applied through Solve Factor (weights
+    phi'', shift 2 lam); then take the full step A + dx (no line search)."""
+    A = [np.array(a, dtype=np.float64) for a in A]
+    m = cp.model_values(idx, A)
+    w = cp.d2phi(t, m, loss)
+    g = cp.gradient(idx, t, A, loss, lam, dims)
+    B = [-x for x in g]
+    lam2 = 2.0 * lam
+    Gs = [cp.gram(idx, w, A, d, dims[d]) for d in range(len(A))]
+
+    def apply_H(X):
+        return cp.gn_matvec(idx, w, A, X, lam2, dims)
+
+    def apply_Pinv(Rb):
+        return [cp.solve_rows(Gs[d], Rb[d], lam2)[0] for d in range(len(A))]
+
+    dX, iters, rel = pcg(apply_H, apply_Pinv, B, tol, kmax)
+    return [a + dx for a, dx in zip(A, dX)], iters, rel
