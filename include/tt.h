@@ -1,0 +1,259 @@
+/*
+ * tt.h -- C ABI of libtt, the MI355X (gfx950) hot path of generalized-loss
+ * CP tensor completion.
+ *
+ * Problem statement followed by every call (Section 2.1, eq. obj): a sparse
+ * order-N tensor with observed index set Omega (m nonzeros), factor matrices
+ * A_n of shape I_n x R, the CP model m_e = sum_r prod_n A_n[i_n(e), r]
+ * (eq. 1/2; Appendix A for order N), and the objective
+ *     f = sum_{e in Omega} phi(t_e, m_e) + lambda * sum_n ||A_n||_F^2.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ *  - Indices are 0-based int32.  Supported orders: 2 <= N <= 4.  Rank
+ *    1 <= R <= 64.
+ *  - Factor matrices are row-major with leading dimension ldA >= R elements
+ *    (element (i, r) at A + i * ldA + r), stored in the factor dtype `fdt`.
+ *    Row starts must be 16-byte aligned for the vectorized path (ldA * size
+ *    a multiple of 16 and an aligned base); otherwise a scalar path is used.
+ *  - "Value dtype": per-nonzero arrays (observed values, weights, TTTP
+ *    outputs) are double when fdt == TT_F64 and float otherwise.  Dense
+ *    outputs (MTTKRP, gradient, GN matvec, right-hand sides) are double
+ *    when fdt == TT_F64 and float otherwise, contiguous I_n x R.
+ *  - Orders of per-nonzero arrays: TT_ORDER_COO (-1) is the caller's COO
+ *    order; n >= 0 is the order of mode n after the stable sort done by
+ *    tt_build_index (Section 3.4 counting sort).  TT_INDEX_T passed as a
+ *    value pointer selects the observed values t held by the index, already
+ *    in the needed order.  A NULL value/weight pointer means the unit-valued
+ *    pattern tensor Omega-hat.
+ *  - All device pointers are caller-owned (typically torch tensors); the
+ *    library never frees them.  Every call except tt_build_index and calls
+ *    passed TT_SYNC is asynchronous on `stream`, performs no allocation once
+ *    the index workspace has been sized (see tt_index_reserve) and no host
+ *    synchronization, so it may be captured in a hipGraph.
+ *  - Calls that use the same tt_index share its workspace and must be
+ *    ordered on one stream.  Distinct indices may be used concurrently.
+ *  - Argument errors are detected on the host before anything is enqueued;
+ *    the call then returns a negative status and enqueues nothing.
+ *    tt_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef TT_H
+#define TT_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tt_status;
+#define TT_OK 0
+#define TT_ERR_INVALID_ARG (-1)  /* bad pointer, size, order, rank or enum   */
+#define TT_ERR_INDEX_RANGE (-2)  /* some i_n(e) outside [0, I_n)              */
+#define TT_ERR_OOM (-3)          /* device allocation failed                  */
+#define TT_ERR_HIP (-4)          /* HIP runtime error (message has details)   */
+#define TT_ERR_NOT_SPD (-5)      /* TT_SYNC solve met a non-SPD row system    */
+#define TT_ERR_UNSUPPORTED (-6)  /* valid request outside the supported set  */
+
+typedef enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 } tt_dtype;
+
+/* Per-nonzero epilogues of tttp (Section 3.3: TTTP yields the model values
+ * from which the derivative tensors phi', phi'' of eq. deriv_tnsr are formed). */
+typedef enum {
+  TT_EPI_NONE = 0,   /* out_e = s_e * m_e                                   */
+  TT_EPI_RESID = 1,  /* out_e = t_e - m_e                                   */
+  TT_EPI_PHI = 2,    /* out_e = phi(t_e, m_e)                               */
+  TT_EPI_DPHI = 3,   /* out_e = phi'(t_e, m_e)                              */
+  TT_EPI_D2PHI = 4   /* out_e = phi''(t_e, m_e)                             */
+} tt_epilogue;
+
+/* Elementwise losses: least squares (t - m)^2 (Section 2.1) and the Poisson
+ * log-link loss exp(m) - t m (Section 5.7; the log t! constant dropped). */
+typedef enum { TT_LOSS_LS = 0, TT_LOSS_POISSON_LOG = 1 } tt_loss;
+
+#define TT_ORDER_COO (-1)
+#define TT_ORDER_PER_MODE (-2) /* gn_matvec/solve weights: host array of N
+                                  device pointers, entry d in mode-d order */
+#define TT_INDEX_T ((const void *)1)
+#define TT_SYNC 1u
+#define TT_MAX_ORDER 4
+#define TT_MAX_RANK 64
+
+typedef struct tt_index tt_index; /* opaque, library-owned */
+
+/* ---------------------------------------------------------------------------
+ * tt_build_index -- per-mode stable counting sort of the nonzeros
+ * (Section 3.4: sort by the mode-n index so each row's nonzeros are
+ * contiguous; Section 3.1: only nonzero rows are kept, as in the compressed
+ * row layout).  For every mode n it stores on the device: perm_n (sorted
+ * position -> COO position, ties in COO order), the sorted mode-n indices,
+ * the other modes' indices in sorted order, ptr_n (I_n + 1 offsets, int64),
+ * the list of nonzero rows, t pre-permuted into mode-n order (if d_t given),
+ * and the work partitions used by the kernels.
+ *   order    N, 2..4.            dims   host array of N extents (>= 1).
+ *   nnz      m >= 0 (m < 2^31).  d_idx  host array of N device pointers, m
+ *            int32 each.         d_t    device pointer to m observed values
+ *            in COO order, of dtype vdt (TT_F64 or TT_F32), or NULL.
+ *   flags    0.                  stream HIP stream for the build kernels.
+ *   out      receives the new index.
+ * Synchronizes `stream` once.  Returns TT_ERR_INDEX_RANGE (and no index) if
+ * any index lies outside its dimension.  The caller's arrays are not
+ * retained: they may be freed after the call returns.
+ * ------------------------------------------------------------------------- */
+tt_status tt_build_index(int order, const int64_t *dims, int64_t nnz,
+                         const int32_t *const *d_idx, const void *d_t,
+                         tt_dtype vdt, uint32_t flags, hipStream_t stream,
+                         tt_index **out);
+
+/* Frees everything the index owns.  NULL is accepted. */
+tt_status tt_index_destroy(tt_index *ix);
+
+/* Sizes the index workspace for ranks up to R and factor dtype fdt, so that
+ * later calls allocate nothing (needed before hipGraph capture).  Calls
+ * made without it size the workspace on first use. */
+tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt);
+
+/* Read-only views of mode `mode` for tests: device pointers to ptr (int64,
+ * I_n + 1), perm (int32, m), sorted mode indices (int32, m), nonzero rows
+ * (int32, nrows); host count of nonzero rows.  Any output may be NULL. */
+tt_status tt_index_view(const tt_index *ix, int mode, const int64_t **d_ptr,
+                        const int32_t **d_perm, const int32_t **d_key,
+                        const int32_t **d_rows, int64_t *nrows);
+
+/* Sorted index stream of mode `mode` for the other mode `other` (int32, m). */
+tt_status tt_index_other(const tt_index *ix, int mode, int other,
+                         const int32_t **d_sorted_idx);
+
+/* ---------------------------------------------------------------------------
+ * tttp -- tensor-times-tensor product (Section 3.3):
+ *     x_e = s_e * sum_r prod_{n in P} A_n[i_n(e), r]
+ * where P is the set of modes whose d_A[n] is non-NULL (a NULL entry skips
+ * that mode, Section 3.3).  With an epilogue other than TT_EPI_NONE, d_s
+ * holds the observed values t and out_e = the epilogue of (t_e, m_e), using
+ * `loss`; all N factors must then be given.
+ *   d_s, s_order    values and their order (TT_INDEX_T allowed, NULL =
+ *                   Omega-hat for TT_EPI_NONE).
+ *   d_A             host array of N device pointers (entries may be NULL).
+ *   R, ldA, fdt     rank, leading dimension, factor dtype.
+ *   d_out           m values (value dtype) written in `out_order`.
+ *   d_sum           optional device double: receives sum_e out_e (FP64,
+ *                   deterministic order), overwritten.
+ * ------------------------------------------------------------------------- */
+tt_status tttp(const tt_index *ix, const void *d_s, int s_order,
+               const void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+               tt_epilogue epi, tt_loss loss, void *d_out, int out_order,
+               double *d_sum, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * mttkrp -- matricized tensor times Khatri-Rao product (Section 3.2; the
+ * right-hand sides of Section 2.2; the gradient contraction of Appendix A):
+ *     Y[i, r] = sum_{e : i_mode(e) = i} s_e * prod_{p != mode} A_p[i_p(e), r]
+ *   d_s, s_order    weights (TT_INDEX_T = observed t; NULL = Omega-hat).
+ *   d_A             host array of N device pointers; entry [mode] ignored.
+ *   d_out           I_mode x R, dense dtype; overwritten, or added to when
+ *                   accumulate != 0.
+ * Segments are reduced with FP32 chains of at most 128 terms (FP64 for
+ * TT_F64) and partials of rows longer than one work chunk are combined in
+ * FP64 in a fixed order, so results are deterministic.
+ * ------------------------------------------------------------------------- */
+tt_status mttkrp(const tt_index *ix, const void *d_s, int s_order,
+                 const void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+                 int mode, void *d_out, int accumulate, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * solve_factor -- Solve Factor (Section 3.4): for every row i of `mode`
+ *     G^(i) = sum_{e in row i} w_e h_e h_e^T,  h_e = Hadamard_{p != mode} A_p[i_p(e)]
+ *     (G^(i) + lambda I) x_i = M_i
+ * G^(i) is accumulated in FP32 on matrix cores (FP64 for TT_F64), converted
+ * to FP64, shifted by exactly `lambda` (least-squares ALS passes lambda; the
+ * Gauss-Newton block preconditioner passes 2 lambda with w = phi''), factored
+ * by Cholesky and solved in FP64.  Weights may be negative; a row whose
+ * shifted matrix is not positive definite gets x_i = 0 and
+ * info_i = k > 0, the order of the first non-positive leading minor (LAPACK
+ * potrf convention).  Rows without nonzeros solve lambda x = M_i.
+ *   d_w, w_order    weights (NULL = Omega-hat; TT_ORDER_PER_MODE allowed).
+ *   d_rhs           I_mode x R right-hand sides, dense dtype.
+ *   d_X             I_mode x R output in fdt with leading dimension ldA
+ *                   (BF16 is rounded to nearest even); may alias d_A[mode].
+ *   d_info          optional int32[I_mode].
+ *   flags           TT_SYNC: synchronize and return TT_ERR_NOT_SPD if any
+ *                   row failed (requires d_info).
+ * ------------------------------------------------------------------------- */
+tt_status solve_factor(const tt_index *ix, const void *d_w, int w_order,
+                       const void *const *d_A, int R, int64_t ldA,
+                       tt_dtype fdt, int mode, const void *d_rhs,
+                       double lambda, void *d_X, int32_t *d_info,
+                       uint32_t flags, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * gn_matvec -- implicit Gauss-Newton matrix-vector product (Section 2.5
+ * without the phi' terms; the TTTP -> MTTKRP decomposition of Section 2.5;
+ * Appendix A first Hessian term):
+ *     z_e = sum_p sum_r X_p[i_p(e), r] prod_{q != p} A_q[i_q(e), r]
+ *     Y_d = MTTKRP_d(w .* z) + lambda2 * X_d          for every mode d
+ * fused into one pass over each mode's sorted stream.
+ *   d_w, w_order    per-nonzero weights (phi''); TT_ORDER_PER_MODE or a
+ *                   mode order or COO; NULL = the constant w_const.
+ *   d_X, d_Y        host arrays of N device pointers; X in fdt with ldA,
+ *                   Y dense dtype I_d x R (overwritten).
+ * ------------------------------------------------------------------------- */
+tt_status gn_matvec(const tt_index *ix, const void *d_w, int w_order,
+                    double w_const, const void *const *d_A,
+                    const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
+                    double lambda2, void *const *d_Y, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * tt_gradient -- hand-written adjoint of the objective (Table 1 gradient
+ * row; Appendix A):  grad_d = MTTKRP_d(phi'(t, m)) + 2 lambda A_d, with m
+ * recomputed inside each mode's pass (TTTP fused into MTTKRP).
+ *   d_G             host array of N device pointers, dense dtype I_d x R.
+ * Requires the index to hold t.
+ * ------------------------------------------------------------------------- */
+tt_status tt_gradient(const tt_index *ix, const void *const *d_A, int R,
+                      int64_t ldA, tt_dtype fdt, tt_loss loss, double lambda,
+                      void *const *d_G, hipStream_t stream);
+
+/* tt_objective -- f = sum_e phi(t_e, m_e) + lambda sum_n ||A_n||_F^2 into
+ * the device double d_f (FP64 sums, deterministic).  Requires t. */
+tt_status tt_objective(const tt_index *ix, const void *const *d_A, int R,
+                       int64_t ldA, tt_dtype fdt, tt_loss loss, double lambda,
+                       double *d_f, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * tt_als_sweep -- one alternating-least-squares sweep (Section 2.2 and its
+ * Section 4 implementation): for n = 0..N-1, M = MTTKRP_n(t) and
+ * A_n <- Solve Factor(Omega-hat, A, n, M, lambda).  Factors are updated in
+ * place.  Requires t.  d_info: optional int32[sum_n I_n].
+ * ------------------------------------------------------------------------- */
+tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
+                       tt_dtype fdt, double lambda, int32_t *d_info,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * tt_gn_step -- one preconditioned Gauss-Newton iteration (Section 2.5 and
+ * its Section 4 implementation): w = phi''(t, m); b = -grad f; solve
+ * (J^T diag(w) J + 2 lambda I) dx = b by PCG from dx = 0 with the block
+ * diagonal preconditioner applied through Solve Factor (weights w, shift
+ * 2 lambda, factors computed once per call); stop when the unpreconditioned
+ * residual norm relative to the initial one is <= tol or after kmax
+ * iterations; then A <- A + dx (full step).  Dot products in FP64.  The
+ * iteration count runs on the device: convergence sets a device flag that
+ * turns the remaining iterations into no-ops, so no host sync is needed.
+ *   d_stats         optional device double[4]: iterations, final relative
+ *                   residual, initial residual norm, objective before step.
+ * ------------------------------------------------------------------------- */
+tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
+                     tt_dtype fdt, tt_loss loss, double lambda, double tol,
+                     int kmax, double *d_stats, hipStream_t stream);
+
+/* Thread-local text describing the last non-OK status ("" if none). */
+const char *tt_last_error(void);
+
+/* Library version string. */
+const char *tt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_H */

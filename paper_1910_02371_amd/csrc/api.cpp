@@ -1,0 +1,669 @@
+// C ABI of libtt: argument checking, dispatch onto the kernels, and the two
+// completion drivers built from the primitives (ALS sweep, Section 2.2;
+// preconditioned Gauss-Newton step, Section 2.5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace tt {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+tt_status hip_fail(hipError_t e, const char *what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return TT_ERR_HIP;
+}
+
+tt_status ws_get(tt_index *ix, const char *name, size_t bytes, void **out) {
+  Buf &b = ix->ws[name];
+  if (b.bytes < bytes) {
+    if (b.p) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "workspace resize");
+      hipFree(b.p);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      set_error("workspace '%s' of %zu bytes: %s", name, want, hipGetErrorString(e));
+      return TT_ERR_OOM;
+    }
+    b.bytes = want;
+  }
+  *out = b.p;
+  return TT_OK;
+}
+
+#define TT_ST(x)                          \
+  do {                                    \
+    tt_status _s = (x);                   \
+    if (_s != TT_OK) return _s;           \
+  } while (0)
+#define TT_LAUNCH(x, what)                               \
+  do {                                                   \
+    hipError_t _e = (x);                                 \
+    if (_e != hipSuccess) return hip_fail(_e, what);     \
+  } while (0)
+
+static tt_dtype dense_of(tt_dtype fdt) { return fdt == TT_F64 ? TT_F64 : TT_F32; }
+
+static tt_status check_common(const tt_index *ix, int R, int64_t ldA, tt_dtype fdt) {
+  TT_CHECK(ix != nullptr, "index is NULL");
+  TT_CHECK(fdt == TT_F64 || fdt == TT_F32 || fdt == TT_BF16, "bad factor dtype %d", (int)fdt);
+  TT_CHECK(R >= 1 && R <= TT_MAX_RANK, "rank %d outside [1, %d]", R, TT_MAX_RANK);
+  TT_CHECK(ldA >= R, "ldA %lld < R %d", (long long)ldA, R);
+  if (ix->N != 3) {
+    set_error("order %d: the GPU kernels implement order-3 tensors", ix->N);
+    return TT_ERR_UNSUPPORTED;
+  }
+  return TT_OK;
+}
+
+// Per-nonzero array in the order of `mode`: returns (pointer, perm) where
+// perm != NULL means "gather through perm" (COO order input).
+static tt_status resolve_values(const tt_index *ix, const void *v, int order, int mode,
+                                tt_dtype fdt, const void **out, const int32_t **perm,
+                                const char *what) {
+  *perm = nullptr;
+  *out = nullptr;
+  if (v == nullptr) return TT_OK;
+  if (v == TT_INDEX_T) {
+    TT_CHECK(ix->has_t, "%s: the index holds no observed values", what);
+    TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64),
+             "%s: value dtype of the index does not match the factor dtype", what);
+    *out = ix->mode[mode].d_t;
+    return TT_OK;
+  }
+  if (order == TT_ORDER_PER_MODE) {
+    const void *const *arr = reinterpret_cast<const void *const *>(v);
+    TT_CHECK(arr[mode] != nullptr, "%s: per-mode array %d is NULL", what, mode);
+    *out = arr[mode];
+    return TT_OK;
+  }
+  if (order == TT_ORDER_COO) {
+    *out = v;
+    *perm = ix->mode[mode].d_perm;
+    return TT_OK;
+  }
+  TT_CHECK(order >= 0 && order < ix->N, "%s: bad order %d", what, order);
+  if (order != mode) {
+    set_error("%s: values in mode-%d order cannot feed a mode-%d pass", what, order, mode);
+    return TT_ERR_UNSUPPORTED;
+  }
+  *out = v;
+  return TT_OK;
+}
+
+static tt_status carry_ws(tt_index *ix, double **carry) {
+  void *p = nullptr;
+  TT_ST(ws_get(ix, "carry", (size_t)std::max<int64_t>(ix->max_nslot, 1) * 64 * 8, &p));
+  *carry = (double *)p;
+  return TT_OK;
+}
+
+static StreamCall base_call(const tt_index *ix, int mode, int R, int64_t ldA, tt_dtype fdt) {
+  StreamCall c;
+  memset(&c, 0, sizeof(c));
+  c.ix = ix;
+  c.mode = mode;
+  c.R = R;
+  c.ldA = ldA;
+  c.fdt = fdt;
+  c.w_const = 1.0;
+  return c;
+}
+
+// Process TTTP in `mode` order; internal (no argument checks).
+static tt_status tttp_mode(tt_index *ix, int mode, const void *s, const int32_t *s_perm,
+                           const void *const *d_A, int R, int64_t ldA, tt_dtype fdt, int epi,
+                           int loss, void *out, const int32_t *out_perm, double *d_sum,
+                           const double *skip, hipStream_t st) {
+  StreamCall c = base_call(ix, mode, R, ldA, fdt);
+  for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+  c.s = s;
+  c.s_perm = s_perm;
+  c.epi = epi;
+  c.loss = loss;
+  c.out = out;
+  c.out_perm = out_perm;
+  c.skip = skip;
+  if (d_sum) {
+    void *p = nullptr;
+    TT_ST(ws_get(ix, "tsum", (size_t)std::max<int64_t>(ix->max_nchunk, 1) * 8, &p));
+    c.sum_parts = (double *)p;
+  }
+  TT_LAUNCH(launch_stream(OP_TTTP, c, st), "tttp kernel");
+  if (d_sum) {
+    if (ix->mode[mode].nchunk > 0)
+      TT_LAUNCH(launch_sum_doubles(c.sum_parts, ix->mode[mode].nchunk, d_sum, 0, st), "sum");
+    else
+      TT_LAUNCH(launch_fill(d_sum, 1, TT_F64, 0.0, st), "sum");
+  }
+  return TT_OK;
+}
+
+static int best_mode(const tt_index *ix) {
+  int b = 0;
+  for (int n = 1; n < ix->N; ++n)
+    if (ix->mode[n].mean_row > ix->mode[b].mean_row) b = n;
+  return b;
+}
+
+static tt_status mttkrp_impl(tt_index *ix, const void *s, const int32_t *s_perm, double w_const,
+                             const void *const *d_A, int R, int64_t ldA, tt_dtype fdt, int mode,
+                             void *out, int accumulate, hipStream_t st) {
+  const ModeIndex &md = ix->mode[mode];
+  if (!accumulate && md.nrows < md.I)
+    TT_LAUNCH(launch_fill(out, md.I * R, dense_of(fdt), 0.0, st), "fill");
+  StreamCall c = base_call(ix, mode, R, ldA, fdt);
+  for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+  c.s = s;
+  c.s_perm = s_perm;
+  c.w_const = w_const;
+  c.out = out;
+  c.accumulate = accumulate;
+  TT_ST(carry_ws(ix, &c.carry));
+  TT_LAUNCH(launch_stream(OP_MTTKRP, c, st), "mttkrp kernel");
+  return TT_OK;
+}
+
+static tt_status gn_matvec_impl(tt_index *ix, const void *const *w, double w_const,
+                                const int32_t *const *w_perm, const void *const *d_A,
+                                const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
+                                double lambda2, void *const *d_Y, const double *skip,
+                                hipStream_t st) {
+  double *carry = nullptr;
+  TT_ST(carry_ws(ix, &carry));
+  for (int d = 0; d < ix->N; ++d) {
+    const ModeIndex &md = ix->mode[d];
+    TT_LAUNCH(launch_scale_rows(d_Y[d], d_X[d], dense_of(fdt), R, md.I, R, lambda2,
+                                dense_of(fdt), st),
+              "gn prefill");
+    StreamCall c = base_call(ix, d, R, ldA, fdt);
+    for (int p = 0; p < ix->N; ++p) {
+      c.A[p] = d_A[p];
+      c.X[p] = d_X[p];
+    }
+    c.s = w ? w[d] : nullptr;
+    c.s_perm = w_perm ? w_perm[d] : nullptr;
+    c.w_const = w_const;
+    c.out = d_Y[d];
+    c.accumulate = 1;
+    c.carry = carry;
+    c.skip = skip;
+    TT_LAUNCH(launch_stream(OP_GN, c, st), "gn kernel");
+  }
+  return TT_OK;
+}
+
+static tt_status gradient_impl(tt_index *ix, const void *const *d_A, int R, int64_t ldA,
+                               tt_dtype fdt, int loss, double lambda, void *const *d_G,
+                               hipStream_t st) {
+  double *carry = nullptr;
+  TT_ST(carry_ws(ix, &carry));
+  for (int d = 0; d < ix->N; ++d) {
+    const ModeIndex &md = ix->mode[d];
+    TT_LAUNCH(launch_scale_rows(d_G[d], d_A[d], fdt, ldA, md.I, R, 2.0 * lambda,
+                                dense_of(fdt), st),
+              "gradient prefill");
+    StreamCall c = base_call(ix, d, R, ldA, fdt);
+    for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+    c.s = md.d_t;
+    c.loss = loss;
+    c.out = d_G[d];
+    c.accumulate = 1;
+    c.carry = carry;
+    TT_LAUNCH(launch_stream(OP_GRAD, c, st), "gradient kernel");
+  }
+  return TT_OK;
+}
+
+static tt_status objective_impl(tt_index *ix, const void *const *d_A, int R, int64_t ldA,
+                                tt_dtype fdt, int loss, double lambda, double *d_f,
+                                hipStream_t st) {
+  const int mode = best_mode(ix);
+  TT_ST(tttp_mode(ix, mode, ix->mode[mode].d_t, nullptr, d_A, R, ldA, fdt, TT_EPI_PHI, loss,
+                  nullptr, nullptr, d_f, nullptr, st));
+  if (lambda != 0.0) {
+    int64_t need = 0;
+    for (int n = 0; n < ix->N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
+    void *p = nullptr;
+    TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &p));
+    for (int n = 0; n < ix->N; ++n) {
+      int64_t np = 0;
+      TT_LAUNCH(launch_sumsq_rows(d_A[n], fdt, ldA, ix->mode[n].I, R, lambda, (double *)p, &np,
+                                  st),
+                "sumsq");
+      TT_LAUNCH(launch_sum_doubles((double *)p, np, d_f, 1, st), "sum");
+    }
+  }
+  return TT_OK;
+}
+
+}  // namespace tt
+
+using namespace tt;
+
+extern "C" {
+
+const char *tt_last_error(void) { return g_err.c_str(); }
+
+const char *tt_version(void) { return "libtt 0.1 (gfx950)"; }
+
+tt_status tt_build_index(int order, const int64_t *dims, int64_t nnz,
+                         const int32_t *const *d_idx, const void *d_t, tt_dtype vdt,
+                         uint32_t flags, hipStream_t stream, tt_index **out) {
+  g_err.clear();
+  TT_CHECK(out != nullptr, "out is NULL");
+  *out = nullptr;
+  TT_CHECK(order >= 2 && order <= TT_MAX_ORDER, "order %d outside [2, %d]", order,
+           TT_MAX_ORDER);
+  TT_CHECK(dims != nullptr && d_idx != nullptr, "dims/d_idx NULL");
+  TT_CHECK(nnz >= 0 && nnz < ((int64_t)1 << 31), "nnz %lld outside [0, 2^31)", (long long)nnz);
+  TT_CHECK(vdt == TT_F64 || vdt == TT_F32, "value dtype must be TT_F64 or TT_F32");
+  TT_CHECK(flags == 0, "flags must be 0");
+  for (int n = 0; n < order; ++n) {
+    TT_CHECK(dims[n] >= 1 && dims[n] < ((int64_t)1 << 31), "dims[%d] = %lld", n,
+             (long long)dims[n]);
+    TT_CHECK(nnz == 0 || d_idx[n] != nullptr, "d_idx[%d] is NULL", n);
+  }
+  if (order != 3) {
+    set_error("order %d: the GPU kernels implement order-3 tensors", order);
+    return TT_ERR_UNSUPPORTED;
+  }
+  tt_index *ix = new (std::nothrow) tt_index();
+  if (!ix) {
+    set_error("host allocation failed");
+    return TT_ERR_OOM;
+  }
+  tt_status st = build_index_impl(order, dims, nnz, d_idx, d_t, vdt, stream, ix);
+  if (st != TT_OK) {
+    std::string keep = g_err;
+    tt_index_destroy(ix);
+    g_err = keep;
+    return st;
+  }
+  *out = ix;
+  return TT_OK;
+}
+
+tt_status tt_index_destroy(tt_index *ix) {
+  if (!ix) return TT_OK;
+  hipDeviceSynchronize();
+  for (void *p : ix->owned) hipFree(p);
+  for (auto &kv : ix->ws)
+    if (kv.second.p) hipFree(kv.second.p);
+  delete ix;
+  return TT_OK;
+}
+
+tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, R, fdt));
+  double *c = nullptr;
+  TT_ST(carry_ws(ix, &c));
+  void *p = nullptr;
+  TT_ST(ws_get(ix, "tsum", (size_t)std::max<int64_t>(ix->max_nchunk, 1) * 8, &p));
+  TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &p));
+  const int RP = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+  const int64_t task_bytes = (int64_t)RP * RP * (fdt == TT_F64 ? 8 : 4);
+  int64_t wt = 1;
+  for (int n = 0; n < ix->N; ++n) {
+    const ModeIndex &md = ix->mode[n];
+    int64_t w = std::max<int64_t>(kGramBatchBytes / task_bytes, md.max_task_per_row);
+    w = std::min<int64_t>(w, std::max<int64_t>(md.ntask, 1));
+    wt = std::max(wt, w);
+  }
+  TT_ST(ws_get(ix, "gram", (size_t)(wt * task_bytes), &p));
+  int64_t need = 0;
+  for (int n = 0; n < ix->N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
+  TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &p));
+  return TT_OK;
+}
+
+tt_status tt_index_view(const tt_index *ix, int mode, const int64_t **d_ptr,
+                        const int32_t **d_perm, const int32_t **d_key,
+                        const int32_t **d_rows, int64_t *nrows) {
+  TT_CHECK(ix != nullptr, "index is NULL");
+  TT_CHECK(mode >= 0 && mode < ix->N, "bad mode %d", mode);
+  const ModeIndex &md = ix->mode[mode];
+  if (d_ptr) *d_ptr = md.d_ptr;
+  if (d_perm) *d_perm = md.d_perm;
+  if (d_key) *d_key = md.d_key;
+  if (d_rows) *d_rows = md.d_rows;
+  if (nrows) *nrows = md.nrows;
+  return TT_OK;
+}
+
+tt_status tt_index_other(const tt_index *ix, int mode, int other,
+                         const int32_t **d_sorted_idx) {
+  TT_CHECK(ix != nullptr, "index is NULL");
+  TT_CHECK(mode >= 0 && mode < ix->N && other >= 0 && other < ix->N && other != mode,
+           "bad modes %d/%d", mode, other);
+  TT_CHECK(d_sorted_idx != nullptr, "output NULL");
+  *d_sorted_idx = ix->mode[mode].d_oidx[other];
+  return TT_OK;
+}
+
+tt_status tttp(const tt_index *cix, const void *d_s, int s_order, const void *const *d_A, int R,
+               int64_t ldA, tt_dtype fdt, tt_epilogue epi, tt_loss loss, void *d_out,
+               int out_order, double *d_sum, hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(d_A != nullptr, "d_A is NULL");
+  TT_CHECK(epi >= TT_EPI_NONE && epi <= TT_EPI_D2PHI, "bad epilogue %d", (int)epi);
+  TT_CHECK(loss == TT_LOSS_LS || loss == TT_LOSS_POISSON_LOG, "bad loss %d", (int)loss);
+  TT_CHECK(s_order >= TT_ORDER_COO && s_order < ix->N, "bad s_order %d", s_order);
+  TT_CHECK(out_order >= TT_ORDER_COO && out_order < ix->N, "bad out_order %d", out_order);
+  int given = 0;
+  for (int p = 0; p < ix->N; ++p) given += d_A[p] != nullptr;
+  TT_CHECK(given >= 1, "tttp needs at least one factor");
+  if (epi != TT_EPI_NONE) {
+    TT_CHECK(d_s != nullptr, "loss epilogues need the observed values");
+    TT_CHECK(given == ix->N, "loss epilogues need every factor");
+  }
+  TT_CHECK(d_out != nullptr || d_sum != nullptr || ix->m == 0, "no output");
+  // processing order
+  int mode;
+  if (out_order >= 0) {
+    mode = out_order;
+  } else if (d_s != nullptr && d_s != TT_INDEX_T && s_order >= 0) {
+    mode = s_order;
+  } else {
+    mode = best_mode(ix);
+  }
+  const void *s = nullptr;
+  const int32_t *s_perm = nullptr;
+  TT_ST(resolve_values(ix, d_s, s_order, mode, fdt, &s, &s_perm, "tttp values"));
+  const int32_t *out_perm = out_order == TT_ORDER_COO ? ix->mode[mode].d_perm : nullptr;
+  if (ix->m == 0) {
+    if (d_sum) TT_LAUNCH(launch_fill(d_sum, 1, TT_F64, 0.0, stream), "fill");
+    return TT_OK;
+  }
+  return tttp_mode(ix, mode, s, s_perm, d_A, R, ldA, fdt, epi, loss, d_out, out_perm, d_sum,
+                   nullptr, stream);
+}
+
+tt_status mttkrp(const tt_index *cix, const void *d_s, int s_order, const void *const *d_A,
+                 int R, int64_t ldA, tt_dtype fdt, int mode, void *d_out, int accumulate,
+                 hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(mode >= 0 && mode < ix->N, "bad mode %d", mode);
+  TT_CHECK(d_A != nullptr && d_out != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p)
+    TT_CHECK(p == mode || d_A[p] != nullptr, "factor %d is NULL", p);
+  const void *s = nullptr;
+  const int32_t *s_perm = nullptr;
+  TT_ST(resolve_values(ix, d_s, s_order, mode, fdt, &s, &s_perm, "mttkrp values"));
+  return mttkrp_impl(ix, s, s_perm, 1.0, d_A, R, ldA, fdt, mode, d_out, accumulate, stream);
+}
+
+tt_status solve_factor(const tt_index *cix, const void *d_w, int w_order, const void *const *d_A,
+                       int R, int64_t ldA, tt_dtype fdt, int mode, const void *d_rhs,
+                       double lambda, void *d_X, int32_t *d_info, uint32_t flags,
+                       hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(mode >= 0 && mode < ix->N, "bad mode %d", mode);
+  TT_CHECK(d_A != nullptr && d_rhs != nullptr && d_X != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p)
+    TT_CHECK(p == mode || d_A[p] != nullptr, "factor %d is NULL", p);
+  TT_CHECK((flags & ~TT_SYNC) == 0, "bad flags");
+  TT_CHECK(!(flags & TT_SYNC) || d_info != nullptr, "TT_SYNC needs d_info");
+  SolveCall c;
+  memset(&c, 0, sizeof(c));
+  c.ix = ix;
+  c.mode = mode;
+  c.R = R;
+  c.ldA = ldA;
+  c.fdt = fdt;
+  for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+  TT_ST(resolve_values(ix, d_w, w_order, mode, fdt, &c.w, &c.w_perm, "solve_factor weights"));
+  c.w_scale = 1.0;
+  c.lambda = lambda;
+  c.rhs = d_rhs;
+  c.X = d_X;
+  c.info = d_info;
+  TT_ST(run_solve_factor(ix, c, stream));
+  if (flags & TT_SYNC) {
+    const int64_t I = ix->mode[mode].I;
+    std::vector<int32_t> h(I);
+    TT_HIP(hipMemcpyAsync(h.data(), d_info, I * 4, hipMemcpyDeviceToHost, stream));
+    TT_HIP(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < I; ++i)
+      if (h[i] != 0) {
+        set_error("row %lld: leading minor of order %d is not positive", (long long)i, h[i]);
+        return TT_ERR_NOT_SPD;
+      }
+  }
+  return TT_OK;
+}
+
+tt_status gn_matvec(const tt_index *cix, const void *d_w, int w_order, double w_const,
+                    const void *const *d_A, const void *const *d_X, int R, int64_t ldA,
+                    tt_dtype fdt, double lambda2, void *const *d_Y, hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(d_A != nullptr && d_X != nullptr && d_Y != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p)
+    TT_CHECK(d_A[p] && d_X[p] && d_Y[p], "block %d is NULL", p);
+  const void *w[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  const int32_t *wp[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  if (d_w != nullptr) {
+    TT_CHECK(w_order == TT_ORDER_PER_MODE || w_order == TT_ORDER_COO || d_w == TT_INDEX_T,
+             "gn_matvec weights must be per-mode, COO or the index values");
+    for (int d = 0; d < ix->N; ++d)
+      TT_ST(resolve_values(ix, d_w, w_order, d, fdt, &w[d], &wp[d], "gn_matvec weights"));
+  }
+  return gn_matvec_impl(ix, d_w ? w : nullptr, w_const, d_w ? wp : nullptr, d_A, d_X, R, ldA,
+                        fdt, lambda2, d_Y, nullptr, stream);
+}
+
+tt_status tt_gradient(const tt_index *cix, const void *const *d_A, int R, int64_t ldA,
+                      tt_dtype fdt, tt_loss loss, double lambda, void *const *d_G,
+                      hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(loss == TT_LOSS_LS || loss == TT_LOSS_POISSON_LOG, "bad loss %d", (int)loss);
+  TT_CHECK(d_A != nullptr && d_G != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p] && d_G[p], "block %d is NULL", p);
+  return gradient_impl(ix, d_A, R, ldA, fdt, loss, lambda, d_G, stream);
+}
+
+tt_status tt_objective(const tt_index *cix, const void *const *d_A, int R, int64_t ldA,
+                       tt_dtype fdt, tt_loss loss, double lambda, double *d_f,
+                       hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(loss == TT_LOSS_LS || loss == TT_LOSS_POISSON_LOG, "bad loss %d", (int)loss);
+  TT_CHECK(d_A != nullptr && d_f != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
+  return objective_impl(ix, d_A, R, ldA, fdt, loss, lambda, d_f, stream);
+}
+
+tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+                       double lambda, int32_t *d_info, hipStream_t stream) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(d_A != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
+  void *M = nullptr;
+  TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &M));
+  const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
+  int64_t off = 0;
+  for (int n = 0; n < ix->N; ++n) {
+    TT_ST(mttkrp_impl(ix, ix->mode[n].d_t, nullptr, 1.0, A, R, ldA, fdt, n, M, 0, stream));
+    SolveCall c;
+    memset(&c, 0, sizeof(c));
+    c.ix = ix;
+    c.mode = n;
+    c.R = R;
+    c.ldA = ldA;
+    c.fdt = fdt;
+    for (int p = 0; p < ix->N; ++p) c.A[p] = A[p];
+    c.w_scale = 1.0;
+    c.lambda = lambda;
+    c.rhs = M;
+    c.X = d_A[n];
+    c.info = d_info ? d_info + off : nullptr;
+    TT_ST(run_solve_factor(ix, c, stream));
+    off += ix->mode[n].I;
+  }
+  return TT_OK;
+}
+
+tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+                     tt_loss loss, double lambda, double tol, int kmax, double *d_stats,
+                     hipStream_t st) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(loss == TT_LOSS_LS || loss == TT_LOSS_POISSON_LOG, "bad loss %d", (int)loss);
+  TT_CHECK(kmax >= 0, "kmax < 0");
+  TT_CHECK(d_A != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
+  const int N = ix->N;
+  const tt_dtype dn = dense_of(fdt);
+  const size_t dsz = value_size(fdt);
+  const int RP = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+  int64_t off[TT_MAX_ORDER + 1] = {0};
+  for (int d = 0; d < N; ++d) off[d + 1] = off[d] + ix->mode[d].I * R;
+  const int64_t ntot = off[N];
+  // workspace
+  void *vx, *vr, *vz, *vp, *vq, *vsc, *vparts, *vw = nullptr, *vL;
+  TT_ST(ws_get(ix, "pcg_x", ntot * dsz, &vx));
+  TT_ST(ws_get(ix, "pcg_r", ntot * dsz, &vr));
+  TT_ST(ws_get(ix, "pcg_z", ntot * dsz, &vz));
+  TT_ST(ws_get(ix, "pcg_p", ntot * dsz, &vp));
+  TT_ST(ws_get(ix, "pcg_q", ntot * dsz, &vq));
+  TT_ST(ws_get(ix, "pcg_sc", 32 * 8, &vsc));
+  TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &vparts));
+  int64_t Ltot = 0;
+  for (int d = 0; d < N; ++d) Ltot += ix->mode[d].I * (int64_t)RP * RP;
+  TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * 8, &vL));
+  if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &vw));
+  char *X = (char *)vx, *Rv = (char *)vr, *Z = (char *)vz, *P = (char *)vp, *Q = (char *)vq;
+  double *sc = (double *)vsc, *parts = (double *)vparts, *L = (double *)vL;
+  const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
+  auto blk = [&](char *base, int d) -> void * { return base + off[d] * dsz; };
+  double *Lb[TT_MAX_ORDER];
+  {
+    int64_t lo = 0;
+    for (int d = 0; d < N; ++d) {
+      Lb[d] = L + lo;
+      lo += ix->mode[d].I * (int64_t)RP * RP;
+    }
+  }
+  // objective before the step (slot 10)
+  TT_ST(objective_impl(ix, A, R, ldA, fdt, loss, lambda, sc + 10, st));
+  // weights phi'' in each mode's order
+  const void *w[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  double w_const = 2.0;
+  if (loss == TT_LOSS_POISSON_LOG) {
+    for (int d = 0; d < N; ++d) {
+      w[d] = (char *)vw + (size_t)d * ix->m * dsz;
+      TT_ST(tttp_mode(ix, d, ix->mode[d].d_t, nullptr, A, R, ldA, fdt, TT_EPI_D2PHI, loss,
+                      (void *)w[d], nullptr, nullptr, nullptr, st));
+    }
+  }
+  // b = -grad f ; x = 0 ; r = b
+  void *G[TT_MAX_ORDER];
+  for (int d = 0; d < N; ++d) G[d] = blk(Q, d);
+  TT_ST(gradient_impl(ix, A, R, ldA, fdt, loss, lambda, G, st));
+  TT_LAUNCH(launch_scale_rows(Rv, Q, dn, R, ntot / R, R, -1.0, dn, st), "negate");
+  TT_LAUNCH(launch_fill(X, ntot, dn, 0.0, st), "fill");
+  // block-diagonal preconditioner: factor (G_phi'' + 2 lambda I) per mode
+  for (int d = 0; d < N; ++d) {
+    SolveCall c;
+    memset(&c, 0, sizeof(c));
+    c.ix = ix;
+    c.mode = d;
+    c.R = R;
+    c.ldA = ldA;
+    c.fdt = fdt;
+    for (int p = 0; p < N; ++p) c.A[p] = A[p];
+    c.w = w[d];
+    c.w_scale = w[d] ? 1.0 : w_const;
+    c.lambda = 2.0 * lambda;
+    c.Lstore = Lb[d];
+    c.factor_only = 1;
+    TT_ST(run_solve_factor(ix, c, st));
+  }
+  auto precond = [&](const double *skip) -> tt_status {
+    for (int d = 0; d < N; ++d)
+      TT_LAUNCH(launch_apply_factor(ix, d, R, fdt, Lb[d], blk(Rv, d), blk(Z, d), skip, st),
+                "precond");
+    return TT_OK;
+  };
+  auto dot = [&](const void *a, const void *b, int slot) -> tt_status {
+    int64_t np = 0;
+    TT_LAUNCH(launch_dot_parts(a, b, ntot, dn, parts, &np, st), "dot");
+    TT_LAUNCH(launch_sum_doubles(parts, np, sc + slot, 0, st), "dot sum");
+    return TT_OK;
+  };
+  const double *done = sc + 5;
+  TT_ST(precond(nullptr));
+  TT_ST(dot(Rv, Z, 0));
+  TT_ST(dot(Rv, Rv, 2));
+  TT_LAUNCH(launch_pcg_scalar(sc, 0, tol, st), "pcg");
+  TT_LAUNCH(launch_scale_rows(P, Z, dn, R, ntot / R, R, 1.0, dn, st), "copy");
+  void *Pb[TT_MAX_ORDER], *Qb[TT_MAX_ORDER];
+  const void *Pc[TT_MAX_ORDER];
+  for (int d = 0; d < N; ++d) {
+    Pb[d] = blk(P, d);
+    Pc[d] = Pb[d];
+    Qb[d] = blk(Q, d);
+  }
+  for (int k = 0; k < kmax; ++k) {
+    TT_ST(gn_matvec_impl(ix, loss == TT_LOSS_POISSON_LOG ? w : nullptr, w_const, nullptr, A, Pc,
+                         R, ldA, fdt, 2.0 * lambda, Qb, done, st));
+    TT_ST(dot(P, Q, 1));
+    TT_LAUNCH(launch_pcg_scalar(sc, 1, tol, st), "pcg");
+    TT_LAUNCH(launch_axpy2(X, P, Rv, Q, ntot, dn, sc, 0, st), "axpy");
+    TT_ST(dot(Rv, Rv, 2));
+    TT_LAUNCH(launch_pcg_scalar(sc, 2, tol, st), "pcg");
+    TT_ST(precond(done));
+    TT_ST(dot(Rv, Z, 4));
+    TT_LAUNCH(launch_pcg_scalar(sc, 3, tol, st), "pcg");
+    TT_LAUNCH(launch_xpby(P, Z, ntot, dn, sc, 0, st), "xpby");
+  }
+  for (int d = 0; d < N; ++d)
+    TT_LAUNCH(launch_add_to_factor(d_A[d], fdt, ldA, ix->mode[d].I, R, blk(X, d), st), "step");
+  if (d_stats) TT_LAUNCH(launch_pcg_stats(sc, sc + 10, d_stats, st), "stats");
+  return TT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// Index construction: per-mode stable counting sort of the nonzeros
+// (Section 3.4 sorts by the mode-n index with a counting sort; ties keep
+// COO order), row pointers, nonzero rows (Section 3.1 compressed rows) and
+// the work partitions of the streaming and Gram kernels.
+//
+// The sort is an LSD radix sort with 4-bit digits: per pass a block digit
+// histogram, an exclusive scan of the digit-major (digit, block) counts, and
+// a stable scatter whose in-block ranks follow (thread, item) order, so every
+// pass is stable and the result equals a stable argsort, bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tt {
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 2048 keys per block
+constexpr int RS_BITS = 4;
+constexpr int RS_BINS = 1 << RS_BITS;
+
+// ---------------------------------------------------------------------------
+__global__ void k_range_check(const int32_t *__restrict__ idx, int64_t m,
+                              int64_t I, int *flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; i < m; i += stride) {
+    int32_t v = idx[i];
+    bad |= (v < 0) | ((int64_t)v >= I);
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+// Digit histogram of one tile per block, written digit-major:
+// hist[d * nblocks + b].
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(
+    const uint32_t *__restrict__ keys, int64_t m, int shift, int64_t nblocks,
+    uint32_t *__restrict__ hist) {
+  __shared__ uint32_t cnt[RS_BINS];
+  if (threadIdx.x < RS_BINS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    int64_t e = base + (int64_t)j * RS_THREADS + threadIdx.x;
+    if (e < m) atomicAdd(&cnt[(keys[e] >> shift) & (RS_BINS - 1)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < RS_BINS)
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads); returns
+// the exclusive prefix and writes the block total to *total.
+__device__ uint32_t block_exscan_u32(uint32_t v, uint32_t *total) {
+  __shared__ uint32_t wsum[RS_THREADS / 64];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < RS_THREADS / 64; ++k) {
+    uint32_t s = wsum[k];
+    if (k < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+// Stable scatter of one tile: thread t owns items [t*ITEMS, (t+1)*ITEMS) of
+// the tile (blocked arrangement), so (thread, item) order is input order.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t m,
+    int shift, int64_t nblocks, const uint32_t *__restrict__ offs, int first) {
+  __shared__ uint32_t cnt[RS_BINS * RS_THREADS];  // [digit][thread]
+  __shared__ uint32_t dstart[RS_BINS];
+  const int t = threadIdx.x;
+  for (int d = 0; d < RS_BINS; ++d) cnt[d * RS_THREADS + t] = 0;
+  int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)t * RS_ITEMS;
+  uint32_t k[RS_ITEMS], v[RS_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    int64_t e = base + j;
+    if (e < m) {
+      k[j] = kin[e];
+      v[j] = first ? (uint32_t)e : vin[e];
+      cnt[((k[j] >> shift) & (RS_BINS - 1)) * RS_THREADS + t] += 1;
+    }
+  }
+  __syncthreads();
+  // exclusive scan of cnt flattened digit-major; thread t owns 16
+  // consecutive counters
+  uint32_t loc[RS_BINS];
+  uint32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < RS_BINS; ++j) {
+    loc[j] = cnt[t * RS_BINS + j];
+    run += loc[j];
+  }
+  uint32_t tot;
+  uint32_t pre = block_exscan_u32(run, &tot);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RS_BINS; ++j) {
+    cnt[t * RS_BINS + j] = pre;
+    pre += loc[j];
+  }
+  __syncthreads();
+  if (t < RS_BINS) dstart[t] = cnt[t * RS_THREADS];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    int64_t e = base + j;
+    if (e < m) {
+      int d = (k[j] >> shift) & (RS_BINS - 1);
+      uint32_t r = cnt[d * RS_THREADS + t]++;
+      uint64_t pos = (uint64_t)offs[(int64_t)d * nblocks + blockIdx.x] + (r - dstart[d]);
+      if (pos < (uint64_t)m) {
+        kout[pos] = k[j];
+        vout[pos] = v[j];
+      }
+    }
+  }
+}
+
+// Generic exclusive scan of uint32 (reduce-then-scan, recursive).
+constexpr int SC_THREADS = 256, SC_ITEMS = 16, SC_TILE = SC_THREADS * SC_ITEMS;
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(
+    const uint32_t *__restrict__ in, int64_t n, uint32_t *__restrict__ sums) {
+  int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+  for (int j = 0; j < SC_ITEMS; ++j) {
+    int64_t e = base + (int64_t)j * SC_THREADS + threadIdx.x;
+    if (e < n) s += in[e];
+  }
+  uint32_t tot;
+  block_exscan_u32(s, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(
+    const uint32_t *__restrict__ in, int64_t n, const uint32_t *__restrict__ offs,
+    uint32_t *__restrict__ out) {
+  int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+  uint32_t loc[SC_ITEMS];
+  uint32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < SC_ITEMS; ++j) {
+    int64_t e = base + j;
+    loc[j] = e < n ? in[e] : 0u;
+    run += loc[j];
+  }
+  uint32_t tot;
+  uint32_t pre = block_exscan_u32(run, &tot) + (offs ? offs[blockIdx.x] : 0u);
+#pragma unroll
+  for (int j = 0; j < SC_ITEMS; ++j) {
+    int64_t e = base + j;
+    if (e < n) out[e] = pre;
+    pre += loc[j];
+  }
+}
+
+static int64_t scan_tmp_words(int64_t n) {
+  int64_t w = 0;
+  while (n > SC_TILE) {
+    n = (n + SC_TILE - 1) / SC_TILE;
+    w += n + 1;
+  }
+  return w + 1;
+}
+
+static hipError_t exscan_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                             uint32_t *tmp, hipStream_t s) {
+  int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+  if (nb <= 1) {
+    k_scan_down<<<1, SC_THREADS, 0, s>>>(in, n, nullptr, out);
+    return hipGetLastError();
+  }
+  uint32_t *sums = tmp;
+  uint32_t *sums_scan = tmp + nb;  // scanned in place into sums_scan region
+  k_scan_reduce<<<nb, SC_THREADS, 0, s>>>(in, n, sums);
+  hipError_t e = exscan_u32(sums, sums, nb, sums_scan, s);
+  if (e != hipSuccess) return e;
+  k_scan_down<<<nb, SC_THREADS, 0, s>>>(in, n, sums, out);
+  return hipGetLastError();
+}
+
+// ptr[i] = first sorted position whose key >= i, for i in [0, I].
+__global__ void k_row_ptr(const uint32_t *__restrict__ key, int64_t m, int64_t I,
+                          int64_t *__restrict__ ptr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > I) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < i) lo = mid + 1; else hi = mid;
+  }
+  ptr[i] = lo;
+}
+
+__global__ void k_gather_i32(const int32_t *__restrict__ src,
+                             const uint32_t *__restrict__ perm, int64_t m,
+                             int32_t *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) {
+    const uint32_t q = perm[i];
+    dst[i] = q < (uint64_t)m ? src[q] : 0;
+  }
+}
+
+template <class X>
+__global__ void k_gather_val(const X *__restrict__ src, const uint32_t *__restrict__ perm,
+                             int64_t m, X *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) {
+    const uint32_t q = perm[i];
+    dst[i] = q < (uint64_t)m ? src[q] : X(0);
+  }
+}
+
+__global__ void k_copy_u32(const int32_t *__restrict__ src, int64_t m,
+                           uint32_t *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) dst[i] = (uint32_t)src[i];
+}
+
+__global__ void k_iota_u32(uint32_t *__restrict__ dst, int64_t m) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) dst[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n, int threads, int cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <class X>
+static tt_status dev_alloc(tt_index *ix, X **p, size_t count) {
+  void *q = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(X);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return TT_ERR_OOM;
+  }
+  ix->owned.push_back(q);
+  *p = (X *)q;
+  return TT_OK;
+}
+
+template <class X>
+static tt_status upload(tt_index *ix, X **p, const std::vector<X> &h, hipStream_t s) {
+  tt_status st = dev_alloc(ix, p, h.size());
+  if (st != TT_OK) return st;
+  if (!h.empty())
+    TT_HIP(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s));
+  return TT_OK;
+}
+
+#define TT_ST(x)                          \
+  do {                                    \
+    tt_status _s = (x);                   \
+    if (_s != TT_OK) return _s;           \
+  } while (0)
+
+// Host-side partitions from the row pointers of one mode.
+static void partitions(const std::vector<int64_t> &ptr, ModeIndex &md,
+                       std::vector<int64_t> &chunk, std::vector<int32_t> &slot,
+                       std::vector<int32_t> &heavy_row, std::vector<int32_t> &heavy_slot,
+                       std::vector<int32_t> &rows, std::vector<int64_t> &task,
+                       std::vector<int32_t> &row_task) {
+  const int64_t I = md.I;
+  chunk.clear(); slot.clear(); heavy_row.clear(); heavy_slot.clear();
+  rows.clear(); task.clear(); row_task.assign(I + 1, 0);
+  int64_t cur_begin = 0, cur_count = 0, nslot = 0;
+  chunk.push_back(0);
+  task.push_back(0);
+  int32_t max_tpr = 0;
+  for (int64_t i = 0; i < I; ++i) {
+    int64_t b = ptr[i], e = ptr[i + 1], c = e - b;
+    row_task[i] = (int32_t)(task.size() - 1);
+    if (c == 0) continue;
+    rows.push_back((int32_t)i);
+    // Gram tasks
+    int32_t nt = 0;
+    for (int64_t p = b; p < e; p += kGramPiece) {
+      task.push_back(std::min<int64_t>(e, p + kGramPiece));
+      ++nt;
+    }
+    max_tpr = std::max(max_tpr, nt);
+    // streaming chunks
+    if (c > kChunk) {
+      if (cur_count > 0) {
+        chunk.push_back(b);
+        slot.push_back(-1);
+      }
+      heavy_row.push_back((int32_t)i);
+      heavy_slot.push_back((int32_t)nslot);
+      for (int64_t p = b; p < e; p += kChunk) {
+        chunk.push_back(std::min<int64_t>(e, p + kChunk));
+        slot.push_back((int32_t)nslot++);
+      }
+      cur_begin = e;
+      cur_count = 0;
+    } else {
+      if (cur_count + c > kChunk) {
+        chunk.push_back(b);
+        slot.push_back(-1);
+        cur_begin = b;
+        cur_count = 0;
+      }
+      cur_count += c;
+    }
+  }
+  if (cur_count > 0) {
+    chunk.push_back(ptr[I]);
+    slot.push_back(-1);
+  }
+  (void)cur_begin;
+  row_task[I] = (int32_t)(task.size() - 1);
+  heavy_slot.push_back((int32_t)nslot);
+  md.nchunk = (int64_t)slot.size();
+  md.nslot = nslot;
+  md.nheavy = (int64_t)heavy_row.size();
+  md.nrows = (int64_t)rows.size();
+  md.ntask = (int64_t)task.size() - 1;
+  md.max_task_per_row = max_tpr;
+  md.mean_row = md.nrows ? (double)ptr[I] / (double)md.nrows : 0.0;
+}
+
+tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
+                           const int32_t *const *d_idx, const void *d_t,
+                           tt_dtype vdt, hipStream_t s, tt_index *ix) {
+  ix->N = N;
+  ix->m = m;
+  ix->vdt = vdt;
+  ix->has_t = d_t != nullptr || m == 0;  // an empty value set is always available
+  for (int n = 0; n < N; ++n) ix->dims[n] = dims[n];
+  const size_t vsz = vdt == TT_F64 ? 8 : 4;
+
+  // range check
+  int *d_flag = nullptr;
+  TT_HIP(hipMalloc(&d_flag, sizeof(int)));
+  TT_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
+  for (int n = 0; n < N; ++n)
+    if (m > 0)
+      k_range_check<<<grid_for(m, 256, 4096), 256, 0, s>>>(d_idx[n], m, dims[n], d_flag);
+  int h_flag = 0;
+  TT_HIP(hipMemcpyAsync(&h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  TT_HIP(hipStreamSynchronize(s));
+  TT_HIP(hipFree(d_flag));
+  if (h_flag) {
+    set_error("tt_build_index: an index lies outside its dimension");
+    return TT_ERR_INDEX_RANGE;
+  }
+
+  // sort temporaries
+  const int64_t nblocks = std::max<int64_t>(1, (m + RS_TILE - 1) / RS_TILE);
+  const int64_t hn = nblocks * RS_BINS;
+  uint32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr, *hist = nullptr,
+           *offs = nullptr, *tmp = nullptr;
+  const size_t mm = (size_t)std::max<int64_t>(m, 1);
+  hipError_t he = hipSuccess;
+  auto alloc_tmp = [&](uint32_t **p, size_t n) -> bool {
+    he = hipMalloc((void **)p, n * sizeof(uint32_t));
+    return he == hipSuccess;
+  };
+  bool ok = alloc_tmp(&kA, mm) && alloc_tmp(&kB, mm) && alloc_tmp(&vA, mm) &&
+            alloc_tmp(&vB, mm) && alloc_tmp(&hist, hn) && alloc_tmp(&offs, hn) &&
+            alloc_tmp(&tmp, scan_tmp_words(hn));
+  auto free_tmp = [&]() {
+    hipFree(kA); hipFree(kB); hipFree(vA); hipFree(vB);
+    hipFree(hist); hipFree(offs); hipFree(tmp);
+  };
+  if (!ok) {
+    free_tmp();
+    set_error("tt_build_index: temporary allocation failed: %s", hipGetErrorString(he));
+    return TT_ERR_OOM;
+  }
+
+  tt_status st = TT_OK;
+  std::vector<int64_t> h_ptr;
+  for (int n = 0; n < N && st == TT_OK; ++n) {
+    ModeIndex &md = ix->mode[n];
+    md.I = dims[n];
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < dims[n]) ++bits;
+    int passes = (bits + RS_BITS - 1) / RS_BITS;
+    uint32_t *kc = kA, *vc = vA, *kn = kB, *vn = vB;
+    if (m > 0) {
+      k_copy_u32<<<grid_for(m, 256), 256, 0, s>>>(d_idx[n], m, kc);
+      if (passes == 0) k_iota_u32<<<grid_for(m, 256), 256, 0, s>>>(vc, m);
+      for (int p = 0; p < passes; ++p) {
+        int shift = p * RS_BITS;
+        k_rs_hist<<<nblocks, RS_THREADS, 0, s>>>(kc, m, shift, nblocks, hist);
+        if ((he = exscan_u32(hist, offs, hn, tmp, s)) != hipSuccess) break;
+        k_rs_scatter<<<nblocks, RS_THREADS, 0, s>>>(kc, vc, kn, vn, m, shift, nblocks,
+                                                    offs, p == 0);
+        std::swap(kc, kn);
+        std::swap(vc, vn);
+      }
+      if (he == hipSuccess) he = hipGetLastError();
+      if (he != hipSuccess) { st = hip_fail(he, "radix sort"); break; }
+    }
+    // persistent per-mode arrays
+    if ((st = dev_alloc(ix, &md.d_perm, mm)) != TT_OK) break;
+    if ((st = dev_alloc(ix, &md.d_key, mm)) != TT_OK) break;
+    if ((st = dev_alloc(ix, &md.d_ptr, (size_t)dims[n] + 1)) != TT_OK) break;
+    if (m > 0) {
+      hipMemcpyAsync(md.d_perm, vc, m * 4, hipMemcpyDeviceToDevice, s);
+      hipMemcpyAsync(md.d_key, kc, m * 4, hipMemcpyDeviceToDevice, s);
+    }
+    k_row_ptr<<<grid_for(dims[n] + 1, 256, 1 << 30), 256, 0, s>>>(kc, m, dims[n], md.d_ptr);
+    for (int p = 0; p < N; ++p) {
+      if (p == n) continue;
+      if ((st = dev_alloc(ix, &md.d_oidx[p], mm)) != TT_OK) break;
+      if (m > 0)
+        k_gather_i32<<<grid_for(m, 256), 256, 0, s>>>(d_idx[p], vc, m, md.d_oidx[p]);
+    }
+    if (st != TT_OK) break;
+    if (d_t) {
+      void *q = nullptr;
+      if ((he = hipMalloc(&q, mm * vsz)) != hipSuccess) { st = TT_ERR_OOM; break; }
+      ix->owned.push_back(q);
+      md.d_t = q;
+      if (m > 0) {
+        if (vdt == TT_F64)
+          k_gather_val<double><<<grid_for(m, 256), 256, 0, s>>>((const double *)d_t, vc, m,
+                                                                  (double *)q);
+        else
+          k_gather_val<float><<<grid_for(m, 256), 256, 0, s>>>((const float *)d_t, vc, m,
+                                                                 (float *)q);
+      }
+    }
+    // host partitions
+    h_ptr.assign(dims[n] + 1, 0);
+    if ((he = hipMemcpyAsync(h_ptr.data(), md.d_ptr, (dims[n] + 1) * 8,
+                             hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (he = hipStreamSynchronize(s)) != hipSuccess) {
+      st = hip_fail(he, "row pointers");
+      break;
+    }
+    bool mono = h_ptr[0] == 0 && h_ptr[dims[n]] == m;
+    for (int64_t i = 0; mono && i < dims[n]; ++i) mono = h_ptr[i] <= h_ptr[i + 1];
+    if (!mono) {
+      set_error("tt_build_index: internal error, row pointers of mode %d are inconsistent", n);
+      st = TT_ERR_HIP;
+      break;
+    }
+    std::vector<int64_t> chunk, task;
+    std::vector<int32_t> slot, hrow, hslot, rows, row_task;
+    partitions(h_ptr, md, chunk, slot, hrow, hslot, rows, task, row_task);
+    if ((st = upload(ix, &md.d_chunk, chunk, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_chunk_slot, slot, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_heavy_row, hrow, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_heavy_slot, hslot, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_rows, rows, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_task, task, s)) != TT_OK) break;
+    if ((st = upload(ix, &md.d_row_task, row_task, s)) != TT_OK) break;
+    md.h_row_task = row_task;
+    // uploads are asynchronous from pageable vectors: wait before reuse
+    if ((he = hipStreamSynchronize(s)) != hipSuccess) { st = hip_fail(he, "upload"); break; }
+    ix->max_I = std::max(ix->max_I, md.I);
+    ix->sum_I += md.I;
+    ix->max_nchunk = std::max(ix->max_nchunk, md.nchunk);
+    ix->max_nslot = std::max(ix->max_nslot, md.nslot);
+  }
+  hipStreamSynchronize(s);
+  free_tmp();
+  if (st == TT_OK) {
+    he = hipGetLastError();
+    if (he != hipSuccess) st = hip_fail(he, "tt_build_index");
+  }
+  return st;
+}
+
+}  // namespace tt

@@ -1,0 +1,171 @@
+// Host-side internals of libtt: the index object, its workspace and the
+// kernel launchers implemented in the .hip translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+
+namespace tt {
+
+// Work partition constants.
+constexpr int kChunk = 2048;       // nnz per streaming work chunk (max)
+constexpr int kGramPiece = 4096;   // nnz per Gram task (max)
+constexpr int64_t kGramBatchBytes = 128ll << 20;  // Gram workspace per batch
+
+struct ModeIndex {
+  int64_t I = 0;
+  int64_t nrows = 0;            // rows holding >= 1 nonzero
+  int64_t *d_ptr = nullptr;     // I + 1 offsets into the sorted stream
+  int32_t *d_perm = nullptr;    // sorted position -> COO position
+  int32_t *d_key = nullptr;     // sorted mode index
+  int32_t *d_oidx[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  void *d_t = nullptr;          // observed values in this mode's order
+  int32_t *d_rows = nullptr;    // nonzero rows
+  // streaming partition: chunks of whole light rows (<= kChunk nnz) and
+  // single pieces of heavy rows (> kChunk nnz)
+  int64_t nchunk = 0;
+  int64_t *d_chunk = nullptr;       // nchunk + 1 boundaries
+  int32_t *d_chunk_slot = nullptr;  // -1: light chunk; else carry slot
+  int64_t nslot = 0;
+  int64_t nheavy = 0;
+  int32_t *d_heavy_row = nullptr;   // nheavy
+  int32_t *d_heavy_slot = nullptr;  // nheavy + 1
+  // Gram tasks: pieces of <= kGramPiece nnz of one row
+  int64_t ntask = 0;
+  int64_t *d_task = nullptr;        // ntask + 1 boundaries
+  int32_t *d_row_task = nullptr;    // I + 1: tasks of row i
+  std::vector<int32_t> h_row_task;  // host copy, for batching
+  int32_t max_task_per_row = 0;
+  double mean_row = 0.0;            // m / nrows
+};
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace tt
+
+struct tt_index {
+  int N = 0;
+  int64_t dims[TT_MAX_ORDER] = {0, 0, 0, 0};
+  int64_t m = 0;
+  tt_dtype vdt = TT_F32;
+  bool has_t = false;
+  tt::ModeIndex mode[TT_MAX_ORDER];
+  std::vector<void *> owned;                 // device allocations to free
+  std::map<std::string, tt::Buf> ws;         // named workspace buffers
+  int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0;
+};
+
+namespace tt {
+
+// ----- error handling ------------------------------------------------------
+void set_error(const char *fmt, ...);
+tt_status hip_fail(hipError_t e, const char *what);
+#define TT_HIP(call)                                           \
+  do {                                                         \
+    hipError_t _e = (call);                                    \
+    if (_e != hipSuccess) return ::tt::hip_fail(_e, #call);    \
+  } while (0)
+#define TT_CHECK(cond, ...)                                    \
+  do {                                                         \
+    if (!(cond)) {                                             \
+      ::tt::set_error(__VA_ARGS__);                            \
+      return TT_ERR_INVALID_ARG;                               \
+    }                                                          \
+  } while (0)
+
+// Workspace buffer `name` of at least `bytes`, grown (never shrunk) on demand.
+tt_status ws_get(tt_index *ix, const char *name, size_t bytes, void **out);
+
+inline size_t dtype_size(tt_dtype d) { return d == TT_F64 ? 8 : (d == TT_F32 ? 4 : 2); }
+inline size_t value_size(tt_dtype fdt) { return fdt == TT_F64 ? 8 : 4; }
+
+// ----- launchers (return hipError_t of the last launch) ----------------------
+// index.hip
+tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
+                           const int32_t *const *d_idx, const void *d_t,
+                           tt_dtype vdt, hipStream_t s, tt_index *ix);
+
+// stream.hip: per-nonzero and segmented kernels over one mode's sorted stream.
+struct StreamCall {
+  const tt_index *ix;
+  int mode;                 // stream (sorted) order processed
+  int R;
+  int64_t ldA;
+  tt_dtype fdt;
+  const void *A[TT_MAX_ORDER];   // factors (NULL entries allowed for TTTP)
+  const void *X[TT_MAX_ORDER];   // GN direction blocks
+  const void *s;            // per-nonzero values in this mode's order or NULL
+  const int32_t *s_perm;    // if non-NULL, s is in COO order: s[perm[e]]
+  double w_const;
+  int epi, loss;
+  double lam_own;           // GRAD/GN: added lam_own * own row (done by prefill)
+  void *out;                // dense (I x R) or per-nonzero output
+  const int32_t *out_perm;  // TTTP: scatter to out[perm[e]] when non-NULL
+  int accumulate;
+  double *sum_parts;        // TTTP: per-chunk FP64 partial sums (or NULL)
+  double *carry;            // segmented: carry workspace
+  const double *skip;       // optional device flag: launches become no-ops
+};
+enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3 };
+hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s);
+int stream_group_width(tt_dtype fdt, int R);
+int stream_rp(tt_dtype fdt, int R);
+
+// solve.hip: Gram on matrix cores + batched FP64 Cholesky.
+struct SolveCall {
+  const tt_index *ix;
+  int mode, R;
+  int64_t ldA;
+  tt_dtype fdt;
+  const void *A[TT_MAX_ORDER];
+  const void *w;            // weights in this mode's order, or NULL
+  const int32_t *w_perm;    // COO-order weights gathered through perm
+  double w_scale;           // weights are multiplied by this (1 normally)
+  double lambda;
+  const void *rhs;          // I x R dense dtype
+  void *X;                  // I x R in fdt, leading dim ldA (may alias A)
+  int32_t *info;            // optional
+  double *Lstore;           // when non-NULL: keep the Cholesky factors (I x RP x RP)
+  int factor_only;          // 1: factor and store, no solve
+};
+tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);
+// Apply stored factors: X = (L L^T)^{-1} rhs, X dense dtype (not fdt).
+hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt,
+                               const double *Lstore, const void *rhs, void *X,
+                               const double *skip, hipStream_t s);
+
+// vec.hip: dense helpers (dense dtype = double for TT_F64 else float).
+hipError_t launch_fill(void *p, int64_t n, tt_dtype dense, double v, hipStream_t s);
+// y[i*R + r] = a * x[i*ldx + r] (+ b * y) over I rows; x in dtype xdt.
+hipError_t launch_scale_rows(void *y, const void *x, tt_dtype xdt, int64_t ldx,
+                             int64_t I, int R, double a, tt_dtype ydt, hipStream_t s);
+hipError_t launch_sum_doubles(const double *parts, int64_t n, double *out,
+                              int accumulate, hipStream_t s);
+hipError_t launch_sumsq_rows(const void *A, tt_dtype fdt, int64_t ldA, int64_t I,
+                             int R, double scale, double *parts, int64_t *nparts,
+                             hipStream_t s);
+int64_t sumsq_parts_needed(int64_t I, int R);
+
+// PCG vector kernels (blocks concatenated into one contiguous dense array).
+hipError_t launch_dot_parts(const void *x, const void *y, int64_t n, tt_dtype dense,
+                            double *parts, int64_t *nparts, hipStream_t s);
+int64_t dot_parts_needed(int64_t n);
+hipError_t launch_axpy2(void *x, const void *p, void *r, const void *q, int64_t n,
+                        tt_dtype dense, const double *sc, int ia, hipStream_t s);
+hipError_t launch_xpby(void *p, const void *z, int64_t n, tt_dtype dense,
+                       const double *sc, int ib, hipStream_t s);
+hipError_t launch_pcg_scalar(double *sc, int stage, double tol, hipStream_t s);
+// stats[0..3] = iterations, final relative residual, initial residual norm, *f0
+hipError_t launch_pcg_stats(const double *sc, const double *f0, double *stats, hipStream_t s);
+hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
+                                const void *dx, hipStream_t s);
+
+}  // namespace tt

@@ -1,0 +1,92 @@
+// Host dispatch of the streaming kernels: picks the lane-group width G from
+// R and the storage dtype, decides whether the 16-byte vector path applies,
+// and runs the heavy-row carry reduction after segmented operations.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "stream_impl.h"
+
+namespace tt {
+
+hipError_t launch_stream_f32(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
+                             bool vec, hipStream_t s);
+hipError_t launch_stream_bf16(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
+                              bool vec, hipStream_t s);
+hipError_t launch_stream_f64(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
+                             bool vec, hipStream_t s);
+
+static int frag_elems(tt_dtype fdt) { return fdt == TT_F64 ? 2 : (fdt == TT_F32 ? 4 : 8); }
+
+int stream_group_width(tt_dtype fdt, int R) {
+  const int V = frag_elems(fdt);
+  int need = (R + V - 1) / V;
+  int G = 2;
+  while (G < need) G <<= 1;
+  return G;
+}
+
+int stream_rp(tt_dtype fdt, int R) { return stream_group_width(fdt, R) * frag_elems(fdt); }
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
+  const tt_index *ix = c.ix;
+  const ModeIndex &md = ix->mode[c.mode];
+  const int V = frag_elems(c.fdt);
+  const int G = stream_group_width(c.fdt, c.R);
+  StreamDev d = {};
+  d.chunk = md.d_chunk;
+  d.chunk_slot = md.d_chunk_slot;
+  d.key = md.d_key;
+  bool vec = (c.R % V == 0) && (c.ldA % V == 0);
+  int q = 0;
+  for (int p = 0; p < ix->N; ++p) {
+    if (p == c.mode) continue;
+    d.oidx[q] = md.d_oidx[p];
+    d.A_oth[q] = c.A[p];
+    d.X_oth[q] = c.X[p];
+    if (c.A[p] && !aligned16(c.A[p])) vec = false;
+    if (c.X[p] && !aligned16(c.X[p])) vec = false;
+    ++q;
+  }
+  d.A_own = c.A[c.mode];
+  d.X_own = c.X[c.mode];
+  if (d.A_own && !aligned16(d.A_own)) vec = false;
+  if (d.X_own && !aligned16(d.X_own)) vec = false;
+  if (op != OP_TTTP && !aligned16(c.out)) vec = false;
+  d.s = c.s;
+  d.s_perm = c.s_perm;
+  d.w_const = c.w_const;
+  d.R = c.R;
+  d.ldA = c.ldA;
+  d.epi = c.epi;
+  d.loss = c.loss;
+  d.out = c.out;
+  d.out_perm = c.out_perm;
+  d.accumulate = c.accumulate;
+  d.sum_parts = c.sum_parts;
+  d.carry = c.carry;
+  d.skip = c.skip;
+  hipError_t e;
+  if (c.fdt == TT_F32)
+    e = launch_stream_f32(op, d, md.nchunk, G, vec, s);
+  else if (c.fdt == TT_BF16)
+    e = launch_stream_bf16(op, d, md.nchunk, G, vec, s);
+  else
+    e = launch_stream_f64(op, d, md.nchunk, G, vec, s);
+  if (e != hipSuccess) return e;
+  if (op != OP_TTTP && md.nheavy > 0) {
+    const int RP = G * V;
+    if (c.fdt == TT_F64)
+      k_heavy_fixup<double><<<(unsigned)md.nheavy, 256, 0, s>>>(
+          md.d_heavy_row, md.d_heavy_slot, c.carry, RP, c.R, c.out, c.accumulate, c.skip);
+    else
+      k_heavy_fixup<float><<<(unsigned)md.nheavy, 256, 0, s>>>(
+          md.d_heavy_row, md.d_heavy_slot, c.carry, RP, c.R, c.out, c.accumulate, c.skip);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace tt

@@ -1,0 +1,279 @@
+// Dense helper kernels: fills, row scaling (regularization terms), FP64
+// reductions with a fixed order, and the vector/scalar steps of the
+// preconditioned conjugate gradient used by the Gauss-Newton iteration
+// (Section 2.5).  Reductions are two-level (per-block FP64 partials, then one
+// block summing the partials in index order), so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tt {
+
+constexpr int VT_THREADS = 256;
+constexpr int RED_BLOCKS = 1024;  // max partials of a two-level reduction
+
+static int grid_cap(int64_t n, int cap) {
+  int64_t g = (n + VT_THREADS - 1) / VT_THREADS;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <class X>
+__global__ void k_fill(X *p, int64_t n, X v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill(void *p, int64_t n, tt_dtype dense, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dense == TT_F64)
+    k_fill<double><<<grid_cap(n, 8192), VT_THREADS, 0, s>>>((double *)p, n, v);
+  else
+    k_fill<float><<<grid_cap(n, 8192), VT_THREADS, 0, s>>>((float *)p, n, (float)v);
+  return hipGetLastError();
+}
+
+template <class XT, class YT>
+__global__ void k_scale_rows(YT *y, const XT *x, int64_t ldx, int64_t I, int R, double a) {
+  const int64_t n = I * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / R;
+    const int r = (int)(i - row * R);
+    y[i] = (YT)(a * to_double<XT>(x[row * ldx + r]));
+  }
+}
+
+hipError_t launch_scale_rows(void *y, const void *x, tt_dtype xdt, int64_t ldx,
+                             int64_t I, int R, double a, tt_dtype ydt, hipStream_t s) {
+  const int64_t n = I * R;
+  if (n <= 0) return hipSuccess;
+  const int g = grid_cap(n, 8192);
+  if (ydt == TT_F64) {
+    k_scale_rows<double, double><<<g, VT_THREADS, 0, s>>>((double *)y, (const double *)x,
+                                                          ldx, I, R, a);
+  } else if (xdt == TT_F32) {
+    k_scale_rows<float, float><<<g, VT_THREADS, 0, s>>>((float *)y, (const float *)x, ldx,
+                                                        I, R, a);
+  } else if (xdt == TT_BF16) {
+    k_scale_rows<uint16_t, float><<<g, VT_THREADS, 0, s>>>((float *)y, (const uint16_t *)x,
+                                                           ldx, I, R, a);
+  } else {
+    k_scale_rows<double, float><<<g, VT_THREADS, 0, s>>>((float *)y, (const double *)x,
+                                                         ldx, I, R, a);
+  }
+  return hipGetLastError();
+}
+
+// Block-level FP64 sum in a fixed order (wave butterfly, then waves in order).
+__device__ double block_sum_d(double v) {
+  __shared__ double part[VT_THREADS / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < VT_THREADS / 64; ++w) s += part[w];
+  __syncthreads();
+  return s;
+}
+
+__global__ void k_sum_doubles(const double *parts, int64_t n, double *out, int accumulate) {
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += parts[i];
+  const double s = block_sum_d(v);
+  if (threadIdx.x == 0) *out = accumulate ? *out + s : s;
+}
+
+hipError_t launch_sum_doubles(const double *parts, int64_t n, double *out, int accumulate,
+                              hipStream_t s) {
+  k_sum_doubles<<<1, VT_THREADS, 0, s>>>(parts, n, out, accumulate);
+  return hipGetLastError();
+}
+
+template <class XT>
+__global__ void k_sumsq_rows(const XT *A, int64_t ldA, int64_t I, int R, double scale,
+                             double *parts) {
+  const int64_t n = I * R;
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / R;
+    const double a = to_double<XT>(A[row * ldA + (i - row * R)]);
+    v += a * a;
+  }
+  const double s = block_sum_d(v);
+  if (threadIdx.x == 0) parts[blockIdx.x] = scale * s;
+}
+
+int64_t sumsq_parts_needed(int64_t I, int R) { return grid_cap(I * (int64_t)R, RED_BLOCKS); }
+
+hipError_t launch_sumsq_rows(const void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
+                             double scale, double *parts, int64_t *nparts, hipStream_t s) {
+  const int g = grid_cap(I * (int64_t)R, RED_BLOCKS);
+  *nparts = g;
+  if (fdt == TT_F64)
+    k_sumsq_rows<double><<<g, VT_THREADS, 0, s>>>((const double *)A, ldA, I, R, scale, parts);
+  else if (fdt == TT_F32)
+    k_sumsq_rows<float><<<g, VT_THREADS, 0, s>>>((const float *)A, ldA, I, R, scale, parts);
+  else
+    k_sumsq_rows<uint16_t><<<g, VT_THREADS, 0, s>>>((const uint16_t *)A, ldA, I, R, scale, parts);
+  return hipGetLastError();
+}
+
+template <class X>
+__global__ void k_dot_parts(const X *x, const X *y, int64_t n, double *parts) {
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v += (double)x[i] * (double)y[i];
+  const double s = block_sum_d(v);
+  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+}
+
+int64_t dot_parts_needed(int64_t n) { return grid_cap(n, RED_BLOCKS); }
+
+hipError_t launch_dot_parts(const void *x, const void *y, int64_t n, tt_dtype dense,
+                            double *parts, int64_t *nparts, hipStream_t s) {
+  const int g = grid_cap(n, RED_BLOCKS);
+  *nparts = g;
+  if (dense == TT_F64)
+    k_dot_parts<double><<<g, VT_THREADS, 0, s>>>((const double *)x, (const double *)y, n, parts);
+  else
+    k_dot_parts<float><<<g, VT_THREADS, 0, s>>>((const float *)x, (const float *)y, n, parts);
+  return hipGetLastError();
+}
+
+// PCG scalar slots (device doubles).
+enum {
+  SC_RZ = 0, SC_PHP = 1, SC_RR = 2, SC_R0 = 3, SC_RZNEW = 4, SC_DONE = 5,
+  SC_ITERS = 6, SC_ALPHA = 7, SC_BETA = 8, SC_REL = 9
+};
+
+// x += alpha p; r -= alpha q   (skipped once converged)
+template <class X>
+__global__ void k_axpy2(X *x, const X *p, X *r, const X *q, int64_t n, const double *sc) {
+  if (sc[SC_DONE] != 0.0) return;
+  const double a = sc[SC_ALPHA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] = (X)((double)x[i] + a * (double)p[i]);
+    r[i] = (X)((double)r[i] - a * (double)q[i]);
+  }
+}
+
+hipError_t launch_axpy2(void *x, const void *p, void *r, const void *q, int64_t n,
+                        tt_dtype dense, const double *sc, int ia, hipStream_t s) {
+  (void)ia;
+  const int g = grid_cap(n, 8192);
+  if (dense == TT_F64)
+    k_axpy2<double><<<g, VT_THREADS, 0, s>>>((double *)x, (const double *)p, (double *)r,
+                                             (const double *)q, n, sc);
+  else
+    k_axpy2<float><<<g, VT_THREADS, 0, s>>>((float *)x, (const float *)p, (float *)r,
+                                            (const float *)q, n, sc);
+  return hipGetLastError();
+}
+
+// p = z + beta p   (skipped once converged)
+template <class X>
+__global__ void k_xpby(X *p, const X *z, int64_t n, const double *sc) {
+  if (sc[SC_DONE] != 0.0) return;
+  const double b = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (X)((double)z[i] + b * (double)p[i]);
+}
+
+hipError_t launch_xpby(void *p, const void *z, int64_t n, tt_dtype dense, const double *sc,
+                       int ib, hipStream_t s) {
+  (void)ib;
+  const int g = grid_cap(n, 8192);
+  if (dense == TT_F64)
+    k_xpby<double><<<g, VT_THREADS, 0, s>>>((double *)p, (const double *)z, n, sc);
+  else
+    k_xpby<float><<<g, VT_THREADS, 0, s>>>((float *)p, (const float *)z, n, sc);
+  return hipGetLastError();
+}
+
+// Scalar steps of PCG.
+//  stage 0 (after z0 = P^{-1} r0, rz = r.z, rr = r.r): r0 = sqrt(rr); done if r0 == 0
+//  stage 1 (after pHp = p.Hp): alpha = rz / pHp
+//  stage 2 (after rr = r.r): rel = sqrt(rr) / r0; iters += 1; done if rel <= tol
+//  stage 3 (after rznew = r.z): beta = rznew / rz; rz = rznew
+__global__ void k_pcg_scalar(double *sc, int stage, double tol) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (stage == 0) {
+    sc[SC_R0] = sqrt(sc[SC_RR]);
+    sc[SC_ITERS] = 0.0;
+    sc[SC_REL] = 1.0;
+    sc[SC_DONE] = (sc[SC_R0] == 0.0) ? 1.0 : 0.0;
+    if (sc[SC_R0] == 0.0) sc[SC_REL] = 0.0;
+    return;
+  }
+  if (sc[SC_DONE] != 0.0) return;
+  if (stage == 1) {
+    sc[SC_ALPHA] = sc[SC_RZ] / sc[SC_PHP];
+  } else if (stage == 2) {
+    const double rel = sqrt(sc[SC_RR]) / sc[SC_R0];
+    sc[SC_REL] = rel;
+    sc[SC_ITERS] += 1.0;
+    if (rel <= tol) sc[SC_DONE] = 1.0;
+  } else if (stage == 3) {
+    sc[SC_BETA] = sc[SC_RZNEW] / sc[SC_RZ];
+    sc[SC_RZ] = sc[SC_RZNEW];
+  }
+}
+
+hipError_t launch_pcg_scalar(double *sc, int stage, double tol, hipStream_t s) {
+  k_pcg_scalar<<<1, 64, 0, s>>>(sc, stage, tol);
+  return hipGetLastError();
+}
+
+__global__ void k_pcg_stats(const double *sc, const double *f0, double *stats) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  stats[0] = sc[SC_ITERS];
+  stats[1] = sc[SC_REL];
+  stats[2] = sc[SC_R0];
+  stats[3] = f0 ? *f0 : 0.0;
+}
+
+hipError_t launch_pcg_stats(const double *sc, const double *f0, double *stats, hipStream_t s) {
+  k_pcg_stats<<<1, 64, 0, s>>>(sc, f0, stats);
+  return hipGetLastError();
+}
+
+// A[i, r] += dx[i * R + r]  (storage dtype; bfloat16 rounded to nearest even)
+template <class T, class D>
+__global__ void k_add_to_factor(T *A, int64_t ldA, int64_t I, int R, const D *dx) {
+  const int64_t n = I * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / R;
+    T *p = A + row * ldA + (i - row * R);
+    *p = from_double<T>(to_double<T>(*p) + (double)dx[i]);
+  }
+}
+
+hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
+                                const void *dx, hipStream_t s) {
+  const int64_t n = I * R;
+  if (n <= 0) return hipSuccess;
+  const int g = grid_cap(n, 8192);
+  if (fdt == TT_F64)
+    k_add_to_factor<double, double><<<g, VT_THREADS, 0, s>>>((double *)A, ldA, I, R,
+                                                             (const double *)dx);
+  else if (fdt == TT_F32)
+    k_add_to_factor<float, float><<<g, VT_THREADS, 0, s>>>((float *)A, ldA, I, R,
+                                                           (const float *)dx);
+  else
+    k_add_to_factor<uint16_t, float><<<g, VT_THREADS, 0, s>>>((uint16_t *)A, ldA, I, R,
+                                                              (const float *)dx);
+  return hipGetLastError();
+}
+
+}  // namespace tt

@@ -1,0 +1,359 @@
+"""GPU parity of the libtt primitives against the FP64 oracle, through the
+C ABI (ctypes binding).  Small tensors spanning several work chunks, heavy
+rows (> one chunk, > one Gram task), ragged ranks and every storage dtype."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1910_02371_amd import workloads as W
+from gpu_helpers import (TAU, TAU_BF16_VS_F32, assert_close_abs, backward_error, dev_factor,
+                         dev_idx, dev_vals, host, stored_factors, stored_values)
+
+pytestmark = pytest.mark.gpu
+
+
+def make_case(kind, seed=1):
+    if kind == "uniform":
+        wl = W.random_tensor((37, 41, 29), 3000, seed, rank=3)
+    elif kind == "heavy":
+        # mode-0 rows of ~5000 nonzeros: several streaming chunks and two
+        # Gram tasks per row
+        wl = W.random_tensor((3, 300, 200), 15000, seed, rank=2)
+    elif kind == "zipf":
+        rng = W.rng_for(seed)
+        idx, _ = W.zipf_coords(rng, (3000, 400, 60), 60000, chunk=1 << 16)
+        P = [rng.random((d, 4)) for d in (3000, 400, 60)]
+        t = W._planted_values(idx, P)
+        wl = W.Workload("zipf", (3000, 400, 60), idx, t, P)
+    else:
+        raise ValueError(kind)
+    return wl
+
+
+def factors(dims, R, seed, positive=False):
+    rng = np.random.default_rng(seed)
+    if positive:
+        return [rng.random((d, R)) for d in dims]
+    return [rng.standard_normal((d, R)) * 0.5 for d in dims]
+
+
+_IX = {}
+
+
+def get_index(tt, kind, form):
+    key = (kind, form)
+    if key not in _IX:
+        wl = make_case(kind)
+        ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(wl.t, form))
+        _IX[key] = (wl, ix)
+    return _IX[key]
+
+
+# ---------------------------------------------------------------- index ----
+@pytest.mark.parametrize("case", ["uniform", "heavy", "zipf", "sorted", "reverse",
+                                  "one_row", "empty_rows", "single"])
+def test_index_bit_exact(gpu_lib, case):
+    tt = gpu_lib
+    rng = np.random.default_rng(5)
+    if case in ("uniform", "heavy", "zipf"):
+        wl = make_case(case)
+        idx, dims = wl.idx, wl.dims
+    else:
+        dims = (50, 7, 300)
+        m = 5000
+        idx = [rng.integers(0, d, m) for d in dims]
+        if case == "sorted":
+            o = np.lexsort((idx[2], idx[1], idx[0]))
+            idx = [a[o] for a in idx]
+        elif case == "reverse":
+            o = np.lexsort((idx[2], idx[1], idx[0]))[::-1]
+            idx = [a[o] for a in idx]
+        elif case == "one_row":
+            idx[0][:] = 17
+        elif case == "empty_rows":
+            idx[2] = (idx[2] // 10) * 10
+        elif case == "single":
+            idx = [np.array([49]), np.array([0]), np.array([123])]
+    ix = tt.build_index(dev_idx(idx), dims)
+    ref = O.build_index(idx, dims)
+    for n in range(3):
+        ptr, perm, key, rows = ix.view(n)
+        r = ref[n]
+        assert np.array_equal(ptr.cpu().numpy(), r["ptr"]), f"ptr mode {n}"
+        assert np.array_equal(perm.cpu().numpy(), r["perm"]), f"perm mode {n}"
+        assert np.array_equal(key.cpu().numpy(), r["key"]), f"key mode {n}"
+        assert np.array_equal(rows.cpu().numpy(), r["rows"]), f"rows mode {n}"
+        for p in range(3):
+            if p != n:
+                assert np.array_equal(ix.other(n, p).cpu().numpy(), r["other"][p])
+
+
+def test_index_range_error(gpu_lib):
+    tt = gpu_lib
+    idx = [np.array([0, 1, 2]), np.array([0, 5, 1]), np.array([0, 0, 0])]
+    with pytest.raises(tt.TTError) as e:
+        tt.build_index(dev_idx(idx), (3, 5, 1))
+    assert e.value.status == -2
+
+
+def test_index_empty(gpu_lib):
+    tt = gpu_lib
+    idx = [np.zeros(0, np.int32)] * 3
+    ix = tt.build_index(dev_idx(idx), (4, 5, 6), dev_vals(np.zeros(0), "f32"))
+    A = [dev_factor(np.ones((d, 4)), "f32") for d in (4, 5, 6)]
+    Y = tt.mttkrp(ix, tt.INDEX_T, A, 1)
+    assert torch.count_nonzero(Y).item() == 0
+    _, s = tt.tttp(ix, tt.INDEX_T, A, out=False, epi="phi", want_sum=True)
+    assert s.item() == 0.0
+
+
+# ----------------------------------------------------------------- TTTP ----
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [1, 10, 13, 16, 32, 64])
+@pytest.mark.parametrize("kind", ["uniform", "heavy"])
+def test_tttp_parity(gpu_lib, form, R, kind):
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 100 + R)
+    As = stored_factors(A64, form)
+    s = stored_values(wl.t, form)
+    A = [dev_factor(a, form) for a in A64]
+    x = host(tt.tttp(ix, dev_vals(s, form), A))
+    ref = O.tttp(wl.idx, s, As)
+    ref_abs = O.tttp(wl.idx, np.abs(s), [np.abs(a) for a in As])
+    assert_close_abs(x, ref, ref_abs, TAU[form], f"tttp {form} R={R}")
+    if form == "bf16":
+        ref32 = O.tttp(wl.idx, s, A64)
+        abs32 = O.tttp(wl.idx, np.abs(s), [np.abs(a) for a in A64])
+        assert_close_abs(x, ref32, abs32, TAU_BF16_VS_F32, "tttp bf16 vs unrounded")
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_tttp_orders_skips_and_sum(gpu_lib, form):
+    tt = gpu_lib
+    wl, ix = get_index(tt, "uniform", form)
+    R = 8
+    A64 = factors(wl.dims, R, 7)
+    As = stored_factors(A64, form)
+    s = stored_values(wl.t, form)
+    A = [dev_factor(a, form) for a in A64]
+    ref = O.tttp(wl.idx, s, As)
+    ref_abs = O.tttp(wl.idx, np.abs(s), [np.abs(a) for a in As])
+    for n in range(3):
+        perm = O.build_index(wl.idx, wl.dims)[n]["perm"]
+        # values in mode order, output in mode order
+        xs = host(tt.tttp(ix, dev_vals(s[perm], form), A, s_order=n, out_order=n))
+        assert_close_abs(xs, ref[perm], ref_abs[perm], TAU[form], f"tttp order {n}")
+        # COO values, mode-order output
+        xs = host(tt.tttp(ix, dev_vals(s, form), A, s_order=-1, out_order=n))
+        assert_close_abs(xs, ref[perm], ref_abs[perm], TAU[form], f"tttp coo->{n}")
+    # skipped mode (Section 3.3: the product runs over the provided modes)
+    for skip in range(3):
+        Ask = [None if n == skip else A[n] for n in range(3)]
+        Aok = [None if n == skip else As[n] for n in range(3)]
+        x = host(tt.tttp(ix, dev_vals(s, form), Ask))
+        r = O.tttp(wl.idx, s, Aok)
+        ra = O.tttp(wl.idx, np.abs(s), [None if a is None else np.abs(a) for a in Aok])
+        assert_close_abs(x, r, ra, TAU[form], f"tttp skip {skip}")
+    # Omega-hat and the FP64 sum
+    x, tot = tt.tttp(ix, None, A, want_sum=True)
+    r = O.tttp(wl.idx, None, As)
+    ra = O.tttp(wl.idx, None, [np.abs(a) for a in As])
+    assert_close_abs(host(x), r, ra, TAU[form], "tttp omega-hat")
+    assert abs(tot.item() - r.sum()) <= TAU[form] * ra.sum()
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+@pytest.mark.parametrize("epi", ["resid", "phi", "dphi", "d2phi"])
+def test_tttp_epilogues(gpu_lib, form, loss, epi):
+    tt = gpu_lib
+    wl, ix = get_index(tt, "uniform", form)
+    R = 16
+    A64 = factors(wl.dims, R, 3, positive=True)
+    A64 = [a * 0.4 for a in A64]
+    As = stored_factors(A64, form)
+    t = stored_values(np.abs(np.round(wl.t)), form) if loss == "poisson" else \
+        stored_values(wl.t, form)
+    tdev = dev_vals(t, form)
+    ix2 = tt.build_index(dev_idx(wl.idx), wl.dims, tdev)
+    A = [dev_factor(a, form) for a in A64]
+    x, tot = tt.tttp(ix2, tt.INDEX_T, A, epi=epi, loss=loss, want_sum=True)
+    m = O.tttp(wl.idx, None, As)
+    m_abs = O.tttp(wl.idx, None, [np.abs(a) for a in As])
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    f = {"resid": lambda: t - m, "phi": lambda: O.phi(t, m, L),
+         "dphi": lambda: O.dphi(t, m, L), "d2phi": lambda: O.d2phi(t, m, L)}[epi]()
+    # error in m propagates through the epilogue's slope
+    slope = {"resid": np.ones_like(m), "phi": np.abs(O.dphi(t, m, L)),
+             "dphi": np.abs(O.d2phi(t, m, L)), "d2phi": np.abs(O.d2phi(t, m, L))}[epi]
+    fabs = np.abs(f) + slope * m_abs + (np.abs(t) if epi in ("resid", "phi", "dphi") else 0)
+    assert_close_abs(host(x), f, fabs, 4 * TAU[form], f"epi {epi}")
+    assert abs(tot.item() - f.sum()) <= 4 * TAU[form] * fabs.sum()
+
+
+# --------------------------------------------------------------- MTTKRP ----
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [1, 10, 16, 32, 64])
+@pytest.mark.parametrize("kind", ["uniform", "heavy", "zipf"])
+def test_mttkrp_parity(gpu_lib, form, R, kind):
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 200 + R)
+    As = stored_factors(A64, form)
+    s = stored_values(wl.t, form)
+    A = [dev_factor(a, form) for a in A64]
+    for n in range(3):
+        Y = host(tt.mttkrp(ix, tt.INDEX_T, A, n))
+        ref = O.mttkrp(wl.idx, s, As, n, wl.dims[n])
+        ref_abs = O.mttkrp(wl.idx, np.abs(s), [np.abs(a) for a in As], n, wl.dims[n])
+        assert_close_abs(Y, ref, ref_abs, TAU[form], f"mttkrp {form} R={R} mode {n}")
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_mttkrp_weights_orders_accumulate(gpu_lib, form):
+    tt = gpu_lib
+    wl, ix = get_index(tt, "heavy", form)
+    R = 12
+    A64 = factors(wl.dims, R, 9)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(3)
+    w = stored_values(rng.standard_normal(wl.nnz), form)
+    for n in range(3):
+        ref = O.mttkrp(wl.idx, w, As, n, wl.dims[n])
+        ref_abs = O.mttkrp(wl.idx, np.abs(w), [np.abs(a) for a in As], n, wl.dims[n])
+        Y = host(tt.mttkrp(ix, dev_vals(w, form), A, n, s_order=-1))
+        assert_close_abs(Y, ref, ref_abs, TAU[form], f"coo weights mode {n}")
+        perm = O.build_index(wl.idx, wl.dims)[n]["perm"]
+        Y = host(tt.mttkrp(ix, dev_vals(w[perm], form), A, n, s_order=n))
+        assert_close_abs(Y, ref, ref_abs, TAU[form], f"sorted weights mode {n}")
+        # Omega-hat
+        Y = host(tt.mttkrp(ix, None, A, n))
+        r1 = O.mttkrp(wl.idx, None, As, n, wl.dims[n])
+        ra = O.mttkrp(wl.idx, None, [np.abs(a) for a in As], n, wl.dims[n])
+        assert_close_abs(Y, r1, ra, TAU[form], f"omega-hat mode {n}")
+        # accumulate
+        base = torch.full((wl.dims[n], R), 0.5, dtype=torch.float64 if form == "f64"
+                          else torch.float32, device="cuda")
+        Y = host(tt.mttkrp(ix, None, A, n, out=base, accumulate=True))
+        assert_close_abs(Y, r1 + 0.5, ra + 0.5, TAU[form], f"accumulate mode {n}")
+
+
+# ---------------------------------------------------------- solve factor ----
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [1, 10, 16, 32, 64])
+@pytest.mark.parametrize("kind", ["uniform", "heavy"])
+def test_solve_factor_parity(gpu_lib, form, R, kind):
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 300 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    lam = 0.05
+    rng = np.random.default_rng(R)
+    for n in range(3):
+        M = stored_values(rng.standard_normal((wl.dims[n], R)), form)
+        Md = dev_vals(M, form)
+        X, info = tt.solve_factor(ix, None, A, n, Md, lam)
+        X = host(X)
+        assert (info.cpu().numpy() == 0).all()
+        G = O.gram(wl.idx, None, As, n, wl.dims[n])
+        tau = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}[form]
+        be = backward_error(G, lam, X, M)
+        assert be <= tau, f"backward error {be:.3e} (mode {n})"
+        Xr, _ = O.solve_rows(G, M, lam)
+        if form == "f64":
+            np.testing.assert_allclose(X, Xr, rtol=1e-8, atol=1e-10)
+
+
+def test_solve_factor_weights_and_info(gpu_lib):
+    tt = gpu_lib
+    form = "f64"
+    wl, ix = get_index(tt, "uniform", form)
+    R = 6
+    A64 = factors(wl.dims, R, 11)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(2)
+    w = rng.random(wl.nnz) + 0.2
+    M = rng.standard_normal((wl.dims[1], R))
+    X, info = tt.solve_factor(ix, dev_vals(w, form), A, 1, dev_vals(M, form), 0.3, w_order=-1)
+    G = O.gram(wl.idx, w, A64, 1, wl.dims[1])
+    Xr, _ = O.solve_rows(G, M, 0.3)
+    np.testing.assert_allclose(host(X), Xr, rtol=1e-9, atol=1e-11)
+    # negative weights making rows indefinite, lambda = 0: LAPACK info, x = 0
+    wneg = -np.ones(wl.nnz)
+    X, info = tt.solve_factor(ix, dev_vals(wneg, form), A, 1, dev_vals(M, form), 0.0,
+                              w_order=-1)
+    Gn = O.gram(wl.idx, wneg, A64, 1, wl.dims[1])
+    _, ir = O.solve_rows(Gn, M, 0.0)
+    assert np.array_equal(info.cpu().numpy(), ir)
+    assert (host(X)[ir != 0] == 0).all()
+    with pytest.raises(tt.TTError) as e:
+        tt.solve_factor(ix, dev_vals(wneg, form), A, 1, dev_vals(M, form), 0.0, w_order=-1,
+                        sync=True)
+    assert e.value.status == -5
+
+
+# ------------------------------------------------------ gradient / GN ----
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+@pytest.mark.parametrize("kind", ["uniform", "heavy"])
+def test_gradient_and_objective(gpu_lib, form, loss, kind):
+    tt = gpu_lib
+    wl = make_case(kind)
+    R = 16
+    A64 = [0.5 * a for a in factors(wl.dims, R, 17, positive=True)]
+    As = stored_factors(A64, form)
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    t = np.abs(np.round(wl.t)) if loss == "poisson" else wl.t
+    t = stored_values(t, form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    A = [dev_factor(a, form) for a in A64]
+    lam = 0.1
+    G = host(tt.gradient(ix, A, loss, lam))
+    ref = O.gradient(wl.idx, t, As, L, lam, wl.dims)
+    m = O.tttp(wl.idx, None, As)
+    m_abs = O.tttp(wl.idx, None, [np.abs(a) for a in As])
+    d1 = np.abs(O.dphi(t, m, L)) + np.abs(O.d2phi(t, m, L)) * m_abs
+    for d in range(3):
+        ra = O.mttkrp(wl.idx, d1, [np.abs(a) for a in As], d, wl.dims[d]) + \
+            2 * lam * np.abs(As[d])
+        assert_close_abs(G[d], ref[d], ra, 4 * TAU[form], f"gradient mode {d}")
+    f = tt.objective(ix, A, loss, lam).item()
+    fr = O.objective(wl.idx, t, As, L, lam)
+    fabs = np.sum(np.abs(O.phi(t, m, L)) + np.abs(O.dphi(t, m, L)) * m_abs) + \
+        lam * sum(np.sum(a * a) for a in As)
+    assert abs(f - fr) <= 4 * TAU[form] * fabs
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("weights", ["const", "per_mode"])
+@pytest.mark.parametrize("kind", ["uniform", "heavy"])
+def test_gn_matvec_parity(gpu_lib, form, weights, kind):
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    R = 16
+    A64 = factors(wl.dims, R, 23)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(4)
+    X64 = [stored_values(rng.standard_normal((d, R)), form) for d in wl.dims]
+    Xd = [dev_vals(x, form) for x in X64]
+    lam2 = 0.2
+    if weights == "const":
+        w = np.full(wl.nnz, 2.0)
+        Y = tt.gn_matvec(ix, None, A, Xd, lam2, w_const=2.0)
+    else:
+        w = stored_values(rng.random(wl.nnz) + 0.5, form)
+        ixs = O.build_index(wl.idx, wl.dims)
+        wd = [dev_vals(w[ixs[d]["perm"]], form) for d in range(3)]
+        Y = tt.gn_matvec(ix, wd, A, Xd, lam2)
+    Y = host(Y)
+    ref = O.gn_matvec(wl.idx, w, As, X64, lam2, wl.dims)
+    z_abs = O.jvp(wl.idx, [np.abs(a) for a in As], [np.abs(x) for x in X64])
+    for d in range(3):
+        ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
+            lam2 * np.abs(X64[d])
+        assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn mode {d}")
