@@ -1,0 +1,285 @@
+#!/usr/bin/env python3
+"""Benchmark of the completion hot path on one MI355X.
+
+One step = one pass of the whole hot path over the resident tensor:
+  * one ALS sweep: per mode MTTKRP of t (right-hand sides) and Solve Factor
+    (Gram on matrix cores + FP64 Cholesky) -- Sections 2.2, 3.2, 3.4;
+  * one preconditioned Gauss-Newton step with ``--cg`` CG iterations: the
+    objective through the TTTP loss epilogue, the fused gradient adjoint,
+    the block-diagonal preconditioner factorization, and per CG iteration one
+    fused implicit GN matvec plus one preconditioner application -- Sections
+    2.5 and 3.3.
+The index (per-mode stable sort) is built once before timing and reported
+separately.  ``value`` counts nonzero-rank products: m * R for every pass
+over the nonzeros (TTTP, MTTKRP, gradient and GN-matvec passes, Gram passes)
+divided by the step time.
+
+Prints ONE JSON line.  Single GPU only.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MTTKRP+TTTP nnz·R/s, %HBM peak; ALS/GN sweep s, BF16 vs FP32 @ equal RMSE"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--R", type=int, default=64)
+    p.add_argument("--form", choices=["f32", "bf16"], default="f32")
+    p.add_argument("--cg", type=int, default=2, help="CG iterations in the GN step")
+    p.add_argument("--nnz", type=int, default=100_000_000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=1 << 18)
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1910_02371_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, workload, src_hash):
+    """HBM traffic per launch measured with rocprofv3 counters, if a committed
+    summary for this kernel, workload and kernel source exists."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{kernel}|{workload}")
+    except Exception:
+        return None
+    if not rec or rec.get("src_hash") != src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path is measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1910_02371_amd import tt, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    tt.lib()
+
+    t0 = time.time()
+    wl = W.ratings(m=args.nnz)
+    gen_s = time.time() - t0
+    log(f"generated {wl.name}: {wl.nnz} nnz in {gen_s:.1f}s")
+    R = args.R
+    lam = 1e-5
+    fdt_t = torch.float32 if args.form == "f32" else torch.bfloat16
+    idx = [torch.as_tensor(i).to(dev) for i in wl.idx]
+    t = torch.as_tensor(wl.t).to(dev)
+    A0 = W.init_factors(wl.dims, R, float(np.mean(wl.t)), W.SEED_INIT + 2, dtype=np.float32)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ix = tt.build_index(idx, wl.dims, t)
+    torch.cuda.synchronize()
+    index_s = time.time() - t0
+    log(f"index built in {index_s:.2f}s")
+    del idx
+    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]))
+    A = [torch.as_tensor(a).to(dev).to(fdt_t).contiguous() for a in A0]
+    m = wl.nnz
+
+    stream = torch.cuda.current_stream()
+    names = []
+    events = []
+
+    def timed(name, fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        names.append(name)
+        events.append((e0, e1))
+
+    # per-mode right-hand sides and direction blocks for the separately timed
+    # kernels of the step
+    M = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    fsum = torch.zeros((), dtype=torch.float64, device=dev)
+
+    def step(record):
+        run = timed if record else (lambda n, f: f())
+        for n in range(3):
+            run(f"mttkrp{n}", lambda n=n: tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n]))
+            run(f"solve{n}", lambda n=n: tt.solve_factor(ix, None, A, n, M[n], lam, X=A[n]))
+        run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
+                                          stats=stats))
+
+    # separately timed single kernels (same launch configuration as the step)
+    def kernels(record):
+        run = timed if record else (lambda n, f: f())
+        run("tttp_loss", lambda: tt.tttp(ix, tt.INDEX_T, A, out=False, epi="phi",
+                                         want_sum=True))
+        G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
+        run("gradient", lambda: tt.gradient(ix, A, "ls", lam, G=G))
+        X = [g.clone() for g in G]
+        Y = [torch.empty_like(g) for g in G]
+        run("gn_matvec", lambda: tt.gn_matvec(ix, None, A, X, 2 * lam, Y=Y, w_const=2.0))
+
+    for _ in range(args.warmup):
+        step(False)
+        kernels(False)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    for _ in range(max(1, args.steps)):
+        kernels(True)
+    torch.cuda.synchronize()
+
+    per = {}
+    for nme, (e0, e1) in zip(names, events):
+        per.setdefault(nme, []).append(e0.elapsed_time(e1))
+    avg = {k: float(np.mean(v)) for k, v in per.items()}
+
+    # nonzero passes of one step: ALS 3 MTTKRP + 3 Gram; GN step 1 TTTP +
+    # 3 gradient + 3 Gram (preconditioner) + 3 GN-matvec per CG iteration
+    passes = 6 + 1 + 3 + 3 + 3 * args.cg
+    value = m * R * passes / (ms_per_step / 1000.0)
+
+    # algorithmic bytes (storage precision b; stream = indices + value)
+    b = 4 if args.form == "f32" else 2
+    dims = wl.dims
+    bytes_mttkrp = [m * (8 + 4 + 2 * R * b) + dims[n] * R * 4 for n in range(3)]
+    bytes_matvec = sum(m * (8 + 4 * R * b) + dims[n] * R * (2 * b + 4 + 4) for n in range(3))
+    bytes_tttp = m * (12 + 4) + sum(d * R * b for d in dims)
+    bytes_grad = sum(m * (8 + 4 + 2 * R * b) + dims[n] * R * (b + 4) for n in range(3))
+    krates = {}
+    for n in range(3):
+        ms = avg[f"mttkrp{n}"]
+        krates[f"mttkrp{n}"] = {"ms": ms, "GBps_alg": bytes_mttkrp[n] / ms / 1e6,
+                                "nnzR_per_s": m * R / ms * 1e3}
+        krates[f"solve{n}"] = {"ms": avg[f"solve{n}"]}
+    krates["gn_step"] = {"ms": avg["gn_step"]}
+    krates["tttp_loss"] = {"ms": avg["tttp_loss"], "GBps_alg": bytes_tttp / avg["tttp_loss"] / 1e6}
+    krates["gradient"] = {"ms": avg["gradient"], "GBps_alg": bytes_grad / avg["gradient"] / 1e6}
+    krates["gn_matvec"] = {"ms": avg["gn_matvec"],
+                           "GBps_alg": bytes_matvec / avg["gn_matvec"] / 1e6}
+
+    # dominant streaming kernel by time in the step: the three MTTKRP launches
+    # (one per mode) are reported as one kernel averaged over its launches
+    mt_ms = float(np.mean([avg[f"mttkrp{n}"] for n in range(3)]))
+    mt_bytes = float(np.mean(bytes_mttkrp))
+    achieved = mt_bytes / mt_ms / 1e6
+    src_hash = kernel_source_hash()
+    wname = f"ratings{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}_m{m}_R{R}_{args.form}"
+    traffic = traffic_from_profile("mttkrp", wname, src_hash)
+    roofline = {"bound": "hbm", "kernel": "k_stream<MTTKRP> (mean of the 3 mode launches)",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "alg_bytes_per_launch": mt_bytes, "launch_ms": mt_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, A0, R, lam, args.cpu_sample, passes)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz*R/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.form,
+        "data": "synthetic",
+        "config": {
+            "workload": f"ratings-shaped {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, "
+                        f"{m} distinct nonzeros, Zipf(1.1) mode degrees, values 1..5",
+            "R": R, "factor_storage": args.form, "lambda": lam, "loss": "least squares",
+            "cg_iterations": args.cg, "nnz_passes_per_step": passes,
+            "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": krates,
+        "index_build_s": index_s,
+        "generate_s": gen_s,
+        "src_hash": src_hash,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, A0, R, lam, sample, passes):
+    """The FP64 oracle, as it stands, on a bounded sample: the first `sample`
+    nonzeros (COO order is draw order, i.e. random) of the same tensor, full
+    dimensions, same step composition (ALS sweep over the sampled rows, then
+    objective, gradient, GN preconditioner Grams and CG matvecs)."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        threadpool_limits = None
+    import oracle as O
+
+    idx = [i[:sample].astype(np.int64) for i in wl.idx]
+    t = wl.t[:sample].astype(np.float64)
+    A = [np.asarray(a, dtype=np.float64) for a in A0]
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    t0 = time.time()
+    try:
+        ixs = O.build_index(idx, wl.dims)
+        for n in range(3):
+            Mn = O.mttkrp(idx, t, A, n, wl.dims[n])
+            rows = ixs[n]["rows"]
+            G = O.gram(idx, None, A, n, wl.dims[n], rows=rows)
+            X, _ = O.solve_rows(G, Mn[rows], lam)
+            A[n] = A[n].copy()
+            A[n][rows] = X
+        O.objective(idx, t, A, O.LOSS_LS, lam)
+        g = O.gradient(idx, t, A, O.LOSS_LS, lam, wl.dims)
+        for n in range(3):
+            O.gram(idx, np.full(sample, 2.0), A, n, wl.dims[n], rows=ixs[n]["rows"])
+        w = np.full(sample, 2.0)
+        for _ in range((passes - 13) // 3):
+            O.gn_matvec(idx, w, A, g, 2 * lam, wl.dims)
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    dt = time.time() - t0
+    return {"value": sample * R * passes / dt, "unit": "nnz*R/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {sample} nonzeros (COO draw order) of the same tensor, full "
+                      f"dimensions, one full step of the FP64 NumPy oracle; {dt:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

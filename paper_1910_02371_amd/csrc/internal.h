@@ -15,7 +15,9 @@ namespace tt {
 // Work partition constants.
 constexpr int kChunk = 2048;       // nnz per streaming work chunk (max)
 constexpr int kGramPiece = 4096;   // nnz per Gram task (max)
-constexpr int64_t kGramBatchBytes = 128ll << 20;  // Gram workspace per batch
+constexpr int kGramLight = 512;    // tasks above this run on a whole workgroup
+constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
+constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
 
 struct ModeIndex {
   int64_t I = 0;
@@ -41,6 +43,10 @@ struct ModeIndex {
   int32_t *d_row_task = nullptr;    // I + 1: tasks of row i
   std::vector<int32_t> h_row_task;  // host copy, for batching
   int32_t max_task_per_row = 0;
+  int32_t *d_heavy_task = nullptr;  // tasks with > kGramLight nonzeros
+  std::vector<int32_t> h_heavy_task;
+  int32_t *d_multi_row = nullptr;   // rows with > kReduceMin tasks
+  std::vector<int32_t> h_multi_row;
   double mean_row = 0.0;            // m / nrows
 };
 

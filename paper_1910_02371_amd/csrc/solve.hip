@@ -13,9 +13,10 @@
 //   BF16 factors are widened exactly to FP32 (a product of two bf16 values
 //   is exact in FP32), so the BF16 form accumulates like the FP32 form.
 //   FP64 storage: v_mfma_f64_16x16x4f64 tiles (lower triangle only).
-// Each task writes its lower-triangular G (row-major RP x RP) to a batch
-// workspace; rows with several tasks are summed in FP64 in task order by the
-// solve kernel (deterministic).
+// Each task writes the upper triangle of its G (row-major RP x RP) to a batch
+// workspace; the solve kernel reads it by columns (lane i takes G[j][i] =
+// G[i][j] for j <= i), so its loads are coalesced.  Rows with several tasks
+// are summed in FP64 in task order (deterministic).
 //
 // Solve: one wave per row; lane i keeps row i of S = G + lambda I in FP64
 // registers and a right-looking Cholesky runs over columns, broadcasting
@@ -47,6 +48,7 @@ struct GramDev {
   const int32_t *w_perm;
   double w_scale;
   void *G;                    // workspace: (task - task_base) * RP * RP
+  int split_heavy;            // light kernel skips tasks > kGramLight
 };
 
 template <class TR>
@@ -57,6 +59,15 @@ template <>
 __device__ __forceinline__ float elem_f<TrBF16>(const uint16_t *A, int64_t off) {
   return bf16_to_f32(A[off]);
 }
+// Same load with a 32-bit element offset (factor matrices below 2^32 bytes),
+// which lets the address be a scalar base plus a 32-bit vector offset.
+template <class TR>
+__device__ __forceinline__ float elem_f32off(const typename TR::T *A, uint32_t off) {
+  const typename TR::T *p = reinterpret_cast<const typename TR::T *>(
+      reinterpret_cast<const char *>(A) + (uint32_t)(off * (uint32_t)sizeof(typename TR::T)));
+  if constexpr (sizeof(typename TR::T) == 4) return *p;
+  else return bf16_to_f32(*p);
+}
 
 template <class VT>
 __device__ __forceinline__ VT weight_at(const GramDev &d, int64_t pos) {
@@ -66,79 +77,209 @@ __device__ __forceinline__ VT weight_at(const GramDev &d, int64_t pos) {
 }
 
 // FP32 / BF16 storage, FP32 accumulation on matrix cores.
+// A wave walks a range of nonzeros 64 at a time: lane l loads the indices and
+// weight of nonzero base + l (coalesced; the next block is prefetched), then
+// MFMA steps take their operands from those lanes by ds_bpermute.  GS steps
+// are issued together (all gathers first, then all MFMAs) so that the
+// factor-row gathers of GS steps are in flight at once.  Padding columns
+// (i >= R) use a clamped address and a zero mask, so loads are unconditional.
+template <int RP>
+struct GramAcc {
+  static constexpr int NV = RP == 16 ? 4 : (RP == 32 ? 16 : 48);
+  f32x4 c16;
+  f32x16 c00, c01, c11;
+  __device__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c16[v] = 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { c00[v] = 0.f; c01[v] = 0.f; c11[v] = 0.f; }
+  }
+  __device__ float get(int v) const {
+    if constexpr (RP == 16) return c16[v];
+    else if constexpr (RP == 32) return c00[v];
+    else return v < 16 ? c00[v] : (v < 32 ? c01[v - 16] : c11[v - 32]);
+  }
+  __device__ void set(int v, float x) {
+    if constexpr (RP == 16) c16[v] = x;
+    else if constexpr (RP == 32) c00[v] = x;
+    else if (v < 16) c00[v] = x;
+    else if (v < 32) c01[v - 16] = x;
+    else c11[v - 32] = x;
+  }
+};
+
 template <class TR, int RP>
-__global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
+__device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
+                                           GramAcc<RP> &acc) {
   using T = typename TR::T;
+  constexpr int NPS = (RP == 16) ? 4 : 2;     // nonzeros per MFMA step
+  constexpr int MW = (RP == 16) ? 16 : 32;    // M = N of the instruction
+  constexpr int GS = 8;                       // steps issued together
+  constexpr int SPB = 64 / NPS;               // steps per 64-nonzero block
   const int lane = threadIdx.x & 63;
-  const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= d.task_end) return;
-  const int64_t nb = d.task[t], ne = d.task[t + 1];
   const T *A0 = reinterpret_cast<const T *>(d.A0);
   const T *A1 = reinterpret_cast<const T *>(d.A1);
   const int R = d.R;
-  constexpr int NPS = (RP == 16) ? 4 : 2;     // nonzeros per MFMA step
-  constexpr int MW = (RP == 16) ? 16 : 32;    // M = N of the instruction
+  const int64_t ldA = d.ldA;
   const int i = lane % MW;
   const int kk = lane / MW;
-  f32x4 c16 = {0.f, 0.f, 0.f, 0.f};
-  f32x16 c00, c01, c11;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) { c00[v] = 0.f; c01[v] = 0.f; c11[v] = 0.f; }
+  const int c0 = i < R ? i : 0;
+  const float m0 = i < R ? 1.f : 0.f;
+  const int c1 = (i + 32 < R) ? i + 32 : 0;
+  const float m1 = (i + 32 < R) ? 1.f : 0.f;
 
-  for (int64_t base = nb; base < ne; base += 64) {
-    const int cnt = (int)min((int64_t)64, ne - base);
-    int my0 = 0, my1 = 0;
-    float myw = 0.f;
-    if (lane < cnt) {
-      my0 = d.oidx0[base + lane];
-      my1 = d.oidx1[base + lane];
-      myw = weight_at<float>(d, base + lane);
+  auto load_block = [&](int64_t base, int &j0, int &j1, float &w) {
+    const int64_t e = base + lane;
+    if (e < ne) {
+      j0 = d.oidx0[e];
+      j1 = d.oidx1[e];
+      w = weight_at<float>(d, e);
+    } else {
+      j0 = 0; j1 = 0; w = 0.f;
     }
+  };
+  int n0 = 0, n1 = 0;
+  float nw = 0.f;
+  if (nb < ne) load_block(nb, n0, n1, nw);
+  for (int64_t base = nb; base < ne; base += 64) {
+    const int my0 = n0, my1 = n1;
+    const float myw = nw;
+    if (base + 64 < ne) load_block(base + 64, n0, n1, nw);
+    const int cnt = (int)min((int64_t)64, ne - base);
     const int steps = (cnt + NPS - 1) / NPS;
-    for (int st = 0; st < steps; ++st) {
-      const int src = st * NPS + kk;
-      const int j0 = __shfl(my0, src);
-      const int j1 = __shfl(my1, src);
-      const float w = __shfl(myw, src);
-      float h0 = 0.f, h1 = 0.f;
-      if (i < R) h0 = elem_f<TR>(A0, (int64_t)j0 * d.ldA + i) * elem_f<TR>(A1, (int64_t)j1 * d.ldA + i);
-      if constexpr (RP == 64) {
-        if (i + 32 < R)
-          h1 = elem_f<TR>(A0, (int64_t)j0 * d.ldA + i + 32) *
-               elem_f<TR>(A1, (int64_t)j1 * d.ldA + i + 32);
+    for (int st0 = 0; st0 < steps; st0 += GS) {
+      int j0[GS], j1[GS];
+      float w[GS];
+#pragma unroll
+      for (int u = 0; u < GS; ++u) {
+        const int src = ((st0 + u) % SPB) * NPS + kk;  // lanes >= cnt carry w = 0
+        j0[u] = __shfl(my0, src);
+        j1[u] = __shfl(my1, src);
+        w[u] = __shfl(myw, src);
       }
-      if constexpr (RP == 16) {
-        c16 = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, w * h0, c16, 0, 0, 0);
-      } else {
-        c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w * h0, c00, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);  // keep the GS gathers together
+      float a0[GS], a1[GS], b0[GS], b1[GS];
+#pragma unroll
+      for (int u = 0; u < GS; ++u) {
+        const uint32_t r0 = (uint32_t)j0[u] * (uint32_t)ldA, r1 = (uint32_t)j1[u] * (uint32_t)ldA;
+        a0[u] = elem_f32off<TR>(A0, r0 + c0);
+        a1[u] = elem_f32off<TR>(A1, r1 + c0);
         if constexpr (RP == 64) {
-          c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w * h1, c01, 0, 0, 0);
-          c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, w * h1, c11, 0, 0, 0);
+          b0[u] = elem_f32off<TR>(A0, r0 + c1);
+          b1[u] = elem_f32off<TR>(A1, r1 + c1);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < GS; ++u) {
+        const float h0 = a0[u] * a1[u] * m0;
+        if constexpr (RP == 16) {
+          acc.c16 = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, w[u] * h0, acc.c16, 0, 0, 0);
+        } else {
+          acc.c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w[u] * h0, acc.c00, 0, 0, 0);
+          if constexpr (RP == 64) {
+            const float h1 = b0[u] * b1[u] * m1;
+            acc.c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w[u] * h1, acc.c01, 0, 0, 0);
+            acc.c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, w[u] * h1, acc.c11, 0, 0, 0);
+          }
         }
       }
     }
   }
-  float *G = reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP);
+}
+
+// Write the upper triangle of G (row-major RP x RP) from the accumulators.
+template <int RP>
+__device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
+  const int lane = threadIdx.x & 63;
   if constexpr (RP == 16) {
     // D[row][col]: col = lane % 16, row = 4 * (lane / 16) + v
 #pragma unroll
-    for (int v = 0; v < 4; ++v) G[(4 * (lane / 16) + v) * RP + lane % 16] = c16[v];
+    for (int v = 0; v < 4; ++v) G[(4 * (lane / 16) + v) * RP + lane % 16] = acc.c16[v];
   } else {
     // D[row][col]: col = lane % 32, row = 8 * (v / 4) + 4 * (lane / 32) + v % 4
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int row = 8 * (v / 4) + 4 * (lane / 32) + (v % 4);
       const int col = lane % 32;
-      G[row * RP + col] = c00[v];
+      G[row * RP + col] = acc.c00[v];
       if constexpr (RP == 64) {
-        G[(32 + row) * RP + 32 + col] = c11[v];
-        G[(32 + col) * RP + row] = c01[v];  // block (1,0) = (block (0,1))^T
+        G[(32 + row) * RP + 32 + col] = acc.c11[v];
+        G[row * RP + 32 + col] = acc.c01[v];  // upper block (0,1)
       }
     }
   }
 }
 
-// FP64 storage and accumulation: 16x16x4 FP64 tiles of the lower triangle.
+// Light tasks: one wave per task, four tasks per workgroup; tasks with more
+// than kGramLight nonzeros are left to k_gram_f32_heavy.
+template <class TR, int RP>
+__global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
+  const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= d.task_end) return;
+  const int64_t nb = d.task[t], ne = d.task[t + 1];
+  if (d.split_heavy && ne - nb > kGramLight) return;
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP>(d, nb, ne, acc);
+  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
+}
+
+// Heavy tasks: the eight waves of a workgroup split the task's nonzeros and
+// add their accumulators through LDS in wave order (deterministic).
+template <class TR, int RP>
+__global__ __launch_bounds__(512) void k_gram_f32_heavy(GramDev d, const int32_t *heavy,
+                                                        int64_t nheavy) {
+  constexpr int NV = GramAcc<RP>::NV;
+  __shared__ float buf[NV * 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = heavy[blockIdx.x];
+  const int64_t nb = d.task[t], ne = d.task[t + 1];
+  const int64_t per = (((ne - nb) + 7) / 8 + 1) & ~(int64_t)1;
+  const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP>(d, b0, b1, acc);
+  for (int q = 0; q < 8; ++q) {
+    if (w == q) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        buf[v * 64 + lane] = (q == 0 ? 0.f : buf[v * 64 + lane]) + acc.get(v);
+    }
+    __syncthreads();
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
+    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
+  }
+}
+
+// Rows with more than kReduceMin tasks: sum their tasks' Grams entrywise in
+// FP64, in task order, into the row's first task slot.
+template <class GT, int RP>
+__global__ __launch_bounds__(256) void k_gram_reduce(const int32_t *__restrict__ rows,
+                                                     const int32_t *__restrict__ row_task,
+                                                     int64_t task_base, GT *G) {
+  const int64_t row = rows[blockIdx.x];
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= RP * RP) return;
+  const int32_t t0 = row_task[row], t1 = row_task[row + 1];
+  const GT *g = G + ((int64_t)t0 - task_base) * (RP * RP) + e;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int n = t1 - t0;
+  int q = 0;
+  for (; q + 4 <= n; q += 4) {
+    s0 += (double)g[(int64_t)q * (RP * RP)];
+    s1 += (double)g[(int64_t)(q + 1) * (RP * RP)];
+    s2 += (double)g[(int64_t)(q + 2) * (RP * RP)];
+    s3 += (double)g[(int64_t)(q + 3) * (RP * RP)];
+  }
+  for (; q < n; ++q) s0 += (double)g[(int64_t)q * (RP * RP)];
+  G[((int64_t)t0 - task_base) * (RP * RP) + e] = (GT)((s0 + s1) + (s2 + s3));
+}
+
+// FP64 storage and accumulation: 16x16x4 FP64 tiles of the upper triangle.
 template <int RP>
 __global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
   constexpr int TB = RP / 16;
@@ -179,7 +320,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
 #pragma unroll
       for (int a = 0; a < TB; ++a)
 #pragma unroll
-        for (int bb = 0; bb <= a; ++bb) {
+        for (int bb = a; bb < TB; ++bb) {
           c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[a], w * h[bb], c[q], 0, 0, 0);
           ++q;
         }
@@ -190,14 +331,14 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
 #pragma unroll
   for (int a = 0; a < TB; ++a)
 #pragma unroll
-    for (int bb = 0; bb <= a; ++bb) {
+    for (int bb = a; bb < TB; ++bb) {
       // v_mfma_f64_16x16x4f64 result: D[row][col] at col = lane % 16,
-      // row = 4 * v + lane / 16 (checked on the device)
+      // row = 4 * v + lane / 16 (checked on the device); tile (a, bb) is
+      // block (a, bb) of the upper triangle
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 4 * v + lane / 16, col = lane % 16;
         G[(16 * a + row) * RP + 16 * bb + col] = c[q][v];
-        if (a != bb) G[(16 * bb + col) * RP + 16 * a + row] = c[q][v];
       }
       ++q;
     }
@@ -228,9 +369,12 @@ struct SolveDev {
 };
 
 // Cholesky of the lane-distributed matrix s (lane i = row i), in place:
-// afterwards s[j] on lane i holds L(i, j) for j <= i.  Returns info.
+// afterwards s[j] on lane i holds L(i, j) for j <= i.  Column k of L is
+// published through LDS (`col`, RP doubles) and read back as broadcasts, so
+// the trailing update of step k is RP-k-1 independent FMAs per lane.
+// Returns info (LAPACK potrf convention).  One wave per workgroup.
 template <int RP>
-__device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane) {
+__device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col) {
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
     const double dkk = readlane_d(s[k], k);
@@ -239,38 +383,45 @@ __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane) {
     const double inv = 1.0 / rd;
     const double lik = lane > k ? s[k] * inv : (lane == k ? rd : 0.0);
     s[k] = lik;
+    if (k + 1 < RP) {
+      if (lane < RP) col[lane] = lik;
+      __syncthreads();
 #pragma unroll
-    for (int j = k + 1; j < RP; ++j) {
-      const double ljk = readlane_d(lik, j);
-      s[j] -= lik * ljk;
+      for (int j = k + 1; j < RP; ++j) s[j] -= lik * col[j];
+      __syncthreads();
     }
   }
   return 0;
 }
 
 // Solve L L^T x = b with L held as in chol_lanes; b on lane i is b_i.
+// Lp: packed lower triangle in LDS (RP (RP + 1) / 2 doubles), row k at
+// k (k + 1) / 2, used by the backward solve where lane i needs L(k, i).
 template <int RP>
 __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double b,
-                                                   int lane, double *lds) {
+                                                   int lane, double *Lp) {
   // forward: L y = b (column-oriented, y kept in b)
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
     const double yk = readlane_d(b, k) / readlane_d(s[k], k);
     b = lane == k ? yk : (lane > k ? b - s[k] * yk : b);
   }
-  // backward: L^T x = y; lane i needs L(k, i), staged row-major in LDS
+  if (lane < RP) {
+    double *row = Lp + (lane * (lane + 1)) / 2;
 #pragma unroll
-  for (int j = 0; j < RP; ++j)
-    if (lane < RP) lds[lane * (RP + 1) + j] = s[j];
+    for (int j = 0; j < RP; ++j)
+      if (j <= lane) row[j] = s[j];
+  }
   __syncthreads();
   double diag = 0.0;
 #pragma unroll
   for (int k = 0; k < RP; ++k)
     if (k == lane) diag = s[k];
+  // backward: L^T x = y
 #pragma unroll
   for (int k = RP - 1; k >= 0; --k) {
     const double xk = readlane_d(b, k) / readlane_d(diag, k);
-    const double lki = (lane < k) ? lds[k * (RP + 1) + lane] : 0.0;
+    const double lki = (lane < k) ? Lp[(k * (k + 1)) / 2 + lane] : 0.0;
     b = lane == k ? xk : (lane < k ? b - lki * xk : b);
   }
   return b;
@@ -278,21 +429,24 @@ __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double
 
 template <class GT, class XT, class MT, int RP>
 __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
-  __shared__ double lds[RP * (RP + 1)];
+  __shared__ double Lp[RP * (RP + 1) / 2];
+  __shared__ double col[RP];
   if (d.skip && *d.skip != 0.0) return;
   const int lane = threadIdx.x;
   const int64_t row = d.r0 + blockIdx.x;
   const int R = d.R;
-  const int32_t t0 = d.row_task[row], t1 = d.row_task[row + 1];
+  const int32_t t0 = d.row_task[row];
+  int32_t t1 = d.row_task[row + 1];
+  if (t1 - t0 > kReduceMin) t1 = t0 + 1;  // pre-reduced by k_gram_reduce
   double s[RP];
 #pragma unroll
   for (int j = 0; j < RP; ++j) s[j] = 0.0;
   if (lane < RP) {
     for (int32_t t = t0; t < t1; ++t) {
       const GT *g = reinterpret_cast<const GT *>(d.G) +
-                    ((int64_t)t - d.task_base) * (RP * RP) + lane * RP;
+                    ((int64_t)t - d.task_base) * (RP * RP) + lane;
 #pragma unroll
-      for (int j = 0; j < RP; ++j) s[j] += (double)g[j];
+      for (int j = 0; j < RP; ++j) s[j] += (double)g[j * RP];  // G[j][lane]
     }
   }
 #pragma unroll
@@ -300,20 +454,21 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
     if (lane >= R || j >= R) s[j] = (j == lane) ? 1.0 : 0.0;
     else if (j == lane) s[j] += d.lambda;
   }
-  const int info = chol_lanes<RP>(s, lane);
+  const int info = chol_lanes<RP>(s, lane, col);
   if (d.info && lane == 0) d.info[row] = info;
   if (d.Lstore) {
-    double *L = d.Lstore + row * (int64_t)(RP * RP) + lane * RP;
+    // stored by columns of the lane layout: L(lane, j) at j * RP + lane
+    double *L = d.Lstore + row * (int64_t)(RP * RP) + lane;
     if (lane < RP) {
 #pragma unroll
-      for (int j = 0; j < RP; ++j) L[j] = info ? ((j == lane) ? 1.0 : 0.0) : s[j];
+      for (int j = 0; j < RP; ++j) L[j * RP] = info ? ((j == lane) ? 1.0 : 0.0) : s[j];
     }
   }
   if (d.factor_only) return;
   double x = 0.0;
   if (info == 0) {
     const double b = lane < R ? (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane] : 0.0;
-    x = chol_solve_lanes<RP>(s, b, lane, lds);
+    x = chol_solve_lanes<RP>(s, b, lane, Lp);
   }
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
@@ -323,16 +478,16 @@ template <class MT, int RP>
 __global__ __launch_bounds__(64) void k_apply_rows(const double *__restrict__ Lstore,
                                                    const void *rhs, void *X, int R,
                                                    const double *skip) {
-  __shared__ double lds[RP * (RP + 1)];
+  __shared__ double Lp[RP * (RP + 1) / 2];
   if (skip && *skip != 0.0) return;
   const int lane = threadIdx.x;
   const int64_t row = blockIdx.x;
   double s[RP];
-  const double *L = Lstore + row * (int64_t)(RP * RP) + (lane < RP ? lane : 0) * RP;
+  const double *L = Lstore + row * (int64_t)(RP * RP) + (lane < RP ? lane : 0);
 #pragma unroll
-  for (int j = 0; j < RP; ++j) s[j] = lane < RP ? L[j] : 0.0;
+  for (int j = 0; j < RP; ++j) s[j] = lane < RP ? L[j * RP] : 0.0;
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
-  const double x = chol_solve_lanes<RP>(s, b, lane, lds);
+  const double x = chol_solve_lanes<RP>(s, b, lane, Lp);
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
 }
 
@@ -351,27 +506,60 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
   return hipGetLastError();
 }
 
-static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, hipStream_t s) {
+template <class TR, int RP>
+static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
+                               hipStream_t s) {
+  const int64_t n = d.task_end - d.task_base;
+  d.split_heavy = 1;
+  k_gram_f32<TR, RP><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+  if (nheavy > 0)
+    k_gram_f32_heavy<TR, RP><<<dim3((unsigned)nheavy), dim3(512), 0, s>>>(d, heavy, nheavy);
+}
+
+// Gram of one batch of tasks [task_base, task_end): light tasks one wave
+// each, heavy tasks (the `heavy` slice) one workgroup each, then the
+// pre-reduction of rows with many tasks (the `multi` slice).
+static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int32_t *heavy,
+                              int64_t nheavy, const int32_t *multi, int64_t nmulti,
+                              const int32_t *row_task, hipStream_t s) {
   const int64_t n = d.task_end - d.task_base;
   if (n <= 0) return hipSuccess;
   dim3 g((unsigned)((n + 3) / 4)), b(256);
   if (fdt == TT_F64) {
+    GramDev d2 = d;
+    d2.split_heavy = 0;
     switch (RP) {
-      case 16: k_gram_f64<16><<<g, b, 0, s>>>(d); break;
-      case 32: k_gram_f64<32><<<g, b, 0, s>>>(d); break;
-      default: k_gram_f64<64><<<g, b, 0, s>>>(d); break;
+      case 16: k_gram_f64<16><<<g, b, 0, s>>>(d2); break;
+      case 32: k_gram_f64<32><<<g, b, 0, s>>>(d2); break;
+      default: k_gram_f64<64><<<g, b, 0, s>>>(d2); break;
     }
   } else if (fdt == TT_F32) {
     switch (RP) {
-      case 16: k_gram_f32<TrF32, 16><<<g, b, 0, s>>>(d); break;
-      case 32: k_gram_f32<TrF32, 32><<<g, b, 0, s>>>(d); break;
-      default: k_gram_f32<TrF32, 64><<<g, b, 0, s>>>(d); break;
+      case 16: launch_gram_f32_rp<TrF32, 16>(d, heavy, nheavy, s); break;
+      case 32: launch_gram_f32_rp<TrF32, 32>(d, heavy, nheavy, s); break;
+      default: launch_gram_f32_rp<TrF32, 64>(d, heavy, nheavy, s); break;
     }
   } else {
     switch (RP) {
-      case 16: k_gram_f32<TrBF16, 16><<<g, b, 0, s>>>(d); break;
-      case 32: k_gram_f32<TrBF16, 32><<<g, b, 0, s>>>(d); break;
-      default: k_gram_f32<TrBF16, 64><<<g, b, 0, s>>>(d); break;
+      case 16: launch_gram_f32_rp<TrBF16, 16>(d, heavy, nheavy, s); break;
+      case 32: launch_gram_f32_rp<TrBF16, 32>(d, heavy, nheavy, s); break;
+      default: launch_gram_f32_rp<TrBF16, 64>(d, heavy, nheavy, s); break;
+    }
+  }
+  if (nmulti > 0) {
+    dim3 gr((unsigned)nmulti, (unsigned)((RP * RP + 255) / 256));
+    if (fdt == TT_F64) {
+      switch (RP) {
+        case 16: k_gram_reduce<double, 16><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (double *)d.G); break;
+        case 32: k_gram_reduce<double, 32><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (double *)d.G); break;
+        default: k_gram_reduce<double, 64><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (double *)d.G); break;
+      }
+    } else {
+      switch (RP) {
+        case 16: k_gram_reduce<float, 16><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (float *)d.G); break;
+        case 32: k_gram_reduce<float, 32><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (float *)d.G); break;
+        default: k_gram_reduce<float, 64><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (float *)d.G); break;
+      }
     }
   }
   return hipGetLastError();
@@ -405,6 +593,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.w_perm = c.w_perm;
   gd.w_scale = c.w_scale;
   gd.G = Gws;
+  gd.split_heavy = 1;
 
   SolveDev sd;
   sd.row_task = md.d_row_task;
@@ -432,7 +621,13 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     const int64_t r1 = lo;
     gd.task_base = rt[r0];
     gd.task_end = rt[r1];
-    hipError_t e = launch_gram(c.fdt, RP, gd, s);
+    const std::vector<int32_t> &ht = md.h_heavy_task, &mr = md.h_multi_row;
+    const int64_t h0 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r0]) - ht.begin();
+    const int64_t h1 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r1]) - ht.begin();
+    const int64_t q0 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r0) - mr.begin();
+    const int64_t q1 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r1) - mr.begin();
+    hipError_t e = launch_gram(c.fdt, RP, gd, md.d_heavy_task + h0, h1 - h0,
+                               md.d_multi_row + q0, q1 - q0, md.d_row_task, s);
     if (e != hipSuccess) return hip_fail(e, "gram kernel");
     sd.task_base = rt[r0];
     sd.r0 = r0;

@@ -61,15 +61,34 @@ class Workload:
 
 
 # ---------------------------------------------------------------------------
-# helpers (coordinate decoding and planted-model synthesis)
+# helpers (coordinate decoding, threaded chunk work, planted-model synthesis)
 # ---------------------------------------------------------------------------
+def _threads():
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _pmap(fn, items):
+    items = list(items)
+    if len(items) <= 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(_threads()) as ex:
+        return list(ex.map(fn, items))
+
+
 def _decode(keys, dims):
-    out = []
-    rem = np.asarray(keys, dtype=np.int64)
-    for n in range(len(dims) - 1, -1, -1):
-        out.append((rem % dims[n]).astype(np.int32))
-        rem = rem // dims[n]
-    return out[::-1]
+    keys = np.asarray(keys, dtype=np.int64)
+    strides = [int(np.prod([int(d) for d in dims[n + 1:]], dtype=np.int64))
+               for n in range(len(dims))]
+
+    def dec(n):
+        return ((keys // strides[n]) % int(dims[n])).astype(np.int32)
+    return _pmap(dec, range(len(dims)))
 
 
 def _planted_values(idx, P, chunk=1 << 20):
@@ -78,19 +97,33 @@ def _planted_values(idx, P, chunk=1 << 20):
     rank).  Input synthesis only."""
     m = len(idx[0])
     out = np.empty(m, dtype=np.float64)
-    for b in range(0, m, chunk):
+
+    def work(b):
         e = min(m, b + chunk)
         acc = P[0][idx[0][b:e]].astype(np.float64)
         for n in range(1, len(P)):
             acc *= P[n][idx[n][b:e]]
         out[b:e] = acc.sum(axis=1)
+    _pmap(work, range(0, m, chunk))
     return out
 
 
-def _unique_first(keys):
-    """Distinct keys in order of first appearance."""
+def _first_distinct(keys):
+    """Mask of the first occurrence of every key (draw order kept); keys are
+    split into hash buckets that are deduplicated in parallel."""
     import pandas as pd
-    return pd.unique(keys)
+    keys = np.asarray(keys, dtype=np.int64)
+    if keys.size < (1 << 22):
+        return ~pd.Series(keys).duplicated().values
+    nb = 16
+    bucket = (keys ^ (keys >> 17)) & (nb - 1)
+    keep = np.empty(keys.size, dtype=bool)
+
+    def work(b):
+        pos = np.flatnonzero(bucket == b)
+        keep[pos] = ~pd.Series(keys[pos]).duplicated().values
+    _pmap(work, range(nb))
+    return keep
 
 
 # ---------------------------------------------------------------------------
@@ -108,41 +141,51 @@ def uniform_coords(rng, dims, m):
         while len(keys) < m:
             draw = rng.integers(0, total, size=max(1024, int((m - len(keys)) * 1.05) + 16),
                                 dtype=np.int64)
-            keys = _unique_first(np.concatenate([keys, draw]))
+            allk = np.concatenate([keys, draw])
+            keys = allk[_first_distinct(allk)]
         keys = keys[:m]
     return _decode(keys, dims)
 
 
 def zipf_coords(rng, dims, m, s=1.1, chunk=1 << 24):
     """m distinct coordinates whose per-mode index degrees follow a truncated
-    Zipf(s) law over a random label permutation of each mode; the first m
-    distinct keys in draw order are kept."""
+    Zipf(s) law over a random label permutation of each mode.  Draws come in
+    chunks; chunk c uses its own Philox stream keyed by (a seed drawn from
+    ``rng``, c), and the first m distinct keys in draw order are kept, so the
+    result does not depend on the thread count."""
     dims = [int(d) for d in dims]
     perms = [rng.permutation(I).astype(np.int64) for I in dims]
+    base = int(rng.integers(0, 1 << 31))
     cdfs = []
     for I in dims:
         w = np.arange(1, I + 1, dtype=np.float64) ** (-s)
         c = np.cumsum(w)
         cdfs.append(c / c[-1])
-    parts = []
-    drawn = 0
-    next_check = m
-    keys = None
-    while True:
-        u = rng.random((len(dims), chunk))
+
+    def draw(c):
+        r = rng_for((base << 32) | c)
+        u = r.random((len(dims), chunk))
         key = np.zeros(chunk, dtype=np.int64)
         for n, I in enumerate(dims):
-            r = np.minimum(np.searchsorted(cdfs[n], u[n], side="right"), I - 1)
-            key = key * I + perms[n][r]
-        parts.append(key)
-        drawn += chunk
-        if drawn >= next_check:
-            keys = _unique_first(np.concatenate(parts))
-            parts = [keys]
-            if len(keys) >= m:
-                break
-            next_check = drawn + max(chunk, (m - len(keys)) * 2)
-    return _decode(keys[:m], dims), drawn
+            q = np.minimum(np.searchsorted(cdfs[n], u[n], side="right"), I - 1)
+            key = key * I + perms[n][q]
+        return key
+
+    parts = []
+    nchunk = 0
+    want = max(1, -(-int(1.25 * m) // chunk))
+    while True:
+        parts.extend(_pmap(draw, range(nchunk, nchunk + want)))
+        nchunk += want
+        allk = np.concatenate(parts) if len(parts) > 1 else parts[0]
+        keep = _first_distinct(allk)
+        nd = int(np.count_nonzero(keep))
+        if nd >= m:
+            keys = allk[keep][:m]
+            break
+        parts = [allk]
+        want = max(1, -(-int(2.5 * (m - nd)) // chunk))
+    return _decode(keys, dims), nchunk * chunk
 
 
 def random_tensor(dims, m, seed, rank=3, noise=0.01, dtype=np.float64):
