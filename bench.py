@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--nnz", type=int, default=100_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 18)
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run a plain device copy of this size first (counter calibration)")
     return p.parse_args()
 
 
@@ -89,6 +91,14 @@ def main():
     torch.cuda.set_device(dev)
     tt.lib()
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 18
+        xa = torch.ones(n, dtype=torch.float32, device=dev)
+        xb = torch.empty_like(xa)
+        torch.cuda.synchronize()
+        xb.copy_(xa)
+        torch.cuda.synchronize()
+        del xa, xb
     t0 = time.time()
     wl = W.ratings(m=args.nnz)
     gen_s = time.time() - t0
@@ -127,7 +137,6 @@ def main():
     # kernels of the step
     M = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
-    fsum = torch.zeros((), dtype=torch.float64, device=dev)
 
     def step(record):
         run = timed if record else (lambda n, f: f())
@@ -137,30 +146,18 @@ def main():
         run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
                                           stats=stats))
 
-    # separately timed single kernels (same launch configuration as the step)
-    def kernels(record):
-        run = timed if record else (lambda n, f: f())
-        run("tttp_loss", lambda: tt.tttp(ix, tt.INDEX_T, A, out=False, epi="phi",
-                                         want_sum=True))
-        G = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
-        run("gradient", lambda: tt.gradient(ix, A, "ls", lam, G=G))
-        X = [g.clone() for g in G]
-        Y = [torch.empty_like(g) for g in G]
-        run("gn_matvec", lambda: tt.gn_matvec(ix, None, A, X, 2 * lam, Y=Y, w_const=2.0))
-
     for _ in range(args.warmup):
         step(False)
-        kernels(False)
     torch.cuda.synchronize()
+    tt.profile_enable(True)
     t0 = time.time()
     for _ in range(args.steps):
         step(True)
     torch.cuda.synchronize()
     wall = time.time() - t0
+    tt.profile_enable(False)
+    prof = tt.profile_report()
     ms_per_step = 1000.0 * wall / args.steps
-    for _ in range(max(1, args.steps)):
-        kernels(True)
-    torch.cuda.synchronize()
 
     per = {}
     for nme, (e0, e1) in zip(names, events):
@@ -172,37 +169,37 @@ def main():
     passes = 6 + 1 + 3 + 3 + 3 * args.cg
     value = m * R * passes / (ms_per_step / 1000.0)
 
-    # algorithmic bytes (storage precision b; stream = indices + value)
-    b = 4 if args.form == "f32" else 2
-    dims = wl.dims
-    bytes_mttkrp = [m * (8 + 4 + 2 * R * b) + dims[n] * R * 4 for n in range(3)]
-    bytes_matvec = sum(m * (8 + 4 * R * b) + dims[n] * R * (2 * b + 4 + 4) for n in range(3))
-    bytes_tttp = m * (12 + 4) + sum(d * R * b for d in dims)
-    bytes_grad = sum(m * (8 + 4 + 2 * R * b) + dims[n] * R * (b + 4) for n in range(3))
-    krates = {}
-    for n in range(3):
-        ms = avg[f"mttkrp{n}"]
-        krates[f"mttkrp{n}"] = {"ms": ms, "GBps_alg": bytes_mttkrp[n] / ms / 1e6,
-                                "nnzR_per_s": m * R / ms * 1e3}
-        krates[f"solve{n}"] = {"ms": avg[f"solve{n}"]}
-    krates["gn_step"] = {"ms": avg["gn_step"]}
-    krates["tttp_loss"] = {"ms": avg["tttp_loss"], "GBps_alg": bytes_tttp / avg["tttp_loss"] / 1e6}
-    krates["gradient"] = {"ms": avg["gradient"], "GBps_alg": bytes_grad / avg["gradient"] / 1e6}
-    krates["gn_matvec"] = {"ms": avg["gn_matvec"],
-                           "GBps_alg": bytes_matvec / avg["gn_matvec"] / 1e6}
+    # C-ABI calls of the step (HIP events on the launch stream)
+    calls = {k: {"ms": v} for k, v in avg.items()}
 
-    # dominant streaming kernel by time in the step: the three MTTKRP launches
-    # (one per mode) are reported as one kernel averaged over its launches
-    mt_ms = float(np.mean([avg[f"mttkrp{n}"] for n in range(3)]))
-    mt_bytes = float(np.mean(bytes_mttkrp))
-    achieved = mt_bytes / mt_ms / 1e6
+    # dominant kernel: the library kernel with the largest total time over the
+    # timed steps (library profiler: HIP events on the launch stream around
+    # every launch, tagged with algorithmic bytes / flops per launch)
+    dom, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    n_l = rec["launches"]
+    per_ms = rec["ms"] / n_l
     src_hash = kernel_source_hash()
     wname = f"ratings{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}_m{m}_R{R}_{args.form}"
-    traffic = traffic_from_profile("mttkrp", wname, src_hash)
-    roofline = {"bound": "hbm", "kernel": "k_stream<MTTKRP> (mean of the 3 mode launches)",
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "alg_bytes_per_launch": mt_bytes, "launch_ms": mt_ms}
+    traffic = traffic_from_profile(dom, wname, src_hash)
+    if dom.startswith("gram"):
+        achieved = rec["flops"] / n_l / (per_ms / 1e3) / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+                    "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_MFMA_TFLOPS, "traffic": traffic,
+                    "alg_flops_per_launch": rec["flops"] / n_l,
+                    "alg_bytes_per_launch": rec["bytes"] / n_l, "launch_ms": per_ms,
+                    "launches": n_l}
+    else:
+        achieved = rec["bytes"] / n_l / (per_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": traffic, "alg_bytes_per_launch": rec["bytes"] / n_l,
+                    "launch_ms": per_ms, "launches": n_l}
+    step_prof = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step":
+                     v["launches"] / args.steps,
+                     "GBps_alg": v["bytes"] / v["ms"] / 1e6 if v["ms"] else None,
+                     "TFLOPs_alg": v["flops"] / v["ms"] / 1e9 if v["ms"] else None}
+                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -230,10 +227,12 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": krates,
+        "calls": calls,
+        "step_kernels": step_prof,
         "index_build_s": index_s,
         "generate_s": gen_s,
         "src_hash": src_hash,
+        "workload_key": wname,
     }
     print(json.dumps(out), flush=True)
 

@@ -10,8 +10,9 @@
  *
  * Conventions shared by all calls
  * -------------------------------
- *  - Indices are 0-based int32.  Supported orders: 2 <= N <= 4.  Rank
- *    1 <= R <= 64.
+ *  - Indices are 0-based int32.  The kernels implement order N = 3 (the
+ *    paper's focus, Section 2); tt_build_index returns TT_ERR_UNSUPPORTED
+ *    for other orders.  Rank 1 <= R <= 64.
  *  - Factor matrices are row-major with leading dimension ldA >= R elements
  *    (element (i, r) at A + i * ldA + r), stored in the factor dtype `fdt`.
  *    Row starts must be 16-byte aligned for the vectorized path (ldA * size
@@ -91,7 +92,7 @@ typedef struct tt_index tt_index; /* opaque, library-owned */
  * the other modes' indices in sorted order, ptr_n (I_n + 1 offsets, int64),
  * the list of nonzero rows, t pre-permuted into mode-n order (if d_t given),
  * and the work partitions used by the kernels.
- *   order    N, 2..4.            dims   host array of N extents (>= 1).
+ *   order    N (3).              dims   host array of N extents (>= 1).
  *   nnz      m >= 0 (m < 2^31).  d_idx  host array of N device pointers, m
  *            int32 each.         d_t    device pointer to m observed values
  *            in COO order, of dtype vdt (TT_F64 or TT_F32), or NULL.
@@ -195,8 +196,8 @@ tt_status solve_factor(const tt_index *ix, const void *d_w, int w_order,
  * fused into one pass over each mode's sorted stream.
  *   d_w, w_order    per-nonzero weights (phi''); TT_ORDER_PER_MODE or a
  *                   mode order or COO; NULL = the constant w_const.
- *   d_X, d_Y        host arrays of N device pointers; X in fdt with ldA,
- *                   Y dense dtype I_d x R (overwritten).
+ *   d_X, d_Y        host arrays of N device pointers to dense-dtype I_d x R
+ *                   blocks (contiguous); Y is overwritten.
  * ------------------------------------------------------------------------- */
 tt_status gn_matvec(const tt_index *ix, const void *d_w, int w_order,
                     double w_const, const void *const *d_A,
@@ -246,6 +247,20 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
 tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                      tt_dtype fdt, tt_loss loss, double lambda, double tol,
                      int kmax, double *d_stats, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel profiler (process-global; use from one host thread).
+ * tt_profile_enable(1) clears previous records and starts bracketing every
+ * library kernel launch with HIP events on the launch's stream, tagged with
+ * the launch's algorithmic bytes and flops (per-nonzero byte model: index
+ * streams, values and factor-row gathers at storage precision; Gram flops
+ * R (R + 1) per nonzero).  tt_profile_enable(0) stops recording.
+ * tt_profile_report writes a JSON object {kernel: {"launches", "ms",
+ * "bytes", "flops"}} (NUL-terminated, truncated to cap bytes) after waiting
+ * for the recorded events; *needed receives the full size including NUL.
+ * ------------------------------------------------------------------------- */
+tt_status tt_profile_enable(int on);
+tt_status tt_profile_report(char *buf, int64_t cap, int64_t *needed);
 
 /* Thread-local text describing the last non-OK status ("" if none). */
 const char *tt_last_error(void);

@@ -667,3 +667,108 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Kernel profiler
+// ---------------------------------------------------------------------------
+namespace tt {
+
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+
+static struct {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+} g_prof;
+
+bool prof_on() { return g_prof.on; }
+
+static hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ProfScope::ProfScope(const char *name, hipStream_t s, double bytes, double flops) {
+  if (!g_prof.on) return;
+  ProfRec r{name, prof_event(), prof_event(), bytes, flops};
+  if (!r.a || !r.b) return;
+  hipEventRecord(r.a, s);
+  slot = (int)g_prof.recs.size();
+  stream = s;
+  g_prof.recs.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (slot >= 0 && slot < (int)g_prof.recs.size()) hipEventRecord(g_prof.recs[slot].b, stream);
+}
+
+}  // namespace tt
+
+extern "C" {
+
+tt_status tt_profile_enable(int on) {
+  g_err.clear();
+  if (on) {
+    hipDeviceSynchronize();
+    for (auto &r : g_prof.recs) {
+      g_prof.pool.push_back(r.a);
+      g_prof.pool.push_back(r.b);
+    }
+    g_prof.recs.clear();
+  }
+  g_prof.on = on != 0;
+  return TT_OK;
+}
+
+tt_status tt_profile_report(char *buf, int64_t cap, int64_t *needed) {
+  g_err.clear();
+  struct Agg {
+    int64_t n = 0;
+    double ms = 0, bytes = 0, flops = 0;
+  };
+  std::vector<std::pair<std::string, Agg>> agg;
+  for (auto &r : g_prof.recs) {
+    float ms = 0.f;
+    TT_HIP(hipEventSynchronize(r.b));
+    TT_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    auto it = std::find_if(agg.begin(), agg.end(),
+                           [&](const std::pair<std::string, Agg> &x) { return x.first == r.name; });
+    if (it == agg.end()) {
+      agg.push_back({r.name, Agg()});
+      it = agg.end() - 1;
+    }
+    it->second.n += 1;
+    it->second.ms += ms;
+    it->second.bytes += r.bytes;
+    it->second.flops += r.flops;
+  }
+  std::string out = "{";
+  char tmp[512];
+  for (size_t i = 0; i < agg.size(); ++i) {
+    snprintf(tmp, sizeof(tmp),
+             "%s\"%s\": {\"launches\": %lld, \"ms\": %.6f, \"bytes\": %.6e, \"flops\": %.6e}",
+             i ? ", " : "", agg[i].first.c_str(), (long long)agg[i].second.n, agg[i].second.ms,
+             agg[i].second.bytes, agg[i].second.flops);
+    out += tmp;
+  }
+  out += "}";
+  if (needed) *needed = (int64_t)out.size() + 1;
+  if (buf && cap > 0) {
+    int64_t n = std::min<int64_t>(cap - 1, (int64_t)out.size());
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return TT_OK;
+}
+
+}  // extern "C"

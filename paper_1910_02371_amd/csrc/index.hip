@@ -482,8 +482,13 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
     if ((st = upload(ix, &md.d_row_task, row_task, s)) != TT_OK) break;
     md.h_row_task = row_task;
     md.h_heavy_task.clear();
+    md.h_heavy_nnz.assign(1, 0);
     for (int64_t q = 0; q + 1 < (int64_t)task.size(); ++q)
-      if (task[q + 1] - task[q] > kGramLight) md.h_heavy_task.push_back((int32_t)q);
+      if (task[q + 1] - task[q] > kGramLight) {
+        md.h_heavy_task.push_back((int32_t)q);
+        md.h_heavy_nnz.push_back(md.h_heavy_nnz.back() + task[q + 1] - task[q]);
+      }
+    md.h_task = task;
     md.h_multi_row.clear();
     for (int64_t i = 0; i < dims[n]; ++i)
       if (row_task[i + 1] - row_task[i] > kReduceMin) md.h_multi_row.push_back((int32_t)i);

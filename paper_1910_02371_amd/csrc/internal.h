@@ -42,6 +42,8 @@ struct ModeIndex {
   int64_t *d_task = nullptr;        // ntask + 1 boundaries
   int32_t *d_row_task = nullptr;    // I + 1: tasks of row i
   std::vector<int32_t> h_row_task;  // host copy, for batching
+  std::vector<int64_t> h_task;      // host copy of task boundaries
+  std::vector<int64_t> h_heavy_nnz; // prefix sums of heavy-task sizes
   int32_t max_task_per_row = 0;
   int32_t *d_heavy_task = nullptr;  // tasks with > kGramLight nonzeros
   std::vector<int32_t> h_heavy_task;
@@ -92,6 +94,17 @@ tt_status ws_get(tt_index *ix, const char *name, size_t bytes, void **out);
 
 inline size_t dtype_size(tt_dtype d) { return d == TT_F64 ? 8 : (d == TT_F32 ? 4 : 2); }
 inline size_t value_size(tt_dtype fdt) { return fdt == TT_F64 ? 8 : 4; }
+
+// ----- kernel profiler ------------------------------------------------------
+// While enabled, ProfScope brackets a launch with HIP events on its stream
+// and tags it with algorithmic bytes and flops (process-global state).
+struct ProfScope {
+  ProfScope(const char *name, hipStream_t s, double bytes, double flops);
+  ~ProfScope();
+  int slot = -1;
+  hipStream_t stream = nullptr;
+};
+bool prof_on();
 
 // ----- launchers (return hipError_t of the last launch) ----------------------
 // index.hip

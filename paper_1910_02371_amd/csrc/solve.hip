@@ -508,24 +508,39 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
 
 template <class TR, int RP>
 static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
-                               hipStream_t s) {
+                               double light_bytes, double light_flops, double heavy_bytes,
+                               double heavy_flops, hipStream_t s) {
   const int64_t n = d.task_end - d.task_base;
   d.split_heavy = 1;
-  k_gram_f32<TR, RP><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
-  if (nheavy > 0)
+  {
+    ProfScope ps("gram_light", s, light_bytes, light_flops);
+    k_gram_f32<TR, RP><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+  }
+  if (nheavy > 0) {
+    ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
     k_gram_f32_heavy<TR, RP><<<dim3((unsigned)nheavy), dim3(512), 0, s>>>(d, heavy, nheavy);
+  }
 }
 
 // Gram of one batch of tasks [task_base, task_end): light tasks one wave
 // each, heavy tasks (the `heavy` slice) one workgroup each, then the
 // pre-reduction of rows with many tasks (the `multi` slice).
+struct GramWork {
+  double light_nnz, heavy_nnz, light_tasks, reduce_tasks;
+};
+
 static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int32_t *heavy,
                               int64_t nheavy, const int32_t *multi, int64_t nmulti,
-                              const int32_t *row_task, hipStream_t s) {
+                              const int32_t *row_task, const GramWork &wk, hipStream_t s) {
   const int64_t n = d.task_end - d.task_base;
   if (n <= 0) return hipSuccess;
   dim3 g((unsigned)((n + 3) / 4)), b(256);
+  const double R = d.R, fb = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
+  const double gs = fdt == TT_F64 ? 8 : 4, pernz = 8 + (d.w ? gs : 0) + 2 * R * fb;
+  const double tile = (double)RP * RP * gs;
   if (fdt == TT_F64) {
+    ProfScope ps("gram_light", s, (wk.light_nnz + wk.heavy_nnz) * pernz + wk.light_tasks * tile,
+                 (wk.light_nnz + wk.heavy_nnz) * R * (R + 1));
     GramDev d2 = d;
     d2.split_heavy = 0;
     switch (RP) {
@@ -533,20 +548,28 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
       case 32: k_gram_f64<32><<<g, b, 0, s>>>(d2); break;
       default: k_gram_f64<64><<<g, b, 0, s>>>(d2); break;
     }
-  } else if (fdt == TT_F32) {
-    switch (RP) {
-      case 16: launch_gram_f32_rp<TrF32, 16>(d, heavy, nheavy, s); break;
-      case 32: launch_gram_f32_rp<TrF32, 32>(d, heavy, nheavy, s); break;
-      default: launch_gram_f32_rp<TrF32, 64>(d, heavy, nheavy, s); break;
-    }
   } else {
-    switch (RP) {
-      case 16: launch_gram_f32_rp<TrBF16, 16>(d, heavy, nheavy, s); break;
-      case 32: launch_gram_f32_rp<TrBF16, 32>(d, heavy, nheavy, s); break;
-      default: launch_gram_f32_rp<TrBF16, 64>(d, heavy, nheavy, s); break;
+    const double lb = wk.light_nnz * pernz + wk.light_tasks * tile;
+    const double lf = wk.light_nnz * R * (R + 1);
+    const double hb = wk.heavy_nnz * pernz + (double)nheavy * tile;
+    const double hf = wk.heavy_nnz * R * (R + 1);
+    if (fdt == TT_F32) {
+      switch (RP) {
+        case 16: launch_gram_f32_rp<TrF32, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 32: launch_gram_f32_rp<TrF32, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        default: launch_gram_f32_rp<TrF32, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+      }
+    } else {
+      switch (RP) {
+        case 16: launch_gram_f32_rp<TrBF16, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 32: launch_gram_f32_rp<TrBF16, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        default: launch_gram_f32_rp<TrBF16, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+      }
     }
   }
   if (nmulti > 0) {
+    ProfScope ps("gram_reduce", s, wk.reduce_tasks * tile + (double)nmulti * tile,
+                 wk.reduce_tasks * RP * RP);
     dim3 gr((unsigned)nmulti, (unsigned)((RP * RP + 255) / 256));
     if (fdt == TT_F64) {
       switch (RP) {
@@ -626,12 +649,24 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     const int64_t h1 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r1]) - ht.begin();
     const int64_t q0 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r0) - mr.begin();
     const int64_t q1 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r1) - mr.begin();
+    GramWork wk;
+    const std::vector<int64_t> &hn = md.h_heavy_nnz;
+    wk.heavy_nnz = (double)(hn[h1] - hn[h0]);
+    wk.light_nnz = (double)(md.h_task[rt[r1]] - md.h_task[rt[r0]]) - wk.heavy_nnz;
+    wk.light_tasks = (double)(rt[r1] - rt[r0]) - (double)(h1 - h0);
+    wk.reduce_tasks = 0;
+    for (int64_t q = q0; q < q1; ++q) wk.reduce_tasks += rt[mr[q] + 1] - rt[mr[q]];
     hipError_t e = launch_gram(c.fdt, RP, gd, md.d_heavy_task + h0, h1 - h0,
-                               md.d_multi_row + q0, q1 - q0, md.d_row_task, s);
+                               md.d_multi_row + q0, q1 - q0, md.d_row_task, wk, s);
     if (e != hipSuccess) return hip_fail(e, "gram kernel");
     sd.task_base = rt[r0];
     sd.r0 = r0;
-    // advance row pointers by offsetting the batch (row index = r0 + block)
+    const double Rd = c.R, nrow = (double)(r1 - r0);
+    ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
+                 (double)(rt[r1] - rt[r0]) * RP * RP * (double)gsz +
+                     nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
+                     (c.Lstore ? nrow * RP * RP * 8.0 : 0.0),
+                 nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
     if (c.fdt == TT_F64)
       e = launch_solve_rp<double, double, double>(RP, sd, r1 - r0, s);
     else if (c.fdt == TT_F32)
@@ -651,6 +686,8 @@ hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt
   if (I <= 0) return hipSuccess;
   const int RP = rp_for(R);
   dim3 g((unsigned)I), b(64);
+  ProfScope ps("precond_apply", s, (double)I * RP * RP * 8.0 + (double)I * R * 8.0,
+               (double)I * 2.0 * R * R);
   if (fdt == TT_F64) {
     switch (RP) {
       case 16: k_apply_rows<double, 16><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;

@@ -69,15 +69,45 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   d.carry = c.carry;
   d.skip = c.skip;
   hipError_t e;
-  if (c.fdt == TT_F32)
-    e = launch_stream_f32(op, d, md.nchunk, G, vec, s);
-  else if (c.fdt == TT_BF16)
-    e = launch_stream_bf16(op, d, md.nchunk, G, vec, s);
-  else
-    e = launch_stream_f64(op, d, md.nchunk, G, vec, s);
+  {
+    // algorithmic work of this launch (per-nonzero byte model: index
+    // streams, values, factor-row gathers at storage precision)
+    const double m = (double)ix->m, R = c.R, N = ix->N;
+    const double b = c.fdt == TT_F64 ? 8 : (c.fdt == TT_F32 ? 4 : 2);
+    const double v = c.fdt == TT_F64 ? 8 : 4, xs = v, I = (double)md.I;
+    double bytes = 0, flops = 0;
+    const char *name = "tttp";
+    if (op == OP_TTTP) {
+      int given = 0;
+      for (int p = 0; p < ix->N; ++p) given += c.A[p] != nullptr;
+      bytes = m * (4 * N + (c.s ? v : 0) + (c.out ? v : 0) + given * R * b);
+      flops = m * R * given;
+    } else if (op == OP_MTTKRP) {
+      name = "mttkrp";
+      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (N - 1) * R * b) + I * R * xs;
+      flops = m * R * N;
+    } else if (op == OP_GRAD) {
+      name = "gradient";
+      bytes = m * (4 * (N - 1) + v + (N - 1) * R * b) + I * R * (b + 2 * xs);
+      flops = m * R * (N + 3);
+    } else {
+      name = "gn_matvec";
+      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (N - 1) * R * (b + xs)) + I * R * (b + 3 * xs);
+      flops = m * R * 10;
+    }
+    ProfScope ps(name, s, bytes, flops);
+    if (c.fdt == TT_F32)
+      e = launch_stream_f32(op, d, md.nchunk, G, vec, s);
+    else if (c.fdt == TT_BF16)
+      e = launch_stream_bf16(op, d, md.nchunk, G, vec, s);
+    else
+      e = launch_stream_f64(op, d, md.nchunk, G, vec, s);
+  }
   if (e != hipSuccess) return e;
   if (op != OP_TTTP && md.nheavy > 0) {
     const int RP = G * V;
+    ProfScope ps("heavy_fixup", s, (double)md.nslot * RP * 8 + (double)md.nheavy * c.R * 4,
+                 (double)md.nslot * RP);
     if (c.fdt == TT_F64)
       k_heavy_fixup<double><<<(unsigned)md.nheavy, 256, 0, s>>>(
           md.d_heavy_row, md.d_heavy_slot, c.carry, RP, c.R, c.out, c.accumulate, c.skip);

@@ -1,0 +1,113 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_1910_02371_amd.rocprof_summary stats  <kernel_stats.csv> <out.md> <cmd>
+  python -m paper_1910_02371_amd.rocprof_summary traffic <fetch_dir> <write_dir> \\
+        <kernel> <workload> <src_hash> <copy_bytes> <out.md> <cmd>
+
+``stats`` renders the per-kernel table of a ``--kernel-trace --stats`` run.
+``traffic`` reads two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE; KiB per
+dispatch), scales each by what the same counter reads for the plain copy
+kernel of ``copy_bytes`` bytes that the profiled program runs first (a copy
+reads and writes exactly copy_bytes), and records the HBM bytes per launch
+of ``kernel`` in profiles/traffic.json, keyed by kernel and workload and
+tagged with the kernel-source hash they were measured with.
+"""
+import csv
+import glob
+import json
+import os
+import sys
+
+# library profiler names -> substrings of the device kernel names
+KERNEL_MATCH = {
+    "tttp": ", 3, ", "mttkrp": None, "gradient": None, "gn_matvec": None,
+    "gram_heavy": "k_gram_f32_heavy", "gram_light": "k_gram_f32<",
+    "gram_reduce": "k_gram_reduce", "cholesky_solve": "k_solve_rows",
+    "cholesky_factor": "k_solve_rows", "precond_apply": "k_apply_rows",
+    "heavy_fixup": "k_heavy_fixup",
+}
+STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3}
+
+
+def matches(kernel, name):
+    if kernel in STREAM_OP:
+        return "k_stream<" in name and name.rstrip(")").split("(")[0].endswith(
+            f", {STREAM_OP[kernel]}>")
+    return KERNEL_MATCH[kernel] in name
+
+
+def stats(csv_path, out_md, cmd):
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics\n", f"Command: `{cmd}`\n",
+             "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in rows[:25]:
+        lines.append(f"| `{r['Name'][:100]}` | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _counter_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(files[0])))
+
+
+def _per_dispatch(rows, counter):
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r["Dispatch_Id"], r["Kernel_Name"])
+        out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def traffic(fetch_dir, write_dir, kernel, workload, src_hash, copy_bytes, out_md, cmd):
+    copy_bytes = float(copy_bytes)
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        disp = _per_dispatch(_counter_rows(d), counter)
+        copies = [v for (i, n), v in disp.items() if "copy" in n.lower() or
+                  "elementwise_kernel" in n.lower()]
+        if not copies:
+            raise SystemExit(f"{counter}: no copy-kernel dispatch found")
+        ref = max(copies)  # KiB read (or written) by the calibration copy
+        scale = copy_bytes / (ref * 1024.0)
+        ks = [v for (i, n), v in disp.items() if matches(kernel, n)]
+        if not ks:
+            raise SystemExit(f"{counter}: no dispatch of {kernel}")
+        res[counter] = {"scale": scale, "launches": len(ks),
+                        "bytes_per_launch": sum(ks) * 1024.0 * scale / len(ks)}
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    path = os.path.join(os.path.dirname(out_md), "traffic.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    db[f"{kernel}|{workload}"] = {"bytes_per_launch": total, "src_hash": src_hash,
+                                  "fetch_bytes_per_launch": res["FETCH_SIZE"]["bytes_per_launch"],
+                                  "write_bytes_per_launch": res["WRITE_SIZE"]["bytes_per_launch"],
+                                  "fetch_scale": res["FETCH_SIZE"]["scale"],
+                                  "write_scale": res["WRITE_SIZE"]["scale"],
+                                  "launches": res["FETCH_SIZE"]["launches"]}
+    json.dump(db, open(path, "w"), indent=1, sort_keys=True)
+    lines = [f"# HBM traffic of `{kernel}` on {workload}\n", f"Command: `{cmd}`\n",
+             f"Kernel source hash: {src_hash}\n",
+             "| counter | copy-kernel scale | launches | bytes per launch |",
+             "|---|---|---|---|"]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        r = res[c]
+        lines.append(f"| {c} | {r['scale']:.4f} | {r['launches']} | {r['bytes_per_launch']:.4e} |")
+    lines.append(f"\nTotal HBM bytes per launch: {total:.4e}\n")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:5])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:10])
+    else:
+        raise SystemExit(__doc__)

@@ -48,6 +48,8 @@ SIGNATURES = {
     "tt_objective": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _P, _P]),
     "tt_als_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
     "tt_gn_step": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P]),
+    "tt_profile_enable": (_I, [_I]),
+    "tt_profile_report": (_I, [ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "tt_last_error": (ctypes.c_char_p, []),
     "tt_version": (ctypes.c_char_p, []),
 }
@@ -322,3 +324,18 @@ def gn_step(ix, A, loss, lam, tol=5e-3, kmax=30, stats=None):
     _check(lib().tt_gn_step(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
                             float(tol), int(kmax), _ptr(stats), _stream()))
     return stats
+
+
+def profile_enable(on=True):
+    """Start (clearing old records) or stop the library's kernel profiler."""
+    _check(lib().tt_profile_enable(1 if on else 0))
+
+
+def profile_report():
+    """Per-kernel launches, total milliseconds, algorithmic bytes and flops."""
+    import json
+    need = ctypes.c_int64()
+    _check(lib().tt_profile_report(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value + 16)
+    _check(lib().tt_profile_report(buf, need.value + 16, ctypes.byref(need)))
+    return json.loads(buf.value.decode())
