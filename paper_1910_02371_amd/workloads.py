@@ -277,3 +277,26 @@ def uniform_chunk(c, side=1 << 20, chunk=1 << 26, seed=SEED_DATA + 5, rank=10,
 def uniform_planted(side=1 << 20, seed=SEED_DATA + 5, rank=10):
     rng = rng_for(seed)
     return [rng.random((side, rank)) for _ in range(3)]
+
+
+def uniform(m=1_500_000_000, side=1 << 20, seed=SEED_DATA + 5, rank=10, chunk=1 << 26):
+    """The 2^20-cubed uniform tensor: ceil(m / chunk) chunks (each from its
+    own Philox key), generated in parallel into preallocated arrays and cut
+    to m nonzeros."""
+    P = uniform_planted(side, seed, rank)
+    nch = -(-m // chunk)
+    idx = [np.empty(m, dtype=np.int32) for _ in range(3)]
+    t = np.empty(m, dtype=np.float32)
+
+    def work(c):
+        ci, ct = uniform_chunk(c, side, chunk, seed, rank, P)
+        b = c * chunk
+        e = min(m, b + chunk)
+        for n in range(3):
+            idx[n][b:e] = ci[n][:e - b]
+        t[b:e] = ct[:e - b]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max(1, _threads() // 2)) as ex:
+        list(ex.map(work, range(nch)))
+    return Workload(f"uniform{side}^3_m{m}", (side, side, side), idx, t, P,
+                    dict(lam=1e-5, loss="ls"))
