@@ -45,7 +45,9 @@ def parse():
     p.add_argument("--cg", type=int, default=2, help="CG iterations in the GN step")
     p.add_argument("--nnz", type=int, default=100_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=1 << 18)
+    p.add_argument("--cpu-sample", type=int, default=1 << 19)
+    p.add_argument("--form-sweeps", type=int, default=5,
+                   help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this size first (counter calibration)")
     return p.parse_args()
@@ -201,6 +203,10 @@ def main():
                      "TFLOPs_alg": v["flops"] / v["ms"] / 1e9 if v["ms"] else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
+    forms = None
+    if args.form_sweeps > 0:
+        forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, A0, R, lam, args.cpu_sample, passes)
@@ -227,6 +233,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
         "calls": calls,
         "step_kernels": step_prof,
         "index_build_s": index_s,
@@ -235,6 +242,35 @@ def main():
         "workload_key": wname,
     }
     print(json.dumps(out), flush=True)
+
+
+def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev):
+    """ALS from the same FP32 start with FP32 and with BF16 factor storage:
+    per-sweep wall time (HIP events) and training RMSE (TTTP loss epilogue,
+    lambda = 0).  Equal RMSE means |RMSE_bf16 / RMSE_f32 - 1| <= 1% after the
+    same number of sweeps."""
+    import torch
+    out = {}
+    for form, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        A = [torch.as_tensor(a).to(dev).to(dt).contiguous() for a in A0]
+        info = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
+        ms, rmse = [], []
+        for _ in range(sweeps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tt.als_sweep(ix, A, lam, info)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            rmse.append((tt.objective(ix, A, "ls", 0.0).item() / wl.nnz) ** 0.5)
+        out[form] = {"sweep_ms": ms, "rmse": rmse}
+    r32, r16 = out["f32"]["rmse"][-1], out["bf16"]["rmse"][-1]
+    out["rmse_ratio_bf16_over_f32"] = r16 / r32
+    out["equal_rmse_within_1pct"] = abs(r16 / r32 - 1.0) <= 0.01
+    out["sweep_speedup_bf16"] = (sum(out["f32"]["sweep_ms"][1:]) /
+                                 max(1e-9, sum(out["bf16"]["sweep_ms"][1:])))
+    return out
 
 
 def cpu_baseline(wl, A0, R, lam, sample, passes):

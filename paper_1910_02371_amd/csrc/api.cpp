@@ -115,7 +115,11 @@ static tt_status resolve_values(const tt_index *ix, const void *v, int order, in
 
 static tt_status carry_ws(tt_index *ix, double **carry) {
   void *p = nullptr;
-  TT_ST(ws_get(ix, "carry", (size_t)std::max<int64_t>(ix->max_nslot, 1) * 64 * 8, &p));
+  // carry slots, then first-level partials of the heavy-row reduction
+  TT_ST(ws_get(ix, "carry",
+               (size_t)(std::max<int64_t>(ix->max_nslot, 1) + std::max<int64_t>(ix->max_nseg, 1)) *
+                   64 * 8,
+               &p));
   *carry = (double *)p;
   return TT_OK;
 }
@@ -572,7 +576,7 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   TT_ST(ws_get(ix, "pcg_sc", 32 * 8, &vsc));
   TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &vparts));
   int64_t Ltot = 0;
-  for (int d = 0; d < N; ++d) Ltot += ix->mode[d].I * (int64_t)RP * RP;
+  for (int d = 0; d < N; ++d) Ltot += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
   TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * 8, &vL));
   if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &vw));
   char *X = (char *)vx, *Rv = (char *)vr, *Z = (char *)vz, *P = (char *)vp, *Q = (char *)vq;
@@ -584,7 +588,7 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
     int64_t lo = 0;
     for (int d = 0; d < N; ++d) {
       Lb[d] = L + lo;
-      lo += ix->mode[d].I * (int64_t)RP * RP;
+      lo += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
     }
   }
   // objective before the step (slot 10)

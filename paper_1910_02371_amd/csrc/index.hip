@@ -477,6 +477,19 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
     if ((st = upload(ix, &md.d_chunk_slot, slot, s)) != TT_OK) break;
     if ((st = upload(ix, &md.d_heavy_row, hrow, s)) != TT_OK) break;
     if ((st = upload(ix, &md.d_heavy_slot, hslot, s)) != TT_OK) break;
+    {
+      // carry segments: each heavy row's slots split into runs of kSegSlots
+      std::vector<int32_t> seg(1, 0), hseg(1, 0);
+      for (size_t h = 0; h + 1 < hslot.size(); ++h) {
+        for (int32_t a = hslot[h]; a < hslot[h + 1]; a += kSegSlots)
+          seg.push_back(std::min<int32_t>(hslot[h + 1], a + kSegSlots));
+        hseg.push_back((int32_t)seg.size() - 1);
+      }
+      md.nseg = (int64_t)seg.size() - 1;
+      if ((st = upload(ix, &md.d_seg, seg, s)) != TT_OK) break;
+      if ((st = upload(ix, &md.d_heavy_seg, hseg, s)) != TT_OK) break;
+      if ((he = hipStreamSynchronize(s)) != hipSuccess) { st = hip_fail(he, "upload"); break; }
+    }
     if ((st = upload(ix, &md.d_rows, rows, s)) != TT_OK) break;
     if ((st = upload(ix, &md.d_task, task, s)) != TT_OK) break;
     if ((st = upload(ix, &md.d_row_task, row_task, s)) != TT_OK) break;
@@ -500,6 +513,7 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
     ix->sum_I += md.I;
     ix->max_nchunk = std::max(ix->max_nchunk, md.nchunk);
     ix->max_nslot = std::max(ix->max_nslot, md.nslot);
+    ix->max_nseg = std::max(ix->max_nseg, md.nseg);
   }
   hipStreamSynchronize(s);
   free_tmp();

@@ -17,6 +17,7 @@ constexpr int kChunk = 2048;       // nnz per streaming work chunk (max)
 constexpr int kGramPiece = 4096;   // nnz per Gram task (max)
 constexpr int kGramLight = 512;    // tasks above this run on a whole workgroup
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
+constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
 
 struct ModeIndex {
@@ -37,6 +38,9 @@ struct ModeIndex {
   int64_t nheavy = 0;
   int32_t *d_heavy_row = nullptr;   // nheavy
   int32_t *d_heavy_slot = nullptr;  // nheavy + 1
+  int64_t nseg = 0;                 // carry segments (<= kSegSlots slots each)
+  int32_t *d_seg = nullptr;         // nseg + 1 slot boundaries
+  int32_t *d_heavy_seg = nullptr;   // nheavy + 1 segment ranges
   // Gram tasks: pieces of <= kGramPiece nnz of one row
   int64_t ntask = 0;
   int64_t *d_task = nullptr;        // ntask + 1 boundaries
@@ -68,7 +72,7 @@ struct tt_index {
   tt::ModeIndex mode[TT_MAX_ORDER];
   std::vector<void *> owned;                 // device allocations to free
   std::map<std::string, tt::Buf> ws;         // named workspace buffers
-  int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0;
+  int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
 };
 
 namespace tt {
@@ -152,7 +156,7 @@ struct SolveCall {
   const void *rhs;          // I x R dense dtype
   void *X;                  // I x R in fdt, leading dim ldA (may alias A)
   int32_t *info;            // optional
-  double *Lstore;           // when non-NULL: keep the Cholesky factors (I x RP x RP)
+  double *Lstore;           // when non-NULL: keep the Cholesky factors (I x RP(RP+1)/2)
   int factor_only;          // 1: factor and store, no solve
 };
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);

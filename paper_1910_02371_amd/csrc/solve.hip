@@ -108,28 +108,57 @@ struct GramAcc {
   }
 };
 
+#ifndef TT_GRAM_GS
+#define TT_GRAM_GS 8          // MFMA steps whose gathers are issued together
+#endif
+#ifndef TT_GRAM_PIPE
+#define TT_GRAM_PIPE 0        // 1: double-buffer groups across iterations
+#endif
+#ifndef TT_GRAM_HEAVY_WAVES
+#define TT_GRAM_HEAVY_WAVES 8 // waves of the workgroup that takes a heavy task
+#endif
+
+template <class TR, int RP, int GS>
+struct GramGroup {
+  float a0[GS], a1[GS], b0[GS], b1[GS], w[GS];
+};
+
+// Nonzeros [nb, ne) of one row into acc.  The range is walked in blocks of
+// 64 nonzeros (lane l loads the indices and weight of nonzero base + l,
+// coalesced, one block ahead) and, inside a block, in groups of GS MFMA
+// steps.  Groups are double-buffered: the shuffles and factor-row gathers
+// of group g + 1 are issued before the MFMAs of group g, so a wave overlaps
+// its own gather latency with matrix-core work.  Padding columns (i >= R)
+// use a clamped address and a zero mask, so loads are unconditional; steps
+// past the end read lanes whose weight is 0.
 template <class TR, int RP>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
   using T = typename TR::T;
   constexpr int NPS = (RP == 16) ? 4 : 2;     // nonzeros per MFMA step
   constexpr int MW = (RP == 16) ? 16 : 32;    // M = N of the instruction
-  constexpr int GS = 8;                       // steps issued together
+  constexpr int GS = TT_GRAM_GS;              // steps per group
   constexpr int SPB = 64 / NPS;               // steps per 64-nonzero block
+  constexpr int GPB = SPB / GS;               // groups per block
   const int lane = threadIdx.x & 63;
   const T *A0 = reinterpret_cast<const T *>(d.A0);
   const T *A1 = reinterpret_cast<const T *>(d.A1);
   const int R = d.R;
-  const int64_t ldA = d.ldA;
+  const uint32_t ldA = (uint32_t)d.ldA;
   const int i = lane % MW;
   const int kk = lane / MW;
   const int c0 = i < R ? i : 0;
   const float m0 = i < R ? 1.f : 0.f;
   const int c1 = (i + 32 < R) ? i + 32 : 0;
   const float m1 = (i + 32 < R) ? 1.f : 0.f;
+  const int64_t n = ne - nb;
+  if (n <= 0) return;
+  const int64_t nblk = (n + 63) / 64;
+  const int last_cnt = (int)(n - (nblk - 1) * 64);
+  const int64_t gtot = (nblk - 1) * GPB + ((last_cnt + NPS - 1) / NPS + GS - 1) / GS;
 
-  auto load_block = [&](int64_t base, int &j0, int &j1, float &w) {
-    const int64_t e = base + lane;
+  auto load_block = [&](int64_t blk, int &j0, int &j1, float &w) {
+    const int64_t e = nb + blk * 64 + lane;
     if (e < ne) {
       j0 = d.oidx0[e];
       j1 = d.oidx1[e];
@@ -138,54 +167,82 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
       j0 = 0; j1 = 0; w = 0.f;
     }
   };
-  int n0 = 0, n1 = 0;
-  float nw = 0.f;
-  if (nb < ne) load_block(nb, n0, n1, nw);
-  for (int64_t base = nb; base < ne; base += 64) {
-    const int my0 = n0, my1 = n1;
-    const float myw = nw;
-    if (base + 64 < ne) load_block(base + 64, n0, n1, nw);
-    const int cnt = (int)min((int64_t)64, ne - base);
-    const int steps = (cnt + NPS - 1) / NPS;
-    for (int st0 = 0; st0 < steps; st0 += GS) {
-      int j0[GS], j1[GS];
-      float w[GS];
+  // group gi reads block gi / GPB: `cur` registers hold the block of the
+  // group being prepared, `nxt` the following block
+  int cj0, cj1, nj0 = 0, nj1 = 0;
+  float cw, nw = 0.f;
+  load_block(0, cj0, cj1, cw);
+  if (nblk > 1) load_block(1, nj0, nj1, nw);
+  int64_t cblk = 0;  // block held in cur
+
+  auto prepare = [&](int64_t gi, GramGroup<TR, RP, GS> &g) {
+    const int64_t blk = gi / GPB;
+    if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
+      cj0 = nj0; cj1 = nj1; cw = nw;
+      cblk = blk;
+      if (blk + 1 < nblk) load_block(blk + 1, nj0, nj1, nw);
+    }
+    const int st0 = (int)(gi % GPB) * GS;
+    int j0[GS], j1[GS];
 #pragma unroll
-      for (int u = 0; u < GS; ++u) {
-        const int src = ((st0 + u) % SPB) * NPS + kk;  // lanes >= cnt carry w = 0
-        j0[u] = __shfl(my0, src);
-        j1[u] = __shfl(my1, src);
-        w[u] = __shfl(myw, src);
+    for (int u = 0; u < GS; ++u) {
+      const int src = (st0 + u) * NPS + kk;
+      j0[u] = __shfl(cj0, src);
+      j1[u] = __shfl(cj1, src);
+      g.w[u] = __shfl(cw, src);
+    }
+#pragma unroll
+    for (int u = 0; u < GS; ++u) {
+      const uint32_t r0 = (uint32_t)j0[u] * ldA, r1 = (uint32_t)j1[u] * ldA;
+      g.a0[u] = elem_f32off<TR>(A0, r0 + c0);
+      g.a1[u] = elem_f32off<TR>(A1, r1 + c0);
+      if constexpr (RP == 64) {
+        g.b0[u] = elem_f32off<TR>(A0, r0 + c1);
+        g.b1[u] = elem_f32off<TR>(A1, r1 + c1);
       }
-      __builtin_amdgcn_sched_barrier(0);  // keep the GS gathers together
-      float a0[GS], a1[GS], b0[GS], b1[GS];
+    }
+  };
+  auto consume = [&](const GramGroup<TR, RP, GS> &g) {
 #pragma unroll
-      for (int u = 0; u < GS; ++u) {
-        const uint32_t r0 = (uint32_t)j0[u] * (uint32_t)ldA, r1 = (uint32_t)j1[u] * (uint32_t)ldA;
-        a0[u] = elem_f32off<TR>(A0, r0 + c0);
-        a1[u] = elem_f32off<TR>(A1, r1 + c0);
+    for (int u = 0; u < GS; ++u) {
+      const float h0 = g.a0[u] * g.a1[u] * m0;
+      if constexpr (RP == 16) {
+        acc.c16 = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, g.w[u] * h0, acc.c16, 0, 0, 0);
+      } else {
+        acc.c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, g.w[u] * h0, acc.c00, 0, 0, 0);
         if constexpr (RP == 64) {
-          b0[u] = elem_f32off<TR>(A0, r0 + c1);
-          b1[u] = elem_f32off<TR>(A1, r1 + c1);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int u = 0; u < GS; ++u) {
-        const float h0 = a0[u] * a1[u] * m0;
-        if constexpr (RP == 16) {
-          acc.c16 = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, w[u] * h0, acc.c16, 0, 0, 0);
-        } else {
-          acc.c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w[u] * h0, acc.c00, 0, 0, 0);
-          if constexpr (RP == 64) {
-            const float h1 = b0[u] * b1[u] * m1;
-            acc.c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, w[u] * h1, acc.c01, 0, 0, 0);
-            acc.c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, w[u] * h1, acc.c11, 0, 0, 0);
-          }
+          const float h1 = g.b0[u] * g.b1[u] * m1;
+          acc.c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, g.w[u] * h1, acc.c01, 0, 0, 0);
+          acc.c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, g.w[u] * h1, acc.c11, 0, 0, 0);
         }
       }
     }
+  };
+
+#if TT_GRAM_PIPE
+  GramGroup<TR, RP, GS> ga, gb;
+  prepare(0, ga);
+  int64_t gi = 0;
+  for (; gi + 1 < gtot; gi += 2) {
+    prepare(gi + 1, gb);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(ga);
+    __builtin_amdgcn_sched_barrier(0);
+    if (gi + 2 < gtot) prepare(gi + 2, ga);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(gb);
+    __builtin_amdgcn_sched_barrier(0);
   }
+  if (gi < gtot) consume(ga);
+#else
+  GramGroup<TR, RP, GS> ga;
+  for (int64_t gi = 0; gi < gtot; ++gi) {
+    prepare(gi, ga);
+    __builtin_amdgcn_sched_barrier(0);
+    consume(ga);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#endif
 }
 
 // Write the upper triangle of G (row-major RP x RP) from the accumulators.
@@ -225,22 +282,23 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
 }
 
-// Heavy tasks: the eight waves of a workgroup split the task's nonzeros and
-// add their accumulators through LDS in wave order (deterministic).
+// Heavy tasks: the waves of a workgroup split the task's nonzeros and add
+// their accumulators through LDS in wave order (deterministic).
 template <class TR, int RP>
-__global__ __launch_bounds__(512) void k_gram_f32_heavy(GramDev d, const int32_t *heavy,
-                                                        int64_t nheavy) {
+__global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
+    GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
+  constexpr int NW = TT_GRAM_HEAVY_WAVES;
   __shared__ float buf[NV * 64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t = heavy[blockIdx.x];
   const int64_t nb = d.task[t], ne = d.task[t + 1];
-  const int64_t per = (((ne - nb) + 7) / 8 + 1) & ~(int64_t)1;
+  const int64_t per = (((ne - nb) + NW - 1) / NW + 1) & ~(int64_t)1;
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP>(d, b0, b1, acc);
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
@@ -363,7 +421,7 @@ struct SolveDev {
   void *X;                   // I x R in storage dtype, leading dim ldX
   int64_t ldX;
   int32_t *info;
-  double *Lstore;            // I x RP x RP (optional)
+  double *Lstore;            // I x RP (RP + 1) / 2 packed factors (optional)
   int factor_only;
   const double *skip;
 };
@@ -374,13 +432,15 @@ struct SolveDev {
 // the trailing update of step k is RP-k-1 independent FMAs per lane.
 // Returns info (LAPACK potrf convention).  One wave per workgroup.
 template <int RP>
-__device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col) {
+__device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col,
+                                          double &rdiag) {
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
     const double dkk = readlane_d(s[k], k);
     if (!(dkk > 0.0)) return k + 1;
     const double rd = sqrt(dkk);
     const double inv = 1.0 / rd;
+    if (lane == k) rdiag = inv;
     const double lik = lane > k ? s[k] * inv : (lane == k ? rd : 0.0);
     s[k] = lik;
     if (k + 1 < RP) {
@@ -397,13 +457,14 @@ __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col
 // Solve L L^T x = b with L held as in chol_lanes; b on lane i is b_i.
 // Lp: packed lower triangle in LDS (RP (RP + 1) / 2 doubles), row k at
 // k (k + 1) / 2, used by the backward solve where lane i needs L(k, i).
+// rdiag on lane i holds 1 / L(i, i).
 template <int RP>
 __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double b,
-                                                   int lane, double *Lp) {
+                                                   double rdiag, int lane, double *Lp) {
   // forward: L y = b (column-oriented, y kept in b)
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
-    const double yk = readlane_d(b, k) / readlane_d(s[k], k);
+    const double yk = readlane_d(b, k) * readlane_d(rdiag, k);
     b = lane == k ? yk : (lane > k ? b - s[k] * yk : b);
   }
   if (lane < RP) {
@@ -413,14 +474,10 @@ __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double
       if (j <= lane) row[j] = s[j];
   }
   __syncthreads();
-  double diag = 0.0;
-#pragma unroll
-  for (int k = 0; k < RP; ++k)
-    if (k == lane) diag = s[k];
   // backward: L^T x = y
 #pragma unroll
   for (int k = RP - 1; k >= 0; --k) {
-    const double xk = readlane_d(b, k) / readlane_d(diag, k);
+    const double xk = readlane_d(b, k) * readlane_d(rdiag, k);
     const double lki = (lane < k) ? Lp[(k * (k + 1)) / 2 + lane] : 0.0;
     b = lane == k ? xk : (lane < k ? b - lki * xk : b);
   }
@@ -454,21 +511,26 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
     if (lane >= R || j >= R) s[j] = (j == lane) ? 1.0 : 0.0;
     else if (j == lane) s[j] += d.lambda;
   }
-  const int info = chol_lanes<RP>(s, lane, col);
+  double rdiag = 1.0;
+  const int info = chol_lanes<RP>(s, lane, col, rdiag);
   if (d.info && lane == 0) d.info[row] = info;
   if (d.Lstore) {
-    // stored by columns of the lane layout: L(lane, j) at j * RP + lane
-    double *L = d.Lstore + row * (int64_t)(RP * RP) + lane;
+    // packed lower triangle stored by columns: L(i, j), i >= j, at
+    // col_off(j) + i - j with col_off(j) = j RP - j (j - 1) / 2 (coalesced
+    // over the lanes i of each column)
+    double *L = d.Lstore + row * (int64_t)(RP * (RP + 1) / 2);
     if (lane < RP) {
 #pragma unroll
-      for (int j = 0; j < RP; ++j) L[j * RP] = info ? ((j == lane) ? 1.0 : 0.0) : s[j];
+      for (int j = 0; j < RP; ++j)
+        if (lane >= j)
+          L[j * RP - (j * (j - 1)) / 2 + lane - j] = info ? ((j == lane) ? 1.0 : 0.0) : s[j];
     }
   }
   if (d.factor_only) return;
   double x = 0.0;
   if (info == 0) {
     const double b = lane < R ? (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane] : 0.0;
-    x = chol_solve_lanes<RP>(s, b, lane, Lp);
+    x = chol_solve_lanes<RP>(s, b, rdiag, lane, Lp);
   }
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
@@ -483,11 +545,16 @@ __global__ __launch_bounds__(64) void k_apply_rows(const double *__restrict__ Ls
   const int lane = threadIdx.x;
   const int64_t row = blockIdx.x;
   double s[RP];
-  const double *L = Lstore + row * (int64_t)(RP * RP) + (lane < RP ? lane : 0);
+  const double *L = Lstore + row * (int64_t)(RP * (RP + 1) / 2);
 #pragma unroll
-  for (int j = 0; j < RP; ++j) s[j] = lane < RP ? L[j * RP] : 0.0;
+  for (int j = 0; j < RP; ++j)
+    s[j] = (lane < RP && lane >= j) ? L[j * RP - (j * (j - 1)) / 2 + lane - j] : 0.0;
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
-  const double x = chol_solve_lanes<RP>(s, b, lane, Lp);
+  double rdiag = 1.0;
+#pragma unroll
+  for (int k = 0; k < RP; ++k)
+    if (k == lane) rdiag = 1.0 / s[k];
+  const double x = chol_solve_lanes<RP>(s, b, rdiag, lane, Lp);
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
 }
 
@@ -518,7 +585,8 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   }
   if (nheavy > 0) {
     ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
-    k_gram_f32_heavy<TR, RP><<<dim3((unsigned)nheavy), dim3(512), 0, s>>>(d, heavy, nheavy);
+    k_gram_f32_heavy<TR, RP><<<dim3((unsigned)nheavy), dim3(64 * TT_GRAM_HEAVY_WAVES), 0, s>>>(
+        d, heavy, nheavy);
   }
 }
 
@@ -665,7 +733,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
                  (double)(rt[r1] - rt[r0]) * RP * RP * (double)gsz +
                      nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
-                     (c.Lstore ? nrow * RP * RP * 8.0 : 0.0),
+                     (c.Lstore ? nrow * RP * (RP + 1) / 2 * 8.0 : 0.0),
                  nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
     if (c.fdt == TT_F64)
       e = launch_solve_rp<double, double, double>(RP, sd, r1 - r0, s);
@@ -686,7 +754,7 @@ hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt
   if (I <= 0) return hipSuccess;
   const int RP = rp_for(R);
   dim3 g((unsigned)I), b(64);
-  ProfScope ps("precond_apply", s, (double)I * RP * RP * 8.0 + (double)I * R * 8.0,
+  ProfScope ps("precond_apply", s, (double)I * RP * (RP + 1) / 2 * 8.0 + (double)I * R * 8.0,
                (double)I * 2.0 * R * R);
   if (fdt == TT_F64) {
     switch (RP) {

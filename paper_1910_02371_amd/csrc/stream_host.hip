@@ -106,14 +106,18 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   if (e != hipSuccess) return e;
   if (op != OP_TTTP && md.nheavy > 0) {
     const int RP = G * V;
-    ProfScope ps("heavy_fixup", s, (double)md.nslot * RP * 8 + (double)md.nheavy * c.R * 4,
+    double *partial = c.carry + (int64_t)ix->max_nslot * 64;  // after the slots
+    ProfScope ps("heavy_fixup", s,
+                 (double)md.nslot * RP * 8 + (double)md.nseg * RP * 16 +
+                     (double)md.nheavy * c.R * 4,
                  (double)md.nslot * RP);
+    k_carry_partial<<<(unsigned)md.nseg, 256, 0, s>>>(md.d_seg, c.carry, RP, partial, c.skip);
     if (c.fdt == TT_F64)
       k_heavy_fixup<double><<<(unsigned)md.nheavy, 256, 0, s>>>(
-          md.d_heavy_row, md.d_heavy_slot, c.carry, RP, c.R, c.out, c.accumulate, c.skip);
+          md.d_heavy_row, md.d_heavy_seg, partial, RP, c.R, c.out, c.accumulate, c.skip);
     else
       k_heavy_fixup<float><<<(unsigned)md.nheavy, 256, 0, s>>>(
-          md.d_heavy_row, md.d_heavy_slot, c.carry, RP, c.R, c.out, c.accumulate, c.skip);
+          md.d_heavy_row, md.d_heavy_seg, partial, RP, c.R, c.out, c.accumulate, c.skip);
     e = hipGetLastError();
   }
   return e;

@@ -367,7 +367,32 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   }
 }
 
-// Heavy rows: sum the FP64 carry slots of each heavy row in slot order
+// Heavy rows, first level: each block sums one segment of <= kSegSlots
+// consecutive carry slots (strided over 256/RP partial lanes, then a fixed
+// tree) into an FP64 partial.
+static __global__ __launch_bounds__(256) void k_carry_partial(const int32_t *__restrict__ seg,
+                                                       const double *__restrict__ carry,
+                                                       int RP, double *__restrict__ partial,
+                                                       const double *skip) {
+  __shared__ double part[256];
+  if (skip && *skip != 0.0) return;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lanes = 256 / RP;
+  const int r = tid % RP, q = tid / RP;
+  const int s0 = seg[g], s1 = seg[g + 1];
+  double s = 0.0;
+  for (int sl = s0 + q; sl < s1; sl += lanes) s += carry[(int64_t)sl * RP + r];
+  part[tid] = s;
+  __syncthreads();
+  for (int w = lanes / 2; w > 0; w >>= 1) {
+    if (q < w) part[tid] += part[tid + w * RP];
+    __syncthreads();
+  }
+  if (q == 0) partial[(int64_t)g * RP + r] = part[tid];
+}
+
+// Heavy rows, second level: sum the FP64 partials of each heavy row in order
 // (strided over 256/RP partial lanes, then a fixed tree) and store.
 template <class AT>
 __global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__ hrow,
