@@ -71,6 +71,12 @@ static tt_status check_common(const tt_index *ix, int R, int64_t ldA, tt_dtype f
   TT_CHECK(fdt == TT_F64 || fdt == TT_F32 || fdt == TT_BF16, "bad factor dtype %d", (int)fdt);
   TT_CHECK(R >= 1 && R <= TT_MAX_RANK, "rank %d outside [1, %d]", R, TT_MAX_RANK);
   TT_CHECK(ldA >= R, "ldA %lld < R %d", (long long)ldA, R);
+  // kernels address factor and dense blocks with 32-bit byte offsets
+  if ((double)ix->max_I * (double)ldA * 8.0 >= 4294967296.0) {
+    set_error("factor matrices of %lld x %lld elements exceed the 4 GiB addressing limit",
+              (long long)ix->max_I, (long long)ldA);
+    return TT_ERR_UNSUPPORTED;
+  }
   if (ix->N != 3) {
     set_error("order %d: the GPU kernels implement order-3 tensors", ix->N);
     return TT_ERR_UNSUPPORTED;

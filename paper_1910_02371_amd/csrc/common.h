@@ -78,13 +78,27 @@ __device__ __forceinline__ void load_frag(const typename TR::T *__restrict__ A,
                                           int64_t ldA, int64_t row, int c0,
                                           int R, typename TR::AT (&o)[TR::V]);
 
+// Element pointer from a uniform base and a 32-bit element offset (every
+// factor and dense block is below 2^32 bytes, checked on the host), so the
+// address is a scalar base plus one 32-bit vector offset.
+template <class X>
+__device__ __forceinline__ const X *at32(const X *base, uint32_t elem) {
+  return reinterpret_cast<const X *>(reinterpret_cast<const char *>(base) +
+                                     (uint32_t)(elem * (uint32_t)sizeof(X)));
+}
+template <class X>
+__device__ __forceinline__ X *at32(X *base, uint32_t elem) {
+  return reinterpret_cast<X *>(reinterpret_cast<char *>(base) +
+                               (uint32_t)(elem * (uint32_t)sizeof(X)));
+}
+
 template <>
 __device__ __forceinline__ void load_frag<TrF32, true>(const float *__restrict__ A,
                                                       int64_t ldA, int64_t row,
                                                       int c0, int R,
                                                       float (&o)[4]) {
   if (c0 < R) {
-    float4 v = *reinterpret_cast<const float4 *>(A + row * ldA + c0);
+    float4 v = *reinterpret_cast<const float4 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   } else {
     o[0] = o[1] = o[2] = o[3] = 0.f;
@@ -95,8 +109,9 @@ __device__ __forceinline__ void load_frag<TrF32, false>(const float *__restrict_
                                                        int64_t ldA, int64_t row,
                                                        int c0, int R,
                                                        float (&o)[4]) {
+  const float *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) o[j] = (c0 + j < R) ? A[row * ldA + c0 + j] : 0.f;
+  for (int j = 0; j < 4; ++j) o[j] = (c0 + j < R) ? p[j] : 0.f;
 }
 template <>
 __device__ __forceinline__ void load_frag<TrF64, true>(const double *__restrict__ A,
@@ -104,7 +119,7 @@ __device__ __forceinline__ void load_frag<TrF64, true>(const double *__restrict_
                                                       int c0, int R,
                                                       double (&o)[2]) {
   if (c0 < R) {
-    double2 v = *reinterpret_cast<const double2 *>(A + row * ldA + c0);
+    double2 v = *reinterpret_cast<const double2 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
     o[0] = v.x; o[1] = v.y;
   } else {
     o[0] = o[1] = 0.0;
@@ -115,8 +130,9 @@ __device__ __forceinline__ void load_frag<TrF64, false>(const double *__restrict
                                                        int64_t ldA, int64_t row,
                                                        int c0, int R,
                                                        double (&o)[2]) {
+  const double *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) o[j] = (c0 + j < R) ? A[row * ldA + c0 + j] : 0.0;
+  for (int j = 0; j < 2; ++j) o[j] = (c0 + j < R) ? p[j] : 0.0;
 }
 template <>
 __device__ __forceinline__ void load_frag<TrBF16, true>(const uint16_t *__restrict__ A,
@@ -124,7 +140,7 @@ __device__ __forceinline__ void load_frag<TrBF16, true>(const uint16_t *__restri
                                                        int c0, int R,
                                                        float (&o)[8]) {
   if (c0 < R) {
-    uint4 v = *reinterpret_cast<const uint4 *>(A + row * ldA + c0);
+    uint4 v = *reinterpret_cast<const uint4 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
     o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
     o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
     o[4] = __uint_as_float(v.z << 16); o[5] = __uint_as_float(v.z & 0xffff0000u);
@@ -139,9 +155,9 @@ __device__ __forceinline__ void load_frag<TrBF16, false>(const uint16_t *__restr
                                                         int64_t ldA, int64_t row,
                                                         int c0, int R,
                                                         float (&o)[8]) {
+  const uint16_t *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
 #pragma unroll
-  for (int j = 0; j < 8; ++j)
-    o[j] = (c0 + j < R) ? bf16_to_f32(A[row * ldA + c0 + j]) : 0.f;
+  for (int j = 0; j < 8; ++j) o[j] = (c0 + j < R) ? bf16_to_f32(p[j]) : 0.f;
 }
 
 // Dense (accumulation-type) row fragment with row stride R: V elements
@@ -149,7 +165,7 @@ __device__ __forceinline__ void load_frag<TrBF16, false>(const uint16_t *__restr
 template <class AT, int V, bool VEC>
 __device__ __forceinline__ void load_dense(const AT *__restrict__ X, int64_t row, int c0,
                                            int R, AT (&o)[V]) {
-  const AT *p = X + row * (int64_t)R + c0;
+  const AT *p = at32(X, (uint32_t)row * (uint32_t)R + c0);
   if constexpr (VEC) {
     if (c0 < R) {
       if constexpr (sizeof(AT) == 4) {

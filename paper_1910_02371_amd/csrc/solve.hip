@@ -8,8 +8,9 @@
 // With H the task's rows h_e stacked, G = H^T diag(w) H is a K x R by K x R
 // contraction over the nonzeros, mapped onto MFMA with the nonzero index as
 // the reduction dimension: A-operand = h (R on the M index), B-operand = w h.
-//   FP32/BF16 storage: v_mfma_f32_16x16x4f32 (R <= 16) or
-//                      v_mfma_f32_32x32x2f32 (R <= 32, and 3 tiles for R <= 64).
+//   FP32/BF16 storage: v_mfma_f32_16x16x4f32 tiles, four nonzeros per step,
+//                      each lane reading RP / 16 consecutive columns of a row
+//                      (RP (RP / 16 + 1) / 32 tiles cover the upper triangle).
 //   BF16 factors are widened exactly to FP32 (a product of two bf16 values
 //   is exact in FP32), so the BF16 form accumulates like the FP32 form.
 //   FP64 storage: v_mfma_f64_16x16x4f64 tiles (lower triangle only).
@@ -26,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -76,86 +78,112 @@ __device__ __forceinline__ VT weight_at(const GramDev &d, int64_t pos) {
   return (VT)d.w_scale * reinterpret_cast<const VT *>(d.w)[q];
 }
 
-// FP32 / BF16 storage, FP32 accumulation on matrix cores.
-// A wave walks a range of nonzeros 64 at a time: lane l loads the indices and
-// weight of nonzero base + l (coalesced; the next block is prefetched), then
-// MFMA steps take their operands from those lanes by ds_bpermute.  GS steps
-// are issued together (all gathers first, then all MFMAs) so that the
-// factor-row gathers of GS steps are in flight at once.  Padding columns
-// (i >= R) use a clamped address and a zero mask, so loads are unconditional.
+// FP32 / BF16 storage, FP32 accumulation on v_mfma_f32_16x16x4f32.
+// Vector-fragment layout: lane l = 16 k + i takes nonzero k of a step (four
+// nonzeros per step) and columns VW*i .. VW*i + VW - 1 of its two factor rows
+// (VW = RP / 16), read as one vector load.  Register v of lane (i, k) then
+// holds column VW*i + v, so the register-class pair (p, q) is one 16x16x4
+// MFMA whose tile entry (r, c) is G[VW*r + p][VW*c + q].  The classes
+// p <= q (VW (VW + 1) / 2 tiles) cover every unordered column pair: once when
+// p < q, twice when p == q (only r <= c is stored).
 template <int RP>
 struct GramAcc {
-  static constexpr int NV = RP == 16 ? 4 : (RP == 32 ? 16 : 48);
-  f32x4 c16;
-  f32x16 c00, c01, c11;
+  static constexpr int VW = RP / 16;
+  static constexpr int NT = VW * (VW + 1) / 2;
+  static constexpr int NV = 4 * NT;
+  f32x4 c[NT];
   __device__ void zero() {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) c16[v] = 0.f;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) { c00[v] = 0.f; c01[v] = 0.f; c11[v] = 0.f; }
+    for (int q = 0; q < NT; ++q) c[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
   }
-  __device__ float get(int v) const {
-    if constexpr (RP == 16) return c16[v];
-    else if constexpr (RP == 32) return c00[v];
-    else return v < 16 ? c00[v] : (v < 32 ? c01[v - 16] : c11[v - 32]);
-  }
-  __device__ void set(int v, float x) {
-    if constexpr (RP == 16) c16[v] = x;
-    else if constexpr (RP == 32) c00[v] = x;
-    else if (v < 16) c00[v] = x;
-    else if (v < 32) c01[v - 16] = x;
-    else c11[v - 32] = x;
-  }
+  __device__ float get(int v) const { return c[v / 4][v % 4]; }
+  __device__ void set(int v, float x) { c[v / 4][v % 4] = x; }
 };
 
 #ifndef TT_GRAM_GS
-#define TT_GRAM_GS 8          // MFMA steps whose gathers are issued together
-#endif
-#ifndef TT_GRAM_PIPE
-#define TT_GRAM_PIPE 0        // 1: double-buffer groups across iterations
+#define TT_GRAM_GS 4          // MFMA steps whose gathers are issued together
 #endif
 #ifndef TT_GRAM_HEAVY_WAVES
 #define TT_GRAM_HEAVY_WAVES 8 // waves of the workgroup that takes a heavy task
 #endif
 
+// VW consecutive factor entries starting at element `off`, widened to FP32.
+// VEC: one aligned vector load (the caller guarantees alignment and that
+// the whole vector lies inside the row); otherwise element loads.
+template <class TR, int VW, bool VEC>
+__device__ __forceinline__ void load_cols(const typename TR::T *A, uint32_t off, int cb,
+                                          int R, float (&o)[VW]) {
+  if constexpr (VEC) {
+    const uint32_t e = off + (uint32_t)(cb < R ? cb : 0);
+    if constexpr (std::is_same<TR, TrF32>::value) {
+      if constexpr (VW == 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(at32(A, e));
+        o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
+      } else if constexpr (VW == 2) {
+        const float2 x = *reinterpret_cast<const float2 *>(at32(A, e));
+        o[0] = x.x; o[1] = x.y;
+      } else {
+        o[0] = *at32(A, e);
+      }
+    } else {
+      if constexpr (VW == 4) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(at32(A, e));
+        o[0] = __uint_as_float(x.x << 16); o[1] = __uint_as_float(x.x & 0xffff0000u);
+        o[2] = __uint_as_float(x.y << 16); o[3] = __uint_as_float(x.y & 0xffff0000u);
+      } else if constexpr (VW == 2) {
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(at32(A, e));
+        o[0] = __uint_as_float(x << 16); o[1] = __uint_as_float(x & 0xffff0000u);
+      } else {
+        o[0] = bf16_to_f32(*at32(A, e));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int c = cb + v;
+      const uint32_t e = off + (uint32_t)(c < R ? c : 0);
+      if constexpr (std::is_same<TR, TrF32>::value) o[v] = *at32(A, e);
+      else o[v] = bf16_to_f32(*at32(A, e));
+    }
+  }
+}
+
 template <class TR, int RP, int GS>
 struct GramGroup {
-  float a0[GS], a1[GS], b0[GS], b1[GS], w[GS];
+  float a0[GS][RP / 16], a1[GS][RP / 16], w[GS];
 };
 
 // Nonzeros [nb, ne) of one row into acc.  The range is walked in blocks of
 // 64 nonzeros (lane l loads the indices and weight of nonzero base + l,
 // coalesced, one block ahead) and, inside a block, in groups of GS MFMA
-// steps.  Groups are double-buffered: the shuffles and factor-row gathers
-// of group g + 1 are issued before the MFMAs of group g, so a wave overlaps
-// its own gather latency with matrix-core work.  Padding columns (i >= R)
-// use a clamped address and a zero mask, so loads are unconditional; steps
-// past the end read lanes whose weight is 0.
-template <class TR, int RP>
+// steps: the shuffles and factor-row gathers of a group are issued together,
+// then its MFMAs.  Padding columns (>= R) use a clamped address and a zero
+// mask, so loads are unconditional; steps past the end read lanes whose
+// weight is 0.
+template <class TR, int RP, bool VEC>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
   using T = typename TR::T;
-  constexpr int NPS = (RP == 16) ? 4 : 2;     // nonzeros per MFMA step
-  constexpr int MW = (RP == 16) ? 16 : 32;    // M = N of the instruction
+  constexpr int VW = RP / 16;
   constexpr int GS = TT_GRAM_GS;              // steps per group
-  constexpr int SPB = 64 / NPS;               // steps per 64-nonzero block
+  constexpr int SPB = 16;                     // steps per 64-nonzero block
   constexpr int GPB = SPB / GS;               // groups per block
+  static_assert(SPB % GS == 0, "group size must divide the block");
   const int lane = threadIdx.x & 63;
   const T *A0 = reinterpret_cast<const T *>(d.A0);
   const T *A1 = reinterpret_cast<const T *>(d.A1);
   const int R = d.R;
   const uint32_t ldA = (uint32_t)d.ldA;
-  const int i = lane % MW;
-  const int kk = lane / MW;
-  const int c0 = i < R ? i : 0;
-  const float m0 = i < R ? 1.f : 0.f;
-  const int c1 = (i + 32 < R) ? i + 32 : 0;
-  const float m1 = (i + 32 < R) ? 1.f : 0.f;
+  const int kk = lane >> 4;
+  const int cb = VW * (lane & 15);
+  float m[VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) m[v] = (cb + v < R) ? 1.f : 0.f;
   const int64_t n = ne - nb;
   if (n <= 0) return;
   const int64_t nblk = (n + 63) / 64;
   const int last_cnt = (int)(n - (nblk - 1) * 64);
-  const int64_t gtot = (nblk - 1) * GPB + ((last_cnt + NPS - 1) / NPS + GS - 1) / GS;
+  const int64_t gtot = (nblk - 1) * GPB + ((last_cnt + 3) / 4 + GS - 1) / GS;
 
   auto load_block = [&](int64_t blk, int &j0, int &j1, float &w) {
     const int64_t e = nb + blk * 64 + lane;
@@ -167,15 +195,16 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
       j0 = 0; j1 = 0; w = 0.f;
     }
   };
-  // group gi reads block gi / GPB: `cur` registers hold the block of the
-  // group being prepared, `nxt` the following block
+  // `cur` registers hold the block of the group being prepared, `nxt` the
+  // following block
   int cj0, cj1, nj0 = 0, nj1 = 0;
   float cw, nw = 0.f;
   load_block(0, cj0, cj1, cw);
   if (nblk > 1) load_block(1, nj0, nj1, nw);
-  int64_t cblk = 0;  // block held in cur
+  int64_t cblk = 0;
 
-  auto prepare = [&](int64_t gi, GramGroup<TR, RP, GS> &g) {
+  GramGroup<TR, RP, GS> g;
+  for (int64_t gi = 0; gi < gtot; ++gi) {
     const int64_t blk = gi / GPB;
     if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
       cj0 = nj0; cj1 = nj1; cw = nw;
@@ -186,91 +215,63 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
     int j0[GS], j1[GS];
 #pragma unroll
     for (int u = 0; u < GS; ++u) {
-      const int src = (st0 + u) * NPS + kk;
+      const int src = (st0 + u) * 4 + kk;
       j0[u] = __shfl(cj0, src);
       j1[u] = __shfl(cj1, src);
       g.w[u] = __shfl(cw, src);
     }
 #pragma unroll
     for (int u = 0; u < GS; ++u) {
-      const uint32_t r0 = (uint32_t)j0[u] * ldA, r1 = (uint32_t)j1[u] * ldA;
-      g.a0[u] = elem_f32off<TR>(A0, r0 + c0);
-      g.a1[u] = elem_f32off<TR>(A1, r1 + c0);
-      if constexpr (RP == 64) {
-        g.b0[u] = elem_f32off<TR>(A0, r0 + c1);
-        g.b1[u] = elem_f32off<TR>(A1, r1 + c1);
-      }
+      load_cols<TR, VW, VEC>(A0, (uint32_t)j0[u] * ldA, cb, R, g.a0[u]);
+      load_cols<TR, VW, VEC>(A1, (uint32_t)j1[u] * ldA, cb, R, g.a1[u]);
     }
-  };
-  auto consume = [&](const GramGroup<TR, RP, GS> &g) {
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < GS; ++u) {
-      const float h0 = g.a0[u] * g.a1[u] * m0;
-      if constexpr (RP == 16) {
-        acc.c16 = __builtin_amdgcn_mfma_f32_16x16x4f32(h0, g.w[u] * h0, acc.c16, 0, 0, 0);
-      } else {
-        acc.c00 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, g.w[u] * h0, acc.c00, 0, 0, 0);
-        if constexpr (RP == 64) {
-          const float h1 = g.b0[u] * g.b1[u] * m1;
-          acc.c01 = __builtin_amdgcn_mfma_f32_32x32x2f32(h0, g.w[u] * h1, acc.c01, 0, 0, 0);
-          acc.c11 = __builtin_amdgcn_mfma_f32_32x32x2f32(h1, g.w[u] * h1, acc.c11, 0, 0, 0);
-        }
+      float h[VW], hw[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        h[v] = g.a0[u][v] * g.a1[u][v] * m[v];
+        hw[v] = g.w[u] * h[v];
       }
+      int q = 0;
+#pragma unroll
+      for (int p = 0; p < VW; ++p)
+#pragma unroll
+        for (int pp = p; pp < VW; ++pp) {
+          acc.c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(h[p], hw[pp], acc.c[q], 0, 0, 0);
+          ++q;
+        }
     }
-  };
-
-#if TT_GRAM_PIPE
-  GramGroup<TR, RP, GS> ga, gb;
-  prepare(0, ga);
-  int64_t gi = 0;
-  for (; gi + 1 < gtot; gi += 2) {
-    prepare(gi + 1, gb);
-    __builtin_amdgcn_sched_barrier(0);
-    consume(ga);
-    __builtin_amdgcn_sched_barrier(0);
-    if (gi + 2 < gtot) prepare(gi + 2, ga);
-    __builtin_amdgcn_sched_barrier(0);
-    consume(gb);
     __builtin_amdgcn_sched_barrier(0);
   }
-  if (gi < gtot) consume(ga);
-#else
-  GramGroup<TR, RP, GS> ga;
-  for (int64_t gi = 0; gi < gtot; ++gi) {
-    prepare(gi, ga);
-    __builtin_amdgcn_sched_barrier(0);
-    consume(ga);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-#endif
 }
 
 // Write the upper triangle of G (row-major RP x RP) from the accumulators.
+// v_mfma_f32_16x16x4f32 result: lane l, register v holds D[4 (l / 16) + v][l % 16].
 template <int RP>
 __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
+  constexpr int VW = RP / 16;
   const int lane = threadIdx.x & 63;
-  if constexpr (RP == 16) {
-    // D[row][col]: col = lane % 16, row = 4 * (lane / 16) + v
+  const int c = lane & 15;
+  int q = 0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) G[(4 * (lane / 16) + v) * RP + lane % 16] = acc.c16[v];
-  } else {
-    // D[row][col]: col = lane % 32, row = 8 * (v / 4) + 4 * (lane / 32) + v % 4
+  for (int p = 0; p < VW; ++p)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = 8 * (v / 4) + 4 * (lane / 32) + (v % 4);
-      const int col = lane % 32;
-      G[row * RP + col] = acc.c00[v];
-      if constexpr (RP == 64) {
-        G[(32 + row) * RP + 32 + col] = acc.c11[v];
-        G[row * RP + 32 + col] = acc.c01[v];  // upper block (0,1)
+    for (int pp = p; pp < VW; ++pp) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * (lane >> 4) + v;
+        const int a = VW * r + p, b = VW * c + pp;
+        if (p < pp || r <= c) G[min(a, b) * RP + max(a, b)] = acc.c[q][v];
       }
+      ++q;
     }
-  }
 }
 
 // Light tasks: one wave per task, four tasks per workgroup; tasks with more
 // than kGramLight nonzeros are left to k_gram_f32_heavy.
-template <class TR, int RP>
+template <class TR, int RP, bool VEC>
 __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= d.task_end) return;
@@ -278,13 +279,13 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   if (d.split_heavy && ne - nb > kGramLight) return;
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP>(d, nb, ne, acc);
+  gram_accum<TR, RP, VEC>(d, nb, ne, acc);
   gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
 }
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
-template <class TR, int RP>
+template <class TR, int RP, bool VEC>
 __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
@@ -293,11 +294,11 @@ __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t = heavy[blockIdx.x];
   const int64_t nb = d.task[t], ne = d.task[t + 1];
-  const int64_t per = (((ne - nb) + NW - 1) / NW + 1) & ~(int64_t)1;
+  const int64_t per = (((ne - nb) + NW - 1) / NW + 3) & ~(int64_t)3;
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP>(d, b0, b1, acc);
+  gram_accum<TR, RP, VEC>(d, b0, b1, acc);
   for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
@@ -313,15 +314,16 @@ __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
   }
 }
 
-// Rows with more than kReduceMin tasks: sum their tasks' Grams entrywise in
-// FP64, in task order, into the row's first task slot.
+// Rows with more than kReduceMin tasks: sum the upper triangles of their
+// tasks' Grams entrywise in FP64, in task order, into the row's first task
+// slot.
 template <class GT, int RP>
 __global__ __launch_bounds__(256) void k_gram_reduce(const int32_t *__restrict__ rows,
                                                      const int32_t *__restrict__ row_task,
                                                      int64_t task_base, GT *G) {
   const int64_t row = rows[blockIdx.x];
   const int e = blockIdx.y * 256 + threadIdx.x;
-  if (e >= RP * RP) return;
+  if (e >= RP * RP || e / RP > e % RP) return;  // upper triangle only
   const int32_t t0 = row_task[row], t1 = row_task[row + 1];
   const GT *g = G + ((int64_t)t0 - task_base) * (RP * RP) + e;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -426,11 +428,28 @@ struct SolveDev {
   const double *skip;
 };
 
+// Pivot of step k: 1 / sqrt(d) for d > 0.  The hardware reciprocal square
+// root estimate is refined by two Newton steps y <- y + y (1 - d y^2) / 2
+// (each squares the relative error, so the result is within a few ulp).
+// Pivots below 2^-900 take the IEEE square root and division instead,
+// which stay exact where d y^2 would underflow or overflow.
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+  if (d < 0x1p-900) return 1.0 / sqrt(d);
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Cholesky of the lane-distributed matrix s (lane i = row i), in place:
-// afterwards s[j] on lane i holds L(i, j) for j <= i.  Column k of L is
-// published through LDS (`col`, RP doubles) and read back as broadcasts, so
-// the trailing update of step k is RP-k-1 independent FMAs per lane.
-// Returns info (LAPACK potrf convention).  One wave per workgroup.
+// afterwards s[j] on lane i holds L(i, j) for j <= i and 0 for j > i.
+// Column k of L is published through LDS (`col`, RP doubles) and read back
+// as broadcasts, so the trailing update of step k is RP-k-1 independent FMAs
+// per lane (lanes above the diagonal multiply by 0).  Returns info (LAPACK
+// potrf convention).  One wave per workgroup.
 template <int RP>
 __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col,
                                           double &rdiag) {
@@ -438,10 +457,9 @@ __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col
   for (int k = 0; k < RP; ++k) {
     const double dkk = readlane_d(s[k], k);
     if (!(dkk > 0.0)) return k + 1;
-    const double rd = sqrt(dkk);
-    const double inv = 1.0 / rd;
+    const double inv = rsqrt_pivot(dkk);
     if (lane == k) rdiag = inv;
-    const double lik = lane > k ? s[k] * inv : (lane == k ? rd : 0.0);
+    const double lik = lane >= k ? s[k] * inv : 0.0;
     s[k] = lik;
     if (k + 1 < RP) {
       if (lane < RP) col[lane] = lik;
@@ -454,10 +472,13 @@ __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col
   return 0;
 }
 
-// Solve L L^T x = b with L held as in chol_lanes; b on lane i is b_i.
-// Lp: packed lower triangle in LDS (RP (RP + 1) / 2 doubles), row k at
-// k (k + 1) / 2, used by the backward solve where lane i needs L(k, i).
-// rdiag on lane i holds 1 / L(i, i).
+// Solve L L^T x = b with L held as chol_lanes leaves it (zero above the
+// diagonal); b on lane i is b_i.  Lp: packed lower triangle in LDS
+// (RP (RP + 1) / 2 doubles), row k at k (k + 1) / 2, used by the backward
+// solve where lane i needs L(k, i).  rdiag on lane i holds 1 / L(i, i).
+// Both sweeps update every lane with an FMA whose multiplier is zero where
+// the lane is not below the pivot, then select the pivot lane's value, so
+// the loops carry no lane-dependent branches.
 template <int RP>
 __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double b,
                                                    double rdiag, int lane, double *Lp) {
@@ -465,7 +486,8 @@ __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
     const double yk = readlane_d(b, k) * readlane_d(rdiag, k);
-    b = lane == k ? yk : (lane > k ? b - s[k] * yk : b);
+    const double t = fma(-s[k], yk, b);
+    b = lane == k ? yk : t;
   }
   if (lane < RP) {
     double *row = Lp + (lane * (lane + 1)) / 2;
@@ -478,8 +500,10 @@ __device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double
 #pragma unroll
   for (int k = RP - 1; k >= 0; --k) {
     const double xk = readlane_d(b, k) * readlane_d(rdiag, k);
-    const double lki = (lane < k) ? Lp[(k * (k + 1)) / 2 + lane] : 0.0;
-    b = lane == k ? xk : (lane < k ? b - lki * xk : b);
+    const double lv = Lp[(k * (k + 1)) / 2 + (lane < k ? lane : 0)];
+    const double lki = lane < k ? lv : 0.0;
+    const double t = fma(-lki, xk, b);
+    b = lane == k ? xk : t;
   }
   return b;
 }
@@ -550,11 +574,10 @@ __global__ __launch_bounds__(64) void k_apply_rows(const double *__restrict__ Ls
   for (int j = 0; j < RP; ++j)
     s[j] = (lane < RP && lane >= j) ? L[j * RP - (j * (j - 1)) / 2 + lane - j] : 0.0;
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
-  double rdiag = 1.0;
+  double dg = 1.0;
 #pragma unroll
-  for (int k = 0; k < RP; ++k)
-    if (k == lane) rdiag = 1.0 / s[k];
-  const double x = chol_solve_lanes<RP>(s, b, rdiag, lane, Lp);
+  for (int k = 0; k < RP; ++k) dg = k == lane ? s[k] : dg;
+  const double x = chol_solve_lanes<RP>(s, b, 1.0 / dg, lane, Lp);
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
 }
 
@@ -573,7 +596,7 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
   return hipGetLastError();
 }
 
-template <class TR, int RP>
+template <class TR, int RP, bool VEC>
 static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
                                double light_bytes, double light_flops, double heavy_bytes,
                                double heavy_flops, hipStream_t s) {
@@ -581,13 +604,27 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   d.split_heavy = 1;
   {
     ProfScope ps("gram_light", s, light_bytes, light_flops);
-    k_gram_f32<TR, RP><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+    k_gram_f32<TR, RP, VEC><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
   }
   if (nheavy > 0) {
     ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
-    k_gram_f32_heavy<TR, RP><<<dim3((unsigned)nheavy), dim3(64 * TT_GRAM_HEAVY_WAVES), 0, s>>>(
-        d, heavy, nheavy);
+    k_gram_f32_heavy<TR, RP, VEC>
+        <<<dim3((unsigned)nheavy), dim3(64 * TT_GRAM_HEAVY_WAVES), 0, s>>>(d, heavy, nheavy);
   }
+}
+
+// Vector loads of VW = RP / 16 entries need R, ldA and both factor bases
+// aligned to VW elements.
+template <class TR, int RP>
+static void launch_gram_f32_vec(const GramDev &d, const int32_t *heavy, int64_t nheavy,
+                                double lb, double lf, double hb, double hf, hipStream_t s) {
+  constexpr int VW = RP / 16;
+  constexpr size_t al = VW * sizeof(typename TR::T);
+  const bool vec = d.R % VW == 0 && d.ldA % VW == 0 &&
+                   reinterpret_cast<uintptr_t>(d.A0) % al == 0 &&
+                   reinterpret_cast<uintptr_t>(d.A1) % al == 0;
+  if (vec) launch_gram_f32_rp<TR, RP, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+  else launch_gram_f32_rp<TR, RP, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
 }
 
 // Gram of one batch of tasks [task_base, task_end): light tasks one wave
@@ -623,15 +660,15 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
     const double hf = wk.heavy_nnz * R * (R + 1);
     if (fdt == TT_F32) {
       switch (RP) {
-        case 16: launch_gram_f32_rp<TrF32, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        case 32: launch_gram_f32_rp<TrF32, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        default: launch_gram_f32_rp<TrF32, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 16: launch_gram_f32_vec<TrF32, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 32: launch_gram_f32_vec<TrF32, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        default: launch_gram_f32_vec<TrF32, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
       }
     } else {
       switch (RP) {
-        case 16: launch_gram_f32_rp<TrBF16, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        case 32: launch_gram_f32_rp<TrBF16, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        default: launch_gram_f32_rp<TrBF16, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 16: launch_gram_f32_vec<TrBF16, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 32: launch_gram_f32_vec<TrBF16, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        default: launch_gram_f32_vec<TrBF16, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
       }
     }
   }

@@ -83,7 +83,7 @@ __device__ __forceinline__ void store_row(void *out, int64_t row, int c0, int R,
                                           const typename TR::AT (&v)[TR::V]) {
   using AT = typename TR::AT;
   constexpr int V = TR::V;
-  AT *o = reinterpret_cast<AT *>(out) + row * (int64_t)R + c0;
+  AT *o = at32(reinterpret_cast<AT *>(out), (uint32_t)row * (uint32_t)R + c0);
   if (c0 >= R) return;
   if constexpr (VEC) {
     if constexpr (sizeof(AT) == 4) {

@@ -243,7 +243,7 @@ def test_mttkrp_weights_orders_accumulate(gpu_lib, form):
 
 # ---------------------------------------------------------- solve factor ----
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("R", [1, 10, 16, 32, 64])
+@pytest.mark.parametrize("R", [1, 10, 16, 21, 32, 50, 64])
 @pytest.mark.parametrize("kind", ["uniform", "heavy"])
 def test_solve_factor_parity(gpu_lib, form, R, kind):
     tt = gpu_lib
@@ -266,6 +266,28 @@ def test_solve_factor_parity(gpu_lib, form, R, kind):
         Xr, _ = O.solve_rows(G, M, lam)
         if form == "f64":
             np.testing.assert_allclose(X, Xr, rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("R", [21, 50, 64])
+def test_solve_factor_weighted_lowp(gpu_lib, form, R):
+    """Per-nonzero weights (the Gauss-Newton preconditioner's Gram) on rows
+    with several Gram tasks, with and without vector factor loads."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, "heavy", form)
+    A64 = factors(wl.dims, R, 700 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(5 + R)
+    w = stored_values(rng.random(wl.nnz) + 0.1, form)
+    for n in range(3):
+        M = stored_values(rng.standard_normal((wl.dims[n], R)), form)
+        X, info = tt.solve_factor(ix, dev_vals(w, form), A, n, dev_vals(M, form), 0.05,
+                                  w_order=-1)
+        assert (info.cpu().numpy() == 0).all()
+        G = O.gram(wl.idx, w, As, n, wl.dims[n])
+        be = backward_error(G, 0.05, host(X), M)
+        assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"backward error {be:.3e} (mode {n})"
 
 
 def test_solve_factor_weights_and_info(gpu_lib):
