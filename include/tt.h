@@ -236,7 +236,9 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * its Section 4 implementation): w = phi''(t, m); b = -grad f; solve
  * (J^T diag(w) J + 2 lambda I) dx = b by PCG from dx = 0 with the block
  * diagonal preconditioner applied through Solve Factor (weights w, shift
- * 2 lambda, factors computed once per call); stop when the unpreconditioned
+ * 2 lambda, factors computed once per call in FP64 and kept in FP64 for
+ * the FP64 form, in FP32 for the FP32 and BF16 forms, where they only
+ * precondition); stop when the unpreconditioned
  * residual norm relative to the initial one is <= tol or after kmax
  * iterations; then A <- A + dx (full step).  Dot products in FP64.  The
  * iteration count runs on the device: convergence sets a device flag that

@@ -583,17 +583,19 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &vparts));
   int64_t Ltot = 0;
   for (int d = 0; d < N; ++d) Ltot += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
-  TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * 8, &vL));
+  const size_t lsz = fdt == TT_F64 ? 8 : 4;  // preconditioner factors: dense dtype
+  TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * lsz, &vL));
   if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &vw));
   char *X = (char *)vx, *Rv = (char *)vr, *Z = (char *)vz, *P = (char *)vp, *Q = (char *)vq;
-  double *sc = (double *)vsc, *parts = (double *)vparts, *L = (double *)vL;
+  double *sc = (double *)vsc, *parts = (double *)vparts;
+  char *L = (char *)vL;
   const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
   auto blk = [&](char *base, int d) -> void * { return base + off[d] * dsz; };
-  double *Lb[TT_MAX_ORDER];
+  void *Lb[TT_MAX_ORDER];
   {
     int64_t lo = 0;
     for (int d = 0; d < N; ++d) {
-      Lb[d] = L + lo;
+      Lb[d] = L + lo * lsz;
       lo += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
     }
   }

@@ -156,13 +156,14 @@ struct SolveCall {
   const void *rhs;          // I x R dense dtype
   void *X;                  // I x R in fdt, leading dim ldA (may alias A)
   int32_t *info;            // optional
-  double *Lstore;           // when non-NULL: keep the Cholesky factors (I x RP(RP+1)/2)
+  void *Lstore;             // when non-NULL: keep the Cholesky factors (I x RP(RP+1)/2),
+                            // FP64 for the FP64 form, FP32 otherwise
   int factor_only;          // 1: factor and store, no solve
 };
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);
 // Apply stored factors: X = (L L^T)^{-1} rhs, X dense dtype (not fdt).
 hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt,
-                               const double *Lstore, const void *rhs, void *X,
+                               const void *Lstore, const void *rhs, void *X,
                                const double *skip, hipStream_t s);
 
 // vec.hip: dense helpers (dense dtype = double for TT_F64 else float).

@@ -423,7 +423,7 @@ struct SolveDev {
   void *X;                   // I x R in storage dtype, leading dim ldX
   int64_t ldX;
   int32_t *info;
-  double *Lstore;            // I x RP (RP + 1) / 2 packed factors (optional)
+  void *Lstore;              // I x RP (RP + 1) / 2 packed factors, Gram dtype (optional)
   int factor_only;
   const double *skip;
 };
@@ -431,86 +431,128 @@ struct SolveDev {
 // Pivot of step k: 1 / sqrt(d) for d > 0.  The hardware reciprocal square
 // root estimate is refined by two Newton steps y <- y + y (1 - d y^2) / 2
 // (each squares the relative error, so the result is within a few ulp).
-// Pivots below 2^-900 take the IEEE square root and division instead,
-// which stay exact where d y^2 would underflow or overflow.
+// Pivots below 2^-900 are scaled by 2^960 first and the result by 2^480
+// (both exact), so d y^2 neither underflows nor overflows.
 __device__ __forceinline__ double rsqrt_pivot(double d) {
-  if (d < 0x1p-900) return 1.0 / sqrt(d);
-  double y = __builtin_amdgcn_rsq(d);
+  const bool tiny = d < 0x1p-900;
+  const double ds = tiny ? d * 0x1p960 : d;
+  double y = __builtin_amdgcn_rsq(ds);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    const double e = fma(-d, y * y, 1.0);
+    const double e = fma(-ds, y * y, 1.0);
     y = fma(0.5 * y, e, y);
   }
-  return y;
+  return tiny ? y * 0x1p480 : y;
 }
 
 // Cholesky of the lane-distributed matrix s (lane i = row i), in place:
 // afterwards s[j] on lane i holds L(i, j) for j <= i and 0 for j > i.
 // Column k of L is published through LDS (`col`, RP doubles) and read back
 // as broadcasts, so the trailing update of step k is RP-k-1 independent FMAs
-// per lane (lanes above the diagonal multiply by 0).  Returns info (LAPACK
-// potrf convention).  One wave per workgroup.
+// per lane (lanes above the diagonal multiply by 0).  Look-ahead: step k
+// updates column k+1 first and computes pivot k+1 from it, so the pivot's
+// dependent chain overlaps the rest of step k's update; the test of that
+// pivot closes the step.  The workgroup is one wave, whose LDS accesses
+// complete in program order, so the broadcast needs no barrier.  Returns
+// info (LAPACK potrf convention: the order of the first leading minor that
+// is not positive definite).
 template <int RP>
 __device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col,
                                           double &rdiag) {
+  double dkk = readlane_d(s[0], 0);
+  if (!(dkk > 0.0)) return 1;
+  double inv = rsqrt_pivot(dkk);
 #pragma unroll
   for (int k = 0; k < RP; ++k) {
-    const double dkk = readlane_d(s[k], k);
-    if (!(dkk > 0.0)) return k + 1;
-    const double inv = rsqrt_pivot(dkk);
     if (lane == k) rdiag = inv;
     const double lik = lane >= k ? s[k] * inv : 0.0;
     s[k] = lik;
     if (k + 1 < RP) {
       if (lane < RP) col[lane] = lik;
-      __syncthreads();
+      s[k + 1] -= lik * col[k + 1];
+      dkk = readlane_d(s[k + 1], k + 1);
+      inv = rsqrt_pivot(dkk);
 #pragma unroll
-      for (int j = k + 1; j < RP; ++j) s[j] -= lik * col[j];
-      __syncthreads();
+      for (int j = k + 2; j < RP; ++j) s[j] -= lik * col[j];
+      if (!(dkk > 0.0)) return k + 2;
     }
   }
   return 0;
 }
 
-// Solve L L^T x = b with L held as chol_lanes leaves it (zero above the
-// diagonal); b on lane i is b_i.  Lp: packed lower triangle in LDS
-// (RP (RP + 1) / 2 doubles), row k at k (k + 1) / 2, used by the backward
-// solve where lane i needs L(k, i).  rdiag on lane i holds 1 / L(i, i).
-// Both sweeps update every lane with an FMA whose multiplier is zero where
-// the lane is not below the pivot, then select the pivot lane's value, so
-// the loops carry no lane-dependent branches.
+// A copy of the lane index that the compiler cannot identify with the
+// original (an empty asm statement owns it), so lane comparisons in different
+// phases of a kernel are not merged and kept alive as masks across them.
+__device__ __forceinline__ int opaque_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+
+// Row-packed lower triangle: row i of L at i (i + 1) / 2 .. i (i + 1) / 2 + i.
+// The LDS copy holds PS = RP (RP + 1) / 2 entries, a zero at PS and one
+// scratch slot per lane after it, so that every lane can issue the same
+// loads and stores (no lane-dependent branches around memory operations).
 template <int RP>
-__device__ __forceinline__ double chol_solve_lanes(const double (&s)[RP], double b,
-                                                   double rdiag, int lane, double *Lp) {
-  // forward: L y = b (column-oriented, y kept in b)
+struct Packed {
+  static constexpr int PS = RP * (RP + 1) / 2;
+  static constexpr int ZERO = PS;
+  static constexpr int LDS = PS + 1 + 64;
+};
+
+// Lane i writes its row of L (s[j], j <= i) into the LDS copy and entries
+// j > i into its scratch slot; Lp[ZERO] is set to 0.
+template <int RP>
+__device__ __forceinline__ void put_rows(double *Lp, const double (&s)[RP], int lane_in) {
+  using P = Packed<RP>;
+  const int lane = opaque_lane(lane_in);
+  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+  const int junk = P::ZERO + 1 + lane;
 #pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    const int addr = (j <= lane && lane < RP) ? base + j : junk;
+    Lp[addr] = s[j];
+  }
+  if (lane == 0) Lp[P::ZERO] = 0.0;
+}
+
+// Triangular solves with L read from the LDS copy; b on lane i is b_i and
+// rdiag on lane i is 1 / L(i, i).  At step k every lane subtracts its
+// multiplier times the broadcast pivot value; the multiplier is read from
+// Lp[ZERO] (= 0) on the pivot lane and on lanes already solved, so those
+// lanes keep their value and the result is b * rdiag at the end.  The
+// loops are only partly unrolled: their bodies index nothing by k except
+// through LDS addresses.
+// Forward substitution L y = b (LT: the LDS copy's element type).
+template <int RP, class LT>
+__device__ __forceinline__ double fwd_lds(const LT *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+#pragma unroll 8
   for (int k = 0; k < RP; ++k) {
-    const double yk = readlane_d(b, k) * readlane_d(rdiag, k);
-    const double t = fma(-s[k], yk, b);
-    b = lane == k ? yk : t;
+    const double yk = readlane_d(b * rdiag, k);
+    const double lik = (double)Lp[(lane > k && lane < RP) ? base + k : P::ZERO];
+    b = fma(-lik, yk, b);
   }
-  if (lane < RP) {
-    double *row = Lp + (lane * (lane + 1)) / 2;
-#pragma unroll
-    for (int j = 0; j < RP; ++j)
-      if (j <= lane) row[j] = s[j];
-  }
-  __syncthreads();
-  // backward: L^T x = y
-#pragma unroll
+  return b * rdiag;
+}
+
+// Backward substitution L^T x = y (lane i takes L(k, i), i < k, from row k).
+template <int RP, class LT>
+__device__ __forceinline__ double bwd_lds(const LT *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+#pragma unroll 8
   for (int k = RP - 1; k >= 0; --k) {
-    const double xk = readlane_d(b, k) * readlane_d(rdiag, k);
-    const double lv = Lp[(k * (k + 1)) / 2 + (lane < k ? lane : 0)];
-    const double lki = lane < k ? lv : 0.0;
-    const double t = fma(-lki, xk, b);
-    b = lane == k ? xk : t;
+    const double xk = readlane_d(b * rdiag, k);
+    const double lki = (double)Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+    b = fma(-lki, xk, b);
   }
-  return b;
+  return b * rdiag;
 }
 
 template <class GT, class XT, class MT, int RP>
-__global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
-  __shared__ double Lp[RP * (RP + 1) / 2];
+__global__ __launch_bounds__(64, 2) void k_solve_rows(SolveDev d) {
+  using P = Packed<RP>;
+  __shared__ double Lp[P::LDS];
   __shared__ double col[RP];
   if (d.skip && *d.skip != 0.0) return;
   const int lane = threadIdx.x;
@@ -519,65 +561,88 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   const int32_t t0 = d.row_task[row];
   int32_t t1 = d.row_task[row + 1];
   if (t1 - t0 > kReduceMin) t1 = t0 + 1;  // pre-reduced by k_gram_reduce
+  // lane i reads column i of the task's RP x RP block: G[j][i] for j <= i
+  // is the stored upper triangle (= G[i][j]); entries j > i are not written
+  // by the Gram kernels and are replaced by 0 below
   double s[RP];
 #pragma unroll
   for (int j = 0; j < RP; ++j) s[j] = 0.0;
-  if (lane < RP) {
-    for (int32_t t = t0; t < t1; ++t) {
-      const GT *g = reinterpret_cast<const GT *>(d.G) +
-                    ((int64_t)t - d.task_base) * (RP * RP) + lane;
+  const int li = lane < RP ? lane : 0;
+  for (int32_t t = t0; t < t1; ++t) {
+    const GT *g = reinterpret_cast<const GT *>(d.G) +
+                  ((int64_t)t - d.task_base) * (RP * RP) + li;
 #pragma unroll
-      for (int j = 0; j < RP; ++j) s[j] += (double)g[j * RP];  // G[j][lane]
-    }
+    for (int j = 0; j < RP; ++j) s[j] += (double)g[j * RP];
   }
+  // S = G + lambda I on the R x R block, identity on the padding
+  {
+    const int ln = opaque_lane(lane);
+    const bool pad_row = ln >= R;
 #pragma unroll
-  for (int j = 0; j < RP; ++j) {
-    if (lane >= R || j >= R) s[j] = (j == lane) ? 1.0 : 0.0;
-    else if (j == lane) s[j] += d.lambda;
+    for (int j = 0; j < RP; ++j) {
+      const double v = s[j] + (j == ln ? d.lambda : 0.0);
+      const double kept = j > ln ? 0.0 : v;
+      s[j] = (pad_row || j >= R) ? (j == ln ? 1.0 : 0.0) : kept;
+    }
   }
   double rdiag = 1.0;
   const int info = chol_lanes<RP>(s, lane, col, rdiag);
   if (d.info && lane == 0) d.info[row] = info;
-  if (d.Lstore) {
-    // packed lower triangle stored by columns: L(i, j), i >= j, at
-    // col_off(j) + i - j with col_off(j) = j RP - j (j - 1) / 2 (coalesced
-    // over the lanes i of each column)
-    double *L = d.Lstore + row * (int64_t)(RP * (RP + 1) / 2);
-    if (lane < RP) {
+  if (info && d.Lstore) {
+    // failed rows keep the identity (no preconditioning for that block)
 #pragma unroll
-      for (int j = 0; j < RP; ++j)
-        if (lane >= j)
-          L[j * RP - (j * (j - 1)) / 2 + lane - j] = info ? ((j == lane) ? 1.0 : 0.0) : s[j];
-    }
+    for (int j = 0; j < RP; ++j) s[j] = (j == lane) ? 1.0 : 0.0;
+  }
+  put_rows<RP>(Lp, s, lane);
+  __syncthreads();
+  if (d.Lstore) {
+    GT *L = reinterpret_cast<GT *>(d.Lstore) + row * (int64_t)P::PS;
+    for (int q = lane; q < P::PS; q += 64) L[q] = (GT)Lp[q];
   }
   if (d.factor_only) return;
   double x = 0.0;
   if (info == 0) {
     const double b = lane < R ? (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane] : 0.0;
-    x = chol_solve_lanes<RP>(s, b, rdiag, lane, Lp);
+    x = bwd_lds<RP, double>(Lp, fwd_lds<RP, double>(Lp, b, rdiag, lane), rdiag, lane);
   }
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
 
-// Apply stored factors to a right-hand side: X = (L L^T)^{-1} rhs.
+// Apply stored factors to a right-hand side: X = (L L^T)^{-1} rhs.  The
+// factors (row-packed, RP (RP + 1) / 2 per row) are stored in the dense
+// dtype MT (FP64 for the FP64 form, FP32 otherwise: they only precondition);
+// they are copied into LDS in that dtype with coalesced loads and both
+// triangular solves run in FP64 from there.
 template <class MT, int RP>
-__global__ __launch_bounds__(64) void k_apply_rows(const double *__restrict__ Lstore,
+__global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore,
                                                    const void *rhs, void *X, int R,
                                                    const double *skip) {
-  __shared__ double Lp[RP * (RP + 1) / 2];
+  using P = Packed<RP>;
+  __shared__ MT Lp[P::LDS];
   if (skip && *skip != 0.0) return;
   const int lane = threadIdx.x;
   const int64_t row = blockIdx.x;
-  double s[RP];
-  const double *L = Lstore + row * (int64_t)(RP * (RP + 1) / 2);
+  const MT *L = Lstore + row * (int64_t)P::PS;
+  // all loads of the row's factor are issued before the first LDS write
+  constexpr int NIT = (P::PS + 63) / 64;
+  MT v[NIT];
 #pragma unroll
-  for (int j = 0; j < RP; ++j)
-    s[j] = (lane < RP && lane >= j) ? L[j * RP - (j * (j - 1)) / 2 + lane - j] : 0.0;
+  for (int it = 0; it < NIT; ++it) {
+    const int q = lane + 64 * it;
+    v[it] = L[q < P::PS ? q : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = lane + 64 * it;
+    if (q < P::PS) Lp[q] = v[it];
+  }
+  if (lane == 0) Lp[P::ZERO] = MT(0);
+  __syncthreads();
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
-  double dg = 1.0;
-#pragma unroll
-  for (int k = 0; k < RP; ++k) dg = k == lane ? s[k] : dg;
-  const double x = chol_solve_lanes<RP>(s, b, 1.0 / dg, lane, Lp);
+  const double dg = lane < RP ? (double)Lp[(lane * (lane + 3)) / 2] : 1.0;  // L(i, i)
+  const double rdiag = 1.0 / dg;
+  const double y = fwd_lds<RP, MT>(Lp, b, rdiag, lane);
+  const double x = bwd_lds<RP, MT>(Lp, y, rdiag, lane);
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
 }
 
@@ -770,7 +835,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
                  (double)(rt[r1] - rt[r0]) * RP * RP * (double)gsz +
                      nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
-                     (c.Lstore ? nrow * RP * (RP + 1) / 2 * 8.0 : 0.0),
+                     (c.Lstore ? nrow * RP * (RP + 1) / 2 * (double)gsz : 0.0),
                  nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
     if (c.fdt == TT_F64)
       e = launch_solve_rp<double, double, double>(RP, sd, r1 - r0, s);
@@ -785,25 +850,28 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
 }
 
 hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt,
-                               const double *Lstore, const void *rhs, void *X,
+                               const void *Lstore, const void *rhs, void *X,
                                const double *skip, hipStream_t s) {
   const int64_t I = ix->mode[mode].I;
   if (I <= 0) return hipSuccess;
   const int RP = rp_for(R);
   dim3 g((unsigned)I), b(64);
-  ProfScope ps("precond_apply", s, (double)I * RP * (RP + 1) / 2 * 8.0 + (double)I * R * 8.0,
+  const double es = fdt == TT_F64 ? 8.0 : 4.0;
+  ProfScope ps("precond_apply", s, (double)I * RP * (RP + 1) / 2 * es + (double)I * R * 2 * es,
                (double)I * 2.0 * R * R);
+  const double *Ld = static_cast<const double *>(Lstore);
+  const float *Lf = static_cast<const float *>(Lstore);
   if (fdt == TT_F64) {
     switch (RP) {
-      case 16: k_apply_rows<double, 16><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
-      case 32: k_apply_rows<double, 32><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
-      default: k_apply_rows<double, 64><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
+      case 16: k_apply_rows<double, 16><<<g, b, 0, s>>>(Ld, rhs, X, R, skip); break;
+      case 32: k_apply_rows<double, 32><<<g, b, 0, s>>>(Ld, rhs, X, R, skip); break;
+      default: k_apply_rows<double, 64><<<g, b, 0, s>>>(Ld, rhs, X, R, skip); break;
     }
   } else {
     switch (RP) {
-      case 16: k_apply_rows<float, 16><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
-      case 32: k_apply_rows<float, 32><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
-      default: k_apply_rows<float, 64><<<g, b, 0, s>>>(Lstore, rhs, X, R, skip); break;
+      case 16: k_apply_rows<float, 16><<<g, b, 0, s>>>(Lf, rhs, X, R, skip); break;
+      case 32: k_apply_rows<float, 32><<<g, b, 0, s>>>(Lf, rhs, X, R, skip); break;
+      default: k_apply_rows<float, 64><<<g, b, 0, s>>>(Lf, rhs, X, R, skip); break;
     }
   }
   return hipGetLastError();
