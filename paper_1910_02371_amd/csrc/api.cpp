@@ -335,7 +335,7 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt) {
   TT_ST(ws_get(ix, "tsum", (size_t)std::max<int64_t>(ix->max_nchunk, 1) * 8, &p));
   TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &p));
   const int RP = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
-  const int64_t task_bytes = (int64_t)RP * RP * (fdt == TT_F64 ? 8 : 4);
+  const int64_t task_bytes = (int64_t)gram_task_elems(RP) * (fdt == TT_F64 ? 8 : 4);
   int64_t wt = 1;
   for (int n = 0; n < ix->N; ++n) {
     const ModeIndex &md = ix->mode[n];

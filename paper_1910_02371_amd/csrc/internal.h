@@ -20,6 +20,10 @@ constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
 
+// Elements of one Gram task's matrix in the lower-tile layout (the
+// NB (NB + 1) / 2 lower 16 x 16 tiles of the RP x RP matrix, NB = RP / 16).
+__host__ __device__ constexpr int gram_task_elems(int RP) { return 128 * (RP / 16) * (RP / 16 + 1); }
+
 struct ModeIndex {
   int64_t I = 0;
   int64_t nrows = 0;            // rows holding >= 1 nonzero

@@ -14,16 +14,20 @@
 //   BF16 factors are widened exactly to FP32 (a product of two bf16 values
 //   is exact in FP32), so the BF16 form accumulates like the FP32 form.
 //   FP64 storage: v_mfma_f64_16x16x4f64 tiles (lower triangle only).
-// Each task writes the upper triangle of its G (row-major RP x RP) to a batch
-// workspace; the solve kernel reads it by columns (lane i takes G[j][i] =
-// G[i][j] for j <= i), so its loads are coalesced.  Rows with several tasks
-// are summed in FP64 in task order (deterministic).
+// Each task writes its G to a batch workspace in the lower-tile layout: the
+// NB (NB + 1) / 2 lower 16 x 16 tiles (NB = RP / 16), tile (I, J) at
+// q = I (I + 1) / 2 + J, each row-major, which is the accumulator layout of
+// v_mfma_f64_16x16x4f64 (lane l, register v: row 4 v + l / 16, column
+// l % 16), so the solve kernel loads its tiles with coalesced reads.  Rows
+// with several tasks are summed in FP64 in task order (deterministic).
 //
-// Solve: one wave per row; lane i keeps row i of S = G + lambda I in FP64
-// registers and a right-looking Cholesky runs over columns, broadcasting
-// L(j,k) with readlane; the forward solve stays in registers and the
-// backward solve with L^T reads L from LDS.  Non-positive pivots follow
-// LAPACK potrf: info = order of the failing leading minor, x = 0.
+// Solve: one wave per row.  S = G + lambda I stays in FP64 matrix-core
+// accumulator tiles and a blocked right-looking Cholesky runs over panels
+// of four columns: the panel is factored on the lanes (lane i = row i), and
+// the trailing update S -= L_p L_p^T runs on v_mfma_f64_16x16x4f64.  The
+// factor is collected row-packed in LDS for the triangular solves.
+// Non-positive pivots follow LAPACK potrf: info = order of the failing
+// leading minor, x = 0.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,9 +53,15 @@ struct GramDev {
   const void *w;              // weights in stream order (value dtype) or NULL
   const int32_t *w_perm;
   double w_scale;
-  void *G;                    // workspace: (task - task_base) * RP * RP
+  void *G;                    // workspace: (task - task_base) * gram_task_elems(RP)
   int split_heavy;            // light kernel skips tasks > kGramLight
 };
+
+// Slot of the lower element (r, c), r >= c, in the lower-tile layout.
+__device__ __forceinline__ int lower_slot(int r, int c) {
+  const int I = r >> 4, J = c >> 4;
+  return 256 * (I * (I + 1) / 2 + J) + 16 * (r & 15) + (c & 15);
+}
 
 template <class TR>
 __device__ __forceinline__ float elem_f(const typename TR::T *A, int64_t off);
@@ -247,8 +257,9 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   }
 }
 
-// Write the upper triangle of G (row-major RP x RP) from the accumulators.
-// v_mfma_f32_16x16x4f32 result: lane l, register v holds D[4 (l / 16) + v][l % 16].
+// Write G in the lower-tile layout from the accumulators (each unordered
+// column pair once).  v_mfma_f32_16x16x4f32 result: lane l, register v holds
+// D[4 (l / 16) + v][l % 16].
 template <int RP>
 __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
   constexpr int VW = RP / 16;
@@ -263,7 +274,7 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
       for (int v = 0; v < 4; ++v) {
         const int r = 4 * (lane >> 4) + v;
         const int a = VW * r + p, b = VW * c + pp;
-        if (p < pp || r <= c) G[min(a, b) * RP + max(a, b)] = acc.c[q][v];
+        if (p < pp || r <= c) G[lower_slot(max(a, b), min(a, b))] = acc.c[q][v];
       }
       ++q;
     }
@@ -280,7 +291,7 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP, VEC>(d, nb, ne, acc);
-  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
+  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc);
 }
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
@@ -310,33 +321,33 @@ __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
   if (w == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
-    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP), acc);
+    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc);
   }
 }
 
-// Rows with more than kReduceMin tasks: sum the upper triangles of their
-// tasks' Grams entrywise in FP64, in task order, into the row's first task
-// slot.
+// Rows with more than kReduceMin tasks: sum their tasks' Grams entrywise
+// (lower-tile layout) in FP64, in task order, into the row's first task slot.
 template <class GT, int RP>
 __global__ __launch_bounds__(256) void k_gram_reduce(const int32_t *__restrict__ rows,
                                                      const int32_t *__restrict__ row_task,
                                                      int64_t task_base, GT *G) {
+  constexpr int SZ = 128 * (RP / 16) * (RP / 16 + 1);
   const int64_t row = rows[blockIdx.x];
   const int e = blockIdx.y * 256 + threadIdx.x;
-  if (e >= RP * RP || e / RP > e % RP) return;  // upper triangle only
+  if (e >= SZ) return;
   const int32_t t0 = row_task[row], t1 = row_task[row + 1];
-  const GT *g = G + ((int64_t)t0 - task_base) * (RP * RP) + e;
+  const GT *g = G + ((int64_t)t0 - task_base) * SZ + e;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const int n = t1 - t0;
   int q = 0;
   for (; q + 4 <= n; q += 4) {
-    s0 += (double)g[(int64_t)q * (RP * RP)];
-    s1 += (double)g[(int64_t)(q + 1) * (RP * RP)];
-    s2 += (double)g[(int64_t)(q + 2) * (RP * RP)];
-    s3 += (double)g[(int64_t)(q + 3) * (RP * RP)];
+    s0 += (double)g[(int64_t)q * SZ];
+    s1 += (double)g[(int64_t)(q + 1) * SZ];
+    s2 += (double)g[(int64_t)(q + 2) * SZ];
+    s3 += (double)g[(int64_t)(q + 3) * SZ];
   }
-  for (; q < n; ++q) s0 += (double)g[(int64_t)q * (RP * RP)];
-  G[((int64_t)t0 - task_base) * (RP * RP) + e] = (GT)((s0 + s1) + (s2 + s3));
+  for (; q < n; ++q) s0 += (double)g[(int64_t)q * SZ];
+  G[((int64_t)t0 - task_base) * SZ + e] = (GT)((s0 + s1) + (s2 + s3));
 }
 
 // FP64 storage and accumulation: 16x16x4 FP64 tiles of the upper triangle.
@@ -386,7 +397,7 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
         }
     }
   }
-  double *G = reinterpret_cast<double *>(d.G) + (t - d.task_base) * (int64_t)(RP * RP);
+  double *G = reinterpret_cast<double *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP);
   int q = 0;
 #pragma unroll
   for (int a = 0; a < TB; ++a)
@@ -394,11 +405,12 @@ __global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
     for (int bb = a; bb < TB; ++bb) {
       // v_mfma_f64_16x16x4f64 result: D[row][col] at col = lane % 16,
       // row = 4 * v + lane / 16 (checked on the device); tile (a, bb) is
-      // block (a, bb) of the upper triangle
+      // block (a, bb) of the upper triangle, stored transposed as the lower
+      // element (16 bb + col, 16 a + row)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 4 * v + lane / 16, col = lane % 16;
-        G[(16 * a + row) * RP + 16 * bb + col] = c[q][v];
+        if (a < bb || col >= row) G[lower_slot(16 * bb + col, 16 * a + row)] = c[q][v];
       }
       ++q;
     }
@@ -445,41 +457,6 @@ __device__ __forceinline__ double rsqrt_pivot(double d) {
   return tiny ? y * 0x1p480 : y;
 }
 
-// Cholesky of the lane-distributed matrix s (lane i = row i), in place:
-// afterwards s[j] on lane i holds L(i, j) for j <= i and 0 for j > i.
-// Column k of L is published through LDS (`col`, RP doubles) and read back
-// as broadcasts, so the trailing update of step k is RP-k-1 independent FMAs
-// per lane (lanes above the diagonal multiply by 0).  Look-ahead: step k
-// updates column k+1 first and computes pivot k+1 from it, so the pivot's
-// dependent chain overlaps the rest of step k's update; the test of that
-// pivot closes the step.  The workgroup is one wave, whose LDS accesses
-// complete in program order, so the broadcast needs no barrier.  Returns
-// info (LAPACK potrf convention: the order of the first leading minor that
-// is not positive definite).
-template <int RP>
-__device__ __forceinline__ int chol_lanes(double (&s)[RP], int lane, double *col,
-                                          double &rdiag) {
-  double dkk = readlane_d(s[0], 0);
-  if (!(dkk > 0.0)) return 1;
-  double inv = rsqrt_pivot(dkk);
-#pragma unroll
-  for (int k = 0; k < RP; ++k) {
-    if (lane == k) rdiag = inv;
-    const double lik = lane >= k ? s[k] * inv : 0.0;
-    s[k] = lik;
-    if (k + 1 < RP) {
-      if (lane < RP) col[lane] = lik;
-      s[k + 1] -= lik * col[k + 1];
-      dkk = readlane_d(s[k + 1], k + 1);
-      inv = rsqrt_pivot(dkk);
-#pragma unroll
-      for (int j = k + 2; j < RP; ++j) s[j] -= lik * col[j];
-      if (!(dkk > 0.0)) return k + 2;
-    }
-  }
-  return 0;
-}
-
 // A copy of the lane index that the compiler cannot identify with the
 // original (an empty asm statement owns it), so lane comparisons in different
 // phases of a kernel are not merged and kept alive as masks across them.
@@ -498,22 +475,6 @@ struct Packed {
   static constexpr int ZERO = PS;
   static constexpr int LDS = PS + 1 + 64;
 };
-
-// Lane i writes its row of L (s[j], j <= i) into the LDS copy and entries
-// j > i into its scratch slot; Lp[ZERO] is set to 0.
-template <int RP>
-__device__ __forceinline__ void put_rows(double *Lp, const double (&s)[RP], int lane_in) {
-  using P = Packed<RP>;
-  const int lane = opaque_lane(lane_in);
-  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
-  const int junk = P::ZERO + 1 + lane;
-#pragma unroll
-  for (int j = 0; j < RP; ++j) {
-    const int addr = (j <= lane && lane < RP) ? base + j : junk;
-    Lp[addr] = s[j];
-  }
-  if (lane == 0) Lp[P::ZERO] = 0.0;
-}
 
 // Triangular solves with L read from the LDS copy; b on lane i is b_i and
 // rdiag on lane i is 1 / L(i, i).  At step k every lane subtracts its
@@ -549,11 +510,127 @@ __device__ __forceinline__ double bwd_lds(const LT *Lp, double b, double rdiag, 
   return b * rdiag;
 }
 
+// Blocked Cholesky of one row's S = G + lambda I on the matrix cores.
+// S lives in NT accumulator tiles (lower tiles, layout of the Gram
+// workspace): lane l, register v of tile (I, J) holds
+// S(16 I + 4 v + l / 16, 16 J + l % 16).  For each panel of four columns
+// k0 .. k0 + 3 (inside column block J = k0 / 16):
+//   1. the lanes holding the panel's columns write them to the LDS panel
+//      buffer Pn (row-major, 4 per row);
+//   2. lane i reads row i of the panel and the panel is factored on the
+//      lanes (pivot from the diagonal lane, reciprocal square root, the
+//      three in-panel updates with broadcast multipliers);
+//   3. the factored panel L_p goes back to Pn and into the row-packed LDS
+//      copy Lp of L;
+//   4. the trailing update S(I, J') -= L_p(I) L_p(J')^T for J <= J' <= I
+//      runs as v_mfma_f64_16x16x4f64 with K = the panel's four columns,
+//      operand L_p(I) read from Pn (lane l: L(16 I + l % 16, k0 + l / 16)).
+// Entries of already factored columns in a tile are updated too but never
+// read again.  The workgroup is one wave, whose LDS accesses complete in
+// program order, so the buffers need no barriers.  Returns info (LAPACK
+// potrf convention) and leaves 1 / L(i, i) in rdiag on lane i.
+template <class GT, int RP>
+__device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t t1,
+                                          int lane, double *Lp, double *Pn,
+                                          double &rdiag) {
+  constexpr int NB = RP / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int SZ = 256 * NT;
+  const int R = d.R;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int32_t t = t0; t < t1; ++t) {
+    const GT *g = reinterpret_cast<const GT *>(d.G) + ((int64_t)t - d.task_base) * SZ + lane;
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[q][v] += (double)g[256 * q + 64 * v];
+  }
+  {
+    // shift, identity on the padding, zero above the diagonal of the
+    // diagonal tiles (those slots are not written by the Gram kernels)
+    const int ln = opaque_lane(lane);
+    const int rr = ln >> 4, cc = ln & 15;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = 0; J <= I; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + 4 * v + rr, c = 16 * J + cc;
+          double x = acc[I * (I + 1) / 2 + J][v];
+          if (I == J) x = (4 * v + rr < cc) ? 0.0 : x;
+          x += (r == c) ? d.lambda : 0.0;
+          acc[I * (I + 1) / 2 + J][v] = (r >= R || c >= R) ? (r == c ? 1.0 : 0.0) : x;
+        }
+  }
+  using P = Packed<RP>;
+  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+  const int prow = lane < RP ? 4 * lane : 4 * RP;  // this lane's panel row (or scratch)
+#pragma unroll
+  for (int p = 0; p < RP / 4; ++p) {
+    const int k0 = 4 * p, J = k0 / 16, c0 = k0 % 16;
+    {
+      // 1. panel columns to Pn (lanes whose column is outside the panel
+      // write to their scratch slot)
+      const int ln = opaque_lane(lane);
+      const int cc = ln & 15, rr = ln >> 4;
+      const bool mine = (unsigned)(cc - c0) < 4u;
+#pragma unroll
+      for (int I = J; I < NB; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int addr = mine ? 4 * (16 * I + 4 * v + rr) + (cc - c0) : 4 * RP + 4 + ln;
+          Pn[addr] = acc[I * (I + 1) / 2 + J][v];
+        }
+    }
+    // 2. factor the panel on the lanes
+    double x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = lane < RP ? Pn[prow + c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = k0 + c;
+      const double dkk = readlane_d(x[c], k);
+      if (!(dkk > 0.0)) return k + 1;
+      const double inv = rsqrt_pivot(dkk);
+      if (lane == k) rdiag = inv;
+      const double lik = lane >= k ? x[c] * inv : 0.0;
+      x[c] = lik;
+#pragma unroll
+      for (int c2 = c + 1; c2 < 4; ++c2) x[c2] -= lik * readlane_d(lik, k0 + c2);
+    }
+    // 3. the factored panel to Pn and to the row-packed copy of L
+    {
+      const int ln = opaque_lane(lane);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Pn[prow + c] = x[c];
+        Lp[(k0 + c <= ln && ln < RP) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
+      }
+    }
+    // 4. trailing update on the matrix cores
+    if (k0 + 4 < RP) {
+      double a[NB];
+#pragma unroll
+      for (int I = J; I < NB; ++I) a[I] = Pn[4 * (16 * I + (lane & 15)) + (lane >> 4)];
+#pragma unroll
+      for (int I = J; I < NB; ++I)
+#pragma unroll
+        for (int J2 = J; J2 <= I; ++J2)
+          acc[I * (I + 1) / 2 + J2] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              -a[I], a[J2], acc[I * (I + 1) / 2 + J2], 0, 0, 0);
+    }
+  }
+  return 0;
+}
+
 template <class GT, class XT, class MT, int RP>
-__global__ __launch_bounds__(64, 2) void k_solve_rows(SolveDev d) {
+__global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   using P = Packed<RP>;
   __shared__ double Lp[P::LDS];
-  __shared__ double col[RP];
+  __shared__ double Pn[4 * RP + 4 + 64];
   if (d.skip && *d.skip != 0.0) return;
   const int lane = threadIdx.x;
   const int64_t row = d.r0 + blockIdx.x;
@@ -561,40 +638,15 @@ __global__ __launch_bounds__(64, 2) void k_solve_rows(SolveDev d) {
   const int32_t t0 = d.row_task[row];
   int32_t t1 = d.row_task[row + 1];
   if (t1 - t0 > kReduceMin) t1 = t0 + 1;  // pre-reduced by k_gram_reduce
-  // lane i reads column i of the task's RP x RP block: G[j][i] for j <= i
-  // is the stored upper triangle (= G[i][j]); entries j > i are not written
-  // by the Gram kernels and are replaced by 0 below
-  double s[RP];
-#pragma unroll
-  for (int j = 0; j < RP; ++j) s[j] = 0.0;
-  const int li = lane < RP ? lane : 0;
-  for (int32_t t = t0; t < t1; ++t) {
-    const GT *g = reinterpret_cast<const GT *>(d.G) +
-                  ((int64_t)t - d.task_base) * (RP * RP) + li;
-#pragma unroll
-    for (int j = 0; j < RP; ++j) s[j] += (double)g[j * RP];
-  }
-  // S = G + lambda I on the R x R block, identity on the padding
-  {
-    const int ln = opaque_lane(lane);
-    const bool pad_row = ln >= R;
-#pragma unroll
-    for (int j = 0; j < RP; ++j) {
-      const double v = s[j] + (j == ln ? d.lambda : 0.0);
-      const double kept = j > ln ? 0.0 : v;
-      s[j] = (pad_row || j >= R) ? (j == ln ? 1.0 : 0.0) : kept;
-    }
-  }
+  if (lane == 0) Lp[P::ZERO] = 0.0;
   double rdiag = 1.0;
-  const int info = chol_lanes<RP>(s, lane, col, rdiag);
+  const int info = chol_tiles<GT, RP>(d, t0, t1, lane, Lp, Pn, rdiag);
   if (d.info && lane == 0) d.info[row] = info;
   if (info && d.Lstore) {
     // failed rows keep the identity (no preconditioning for that block)
-#pragma unroll
-    for (int j = 0; j < RP; ++j) s[j] = (j == lane) ? 1.0 : 0.0;
+    for (int q = lane; q < P::PS; q += 64) Lp[q] = 0.0;
+    if (lane < RP) Lp[(lane * (lane + 3)) / 2] = 1.0;
   }
-  put_rows<RP>(Lp, s, lane);
-  __syncthreads();
   if (d.Lstore) {
     GT *L = reinterpret_cast<GT *>(d.Lstore) + row * (int64_t)P::PS;
     for (int q = lane; q < P::PS; q += 64) L[q] = (GT)Lp[q];
@@ -707,7 +759,7 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
   dim3 g((unsigned)((n + 3) / 4)), b(256);
   const double R = d.R, fb = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
   const double gs = fdt == TT_F64 ? 8 : 4, pernz = 8 + (d.w ? gs : 0) + 2 * R * fb;
-  const double tile = (double)RP * RP * gs;
+  const double tile = (double)gram_task_elems(RP) * gs;
   if (fdt == TT_F64) {
     ProfScope ps("gram_light", s, (wk.light_nnz + wk.heavy_nnz) * pernz + wk.light_tasks * tile,
                  (wk.light_nnz + wk.heavy_nnz) * R * (R + 1));
@@ -739,8 +791,8 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
   }
   if (nmulti > 0) {
     ProfScope ps("gram_reduce", s, wk.reduce_tasks * tile + (double)nmulti * tile,
-                 wk.reduce_tasks * RP * RP);
-    dim3 gr((unsigned)nmulti, (unsigned)((RP * RP + 255) / 256));
+                 wk.reduce_tasks * gram_task_elems(RP));
+    dim3 gr((unsigned)nmulti, (unsigned)((gram_task_elems(RP) + 255) / 256));
     if (fdt == TT_F64) {
       switch (RP) {
         case 16: k_gram_reduce<double, 16><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (double *)d.G); break;
@@ -762,7 +814,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   const ModeIndex &md = ix->mode[c.mode];
   const int RP = rp_for(c.R);
   const size_t gsz = c.fdt == TT_F64 ? 8 : 4;
-  const int64_t task_bytes = (int64_t)RP * RP * gsz;
+  const int64_t task_bytes = (int64_t)gram_task_elems(RP) * gsz;
   int64_t wtasks = std::max<int64_t>(kGramBatchBytes / task_bytes, md.max_task_per_row);
   wtasks = std::max<int64_t>(wtasks, 1);
   if (wtasks > md.ntask) wtasks = std::max<int64_t>(md.ntask, 1);
@@ -833,7 +885,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     sd.r0 = r0;
     const double Rd = c.R, nrow = (double)(r1 - r0);
     ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
-                 (double)(rt[r1] - rt[r0]) * RP * RP * (double)gsz +
+                 (double)(rt[r1] - rt[r0]) * gram_task_elems(RP) * (double)gsz +
                      nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
                      (c.Lstore ? nrow * RP * (RP + 1) / 2 * (double)gsz : 0.0),
                  nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
