@@ -1,13 +1,16 @@
 // Device-side helpers shared by the libtt kernels (gfx950, wave64).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace tt {
 
 // ---------------------------------------------------------------------------
 // Storage traits.  T = factor storage type, VT = per-nonzero value type,
-// AT = accumulation type, V = elements per 16-byte lane fragment.
+// AT = accumulation type, V = elements per lane fragment (16 bytes for FP64
+// and FP32, 8 bytes for BF16, so BF16 keeps the FP32 lane layout).
 // ---------------------------------------------------------------------------
 struct TrF64 {
   using T = double;
@@ -25,7 +28,7 @@ struct TrBF16 {
   using T = uint16_t;
   using VT = float;
   using AT = float;
-  static constexpr int V = 8;
+  static constexpr int V = 4;  // 8-byte fragments: the lane layout of the FP32 form
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) {
@@ -69,14 +72,12 @@ __device__ __forceinline__ double to_double<uint16_t>(uint16_t v) {
 
 // ---------------------------------------------------------------------------
 // Factor-row fragment loads: lane `c0 / V` of a group reads elements
-// [c0, c0 + V) of row `row`.  VEC: one 16-byte load (requires R % V == 0,
-// 16-byte aligned rows); otherwise element loads with the bound r < R.
-// Elements at or beyond R read as 0.
+// [c0, c0 + V) of row `row`.  VEC: one vector load (requires R % V == 0,
+// 16-byte aligned rows); otherwise element loads.  Elements at or beyond R
+// read as 0.  The loads are unconditional (out-of-range lanes read column 0
+// or R - 1 of the row and select 0 afterwards), so no branch separates a
+// load from its use and the compiler can keep many gathers in flight.
 // ---------------------------------------------------------------------------
-template <class TR, bool VEC>
-__device__ __forceinline__ void load_frag(const typename TR::T *__restrict__ A,
-                                          int64_t ldA, int64_t row, int c0,
-                                          int R, typename TR::AT (&o)[TR::V]);
 
 // Element pointer from a uniform base and a 32-bit element offset (every
 // factor and dense block is below 2^32 bytes, checked on the host), so the
@@ -92,111 +93,151 @@ __device__ __forceinline__ X *at32(X *base, uint32_t elem) {
                                (uint32_t)(elem * (uint32_t)sizeof(X)));
 }
 
+template <class T>
+__device__ __forceinline__ float widen_f(T x);
 template <>
-__device__ __forceinline__ void load_frag<TrF32, true>(const float *__restrict__ A,
-                                                      int64_t ldA, int64_t row,
-                                                      int c0, int R,
-                                                      float (&o)[4]) {
-  if (c0 < R) {
-    float4 v = *reinterpret_cast<const float4 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-  } else {
-    o[0] = o[1] = o[2] = o[3] = 0.f;
-  }
-}
+__device__ __forceinline__ float widen_f<float>(float x) { return x; }
 template <>
-__device__ __forceinline__ void load_frag<TrF32, false>(const float *__restrict__ A,
-                                                       int64_t ldA, int64_t row,
-                                                       int c0, int R,
-                                                       float (&o)[4]) {
-  const float *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
-#pragma unroll
-  for (int j = 0; j < 4; ++j) o[j] = (c0 + j < R) ? p[j] : 0.f;
-}
+__device__ __forceinline__ float widen_f<uint16_t>(uint16_t x) { return bf16_to_f32(x); }
+
+// Traits of dense accumulation-type rows (X blocks of the matvec): the FP32
+// or FP64 storage traits of the same lane layout.
+template <class AT> struct DenseTrSel;
+template <> struct DenseTrSel<float> { using type = TrF32; };
+template <> struct DenseTrSel<double> { using type = TrF64; };
+template <class AT> using DenseTr = typename DenseTrSel<AT>::type;
+
+// A fragment as loaded (before widening and masking).  Gathers keep the raw
+// form until the values are used, so that the compiler does not fold the
+// masking into a branch around the load.
+template <class TR, bool VEC>
+struct FragRaw {
+  typename TR::AT v[TR::V];
+};
 template <>
-__device__ __forceinline__ void load_frag<TrF64, true>(const double *__restrict__ A,
-                                                      int64_t ldA, int64_t row,
-                                                      int c0, int R,
-                                                      double (&o)[2]) {
-  if (c0 < R) {
-    double2 v = *reinterpret_cast<const double2 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
-    o[0] = v.x; o[1] = v.y;
-  } else {
-    o[0] = o[1] = 0.0;
-  }
-}
+struct FragRaw<TrF32, true> { float4 v; };
 template <>
-__device__ __forceinline__ void load_frag<TrF64, false>(const double *__restrict__ A,
-                                                       int64_t ldA, int64_t row,
-                                                       int c0, int R,
-                                                       double (&o)[2]) {
-  const double *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
-#pragma unroll
-  for (int j = 0; j < 2; ++j) o[j] = (c0 + j < R) ? p[j] : 0.0;
-}
+struct FragRaw<TrF64, true> { double2 v; };
 template <>
-__device__ __forceinline__ void load_frag<TrBF16, true>(const uint16_t *__restrict__ A,
-                                                       int64_t ldA, int64_t row,
-                                                       int c0, int R,
-                                                       float (&o)[8]) {
-  if (c0 < R) {
-    uint4 v = *reinterpret_cast<const uint4 *>(at32(A, (uint32_t)row * (uint32_t)ldA + c0));
-    o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xffff0000u);
-    o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xffff0000u);
-    o[4] = __uint_as_float(v.z << 16); o[5] = __uint_as_float(v.z & 0xffff0000u);
-    o[6] = __uint_as_float(v.w << 16); o[7] = __uint_as_float(v.w & 0xffff0000u);
+struct FragRaw<TrBF16, true> { uint2 v; };
+
+template <class TR, bool VEC>
+__device__ __forceinline__ void gather_frag(const typename TR::T *__restrict__ A,
+                                            int64_t ldA, int64_t row, int c0, int R,
+                                            FragRaw<TR, VEC> &f) {
+  using T = typename TR::T;
+  using AT = typename TR::AT;
+  const uint32_t rb = (uint32_t)row * (uint32_t)ldA;
+  if constexpr (VEC) {
+    const uint32_t e = rb + (uint32_t)(c0 < R ? c0 : 0);
+    f.v = *reinterpret_cast<const decltype(f.v) *>(at32(A, e));
   } else {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = 0.f;
+    for (int j = 0; j < TR::V; ++j) {
+      const int c = c0 + j;
+      const T x = *at32(A, rb + (uint32_t)(c < R ? c : R - 1));
+      if constexpr (std::is_same<TR, TrF64>::value) f.v[j] = x;
+      else f.v[j] = widen_f<T>(x);
+    }
   }
-}
-template <>
-__device__ __forceinline__ void load_frag<TrBF16, false>(const uint16_t *__restrict__ A,
-                                                        int64_t ldA, int64_t row,
-                                                        int c0, int R,
-                                                        float (&o)[8]) {
-  const uint16_t *p = at32(A, (uint32_t)row * (uint32_t)ldA + c0);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) o[j] = (c0 + j < R) ? bf16_to_f32(p[j]) : 0.f;
 }
 
-// Dense (accumulation-type) row fragment with row stride R: V elements
-// [c0, c0 + V) of row `row`; elements at or beyond R read as 0.
-template <class AT, int V, bool VEC>
-__device__ __forceinline__ void load_dense(const AT *__restrict__ X, int64_t row, int c0,
-                                           int R, AT (&o)[V]) {
-  const AT *p = at32(X, (uint32_t)row * (uint32_t)R + c0);
+template <class TR, bool VEC>
+__device__ __forceinline__ void widen_frag(const FragRaw<TR, VEC> &f, int c0, int R,
+                                           typename TR::AT (&o)[TR::V]) {
+  using AT = typename TR::AT;
   if constexpr (VEC) {
-    if (c0 < R) {
-      if constexpr (sizeof(AT) == 4) {
-#pragma unroll
-        for (int q = 0; q < V / 4; ++q) {
-          float4 v = reinterpret_cast<const float4 *>(p)[q];
-          o[4 * q] = v.x; o[4 * q + 1] = v.y; o[4 * q + 2] = v.z; o[4 * q + 3] = v.w;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < V / 2; ++q) {
-          double2 v = reinterpret_cast<const double2 *>(p)[q];
-          o[2 * q] = v.x; o[2 * q + 1] = v.y;
-        }
-      }
+    const bool ok = c0 < R;
+    if constexpr (std::is_same<TR, TrF32>::value) {
+      o[0] = ok ? f.v.x : 0.f; o[1] = ok ? f.v.y : 0.f;
+      o[2] = ok ? f.v.z : 0.f; o[3] = ok ? f.v.w : 0.f;
+    } else if constexpr (std::is_same<TR, TrF64>::value) {
+      o[0] = ok ? f.v.x : 0.0; o[1] = ok ? f.v.y : 0.0;
     } else {
-#pragma unroll
-      for (int j = 0; j < V; ++j) o[j] = AT(0);
+      o[0] = ok ? __uint_as_float(f.v.x << 16) : 0.f;
+      o[1] = ok ? __uint_as_float(f.v.x & 0xffff0000u) : 0.f;
+      o[2] = ok ? __uint_as_float(f.v.y << 16) : 0.f;
+      o[3] = ok ? __uint_as_float(f.v.y & 0xffff0000u) : 0.f;
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < V; ++j) o[j] = (c0 + j < R) ? p[j] : AT(0);
+    for (int j = 0; j < TR::V; ++j) o[j] = c0 + j < R ? f.v[j] : AT(0);
   }
 }
 
-// Butterfly sum over aligned groups of G lanes (G a power of two <= 64);
-// every lane of the group receives the total.
+template <class TR, bool VEC>
+__device__ __forceinline__ void load_frag(const typename TR::T *__restrict__ A,
+                                          int64_t ldA, int64_t row, int c0, int R,
+                                          typename TR::AT (&o)[TR::V]) {
+  FragRaw<TR, VEC> f;
+  gather_frag<TR, VEC>(A, ldA, row, c0, R, f);
+  widen_frag<TR, VEC>(f, c0, R, o);
+}
+
+// Dense (accumulation-type) row fragment with row stride R: V elements
+// [c0, c0 + V) of row `row`; elements at or beyond R read as 0 (loads are
+// unconditional as above).
+template <class AT, int V, bool VEC>
+__device__ __forceinline__ void load_dense(const AT *__restrict__ X, int64_t row, int c0,
+                                           int R, AT (&o)[V]) {
+  const uint32_t rb = (uint32_t)row * (uint32_t)R;
+  if constexpr (VEC) {
+    const bool ok = c0 < R;
+    const AT *p = at32(X, rb + (uint32_t)(ok ? c0 : 0));
+    if constexpr (sizeof(AT) == 4) {
+#pragma unroll
+      for (int q = 0; q < V / 4; ++q) {
+        const float4 v = reinterpret_cast<const float4 *>(p)[q];
+        o[4 * q] = ok ? v.x : 0.f; o[4 * q + 1] = ok ? v.y : 0.f;
+        o[4 * q + 2] = ok ? v.z : 0.f; o[4 * q + 3] = ok ? v.w : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < V / 2; ++q) {
+        const double2 v = reinterpret_cast<const double2 *>(p)[q];
+        o[2 * q] = ok ? v.x : 0.0; o[2 * q + 1] = ok ? v.y : 0.0;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int c = c0 + j;
+      const AT x = *at32(X, rb + (uint32_t)(c < R ? c : R - 1));
+      o[j] = c < R ? x : AT(0);
+    }
+  }
+}
+
+// Lane permutations inside 16-lane rows (DPP controls): swap neighbours,
+// swap pairs, mirror each half row, mirror the row.
+enum : int { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of
+// the group receives the total.  Inside a 16-lane row the partners come from
+// DPP moves (two quad swaps, then the half-row and row mirrors, each of
+// which pairs the lane with a lane of the other half); wider groups add
+// butterfly steps across rows.  Every lane adds the same two operands at
+// each step (in either order), so all lanes of a group get the same bits.
 template <int G, class X>
 __device__ __forceinline__ X group_sum(X v) {
+  if constexpr (G >= 2) v += dpp_move<DPP_XOR1>(v);
+  if constexpr (G >= 4) v += dpp_move<DPP_XOR2>(v);
+  if constexpr (G >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
+  if constexpr (G >= 16) v += dpp_move<DPP_MIRROR>(v);
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  for (int o = 16; o < G; o <<= 1) v += __shfl_xor(v, o);
   return v;
 }
 

@@ -13,7 +13,10 @@
 namespace tt {
 
 // Work partition constants.
-constexpr int kChunk = 2048;       // nnz per streaming work chunk (max)
+#ifndef TT_CHUNK
+#define TT_CHUNK 1024
+#endif
+constexpr int kChunk = TT_CHUNK;   // nnz per streaming work chunk (max)
 constexpr int kGramPiece = 4096;   // nnz per Gram task (max)
 constexpr int kGramLight = 512;    // tasks above this run on a whole workgroup
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced

@@ -16,7 +16,7 @@ hipError_t launch_stream_bf16(StreamOp op, const StreamDev &d, int64_t nchunk, i
 hipError_t launch_stream_f64(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
                              bool vec, hipStream_t s);
 
-static int frag_elems(tt_dtype fdt) { return fdt == TT_F64 ? 2 : (fdt == TT_F32 ? 4 : 8); }
+static int frag_elems(tt_dtype fdt) { return fdt == TT_F64 ? 2 : 4; }
 
 int stream_group_width(tt_dtype fdt, int R) {
   const int V = frag_elems(fdt);

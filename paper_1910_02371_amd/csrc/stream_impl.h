@@ -7,8 +7,8 @@
 // a heavy row.  The chunk's sorted mode indices, other-mode indices and
 // per-nonzero values are staged into LDS with coalesced loads.  The chunk is
 // split into NG = 256 / G contiguous sub-ranges, one per group of G lanes;
-// a group holds R on its lanes (V elements per lane, one 16-byte fragment of
-// each factor row) and walks its sub-range in order, gathering the factor
+// a group holds R on its lanes (V elements per lane, one 16-byte (8-byte for
+// BF16) fragment of each factor row) and walks its sub-range in order, gathering the factor
 // rows of the other modes.  Rows that begin and end inside a sub-range are
 // written directly; pieces cut by sub-range boundaries are combined by an
 // in-order scan over the groups; pieces of heavy rows go to FP64 carry slots
@@ -31,6 +31,10 @@ namespace tt {
 
 constexpr int ST_THREADS = 256;
 constexpr int ST_UNROLL = 4;
+
+// Gather source for a mode that TTTP skips: the row is read (so that the
+// gather phase has no branch) and then replaced by ones.
+static __device__ double g_skip_row[64];
 
 struct StreamDev {
   const int64_t *chunk;
@@ -212,28 +216,42 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
     bool ol = sm.key[e0] == cur;
     load_own(cur);
     for (int eb = e0; eb < e1; eb += ST_UNROLL) {
-      AT fa[ST_UNROLL][2][V];
-      AT fx[ST_UNROLL][2][V];
+      // gathers of ST_UNROLL nonzeros, issued back to back and kept raw until
+      // used; slots past the end of the sub-range reload its last nonzero and
+      // are skipped below
+      FragRaw<TR, VEC> ra[ST_UNROLL][2];
+      FragRaw<DenseTr<AT>, VEC> rx[ST_UNROLL][2];
 #pragma unroll
       for (int u = 0; u < ST_UNROLL; ++u) {
-        const int e = eb + u;
-        if (e < e1) {
+        const int e = min(eb + u, e1 - 1);
 #pragma unroll
-          for (int p = 0; p < NO; ++p) {
-            const int ip = sm.oi[p][e];
-            if (OP == OP_TTTP && Ao[p] == nullptr) {
-#pragma unroll
-              for (int j = 0; j < V; ++j) fa[u][p][j] = (c0 + j < R) ? AT(1) : AT(0);
-            } else {
-              load_frag<TR, VEC>(Ao[p], ldA, ip, c0, R, fa[u][p]);
-            }
-            if constexpr (OP == OP_GN) load_dense<AT, V, VEC>(Xo[p], ip, c0, R, fx[u][p]);
+        for (int p = 0; p < NO; ++p) {
+          const int ip = sm.oi[p][e];
+          if constexpr (OP == OP_TTTP) {
+            const bool skip = Ao[p] == nullptr;
+            gather_frag<TR, VEC>(skip ? reinterpret_cast<const T *>(g_skip_row) : Ao[p], ldA,
+                                 skip ? 0 : ip, c0, R, ra[u][p]);
+          } else {
+            gather_frag<TR, VEC>(Ao[p], ldA, ip, c0, R, ra[u][p]);
           }
+          if constexpr (OP == OP_GN)
+            gather_frag<DenseTr<AT>, VEC>(Xo[p], R, ip, c0, R, rx[u][p]);
         }
       }
 #pragma unroll
       for (int u = 0; u < ST_UNROLL; ++u) {
         const int e = eb + u;
+        AT fa[2][V], fx[2][V];
+#pragma unroll
+        for (int p = 0; p < NO; ++p) {
+          if (OP == OP_TTTP && Ao[p] == nullptr) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) fa[p][j] = (c0 + j < R) ? AT(1) : AT(0);
+          } else {
+            widen_frag<TR, VEC>(ra[u][p], c0, R, fa[p]);
+          }
+          if constexpr (OP == OP_GN) widen_frag<DenseTr<AT>, VEC>(rx[u][p], c0, R, fx[p]);
+        }
         if (e < e1) {
           const int row = sm.key[e + 1];
           if (row != cur) {
@@ -248,9 +266,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
           AT h[V];
 #pragma unroll
           for (int j = 0; j < V; ++j) {
-            h[j] = fa[u][0][j];
+            h[j] = fa[0][j];
 #pragma unroll
-            for (int p = 1; p < NO; ++p) h[j] *= fa[u][p][j];
+            for (int p = 1; p < NO; ++p) h[j] *= fa[p][j];
           }
           if constexpr (OP == OP_MTTKRP) {
             const AT sv = (AT)sm.val[e];
@@ -270,9 +288,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
             for (int j = 0; j < V; ++j) {
               AT dh;
               if constexpr (NO == 1) {
-                dh = fx[u][0][j];
+                dh = fx[0][j];
               } else {
-                dh = fx[u][0][j] * fa[u][1][j] + fa[u][0][j] * fx[u][1][j];
+                dh = fx[0][j] * fa[1][j] + fa[0][j] * fx[1][j];
               }
               zz += xown[j] * h[j] + own[j] * dh;
             }
