@@ -197,6 +197,11 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "traffic": traffic, "alg_bytes_per_launch": rec["bytes"] / n_l,
                     "launch_ms": per_ms, "launches": n_l}
+        # algorithmic bytes count every factor-row gather; above the HBM peak
+        # the rate is an effective one (gathers served by L2 / Infinity Cache)
+        roofline["effective"] = achieved > HBM_PEAK_GBS
+    if traffic is not None:
+        roofline["hbm_frac_measured"] = traffic / (per_ms / 1e3) / 1e9 / HBM_PEAK_GBS
     step_prof = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step":
                      v["launches"] / args.steps,
                      "GBps_alg": v["bytes"] / v["ms"] / 1e6 if v["ms"] else None,
