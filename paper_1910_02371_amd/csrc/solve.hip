@@ -110,11 +110,8 @@ struct GramAcc {
   __device__ void set(int v, float x) { c[v / 4][v % 4] = x; }
 };
 
-#ifndef TT_GRAM_GS
-#define TT_GRAM_GS 4          // MFMA steps whose gathers are issued together
-#endif
 #ifndef TT_GRAM_HEAVY_WAVES
-#define TT_GRAM_HEAVY_WAVES 8 // waves of the workgroup that takes a heavy task
+#define TT_GRAM_HEAVY_WAVES 4 // waves of the workgroup that takes a heavy task
 #endif
 
 // VW consecutive factor entries starting at element `off`, widened to FP32.
@@ -158,27 +155,70 @@ __device__ __forceinline__ void load_cols(const typename TR::T *A, uint32_t off,
   }
 }
 
-template <class TR, int RP, int GS>
-struct GramGroup {
-  float a0[GS][RP / 16], a1[GS][RP / 16], w[GS];
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Bits of the leading bf16 part of x (truncation): x minus this part is
+// exact in FP32.
+__device__ __forceinline__ uint32_t bf16_head(float x) { return __float_as_uint(x) & 0xffff0000u; }
+
+// Two bf16 parts (in the upper halves of a and b) packed as elements
+// 2t (a) and 2t + 1 (b) of an MFMA operand word.
+__device__ __forceinline__ uint32_t pack_bf16(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+
+// Exact split of x into NP bf16 parts (NP = 3 for any FP32 value; NP = 2 is
+// exact for a product of two bf16 values, which has at most 16 significant
+// bits): x = sum of the parts, largest first.
+template <int NP>
+__device__ __forceinline__ void split_bf16(float x, uint32_t (&p)[NP]) {
+  float r = x;
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    p[i] = bf16_head(r);
+    r -= __uint_as_float(p[i]);
+  }
+}
+
+// Products of parts kept for h_a h_b^T: part i of the A side times part j of
+// the B side, for i + j <= 4 (1-based; the dropped terms are below 2^-24 of
+// the product).  With two parts on both sides all four products are kept,
+// which is exact.
+template <int PA, int PB>
+struct PartPairs {
+  static constexpr int N = (PA == 2 && PB == 2) ? 4 : (PA == 2 ? 5 : 6);
+  __device__ static constexpr int a(int k) {
+    return (PA == 2 && PB == 2) ? (k < 2 ? 0 : 1) : (k == 0 ? 0 : k == 1 ? 0 : k == 2 ? 1 : k == 3 ? 0 : k == 4 ? (PA == 3 ? 2 : 1) : 1);
+  }
+  __device__ static constexpr int b(int k) {
+    return (PA == 2 && PB == 2) ? (k % 2) : (k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 0 : k == 3 ? 2 : k == 4 ? (PA == 3 ? 0 : 1) : 1);
+  }
 };
 
-// Nonzeros [nb, ne) of one row into acc.  The range is walked in blocks of
-// 64 nonzeros (lane l loads the indices and weight of nonzero base + l,
-// coalesced, one block ahead) and, inside a block, in groups of GS MFMA
-// steps: the shuffles and factor-row gathers of a group are issued together,
-// then its MFMAs.  Padding columns (>= R) use a clamped address and a zero
-// mask, so loads are unconditional; steps past the end read lanes whose
-// weight is 0.
-template <class TR, int RP, bool VEC>
+// Nonzeros [nb, ne) of one row into acc, on v_mfma_f32_16x16x32_bf16.  The
+// range is walked in blocks of 64 nonzeros (lane l loads the indices and
+// weight of nonzero base + l, coalesced, one block ahead) and steps of 32:
+// a step is 8 substeps of 4 nonzeros in the vector-fragment layout, so lane
+// (i, k) holds, for column class p, the values h_e[VW i + p] of the 8
+// nonzeros e = 4 s + k (s = 0..7).  Those 8 values are exactly the lane's
+// K-run of an MFMA operand (lanes 16 g + i take K = 8 g .. 8 g + 7), so the
+// operands are built in registers with no transposition.  Each FP32 value
+// is split exactly into bf16 parts (three for FP32 factors, two for BF16
+// factors, whose products have 16 significant bits) and the parts' products
+// are accumulated in FP32 (PartPairs).  Without per-nonzero weights both
+// operands are the parts of h; with weights the B operand is the parts of
+// w h.  Padding columns (>= R) use a clamped address and a zero mask, and
+// nonzeros past the end have weight (or validity) 0.
+template <class TR, int RP, bool VEC, bool WEIGHTED>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
   using T = typename TR::T;
   constexpr int VW = RP / 16;
-  constexpr int GS = TT_GRAM_GS;              // steps per group
-  constexpr int SPB = 16;                     // steps per 64-nonzero block
-  constexpr int GPB = SPB / GS;               // groups per block
-  static_assert(SPB % GS == 0, "group size must divide the block");
+  constexpr bool F32 = std::is_same<TR, TrF32>::value;
+  constexpr int PA = F32 ? 3 : 2;
+  constexpr int PB = WEIGHTED ? 3 : PA;
+  using PP = PartPairs<PA, PB>;
   const int lane = threadIdx.x & 63;
   const T *A0 = reinterpret_cast<const T *>(d.A0);
   const T *A1 = reinterpret_cast<const T *>(d.A1);
@@ -192,67 +232,91 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   const int64_t n = ne - nb;
   if (n <= 0) return;
   const int64_t nblk = (n + 63) / 64;
-  const int last_cnt = (int)(n - (nblk - 1) * 64);
-  const int64_t gtot = (nblk - 1) * GPB + ((last_cnt + 3) / 4 + GS - 1) / GS;
+  const int64_t nst = (n + 31) / 32;
 
   auto load_block = [&](int64_t blk, int &j0, int &j1, float &w) {
     const int64_t e = nb + blk * 64 + lane;
     if (e < ne) {
       j0 = d.oidx0[e];
       j1 = d.oidx1[e];
-      w = weight_at<float>(d, e);
+      w = WEIGHTED ? weight_at<float>(d, e) : 1.f;
     } else {
       j0 = 0; j1 = 0; w = 0.f;
     }
   };
-  // `cur` registers hold the block of the group being prepared, `nxt` the
-  // following block
   int cj0, cj1, nj0 = 0, nj1 = 0;
   float cw, nw = 0.f;
   load_block(0, cj0, cj1, cw);
   if (nblk > 1) load_block(1, nj0, nj1, nw);
   int64_t cblk = 0;
 
-  GramGroup<TR, RP, GS> g;
-  for (int64_t gi = 0; gi < gtot; ++gi) {
-    const int64_t blk = gi / GPB;
+  for (int64_t st = 0; st < nst; ++st) {
+    const int64_t blk = st >> 1;
     if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
       cj0 = nj0; cj1 = nj1; cw = nw;
       cblk = blk;
       if (blk + 1 < nblk) load_block(blk + 1, nj0, nj1, nw);
     }
-    const int st0 = (int)(gi % GPB) * GS;
-    int j0[GS], j1[GS];
+    const int sb = 32 * (int)(st & 1) + kk;
+    int j0[8], j1[8];
+    float w[8];
 #pragma unroll
-    for (int u = 0; u < GS; ++u) {
-      const int src = (st0 + u) * 4 + kk;
-      j0[u] = __shfl(cj0, src);
-      j1[u] = __shfl(cj1, src);
-      g.w[u] = __shfl(cw, src);
+    for (int u = 0; u < 8; ++u) {
+      j0[u] = __shfl(cj0, sb + 4 * u);
+      j1[u] = __shfl(cj1, sb + 4 * u);
+      w[u] = __shfl(cw, sb + 4 * u);
     }
+    float a0[8][VW], a1[8][VW];
 #pragma unroll
-    for (int u = 0; u < GS; ++u) {
-      load_cols<TR, VW, VEC>(A0, (uint32_t)j0[u] * ldA, cb, R, g.a0[u]);
-      load_cols<TR, VW, VEC>(A1, (uint32_t)j1[u] * ldA, cb, R, g.a1[u]);
+    for (int u = 0; u < 8; ++u) {
+      load_cols<TR, VW, VEC>(A0, (uint32_t)j0[u] * ldA, cb, R, a0[u]);
+      load_cols<TR, VW, VEC>(A1, (uint32_t)j1[u] * ldA, cb, R, a1[u]);
     }
     __builtin_amdgcn_sched_barrier(0);
+    // operand words: [class][part][word], word t holds substeps 2t, 2t + 1
+    uint32_t opa[VW][PA][4], opb[VW][PB][4];
 #pragma unroll
-    for (int u = 0; u < GS; ++u) {
-      float h[VW], hw[VW];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int v = 0; v < VW; ++v) {
-        h[v] = g.a0[u][v] * g.a1[u][v] * m[v];
-        hw[v] = g.w[u] * h[v];
-      }
-      int q = 0;
+        uint32_t pa[2][PA], pb[2][PB];
 #pragma unroll
-      for (int p = 0; p < VW; ++p)
-#pragma unroll
-        for (int pp = p; pp < VW; ++pp) {
-          acc.c[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(h[p], hw[pp], acc.c[q], 0, 0, 0);
-          ++q;
+        for (int q = 0; q < 2; ++q) {
+          const int u = 2 * t + q;
+          const float h = a0[u][v] * a1[u][v] * m[v];
+          if constexpr (WEIGHTED) {
+            split_bf16<PA>(h, pa[q]);
+            split_bf16<PB>(w[u] * h, pb[q]);
+          } else {
+            split_bf16<PA>(h * w[u], pa[q]);  // w = validity (1 or 0)
+          }
         }
-    }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) opa[v][i][t] = pack_bf16(pa[0][i], pa[1][i]);
+        if constexpr (WEIGHTED) {
+#pragma unroll
+          for (int i = 0; i < PB; ++i) opb[v][i][t] = pack_bf16(pb[0][i], pb[1][i]);
+        }
+      }
+    int q = 0;
+#pragma unroll
+    for (int p = 0; p < VW; ++p)
+#pragma unroll
+      for (int pp = p; pp < VW; ++pp) {
+#pragma unroll
+        for (int k = 0; k < PP::N; ++k) {
+          const int ia = PP::a(k), ib = PP::b(k);
+          const u32x4 wa = {opa[p][ia][0], opa[p][ia][1], opa[p][ia][2], opa[p][ia][3]};
+          u32x4 wb;
+          if constexpr (WEIGHTED)
+            wb = (u32x4){opb[pp][ib][0], opb[pp][ib][1], opb[pp][ib][2], opb[pp][ib][3]};
+          else
+            wb = (u32x4){opa[pp][ib][0], opa[pp][ib][1], opa[pp][ib][2], opa[pp][ib][3]};
+          acc.c[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, wa), __builtin_bit_cast(bf16x8, wb), acc.c[q], 0, 0, 0);
+        }
+        ++q;
+      }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -261,7 +325,7 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
 // column pair once).  v_mfma_f32_16x16x4f32 result: lane l, register v holds
 // D[4 (l / 16) + v][l % 16].
 template <int RP>
-__device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
+__device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, float scale) {
   constexpr int VW = RP / 16;
   const int lane = threadIdx.x & 63;
   const int c = lane & 15;
@@ -274,7 +338,7 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
       for (int v = 0; v < 4; ++v) {
         const int r = 4 * (lane >> 4) + v;
         const int a = VW * r + p, b = VW * c + pp;
-        if (p < pp || r <= c) G[lower_slot(max(a, b), min(a, b))] = acc.c[q][v];
+        if (p < pp || r <= c) G[lower_slot(max(a, b), min(a, b))] = acc.c[q][v] * scale;
       }
       ++q;
     }
@@ -282,7 +346,7 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc) {
 
 // Light tasks: one wave per task, four tasks per workgroup; tasks with more
 // than kGramLight nonzeros are left to k_gram_f32_heavy.
-template <class TR, int RP, bool VEC>
+template <class TR, int RP, bool VEC, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= d.task_end) return;
@@ -290,13 +354,14 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   if (d.split_heavy && ne - nb > kGramLight) return;
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC>(d, nb, ne, acc);
-  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc);
+  gram_accum<TR, RP, VEC, WEIGHTED>(d, nb, ne, acc);
+  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
+                 d.w ? 1.f : (float)d.w_scale);
 }
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
-template <class TR, int RP, bool VEC>
+template <class TR, int RP, bool VEC, bool WEIGHTED>
 __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
@@ -309,7 +374,7 @@ __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC>(d, b0, b1, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED>(d, b0, b1, acc);
   for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
@@ -321,7 +386,8 @@ __global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
   if (w == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
-    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc);
+    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
+                 d.w ? 1.f : (float)d.w_scale);
   }
 }
 
@@ -713,7 +779,7 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
   return hipGetLastError();
 }
 
-template <class TR, int RP, bool VEC>
+template <class TR, int RP, bool VEC, bool WEIGHTED>
 static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
                                double light_bytes, double light_flops, double heavy_bytes,
                                double heavy_flops, hipStream_t s) {
@@ -721,11 +787,11 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   d.split_heavy = 1;
   {
     ProfScope ps("gram_light", s, light_bytes, light_flops);
-    k_gram_f32<TR, RP, VEC><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+    k_gram_f32<TR, RP, VEC, WEIGHTED><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
   }
   if (nheavy > 0) {
     ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
-    k_gram_f32_heavy<TR, RP, VEC>
+    k_gram_f32_heavy<TR, RP, VEC, WEIGHTED>
         <<<dim3((unsigned)nheavy), dim3(64 * TT_GRAM_HEAVY_WAVES), 0, s>>>(d, heavy, nheavy);
   }
 }
@@ -740,8 +806,13 @@ static void launch_gram_f32_vec(const GramDev &d, const int32_t *heavy, int64_t 
   const bool vec = d.R % VW == 0 && d.ldA % VW == 0 &&
                    reinterpret_cast<uintptr_t>(d.A0) % al == 0 &&
                    reinterpret_cast<uintptr_t>(d.A1) % al == 0;
-  if (vec) launch_gram_f32_rp<TR, RP, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
-  else launch_gram_f32_rp<TR, RP, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+  if (d.w) {
+    if (vec) launch_gram_f32_rp<TR, RP, true, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    else launch_gram_f32_rp<TR, RP, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+  } else {
+    if (vec) launch_gram_f32_rp<TR, RP, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    else launch_gram_f32_rp<TR, RP, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+  }
 }
 
 // Gram of one batch of tasks [task_base, task_end): light tasks one wave
