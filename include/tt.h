@@ -112,8 +112,13 @@ tt_status tt_index_destroy(tt_index *ix);
 
 /* Sizes the index workspace for ranks up to R and factor dtype fdt, so that
  * later calls allocate nothing (needed before hipGraph capture).  Calls
- * made without it size the workspace on first use. */
-tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt);
+ * made without it size the workspace on first use.  `flags` adds the
+ * workspaces of tt_gn_step: TT_RESERVE_GN (PCG vectors and preconditioner
+ * factors, least squares) and TT_RESERVE_GN_POISSON (also the per-mode
+ * phi'' weights of the Poisson loss). */
+#define TT_RESERVE_GN 1u
+#define TT_RESERVE_GN_POISSON 2u
+tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
 
 /* Read-only views of mode `mode` for tests: device pointers to ptr (int64,
  * I_n + 1), perm (int32, m), sorted mode indices (int32, m), nonzero rows
@@ -249,6 +254,29 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
 tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                      tt_dtype fdt, tt_loss loss, double lambda, double tol,
                      int kmax, double *d_stats, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batching (graph capture).  The ALS sweep and the Gauss-Newton step
+ * enqueue many kernels (per-mode streams, row batches of Gram and solve
+ * kernels, and kmax fixed PCG iterations whose early exit is a device flag);
+ * a caller that repeats them can record the sequence once and replay it as
+ * one launch.
+ *   tt_graph_begin  starts capturing `stream` (which must not be the null
+ *                   stream; thread-local capture mode).  Every library call
+ *                   made on it until tt_graph_end is recorded, not run.  The
+ *                   index workspace must be reserved first (tt_index_reserve
+ *                   with the flags of the recorded calls) and the kernel
+ *                   profiler must be off.
+ *   tt_graph_end    ends the capture and instantiates it into *out
+ *                   (library-owned until tt_graph_destroy).
+ *   tt_graph_launch replays the recorded work on `stream`; pointers and
+ *                   scalars are those of the captured calls.
+ * ------------------------------------------------------------------------- */
+typedef struct tt_graph tt_graph;
+tt_status tt_graph_begin(hipStream_t stream);
+tt_status tt_graph_end(hipStream_t stream, tt_graph **out);
+tt_status tt_graph_launch(tt_graph *graph, hipStream_t stream);
+tt_status tt_graph_destroy(tt_graph *graph);
 
 /* ---------------------------------------------------------------------------
  * Kernel profiler (process-global; use from one host thread).

@@ -326,9 +326,43 @@ tt_status tt_index_destroy(tt_index *ix) {
   return TT_OK;
 }
 
-tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt) {
+}  // extern "C"
+
+// Workspace of tt_gn_step: PCG vectors (dense dtype, all modes' blocks),
+// FP64 scalars and dot-product partials, the preconditioner's row-packed
+// Cholesky factors (dense dtype) and, for the Poisson loss, phi'' per mode.
+struct GnWs {
+  void *x, *r, *z, *p, *q, *sc, *parts, *w, *L;
+};
+
+static tt_status gn_workspace(tt_index *ix, int R, tt_dtype fdt, tt_loss loss, GnWs *ws) {
+  const int N = ix->N;
+  const size_t dsz = value_size(fdt);
+  const int RP = R <= 16 ? 16 : (R <= 32 ? 32 : 64);
+  int64_t ntot = 0, Ltot = 0;
+  for (int d = 0; d < N; ++d) {
+    ntot += ix->mode[d].I * R;
+    Ltot += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
+  }
+  TT_ST(ws_get(ix, "pcg_x", ntot * dsz, &ws->x));
+  TT_ST(ws_get(ix, "pcg_r", ntot * dsz, &ws->r));
+  TT_ST(ws_get(ix, "pcg_z", ntot * dsz, &ws->z));
+  TT_ST(ws_get(ix, "pcg_p", ntot * dsz, &ws->p));
+  TT_ST(ws_get(ix, "pcg_q", ntot * dsz, &ws->q));
+  TT_ST(ws_get(ix, "pcg_sc", 32 * 8, &ws->sc));
+  TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &ws->parts));
+  TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * (fdt == TT_F64 ? 8 : 4), &ws->L));
+  ws->w = nullptr;
+  if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &ws->w));
+  return TT_OK;
+}
+
+extern "C" {
+
+tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags) {
   g_err.clear();
   TT_ST(check_common(ix, R, R, fdt));
+  TT_CHECK((flags & ~(TT_RESERVE_GN | TT_RESERVE_GN_POISSON)) == 0, "bad flags 0x%x", flags);
   double *c = nullptr;
   TT_ST(carry_ws(ix, &c));
   void *p = nullptr;
@@ -347,6 +381,11 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt) {
   int64_t need = 0;
   for (int n = 0; n < ix->N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
   TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &p));
+  if (flags) {
+    GnWs ws;
+    TT_ST(gn_workspace(ix, R, fdt,
+                       (flags & TT_RESERVE_GN_POISSON) ? TT_LOSS_POISSON_LOG : TT_LOSS_LS, &ws));
+  }
   return TT_OK;
 }
 
@@ -573,19 +612,11 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   for (int d = 0; d < N; ++d) off[d + 1] = off[d] + ix->mode[d].I * R;
   const int64_t ntot = off[N];
   // workspace
-  void *vx, *vr, *vz, *vp, *vq, *vsc, *vparts, *vw = nullptr, *vL;
-  TT_ST(ws_get(ix, "pcg_x", ntot * dsz, &vx));
-  TT_ST(ws_get(ix, "pcg_r", ntot * dsz, &vr));
-  TT_ST(ws_get(ix, "pcg_z", ntot * dsz, &vz));
-  TT_ST(ws_get(ix, "pcg_p", ntot * dsz, &vp));
-  TT_ST(ws_get(ix, "pcg_q", ntot * dsz, &vq));
-  TT_ST(ws_get(ix, "pcg_sc", 32 * 8, &vsc));
-  TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &vparts));
-  int64_t Ltot = 0;
-  for (int d = 0; d < N; ++d) Ltot += ix->mode[d].I * (int64_t)RP * (RP + 1) / 2;
+  GnWs ws;
+  TT_ST(gn_workspace(ix, R, fdt, loss, &ws));
+  void *vx = ws.x, *vr = ws.r, *vz = ws.z, *vp = ws.p, *vq = ws.q, *vsc = ws.sc,
+       *vparts = ws.parts, *vw = ws.w, *vL = ws.L;
   const size_t lsz = fdt == TT_F64 ? 8 : 4;  // preconditioner factors: dense dtype
-  TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * lsz, &vL));
-  if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &vw));
   char *X = (char *)vx, *Rv = (char *)vr, *Z = (char *)vz, *P = (char *)vp, *Q = (char *)vq;
   double *sc = (double *)vsc, *parts = (double *)vparts;
   char *L = (char *)vL;
@@ -675,6 +706,58 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   for (int d = 0; d < N; ++d)
     TT_LAUNCH(launch_add_to_factor(d_A[d], fdt, ldA, ix->mode[d].I, R, blk(X, d), st), "step");
   if (d_stats) TT_LAUNCH(launch_pcg_stats(sc, sc + 10, d_stats, st), "stats");
+  return TT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Graph capture
+// ---------------------------------------------------------------------------
+struct tt_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" {
+
+tt_status tt_graph_begin(hipStream_t stream) {
+  g_err.clear();
+  TT_CHECK(stream != nullptr, "graph capture needs a non-null stream");
+  TT_CHECK(!tt::prof_on(), "turn the kernel profiler off before capturing");
+  TT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  return TT_OK;
+}
+
+tt_status tt_graph_end(hipStream_t stream, tt_graph **out) {
+  g_err.clear();
+  TT_CHECK(stream != nullptr && out != nullptr, "NULL argument");
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  TT_HIP(hipStreamEndCapture(stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return hip_fail(e, "graph instantiate");
+  }
+  *out = new tt_graph{g, ex};
+  return TT_OK;
+}
+
+tt_status tt_graph_launch(tt_graph *graph, hipStream_t stream) {
+  g_err.clear();
+  TT_CHECK(graph != nullptr, "graph is NULL");
+  TT_HIP(hipGraphLaunch(graph->exec, stream));
+  return TT_OK;
+}
+
+tt_status tt_graph_destroy(tt_graph *graph) {
+  g_err.clear();
+  if (!graph) return TT_OK;
+  hipGraphExecDestroy(graph->exec);
+  hipGraphDestroy(graph->graph);
+  delete graph;
   return TT_OK;
 }
 

@@ -17,8 +17,14 @@ namespace tt {
 #define TT_CHUNK 1024
 #endif
 constexpr int kChunk = TT_CHUNK;   // nnz per streaming work chunk (max)
-constexpr int kGramPiece = 4096;   // nnz per Gram task (max)
-constexpr int kGramLight = 512;    // tasks above this run on a whole workgroup
+#ifndef TT_GRAM_PIECE
+#define TT_GRAM_PIECE 4096
+#endif
+#ifndef TT_GRAM_LIGHT
+#define TT_GRAM_LIGHT 512
+#endif
+constexpr int kGramPiece = TT_GRAM_PIECE;  // nnz per Gram task (max)
+constexpr int kGramLight = TT_GRAM_LIGHT;  // tasks above this run on a whole workgroup
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch

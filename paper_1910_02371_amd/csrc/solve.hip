@@ -197,19 +197,22 @@ struct PartPairs {
 };
 
 // Nonzeros [nb, ne) of one row into acc, on v_mfma_f32_16x16x32_bf16.  The
-// range is walked in blocks of 64 nonzeros (lane l loads the indices and
-// weight of nonzero base + l, coalesced, one block ahead) and steps of 32:
-// a step is 8 substeps of 4 nonzeros in the vector-fragment layout, so lane
-// (i, k) holds, for column class p, the values h_e[VW i + p] of the 8
-// nonzeros e = 4 s + k (s = 0..7).  Those 8 values are exactly the lane's
-// K-run of an MFMA operand (lanes 16 g + i take K = 8 g .. 8 g + 7), so the
-// operands are built in registers with no transposition.  Each FP32 value
-// is split exactly into bf16 parts (three for FP32 factors, two for BF16
-// factors, whose products have 16 significant bits) and the parts' products
-// are accumulated in FP32 (PartPairs).  Without per-nonzero weights both
+// range is walked in blocks of 64 nonzeros (lane l loads the row offsets of
+// the two gathered factor rows and the weight of nonzero base + l,
+// coalesced, one block ahead) and steps of 32: a step is 8 substeps of 4
+// nonzeros in the vector-fragment layout, so lane (i, k) holds, for column
+// class p, the values h_e[VW i + p] of the 8 nonzeros e = 4 s + k
+// (s = 0..7).  Those 8 values are exactly the lane's K-run of an MFMA
+// operand (lanes 16 g + i take K = 8 g .. 8 g + 7), so the operands are
+// built in registers with no transposition.  Each FP32 value is split
+// exactly into bf16 parts (three for FP32 factors, two for BF16 factors,
+// whose products have 16 significant bits) and the parts' products are
+// accumulated in FP32 (PartPairs).  Without per-nonzero weights both
 // operands are the parts of h; with weights the B operand is the parts of
-// w h.  Padding columns (>= R) use a clamped address and a zero mask, and
-// nonzeros past the end have weight (or validity) 0.
+// w h.  Columns at or beyond R read a clamped address and hold finite values
+// that only reach padding entries of G, which the solve replaces by the
+// identity.  Nonzeros past the end of the range (only in the last step)
+// read row 0 and are zeroed by their weight or validity.
 template <class TR, int RP, bool VEC, bool WEIGHTED>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
@@ -226,51 +229,50 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   const uint32_t ldA = (uint32_t)d.ldA;
   const int kk = lane >> 4;
   const int cb = VW * (lane & 15);
-  float m[VW];
-#pragma unroll
-  for (int v = 0; v < VW; ++v) m[v] = (cb + v < R) ? 1.f : 0.f;
   const int64_t n = ne - nb;
   if (n <= 0) return;
   const int64_t nblk = (n + 63) / 64;
   const int64_t nst = (n + 31) / 32;
+  const bool ragged = (n & 31) != 0;  // the last step has nonzeros past the end
 
-  auto load_block = [&](int64_t blk, int &j0, int &j1, float &w) {
+  auto load_block = [&](int64_t blk, uint32_t &r0, uint32_t &r1, float &w) {
     const int64_t e = nb + blk * 64 + lane;
     if (e < ne) {
-      j0 = d.oidx0[e];
-      j1 = d.oidx1[e];
+      r0 = (uint32_t)d.oidx0[e] * ldA;
+      r1 = (uint32_t)d.oidx1[e] * ldA;
       w = WEIGHTED ? weight_at<float>(d, e) : 1.f;
     } else {
-      j0 = 0; j1 = 0; w = 0.f;
+      r0 = 0; r1 = 0; w = 0.f;
     }
   };
-  int cj0, cj1, nj0 = 0, nj1 = 0;
+  uint32_t cr0, cr1, nr0 = 0, nr1 = 0;
   float cw, nw = 0.f;
-  load_block(0, cj0, cj1, cw);
-  if (nblk > 1) load_block(1, nj0, nj1, nw);
+  load_block(0, cr0, cr1, cw);
+  if (nblk > 1) load_block(1, nr0, nr1, nw);
   int64_t cblk = 0;
 
   for (int64_t st = 0; st < nst; ++st) {
+    const bool tail = ragged && st == nst - 1;  // uniform
     const int64_t blk = st >> 1;
     if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
-      cj0 = nj0; cj1 = nj1; cw = nw;
+      cr0 = nr0; cr1 = nr1; cw = nw;
       cblk = blk;
-      if (blk + 1 < nblk) load_block(blk + 1, nj0, nj1, nw);
+      if (blk + 1 < nblk) load_block(blk + 1, nr0, nr1, nw);
     }
     const int sb = 32 * (int)(st & 1) + kk;
-    int j0[8], j1[8];
+    uint32_t r0[8], r1[8];
     float w[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      j0[u] = __shfl(cj0, sb + 4 * u);
-      j1[u] = __shfl(cj1, sb + 4 * u);
-      w[u] = __shfl(cw, sb + 4 * u);
+      r0[u] = __shfl(cr0, sb + 4 * u);
+      r1[u] = __shfl(cr1, sb + 4 * u);
+      w[u] = (WEIGHTED || tail) ? __shfl(cw, sb + 4 * u) : 1.f;
     }
     float a0[8][VW], a1[8][VW];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      load_cols<TR, VW, VEC>(A0, (uint32_t)j0[u] * ldA, cb, R, a0[u]);
-      load_cols<TR, VW, VEC>(A1, (uint32_t)j1[u] * ldA, cb, R, a1[u]);
+      load_cols<TR, VW, VEC>(A0, r0[u], cb, R, a0[u]);
+      load_cols<TR, VW, VEC>(A1, r1[u], cb, R, a1[u]);
     }
     __builtin_amdgcn_sched_barrier(0);
     // operand words: [class][part][word], word t holds substeps 2t, 2t + 1
@@ -283,12 +285,13 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int u = 2 * t + q;
-          const float h = a0[u][v] * a1[u][v] * m[v];
+          float h = a0[u][v] * a1[u][v];
           if constexpr (WEIGHTED) {
             split_bf16<PA>(h, pa[q]);
             split_bf16<PB>(w[u] * h, pb[q]);
           } else {
-            split_bf16<PA>(h * w[u], pa[q]);  // w = validity (1 or 0)
+            if (tail) h *= w[u];  // validity (1 or 0)
+            split_bf16<PA>(h, pa[q]);
           }
         }
 #pragma unroll

@@ -20,6 +20,8 @@ ORDER_COO = -1
 ORDER_PER_MODE = -2
 INDEX_T = "t"          # selects the observed values held by the index
 TT_SYNC = 1
+RESERVE_GN = 1
+RESERVE_GN_POISSON = 2
 
 STATUS = {0: "TT_OK", -1: "TT_ERR_INVALID_ARG", -2: "TT_ERR_INDEX_RANGE",
           -3: "TT_ERR_OOM", -4: "TT_ERR_HIP", -5: "TT_ERR_NOT_SPD",
@@ -36,7 +38,7 @@ SIGNATURES = {
     "tt_build_index": (_I, [_I, ctypes.POINTER(_I64), _I64, _PP, _P, _I, _U32, _P,
                             ctypes.POINTER(_P)]),
     "tt_index_destroy": (_I, [_P]),
-    "tt_index_reserve": (_I, [_P, _I, _I]),
+    "tt_index_reserve": (_I, [_P, _I, _I, _U32]),
     "tt_index_view": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
                            ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_I64)]),
     "tt_index_other": (_I, [_P, _I, _I, ctypes.POINTER(_P)]),
@@ -48,6 +50,10 @@ SIGNATURES = {
     "tt_objective": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _P, _P]),
     "tt_als_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
     "tt_gn_step": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P]),
+    "tt_graph_begin": (_I, [_P]),
+    "tt_graph_end": (_I, [_P, ctypes.POINTER(_P)]),
+    "tt_graph_launch": (_I, [_P, _P]),
+    "tt_graph_destroy": (_I, [_P]),
     "tt_profile_enable": (_I, [_I]),
     "tt_profile_report": (_I, [ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "tt_last_error": (ctypes.c_char_p, []),
@@ -156,8 +162,11 @@ class Index:
         except Exception:
             pass
 
-    def reserve(self, R, fdt):
-        _check(lib().tt_index_reserve(self._h, R, fdt))
+    def reserve(self, R, fdt, gn=None):
+        """Size the workspace (needed before graph capture); gn = "ls" or
+        "poisson" also sizes the Gauss-Newton step's workspace."""
+        flags = {None: 0, "ls": RESERVE_GN, "poisson": RESERVE_GN | RESERVE_GN_POISSON}[gn]
+        _check(lib().tt_index_reserve(self._h, R, fdt, flags))
 
     def view(self, mode):
         """(ptr int64[I+1], perm int32[m], key int32[m], rows int32[nrows]) as
@@ -324,6 +333,45 @@ def gn_step(ix, A, loss, lam, tol=5e-3, kmax=30, stats=None):
     _check(lib().tt_gn_step(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
                             float(tol), int(kmax), _ptr(stats), _stream()))
     return stats
+
+
+class Graph:
+    """Library calls recorded once (tt_graph_begin/end) and replayed as one
+    launch on the current stream."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self):
+        _check(lib().tt_graph_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h:
+            lib().tt_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def capture(fn):
+    """Record the library calls that fn() makes on the current stream (not the
+    null stream) into a Graph.  fn must allocate nothing: pass preallocated
+    outputs and reserve the index workspace first."""
+    s = _stream()
+    _check(lib().tt_graph_begin(s))
+    h = ctypes.c_void_p()
+    try:
+        fn()
+    except BaseException:
+        if lib().tt_graph_end(s, ctypes.byref(h)) == 0 and h.value:
+            lib().tt_graph_destroy(h)
+        raise
+    _check(lib().tt_graph_end(s, ctypes.byref(h)))
+    return Graph(h)
 
 
 def profile_enable(on=True):
