@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--nnz", type=int, default=100_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 19)
+    p.add_argument("--no-batching", dest="batching", action="store_false",
+                   help="skip the graph-replay vs plain-launch comparison")
     p.add_argument("--form-sweeps", type=int, default=5,
                    help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
@@ -118,7 +120,7 @@ def main():
     index_s = time.time() - t0
     log(f"index built in {index_s:.2f}s")
     del idx
-    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]))
+    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls")
     A = [torch.as_tensor(a).to(dev).to(fdt_t).contiguous() for a in A0]
     m = wl.nnz
 
@@ -208,6 +210,10 @@ def main():
                      "TFLOPs_alg": v["flops"] / v["ms"] / 1e9 if v["ms"] else None}
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
+    batching = None
+    if args.batching:
+        batching = compare_batching(tt, ix, A, M, R, lam, args.cg, stats, dev)
+
     forms = None
     if args.form_sweeps > 0:
         forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev)
@@ -239,6 +245,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "batching": batching,
         "calls": calls,
         "step_kernels": step_prof,
         "index_build_s": index_s,
@@ -247,6 +254,64 @@ def main():
         "workload_key": wname,
     }
     print(json.dumps(out), flush=True)
+
+
+def compare_batching(tt, ix, A, M, R, lam, cg, stats, dev, reps=3):
+    """The step recorded once as a graph (tt_graph_begin/end) and replayed,
+    against the same calls launched one by one; and the same comparison for
+    one ALS sweep on the 200^3 cube (40,000 nonzeros, R = 10, FP64), where
+    launch overheads dominate.  Milliseconds per step / sweep (HIP events)."""
+    import numpy as np
+    import torch
+    from paper_1910_02371_amd import workloads as W
+
+    def timed_ms(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    info = [torch.empty(d, dtype=torch.int32, device=dev) for d in ix.dims]
+
+    def step():
+        for n in range(3):
+            tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n])
+            tt.solve_factor(ix, None, A, n, M[n], lam, X=A[n], info=info[n])
+        tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=cg, stats=stats)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plain = timed_ms(step, reps)
+        g = tt.capture(step)
+        g.launch()
+        graph = timed_ms(g.launch, reps)
+    torch.cuda.current_stream().wait_stream(side)
+    g.close()
+
+    wl = W.cube()
+    Rc = 10
+    Ac = [torch.as_tensor(a).to(dev) for a in
+          W.init_factors(wl.dims, Rc, float(np.mean(wl.t)), W.SEED_INIT + 1, dtype=np.float64)]
+    ixc = tt.build_index([torch.as_tensor(i).to(dev) for i in wl.idx], wl.dims,
+                         torch.as_tensor(wl.t).to(dev))
+    ixc.reserve(Rc, tt.TT_F64)
+    infoc = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
+    with torch.cuda.stream(side):
+        sweep = lambda: tt.als_sweep(ixc, Ac, 1e-5, infoc)
+        sweep()
+        plain_c = timed_ms(sweep, 20)
+        gc = tt.capture(sweep)
+        gc.launch()
+        graph_c = timed_ms(gc.launch, 20)
+    torch.cuda.current_stream().wait_stream(side)
+    gc.close()
+    return {"ratings_step_ms": {"plain": plain, "graph": graph},
+            "cube_als_sweep_ms": {"plain": plain_c, "graph": graph_c,
+                                  "workload": "200^3, 40,000 nonzeros, R = 10, FP64"}}
 
 
 def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev):
