@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--nnz", type=int, default=100_000_000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 19)
+    p.add_argument("--no-tune", dest="tune", action="store_false",
+                   help="keep the default work partitions (no autotuner)")
     p.add_argument("--no-batching", dest="batching", action="store_false",
                    help="skip the graph-replay vs plain-launch comparison")
     p.add_argument("--form-sweeps", type=int, default=5,
@@ -120,8 +122,16 @@ def main():
     index_s = time.time() - t0
     log(f"index built in {index_s:.2f}s")
     del idx
-    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls")
     A = [torch.as_tensor(a).to(dev).to(fdt_t).contiguous() for a in A0]
+    tuning = None
+    if args.tune:
+        # work-partition autotuner (cached per shape class; outside the timing)
+        from paper_1910_02371_amd import autotune
+        t0 = time.time()
+        tuning = autotune.tune(tt, ix, A, R, lam)
+        tuning["seconds"] = time.time() - t0
+        log(f"tuning {tuning['tuning']} ({'cached' if tuning['from_cache'] else 'measured'})")
+    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls")
     m = wl.nnz
 
     stream = torch.cuda.current_stream()
@@ -246,6 +256,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "batching": batching,
+        "tuning": tuning,
         "calls": calls,
         "step_kernels": step_prof,
         "index_build_s": index_s,

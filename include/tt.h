@@ -120,6 +120,30 @@ tt_status tt_index_destroy(tt_index *ix);
 #define TT_RESERVE_GN_POISSON 2u
 tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
 
+/* ---------------------------------------------------------------------------
+ * Work-partition tuning of an index (the tile selection that an autotuner
+ * varies).  Results do not depend on it beyond floating-point summation
+ * order.
+ *   chunk       nonzeros per streaming work chunk: 512, 1024 or 2048
+ *               (heavier rows are cut into pieces of this size)
+ *   gram_piece  nonzeros per Gram task, 1024 .. 65536 (rows with more are
+ *               split into tasks and their Grams summed in FP64)
+ *   gram_light  Gram tasks with more nonzeros than this run on a workgroup
+ *               of gram_waves waves, the others on one wave; 0 .. gram_piece
+ *   gram_waves  2, 4 or 8
+ * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
+ * is not capturable); call tt_index_reserve again afterwards if the
+ * workspace was reserved.  Defaults: 1024, 4096, 512, 4.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t chunk;
+  int32_t gram_piece;
+  int32_t gram_light;
+  int32_t gram_waves;
+} tt_tuning;
+tt_status tt_index_tune(tt_index *ix, const tt_tuning *tuning, hipStream_t stream);
+tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out);
+
 /* Read-only views of mode `mode` for tests: device pointers to ptr (int64,
  * I_n + 1), perm (int32, m), sorted mode indices (int32, m), nonzero rows
  * (int32, nrows); host count of nonzero rows.  Any output may be NULL. */

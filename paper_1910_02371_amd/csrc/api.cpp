@@ -320,6 +320,8 @@ tt_status tt_index_destroy(tt_index *ix) {
   if (!ix) return TT_OK;
   hipDeviceSynchronize();
   for (void *p : ix->owned) hipFree(p);
+  for (int n = 0; n < ix->N; ++n)
+    for (void *p : ix->mode[n].part) hipFree(p);
   for (auto &kv : ix->ws)
     if (kv.second.p) hipFree(kv.second.p);
   delete ix;
@@ -386,6 +388,29 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags) {
     TT_ST(gn_workspace(ix, R, fdt,
                        (flags & TT_RESERVE_GN_POISSON) ? TT_LOSS_POISSON_LOG : TT_LOSS_LS, &ws));
   }
+  return TT_OK;
+}
+
+tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
+  g_err.clear();
+  TT_CHECK(ix != nullptr && t != nullptr, "NULL argument");
+  TT_CHECK(t->chunk == 512 || t->chunk == 1024 || t->chunk == 2048,
+           "chunk %d is not 512, 1024 or 2048", t->chunk);
+  TT_CHECK(t->gram_piece >= 1024 && t->gram_piece <= 65536, "gram_piece %d outside [1024, 65536]",
+           t->gram_piece);
+  TT_CHECK(t->gram_light >= 0 && t->gram_light <= t->gram_piece,
+           "gram_light %d outside [0, gram_piece]", t->gram_light);
+  TT_CHECK(t->gram_waves == 2 || t->gram_waves == 4 || t->gram_waves == 8,
+           "gram_waves %d is not 2, 4 or 8", t->gram_waves);
+  ix->tune = *t;
+  for (int n = 0; n < ix->N; ++n) TT_ST(build_partitions(ix, n, stream));
+  return TT_OK;
+}
+
+tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out) {
+  g_err.clear();
+  TT_CHECK(ix != nullptr && out != nullptr, "NULL argument");
+  *out = ix->tune;
   return TT_OK;
 }
 

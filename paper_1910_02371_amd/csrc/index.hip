@@ -271,27 +271,101 @@ static tt_status dev_alloc(tt_index *ix, X **p, size_t count) {
   return TT_OK;
 }
 
-template <class X>
-static tt_status upload(tt_index *ix, X **p, const std::vector<X> &h, hipStream_t s) {
-  tt_status st = dev_alloc(ix, p, h.size());
-  if (st != TT_OK) return st;
-  if (!h.empty())
-    TT_HIP(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s));
-  return TT_OK;
-}
-
 #define TT_ST(x)                          \
   do {                                    \
     tt_status _s = (x);                   \
     if (_s != TT_OK) return _s;           \
   } while (0)
 
+// Device copy of a host vector, recorded in `list` (freed by the caller).
+template <class X>
+static tt_status upload(std::vector<void *> &list, X **p, const std::vector<X> &h,
+                        hipStream_t s) {
+  const size_t n = std::max<size_t>(h.size(), 1);
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(X));
+  if (e != hipSuccess) {
+    set_error("hipMalloc of %zu bytes failed: %s", n * sizeof(X), hipGetErrorString(e));
+    return TT_ERR_OOM;
+  }
+  list.push_back(q);
+  *p = (X *)q;
+  if (!h.empty())
+    TT_HIP(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s));
+  return TT_OK;
+}
+
+static void partitions(const std::vector<int64_t> &ptr, ModeIndex &md, int64_t kChunk,
+                       int64_t kGramPiece, std::vector<int64_t> &chunk,
+                       std::vector<int32_t> &slot, std::vector<int32_t> &heavy_row,
+                       std::vector<int32_t> &heavy_slot, std::vector<int32_t> &rows,
+                       std::vector<int64_t> &task, std::vector<int32_t> &row_task);
+
+// (Re)build the streaming chunks, carry segments, Gram tasks and their
+// heavy/multi-task lists of mode n from its host row pointers and the
+// index's tuning; frees the previous partition arrays first.
+tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
+  ModeIndex &md = ix->mode[n];
+  hipError_t he;
+  if (!md.part.empty()) {
+    TT_HIP(hipStreamSynchronize(s));
+    for (void *q : md.part) hipFree(q);
+    md.part.clear();
+  }
+  std::vector<int64_t> chunk, task;
+  std::vector<int32_t> slot, hrow, hslot, rows, row_task;
+  partitions(md.h_ptr, md, ix->tune.chunk, ix->tune.gram_piece, chunk, slot, hrow, hslot, rows,
+             task, row_task);
+  std::vector<void *> &L = md.part;
+  TT_ST(upload(L, &md.d_chunk, chunk, s));
+  TT_ST(upload(L, &md.d_chunk_slot, slot, s));
+  TT_ST(upload(L, &md.d_heavy_row, hrow, s));
+  TT_ST(upload(L, &md.d_heavy_slot, hslot, s));
+  // carry segments: each heavy row's slots split into runs of kSegSlots
+  std::vector<int32_t> seg(1, 0), hseg(1, 0);
+  for (size_t h = 0; h + 1 < hslot.size(); ++h) {
+    for (int32_t a = hslot[h]; a < hslot[h + 1]; a += kSegSlots)
+      seg.push_back(std::min<int32_t>(hslot[h + 1], a + kSegSlots));
+    hseg.push_back((int32_t)seg.size() - 1);
+  }
+  md.nseg = (int64_t)seg.size() - 1;
+  TT_ST(upload(L, &md.d_seg, seg, s));
+  TT_ST(upload(L, &md.d_heavy_seg, hseg, s));
+  TT_ST(upload(L, &md.d_rows, rows, s));
+  TT_ST(upload(L, &md.d_task, task, s));
+  TT_ST(upload(L, &md.d_row_task, row_task, s));
+  md.h_row_task = row_task;
+  md.h_heavy_task.clear();
+  md.h_heavy_nnz.assign(1, 0);
+  for (int64_t q = 0; q + 1 < (int64_t)task.size(); ++q)
+    if (task[q + 1] - task[q] > ix->tune.gram_light) {
+      md.h_heavy_task.push_back((int32_t)q);
+      md.h_heavy_nnz.push_back(md.h_heavy_nnz.back() + task[q + 1] - task[q]);
+    }
+  md.h_task = task;
+  md.h_multi_row.clear();
+  for (int64_t i = 0; i < md.I; ++i)
+    if (row_task[i + 1] - row_task[i] > kReduceMin) md.h_multi_row.push_back((int32_t)i);
+  TT_ST(upload(L, &md.d_heavy_task, md.h_heavy_task, s));
+  TT_ST(upload(L, &md.d_multi_row, md.h_multi_row, s));
+  // uploads are asynchronous from pageable vectors: wait before they go
+  if ((he = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(he, "upload");
+  ix->max_nchunk = ix->max_nslot = ix->max_nseg = 0;
+  for (int d = 0; d < ix->N; ++d) {
+    ix->max_nchunk = std::max(ix->max_nchunk, ix->mode[d].nchunk);
+    ix->max_nslot = std::max(ix->max_nslot, ix->mode[d].nslot);
+    ix->max_nseg = std::max(ix->max_nseg, ix->mode[d].nseg);
+  }
+  return TT_OK;
+}
+
+
 // Host-side partitions from the row pointers of one mode.
-static void partitions(const std::vector<int64_t> &ptr, ModeIndex &md,
-                       std::vector<int64_t> &chunk, std::vector<int32_t> &slot,
-                       std::vector<int32_t> &heavy_row, std::vector<int32_t> &heavy_slot,
-                       std::vector<int32_t> &rows, std::vector<int64_t> &task,
-                       std::vector<int32_t> &row_task) {
+static void partitions(const std::vector<int64_t> &ptr, ModeIndex &md, int64_t kChunk,
+                       int64_t kGramPiece, std::vector<int64_t> &chunk,
+                       std::vector<int32_t> &slot, std::vector<int32_t> &heavy_row,
+                       std::vector<int32_t> &heavy_slot, std::vector<int32_t> &rows,
+                       std::vector<int64_t> &task, std::vector<int32_t> &row_task) {
   const int64_t I = md.I;
   chunk.clear(); slot.clear(); heavy_row.clear(); heavy_slot.clear();
   rows.clear(); task.clear(); row_task.assign(I + 1, 0);
@@ -470,50 +544,10 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
       st = TT_ERR_HIP;
       break;
     }
-    std::vector<int64_t> chunk, task;
-    std::vector<int32_t> slot, hrow, hslot, rows, row_task;
-    partitions(h_ptr, md, chunk, slot, hrow, hslot, rows, task, row_task);
-    if ((st = upload(ix, &md.d_chunk, chunk, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_chunk_slot, slot, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_heavy_row, hrow, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_heavy_slot, hslot, s)) != TT_OK) break;
-    {
-      // carry segments: each heavy row's slots split into runs of kSegSlots
-      std::vector<int32_t> seg(1, 0), hseg(1, 0);
-      for (size_t h = 0; h + 1 < hslot.size(); ++h) {
-        for (int32_t a = hslot[h]; a < hslot[h + 1]; a += kSegSlots)
-          seg.push_back(std::min<int32_t>(hslot[h + 1], a + kSegSlots));
-        hseg.push_back((int32_t)seg.size() - 1);
-      }
-      md.nseg = (int64_t)seg.size() - 1;
-      if ((st = upload(ix, &md.d_seg, seg, s)) != TT_OK) break;
-      if ((st = upload(ix, &md.d_heavy_seg, hseg, s)) != TT_OK) break;
-      if ((he = hipStreamSynchronize(s)) != hipSuccess) { st = hip_fail(he, "upload"); break; }
-    }
-    if ((st = upload(ix, &md.d_rows, rows, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_task, task, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_row_task, row_task, s)) != TT_OK) break;
-    md.h_row_task = row_task;
-    md.h_heavy_task.clear();
-    md.h_heavy_nnz.assign(1, 0);
-    for (int64_t q = 0; q + 1 < (int64_t)task.size(); ++q)
-      if (task[q + 1] - task[q] > kGramLight) {
-        md.h_heavy_task.push_back((int32_t)q);
-        md.h_heavy_nnz.push_back(md.h_heavy_nnz.back() + task[q + 1] - task[q]);
-      }
-    md.h_task = task;
-    md.h_multi_row.clear();
-    for (int64_t i = 0; i < dims[n]; ++i)
-      if (row_task[i + 1] - row_task[i] > kReduceMin) md.h_multi_row.push_back((int32_t)i);
-    if ((st = upload(ix, &md.d_heavy_task, md.h_heavy_task, s)) != TT_OK) break;
-    if ((st = upload(ix, &md.d_multi_row, md.h_multi_row, s)) != TT_OK) break;
-    // uploads are asynchronous from pageable vectors: wait before reuse
-    if ((he = hipStreamSynchronize(s)) != hipSuccess) { st = hip_fail(he, "upload"); break; }
+    md.h_ptr = h_ptr;
+    if ((st = build_partitions(ix, n, s)) != TT_OK) break;
     ix->max_I = std::max(ix->max_I, md.I);
     ix->sum_I += md.I;
-    ix->max_nchunk = std::max(ix->max_nchunk, md.nchunk);
-    ix->max_nslot = std::max(ix->max_nslot, md.nslot);
-    ix->max_nseg = std::max(ix->max_nseg, md.nseg);
   }
   hipStreamSynchronize(s);
   free_tmp();

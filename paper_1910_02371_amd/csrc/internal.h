@@ -12,19 +12,14 @@
 
 namespace tt {
 
-// Work partition constants.
-#ifndef TT_CHUNK
-#define TT_CHUNK 1024
-#endif
-constexpr int kChunk = TT_CHUNK;   // nnz per streaming work chunk (max)
-#ifndef TT_GRAM_PIECE
-#define TT_GRAM_PIECE 4096
-#endif
-#ifndef TT_GRAM_LIGHT
-#define TT_GRAM_LIGHT 512
-#endif
-constexpr int kGramPiece = TT_GRAM_PIECE;  // nnz per Gram task (max)
-constexpr int kGramLight = TT_GRAM_LIGHT;  // tasks above this run on a whole workgroup
+// Work partition constants.  The streaming chunk size, the Gram task size,
+// the light/heavy Gram threshold and the heavy-task workgroup width are
+// per-index tuning parameters (tt_index_tune); these are their defaults and
+// the supported streaming chunk sizes.
+constexpr int kChunkDefault = 1024;
+constexpr int kGramPieceDefault = 4096;
+constexpr int kGramLightDefault = 512;
+constexpr int kGramWavesDefault = 4;
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
@@ -35,6 +30,8 @@ __host__ __device__ constexpr int gram_task_elems(int RP) { return 128 * (RP / 1
 
 struct ModeIndex {
   int64_t I = 0;
+  std::vector<int64_t> h_ptr;   // host copy of the row pointers (partitions)
+  std::vector<void *> part;     // device arrays of the current partitions
   int64_t nrows = 0;            // rows holding >= 1 nonzero
   int64_t *d_ptr = nullptr;     // I + 1 offsets into the sorted stream
   int32_t *d_perm = nullptr;    // sorted position -> COO position
@@ -42,8 +39,8 @@ struct ModeIndex {
   int32_t *d_oidx[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
   void *d_t = nullptr;          // observed values in this mode's order
   int32_t *d_rows = nullptr;    // nonzero rows
-  // streaming partition: chunks of whole light rows (<= kChunk nnz) and
-  // single pieces of heavy rows (> kChunk nnz)
+  // streaming partition: chunks of whole light rows (<= chunk nnz) and
+  // single pieces of heavy rows (> chunk nnz)
   int64_t nchunk = 0;
   int64_t *d_chunk = nullptr;       // nchunk + 1 boundaries
   int32_t *d_chunk_slot = nullptr;  // -1: light chunk; else carry slot
@@ -54,7 +51,7 @@ struct ModeIndex {
   int64_t nseg = 0;                 // carry segments (<= kSegSlots slots each)
   int32_t *d_seg = nullptr;         // nseg + 1 slot boundaries
   int32_t *d_heavy_seg = nullptr;   // nheavy + 1 segment ranges
-  // Gram tasks: pieces of <= kGramPiece nnz of one row
+  // Gram tasks: pieces of <= gram_piece nnz of one row
   int64_t ntask = 0;
   int64_t *d_task = nullptr;        // ntask + 1 boundaries
   int32_t *d_row_task = nullptr;    // I + 1: tasks of row i
@@ -62,7 +59,7 @@ struct ModeIndex {
   std::vector<int64_t> h_task;      // host copy of task boundaries
   std::vector<int64_t> h_heavy_nnz; // prefix sums of heavy-task sizes
   int32_t max_task_per_row = 0;
-  int32_t *d_heavy_task = nullptr;  // tasks with > kGramLight nonzeros
+  int32_t *d_heavy_task = nullptr;  // tasks with > gram_light nonzeros
   std::vector<int32_t> h_heavy_task;
   int32_t *d_multi_row = nullptr;   // rows with > kReduceMin tasks
   std::vector<int32_t> h_multi_row;
@@ -86,9 +83,14 @@ struct tt_index {
   std::vector<void *> owned;                 // device allocations to free
   std::map<std::string, tt::Buf> ws;         // named workspace buffers
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
+  tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
+                    tt::kGramWavesDefault};
 };
 
 namespace tt {
+
+// ----- index partitions (index.hip) ------------------------------------------
+tt_status build_partitions(tt_index *ix, int n, hipStream_t s);
 
 // ----- error handling ------------------------------------------------------
 void set_error(const char *fmt, ...);

@@ -4,7 +4,7 @@
 // an FP64 Cholesky factorization and two triangular solves (the SPD solve of
 // Section 3.4; the normal equations of Section 2.2).
 //
-// Gram: one wave per task (a piece of <= kGramPiece nonzeros of one row).
+// Gram: one wave per task (a piece of <= gram_piece nonzeros of one row).
 // With H the task's rows h_e stacked, G = H^T diag(w) H is a K x R by K x R
 // contraction over the nonzeros, mapped onto MFMA with the nonzero index as
 // the reduction dimension: A-operand = h (R on the M index), B-operand = w h.
@@ -54,7 +54,9 @@ struct GramDev {
   const int32_t *w_perm;
   double w_scale;
   void *G;                    // workspace: (task - task_base) * gram_task_elems(RP)
-  int split_heavy;            // light kernel skips tasks > kGramLight
+  int split_heavy;            // light kernel skips tasks > light
+  int light;                  // light/heavy task threshold (nonzeros)
+  int waves;                  // waves of a heavy-task workgroup (2, 4, 8)
 };
 
 // Slot of the lower element (r, c), r >= c, in the lower-tile layout.
@@ -110,9 +112,6 @@ struct GramAcc {
   __device__ void set(int v, float x) { c[v / 4][v % 4] = x; }
 };
 
-#ifndef TT_GRAM_HEAVY_WAVES
-#define TT_GRAM_HEAVY_WAVES 4 // waves of the workgroup that takes a heavy task
-#endif
 
 // VW consecutive factor entries starting at element `off`, widened to FP32.
 // VEC: one aligned vector load (the caller guarantees alignment and that
@@ -348,13 +347,13 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, flo
 }
 
 // Light tasks: one wave per task, four tasks per workgroup; tasks with more
-// than kGramLight nonzeros are left to k_gram_f32_heavy.
+// than d.light nonzeros are left to k_gram_f32_heavy.
 template <class TR, int RP, bool VEC, bool WEIGHTED>
 __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= d.task_end) return;
   const int64_t nb = d.task[t], ne = d.task[t + 1];
-  if (d.split_heavy && ne - nb > kGramLight) return;
+  if (d.split_heavy && ne - nb > d.light) return;
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP, VEC, WEIGHTED>(d, nb, ne, acc);
@@ -364,11 +363,10 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
-template <class TR, int RP, bool VEC, bool WEIGHTED>
-__global__ __launch_bounds__(64 * TT_GRAM_HEAVY_WAVES) void k_gram_f32_heavy(
+template <class TR, int RP, bool VEC, bool WEIGHTED, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
-  constexpr int NW = TT_GRAM_HEAVY_WAVES;
   __shared__ float buf[NV * 64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t = heavy[blockIdx.x];
@@ -794,8 +792,12 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   }
   if (nheavy > 0) {
     ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
-    k_gram_f32_heavy<TR, RP, VEC, WEIGHTED>
-        <<<dim3((unsigned)nheavy), dim3(64 * TT_GRAM_HEAVY_WAVES), 0, s>>>(d, heavy, nheavy);
+    const dim3 g((unsigned)nheavy);
+    switch (d.waves) {
+      case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 2><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
+      case 8: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 8><<<g, dim3(512), 0, s>>>(d, heavy, nheavy); break;
+      default: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 4><<<g, dim3(256), 0, s>>>(d, heavy, nheavy); break;
+    }
   }
 }
 
@@ -913,6 +915,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.w_scale = c.w_scale;
   gd.G = Gws;
   gd.split_heavy = 1;
+  gd.light = ix->tune.gram_light;
+  gd.waves = ix->tune.gram_waves;
 
   SolveDev sd;
   sd.row_task = md.d_row_task;

@@ -10,11 +10,11 @@
 namespace tt {
 
 hipError_t launch_stream_f32(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                             bool vec, hipStream_t s);
+                             bool vec, int chunk, hipStream_t s);
 hipError_t launch_stream_bf16(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                              bool vec, hipStream_t s);
+                              bool vec, int chunk, hipStream_t s);
 hipError_t launch_stream_f64(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                             bool vec, hipStream_t s);
+                             bool vec, int chunk, hipStream_t s);
 
 static int frag_elems(tt_dtype fdt) { return fdt == TT_F64 ? 2 : 4; }
 
@@ -97,11 +97,11 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
     }
     ProfScope ps(name, s, bytes, flops);
     if (c.fdt == TT_F32)
-      e = launch_stream_f32(op, d, md.nchunk, G, vec, s);
+      e = launch_stream_f32(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
     else if (c.fdt == TT_BF16)
-      e = launch_stream_bf16(op, d, md.nchunk, G, vec, s);
+      e = launch_stream_bf16(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
     else
-      e = launch_stream_f64(op, d, md.nchunk, G, vec, s);
+      e = launch_stream_f64(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
   }
   if (e != hipSuccess) return e;
   if (op != OP_TTTP && md.nheavy > 0) {

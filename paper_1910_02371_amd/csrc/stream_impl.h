@@ -3,7 +3,7 @@
 // stream_f64.hip).
 //
 // One workgroup (256 threads) takes one chunk of the partition built with
-// the index: either whole rows totalling <= kChunk nonzeros, or one piece of
+// the index: either whole rows totalling <= CHUNK nonzeros, or one piece of
 // a heavy row.  The chunk's sorted mode indices, other-mode indices and
 // per-nonzero values are staged into LDS with coalesced loads.  The chunk is
 // split into NG = 256 / G contiguous sub-ranges, one per group of G lanes;
@@ -59,15 +59,15 @@ struct StreamDev {
   const double *skip;       // when set and *skip != 0 the launch is a no-op
 };
 
-template <class TR, int G>
+template <class TR, int G, int CHUNK>
 struct StreamSmem {
   using VT = typename TR::VT;
   using AT = typename TR::AT;
   static constexpr int NG = ST_THREADS / G;
   static constexpr int RP = G * TR::V;
-  int32_t key[kChunk + 2];
-  int32_t oi[2][kChunk];
-  VT val[kChunk];
+  int32_t key[CHUNK + 2];
+  int32_t oi[2][CHUNK];
+  VT val[CHUNK];
   union {
     struct {
       AT piece[NG][2][RP];
@@ -75,7 +75,7 @@ struct StreamSmem {
       int32_t pfl[NG][2];
     } seg;
     struct {
-      VT out[kChunk];
+      VT out[CHUNK];
       double part[ST_THREADS / 64];
     } tttp;
   } u;
@@ -125,7 +125,7 @@ __device__ __forceinline__ typename TR::VT load_value(const StreamDev &a, int64_
   return reinterpret_cast<const VT *>(a.s)[q];
 }
 
-template <class TR, int N, int G, bool VEC, int OP>
+template <class TR, int N, int G, bool VEC, int OP, int CHUNK>
 __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   using T = typename TR::T;
   using VT = typename TR::VT;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   constexpr int NO = N - 1;
   constexpr int NG = ST_THREADS / G;
   static_assert(NO <= 2, "order 3 streams");
-  __shared__ StreamSmem<TR, G> sm;
+  __shared__ StreamSmem<TR, G, CHUNK> sm;
   if (a.skip && *a.skip != 0.0) return;
 
   const int tid = threadIdx.x;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   const int64_t b = a.chunk[k];
   const int len = (int)(a.chunk[k + 1] - b);
   const int slot = a.chunk_slot[k];
-  if (len <= 0 || len > kChunk) return;  // partition invariant: 0 < len <= kChunk
+  if (len <= 0 || len > CHUNK) return;  // partition invariant: 0 < len <= CHUNK
   const bool use_val = (OP == OP_TTTP) ? (a.s != nullptr) : true;
 
   // ---- stage the chunk into LDS (coalesced) ------------------------------
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
       bool active = false;
       auto finalize = [&]() {
         if (slot >= 0) {
-          double *cs = a.carry + (int64_t)slot * StreamSmem<TR, G>::RP + c0;
+          double *cs = a.carry + (int64_t)slot * StreamSmem<TR, G, CHUNK>::RP + c0;
 #pragma unroll
           for (int j = 0; j < V; ++j) cs[j] = (double)run[j];
         } else {
@@ -441,25 +441,32 @@ __global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__
   }
 }
 
-template <class TR, int N, int G, bool VEC>
+template <class TR, int N, int G, bool VEC, int CHUNK>
 hipError_t launch_stream_t(StreamOp op, const StreamDev &d, int64_t nchunk,
                            hipStream_t s) {
   if (nchunk <= 0) return hipSuccess;
   dim3 grid((unsigned)nchunk), block(ST_THREADS);
   switch (op) {
-    case OP_TTTP: k_stream<TR, N, G, VEC, OP_TTTP><<<grid, block, 0, s>>>(d); break;
-    case OP_MTTKRP: k_stream<TR, N, G, VEC, OP_MTTKRP><<<grid, block, 0, s>>>(d); break;
-    case OP_GRAD: k_stream<TR, N, G, VEC, OP_GRAD><<<grid, block, 0, s>>>(d); break;
-    case OP_GN: k_stream<TR, N, G, VEC, OP_GN><<<grid, block, 0, s>>>(d); break;
+    case OP_TTTP: k_stream<TR, N, G, VEC, OP_TTTP, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_MTTKRP: k_stream<TR, N, G, VEC, OP_MTTKRP, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_GRAD: k_stream<TR, N, G, VEC, OP_GRAD, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_GN: k_stream<TR, N, G, VEC, OP_GN, CHUNK><<<grid, block, 0, s>>>(d); break;
   }
   return hipGetLastError();
 }
 
+// The vector path has one instantiation per supported chunk size (the LDS
+// footprint sets the occupancy); the element path, for unaligned ranks, uses
+// the largest, which serves every chunk size.
 template <class TR, int G>
 hipError_t launch_stream_g(StreamOp op, const StreamDev &d, int64_t nchunk, bool vec,
-                           hipStream_t s) {
-  return vec ? launch_stream_t<TR, 3, G, true>(op, d, nchunk, s)
-             : launch_stream_t<TR, 3, G, false>(op, d, nchunk, s);
+                           int chunk, hipStream_t s) {
+  if (!vec) return launch_stream_t<TR, 3, G, false, 2048>(op, d, nchunk, s);
+  switch (chunk) {
+    case 512: return launch_stream_t<TR, 3, G, true, 512>(op, d, nchunk, s);
+    case 1024: return launch_stream_t<TR, 3, G, true, 1024>(op, d, nchunk, s);
+    default: return launch_stream_t<TR, 3, G, true, 2048>(op, d, nchunk, s);
+  }
 }
 
 }  // namespace tt

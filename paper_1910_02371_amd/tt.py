@@ -39,6 +39,8 @@ SIGNATURES = {
                             ctypes.POINTER(_P)]),
     "tt_index_destroy": (_I, [_P]),
     "tt_index_reserve": (_I, [_P, _I, _I, _U32]),
+    "tt_index_tune": (_I, [_P, _P, _P]),
+    "tt_index_get_tuning": (_I, [_P, _P]),
     "tt_index_view": (_I, [_P, _I, ctypes.POINTER(_P), ctypes.POINTER(_P),
                            ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_I64)]),
     "tt_index_other": (_I, [_P, _I, _I, ctypes.POINTER(_P)]),
@@ -61,6 +63,15 @@ SIGNATURES = {
 }
 
 _lib = None
+
+
+class Tuning(ctypes.Structure):
+    """tt_tuning: the work-partition parameters of an index."""
+    _fields_ = [("chunk", ctypes.c_int32), ("gram_piece", ctypes.c_int32),
+                ("gram_light", ctypes.c_int32), ("gram_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class TTError(RuntimeError):
@@ -161,6 +172,23 @@ class Index:
             self.close()
         except Exception:
             pass
+
+    def tuning(self):
+        t = Tuning()
+        _check(lib().tt_index_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tune(self, **kw):
+        """Set work-partition parameters (chunk, gram_piece, gram_light,
+        gram_waves; unspecified ones keep their value) and rebuild the
+        partitions; reserve the workspace again afterwards."""
+        cur = self.tuning()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning parameters {sorted(unknown)}")
+        cur.update(kw)
+        t = Tuning(**cur)
+        _check(lib().tt_index_tune(self._h, ctypes.byref(t), _stream()))
 
     def reserve(self, R, fdt, gn=None):
         """Size the workspace (needed before graph capture); gn = "ls" or

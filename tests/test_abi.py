@@ -65,3 +65,12 @@ def test_host_argument_checks(lib):
     assert L.tt_build_index(3, dims, 0, arr, None, 7, 0, None, ctypes.byref(out)) == -1
     assert L.tt_index_destroy(None) == 0
     assert L.tt_version().startswith(b"libtt")
+    # tuning and graph entry points validate on the host
+    t = tt.Tuning(1024, 4096, 512, 4)
+    assert L.tt_index_tune(None, ctypes.byref(t), None) == -1
+    assert L.tt_index_get_tuning(None, ctypes.byref(t)) == -1
+    assert L.tt_graph_begin(None) == -1
+    assert b"stream" in L.tt_last_error()
+    assert L.tt_graph_launch(None, None) == -1
+    assert L.tt_graph_destroy(None) == 0
+    assert L.tt_index_reserve(None, 8, 1, 0) == -1

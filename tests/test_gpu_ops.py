@@ -379,3 +379,57 @@ def test_gn_matvec_parity(gpu_lib, form, weights, kind):
         ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
             lam2 * np.abs(X64[d])
         assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn mode {d}")
+
+
+# --------------------------------------------------------------- tuning ----
+TUNINGS = [
+    dict(chunk=512, gram_piece=2048, gram_light=256, gram_waves=2),
+    dict(chunk=2048, gram_piece=8192, gram_light=1024, gram_waves=8),
+    dict(chunk=1024, gram_piece=1024, gram_light=0, gram_waves=4),
+]
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("kind", ["heavy", "zipf"])
+def test_tuning_parity(gpu_lib, form, kind):
+    """Every work-partition setting (chunk sizes, Gram task sizes, light and
+    heavy thresholds, heavy workgroup widths) gives results within the same
+    tolerances of the oracle: MTTKRP, TTTP sum, gradient, GN matvec and
+    Solve Factor, at aligned and unaligned ranks."""
+    tt = gpu_lib
+    wl = make_case(kind)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(wl.t, form))
+    s = stored_values(wl.t, form)
+    rng = np.random.default_rng(17)
+    for tune in TUNINGS:
+        ix.tune(**tune)
+        assert ix.tuning() == tune
+        for R in (64, 21):
+            A64 = factors(wl.dims, R, 500 + R)
+            As = stored_factors(A64, form)
+            A = [dev_factor(a, form) for a in A64]
+            for n in range(3):
+                Y = host(tt.mttkrp(ix, tt.INDEX_T, A, n))
+                ref = O.mttkrp(wl.idx, s, As, n, wl.dims[n])
+                ref_abs = O.mttkrp(wl.idx, np.abs(s), [np.abs(a) for a in As], n, wl.dims[n])
+                assert_close_abs(Y, ref, ref_abs, TAU[form], f"{tune} mttkrp R={R} mode {n}")
+            _, tot = tt.tttp(ix, None, A, out=False, want_sum=True)
+            m = O.tttp(wl.idx, None, As)
+            m_abs = O.tttp(wl.idx, None, [np.abs(a) for a in As])
+            assert abs(tot.item() - m.sum()) <= TAU[form] * m_abs.sum() + 1e-12
+            X64 = [stored_values(rng.standard_normal((d, R)), form) for d in wl.dims]
+            Yg = host(tt.gn_matvec(ix, None, A, [dev_vals(x, form) for x in X64], 0.1,
+                                   w_const=2.0))
+            refg = O.gn_matvec(wl.idx, np.full(wl.nnz, 2.0), As, X64, 0.1, wl.dims)
+            z_abs = O.jvp(wl.idx, [np.abs(a) for a in As], [np.abs(x) for x in X64])
+            for d in range(3):
+                ra = O.mttkrp(wl.idx, 2.0 * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
+                    0.1 * np.abs(X64[d])
+                assert_close_abs(Yg[d], refg[d], ra, 4 * TAU[form], f"{tune} gn R={R} mode {d}")
+            for n in range(3):
+                M = stored_values(rng.standard_normal((wl.dims[n], R)), form)
+                X, info = tt.solve_factor(ix, None, A, n, dev_vals(M, form), 0.05)
+                assert (info.cpu().numpy() == 0).all()
+                G = O.gram(wl.idx, None, As, n, wl.dims[n])
+                be = backward_error(G, 0.05, host(X), M)
+                assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"{tune} solve R={R} mode {n}"
