@@ -40,10 +40,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--R", type=int, default=64)
+    p.add_argument("--workload", choices=["ratings", "uniform"], default="ratings",
+                   help="ratings: 100M-nonzero Zipf ratings tensor, ALS sweep + GN step; "
+                        "uniform: 1.5B-nonzero 2^20-cubed tensor, TTTP + ALS sweep")
+    p.add_argument("--R", type=int, default=None, help="rank (64 ratings, 32 uniform)")
     p.add_argument("--form", choices=["f32", "bf16"], default="f32")
     p.add_argument("--cg", type=int, default=2, help="CG iterations in the GN step")
-    p.add_argument("--nnz", type=int, default=100_000_000)
+    p.add_argument("--nnz", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1 << 19)
     p.add_argument("--no-tune", dest="tune", action="store_false",
@@ -106,10 +109,14 @@ def main():
         torch.cuda.synchronize()
         del xa, xb
     t0 = time.time()
-    wl = W.ratings(m=args.nnz)
+    ratings = args.workload == "ratings"
+    if ratings:
+        wl = W.ratings(m=args.nnz or 100_000_000)
+    else:
+        wl = W.uniform(m=args.nnz or 1_500_000_000)
     gen_s = time.time() - t0
     log(f"generated {wl.name}: {wl.nnz} nnz in {gen_s:.1f}s")
-    R = args.R
+    R = args.R or (64 if ratings else 32)
     lam = 1e-5
     fdt_t = torch.float32 if args.form == "f32" else torch.bfloat16
     idx = [torch.as_tensor(i).to(dev) for i in wl.idx]
@@ -121,7 +128,7 @@ def main():
     torch.cuda.synchronize()
     index_s = time.time() - t0
     log(f"index built in {index_s:.2f}s")
-    del idx
+    del idx, t  # the index holds its own sorted copies
     A = [torch.as_tensor(a).to(dev).to(fdt_t).contiguous() for a in A0]
     tuning = None
     if args.tune:
@@ -152,13 +159,18 @@ def main():
     M = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
 
+    out_m = None if ratings else torch.empty(m, dtype=torch.float32, device=dev)
+
     def step(record):
         run = timed if record else (lambda n, f: f())
+        if not ratings:
+            run("tttp", lambda: tt.tttp(ix, None, A, out=out_m))
         for n in range(3):
             run(f"mttkrp{n}", lambda n=n: tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n]))
             run(f"solve{n}", lambda n=n: tt.solve_factor(ix, None, A, n, M[n], lam, X=A[n]))
-        run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
-                                          stats=stats))
+        if ratings:
+            run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
+                                              stats=stats))
 
     for _ in range(args.warmup):
         step(False)
@@ -179,8 +191,9 @@ def main():
     avg = {k: float(np.mean(v)) for k, v in per.items()}
 
     # nonzero passes of one step: ALS 3 MTTKRP + 3 Gram; GN step 1 TTTP +
-    # 3 gradient + 3 Gram (preconditioner) + 3 GN-matvec per CG iteration
-    passes = 6 + 1 + 3 + 3 + 3 * args.cg
+    # 3 gradient + 3 Gram (preconditioner) + 3 GN-matvec per CG iteration;
+    # the uniform workload: 1 TTTP + ALS
+    passes = (6 + 1 + 3 + 3 + 3 * args.cg) if ratings else 7
     value = m * R * passes / (ms_per_step / 1000.0)
 
     # C-ABI calls of the step (HIP events on the launch stream)
@@ -193,7 +206,8 @@ def main():
     n_l = rec["launches"]
     per_ms = rec["ms"] / n_l
     src_hash = kernel_source_hash()
-    wname = f"ratings{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}_m{m}_R{R}_{args.form}"
+    wname = (f"{'ratings' if ratings else 'uniform'}{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}"
+             f"_m{m}_R{R}_{args.form}")
     traffic = traffic_from_profile(dom, wname, src_hash)
     if dom.startswith("gram"):
         achieved = rec["flops"] / n_l / (per_ms / 1e3) / 1e12
@@ -209,9 +223,12 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "traffic": traffic, "alg_bytes_per_launch": rec["bytes"] / n_l,
                     "launch_ms": per_ms, "launches": n_l}
-        # algorithmic bytes count every factor-row gather; above the HBM peak
-        # the rate is an effective one (gathers served by L2 / Infinity Cache)
-        roofline["effective"] = achieved > HBM_PEAK_GBS
+        # algorithmic bytes count every factor-row gather; when most of them
+        # are served by L2 / Infinity Cache (measured HBM traffic below half
+        # the algorithmic bytes, or a rate above the HBM peak) the rate is an
+        # effective one
+        roofline["effective"] = achieved > HBM_PEAK_GBS or (
+            traffic is not None and traffic < 0.5 * rec["bytes"] / n_l)
     if traffic is not None:
         roofline["hbm_frac_measured"] = traffic / (per_ms / 1e3) / 1e9 / HBM_PEAK_GBS
     step_prof = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step":
@@ -221,7 +238,7 @@ def main():
                  for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
     batching = None
-    if args.batching:
+    if args.batching and ratings:
         batching = compare_batching(tt, ix, A, M, R, lam, args.cg, stats, dev)
 
     forms = None
@@ -230,7 +247,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, A0, R, lam, args.cpu_sample, passes)
+        cpu = cpu_baseline(wl, A0, R, lam, args.cpu_sample, passes, gn=ratings)
 
     out = {
         "metric": METRIC,
@@ -246,10 +263,15 @@ def main():
         "dtype": args.form,
         "data": "synthetic",
         "config": {
-            "workload": f"ratings-shaped {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, "
-                        f"{m} distinct nonzeros, Zipf(1.1) mode degrees, values 1..5",
+            "workload": (f"ratings-shaped {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, "
+                         f"{m} distinct nonzeros, Zipf(1.1) mode degrees, values 1..5"
+                         if ratings else
+                         f"uniform {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, {m} nonzeros, "
+                         f"planted rank 10 + N(0, 0.01^2)"),
+            "step": ("ALS sweep (3 x [MTTKRP + Solve Factor]) + Gauss-Newton step"
+                     if ratings else "TTTP + ALS sweep (3 x [MTTKRP + Solve Factor])"),
             "R": R, "factor_storage": args.form, "lambda": lam, "loss": "least squares",
-            "cg_iterations": args.cg, "nnz_passes_per_step": passes,
+            "cg_iterations": args.cg if ratings else None, "nnz_passes_per_step": passes,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
@@ -354,7 +376,7 @@ def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev):
     return out
 
 
-def cpu_baseline(wl, A0, R, lam, sample, passes):
+def cpu_baseline(wl, A0, R, lam, sample, passes, gn=True):
     """The FP64 oracle, as it stands, on a bounded sample: the first `sample`
     nonzeros (COO order is draw order, i.e. random) of the same tensor, full
     dimensions, same step composition (ALS sweep over the sampled rows, then
@@ -373,6 +395,8 @@ def cpu_baseline(wl, A0, R, lam, sample, passes):
     t0 = time.time()
     try:
         ixs = O.build_index(idx, wl.dims)
+        if not gn:
+            O.tttp(idx, None, A)
         for n in range(3):
             Mn = O.mttkrp(idx, t, A, n, wl.dims[n])
             rows = ixs[n]["rows"]
@@ -380,13 +404,14 @@ def cpu_baseline(wl, A0, R, lam, sample, passes):
             X, _ = O.solve_rows(G, Mn[rows], lam)
             A[n] = A[n].copy()
             A[n][rows] = X
-        O.objective(idx, t, A, O.LOSS_LS, lam)
-        g = O.gradient(idx, t, A, O.LOSS_LS, lam, wl.dims)
-        for n in range(3):
-            O.gram(idx, np.full(sample, 2.0), A, n, wl.dims[n], rows=ixs[n]["rows"])
-        w = np.full(sample, 2.0)
-        for _ in range((passes - 13) // 3):
-            O.gn_matvec(idx, w, A, g, 2 * lam, wl.dims)
+        if gn:
+            O.objective(idx, t, A, O.LOSS_LS, lam)
+            g = O.gradient(idx, t, A, O.LOSS_LS, lam, wl.dims)
+            for n in range(3):
+                O.gram(idx, np.full(sample, 2.0), A, n, wl.dims[n], rows=ixs[n]["rows"])
+            w = np.full(sample, 2.0)
+            for _ in range((passes - 13) // 3):
+                O.gn_matvec(idx, w, A, g, 2 * lam, wl.dims)
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)

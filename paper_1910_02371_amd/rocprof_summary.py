@@ -31,8 +31,11 @@ STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3}
 
 def matches(kernel, name):
     if kernel in STREAM_OP:
-        return "k_stream<" in name and name.rstrip(")").split("(")[0].endswith(
-            f", {STREAM_OP[kernel]}>")
+        # k_stream<traits, order, G, vec, op, chunk>: the op is the fifth argument
+        if "k_stream<" not in name:
+            return False
+        args = name.split("k_stream<", 1)[1].split(">")[0].split(",")
+        return len(args) >= 5 and args[4].strip() == str(STREAM_OP[kernel])
     return KERNEL_MATCH[kernel] in name
 
 
