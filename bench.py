@@ -166,8 +166,10 @@ def main():
         if not ratings:
             run("tttp", lambda: tt.tttp(ix, None, A, out=out_m))
         for n in range(3):
-            run(f"mttkrp{n}", lambda n=n: tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n]))
-            run(f"solve{n}", lambda n=n: tt.solve_factor(ix, None, A, n, M[n], lam, X=A[n]))
+            # ALS update of mode n: Solve Factor with the MTTKRP(t) right-hand
+            # side formed in the same pass over the nonzeros as the Gram
+            run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam,
+                                                       X=A[n]))
         if ratings:
             run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
                                               stats=stats))
@@ -268,8 +270,10 @@ def main():
                          if ratings else
                          f"uniform {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, {m} nonzeros, "
                          f"planted rank 10 + N(0, 0.01^2)"),
-            "step": ("ALS sweep (3 x [MTTKRP + Solve Factor]) + Gauss-Newton step"
-                     if ratings else "TTTP + ALS sweep (3 x [MTTKRP + Solve Factor])"),
+            "step": ("ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand "
+                     "side formed in the Gram pass) + Gauss-Newton step" if ratings else
+                     "TTTP + ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand "
+                     "side formed in the Gram pass)"),
             "R": R, "factor_storage": args.form, "lambda": lam, "loss": "least squares",
             "cg_iterations": args.cg if ratings else None, "nnz_passes_per_step": passes,
             "parallelism": "single GPU",
@@ -311,8 +315,7 @@ def compare_batching(tt, ix, A, M, R, lam, cg, stats, dev, reps=3):
 
     def step():
         for n in range(3):
-            tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n])
-            tt.solve_factor(ix, None, A, n, M[n], lam, X=A[n], info=info[n])
+            tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam, X=A[n], info=info[n])
         tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=cg, stats=stats)
 
     side = torch.cuda.Stream()

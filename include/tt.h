@@ -77,6 +77,7 @@ typedef enum { TT_LOSS_LS = 0, TT_LOSS_POISSON_LOG = 1 } tt_loss;
 #define TT_ORDER_PER_MODE (-2) /* gn_matvec/solve weights: host array of N
                                   device pointers, entry d in mode-d order */
 #define TT_INDEX_T ((const void *)1)
+#define TT_RHS_MTTKRP ((const void *)2)
 #define TT_SYNC 1u
 #define TT_MAX_ORDER 4
 #define TT_MAX_RANK 64
@@ -195,7 +196,8 @@ tt_status mttkrp(const tt_index *ix, const void *d_s, int s_order,
  * solve_factor -- Solve Factor (Section 3.4): for every row i of `mode`
  *     G^(i) = sum_{e in row i} w_e h_e h_e^T,  h_e = Hadamard_{p != mode} A_p[i_p(e)]
  *     (G^(i) + lambda I) x_i = M_i
- * G^(i) is accumulated in FP32 on matrix cores (FP64 for TT_F64), converted
+ * G^(i) is accumulated in FP32 on matrix cores (FP64 for TT_F64) from exact
+ * bf16 splits of the FP32 products, converted
  * to FP64, shifted by exactly `lambda` (least-squares ALS passes lambda; the
  * Gauss-Newton block preconditioner passes 2 lambda with w = phi''), factored
  * by Cholesky and solved in FP64.  Weights may be negative; a row whose
@@ -203,7 +205,12 @@ tt_status mttkrp(const tt_index *ix, const void *d_s, int s_order,
  * info_i = k > 0, the order of the first non-positive leading minor (LAPACK
  * potrf convention).  Rows without nonzeros solve lambda x = M_i.
  *   d_w, w_order    weights (NULL = Omega-hat; TT_ORDER_PER_MODE allowed).
- *   d_rhs           I_mode x R right-hand sides, dense dtype.
+ *   d_rhs           I_mode x R right-hand sides, dense dtype; or
+ *                   TT_RHS_MTTKRP: M = MTTKRP of the observed values t with
+ *                   the other factors (the ALS normal-equation right-hand
+ *                   side of Section 2.2; needs d_w NULL), which the FP32 and
+ *                   BF16 forms accumulate in FP64 in the same pass over the
+ *                   nonzeros as the Gram (FP64: a separate MTTKRP).
  *   d_X             I_mode x R output in fdt with leading dimension ldA
  *                   (BF16 is rounded to nearest even); may alias d_A[mode].
  *   d_info          optional int32[I_mode].

@@ -380,6 +380,7 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags) {
     wt = std::max(wt, w);
   }
   TT_ST(ws_get(ix, "gram", (size_t)(wt * task_bytes), &p));
+  if (fdt != TT_F64) TT_ST(ws_get(ix, "gram_rhs", (size_t)(wt * RP * 8), &p));  // fused ALS rhs
   int64_t need = 0;
   for (int n = 0; n < ix->N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
   TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &p));
@@ -494,6 +495,27 @@ tt_status mttkrp(const tt_index *cix, const void *d_s, int s_order, const void *
   return mttkrp_impl(ix, s, s_perm, 1.0, d_A, R, ldA, fdt, mode, d_out, accumulate, stream);
 }
 
+}  // extern "C"
+
+// The ALS right-hand side MTTKRP_n(t) for a Solve Factor call: fused into the
+// Gram pass for the FP32 and BF16 forms (one pass over the mode's nonzeros
+// computes both), a separate MTTKRP into the index workspace for FP64.
+static tt_status als_rhs(tt_index *ix, const void *const *A, int R, int64_t ldA, tt_dtype fdt,
+                         int mode, SolveCall *c, hipStream_t stream) {
+  if (fdt != TT_F64) {
+    c->fused_rhs = 1;
+    c->rhs = nullptr;
+    return TT_OK;
+  }
+  void *M = nullptr;
+  TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &M));
+  TT_ST(mttkrp_impl(ix, ix->mode[mode].d_t, nullptr, 1.0, A, R, ldA, fdt, mode, M, 0, stream));
+  c->rhs = M;
+  return TT_OK;
+}
+
+extern "C" {
+
 tt_status solve_factor(const tt_index *cix, const void *d_w, int w_order, const void *const *d_A,
                        int R, int64_t ldA, tt_dtype fdt, int mode, const void *d_rhs,
                        double lambda, void *d_X, int32_t *d_info, uint32_t flags,
@@ -519,6 +541,13 @@ tt_status solve_factor(const tt_index *cix, const void *d_w, int w_order, const 
   c.w_scale = 1.0;
   c.lambda = lambda;
   c.rhs = d_rhs;
+  if (d_rhs == TT_RHS_MTTKRP) {
+    // right-hand side = MTTKRP of the observed values with the other factors
+    TT_CHECK(ix->has_t, "TT_RHS_MTTKRP needs observed values in the index");
+    TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+    TT_CHECK(d_w == nullptr, "TT_RHS_MTTKRP is defined for unweighted Grams (d_w NULL)");
+    TT_ST(als_rhs(ix, c.A, R, ldA, fdt, mode, &c, stream));
+  }
   c.X = d_X;
   c.info = d_info;
   TT_ST(run_solve_factor(ix, c, stream));
@@ -593,12 +622,9 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
   TT_CHECK(d_A != nullptr, "NULL argument");
   for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
-  void *M = nullptr;
-  TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &M));
   const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
   int64_t off = 0;
   for (int n = 0; n < ix->N; ++n) {
-    TT_ST(mttkrp_impl(ix, ix->mode[n].d_t, nullptr, 1.0, A, R, ldA, fdt, n, M, 0, stream));
     SolveCall c;
     memset(&c, 0, sizeof(c));
     c.ix = ix;
@@ -609,7 +635,7 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
     for (int p = 0; p < ix->N; ++p) c.A[p] = A[p];
     c.w_scale = 1.0;
     c.lambda = lambda;
-    c.rhs = M;
+    TT_ST(als_rhs(ix, A, R, ldA, fdt, n, &c, stream));
     c.X = d_A[n];
     c.info = d_info ? d_info + off : nullptr;
     TT_ST(run_solve_factor(ix, c, stream));

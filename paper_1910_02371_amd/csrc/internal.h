@@ -168,7 +168,9 @@ struct SolveCall {
   const int32_t *w_perm;    // COO-order weights gathered through perm
   double w_scale;           // weights are multiplied by this (1 normally)
   double lambda;
-  const void *rhs;          // I x R dense dtype
+  const void *rhs;          // I x R dense dtype (ignored when fused_rhs)
+  int fused_rhs;            // 1: rhs = MTTKRP of the observed values, formed in the
+                            // Gram pass (FP32 and BF16 forms)
   void *X;                  // I x R in fdt, leading dim ldA (may alias A)
   int32_t *info;            // optional
   void *Lstore;             // when non-NULL: keep the Cholesky factors (I x RP(RP+1)/2),

@@ -57,6 +57,8 @@ struct GramDev {
   int split_heavy;            // light kernel skips tasks > light
   int light;                  // light/heavy task threshold (nonzeros)
   int waves;                  // waves of a heavy-task workgroup (2, 4, 8)
+  const float *rhs_t;         // fused right-hand side: observed values, stream order
+  double *M;                  // fused right-hand side: (task - task_base) * RP partials
 };
 
 // Slot of the lower element (r, c), r >= c, in the lower-tile layout.
@@ -104,9 +106,12 @@ struct GramAcc {
   static constexpr int NT = VW * (VW + 1) / 2;
   static constexpr int NV = 4 * NT;
   f32x4 c[NT];
+  double m[VW];  // fused right-hand side: sum of t_e h_e over this lane's nonzeros
   __device__ void zero() {
 #pragma unroll
     for (int q = 0; q < NT; ++q) c[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < VW; ++v) m[v] = 0.0;
   }
   __device__ float get(int v) const { return c[v / 4][v % 4]; }
   __device__ void set(int v, float x) { c[v / 4][v % 4] = x; }
@@ -212,7 +217,7 @@ struct PartPairs {
 // that only reach padding entries of G, which the solve replaces by the
 // identity.  Nonzeros past the end of the range (only in the last step)
 // read row 0 and are zeroed by their weight or validity.
-template <class TR, int RP, bool VEC, bool WEIGHTED>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
   using T = typename TR::T;
@@ -234,38 +239,40 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   const int64_t nst = (n + 31) / 32;
   const bool ragged = (n & 31) != 0;  // the last step has nonzeros past the end
 
-  auto load_block = [&](int64_t blk, uint32_t &r0, uint32_t &r1, float &w) {
+  auto load_block = [&](int64_t blk, uint32_t &r0, uint32_t &r1, float &w, float &tv) {
     const int64_t e = nb + blk * 64 + lane;
     if (e < ne) {
       r0 = (uint32_t)d.oidx0[e] * ldA;
       r1 = (uint32_t)d.oidx1[e] * ldA;
       w = WEIGHTED ? weight_at<float>(d, e) : 1.f;
+      tv = RHS ? d.rhs_t[e] : 0.f;
     } else {
-      r0 = 0; r1 = 0; w = 0.f;
+      r0 = 0; r1 = 0; w = 0.f; tv = 0.f;
     }
   };
   uint32_t cr0, cr1, nr0 = 0, nr1 = 0;
-  float cw, nw = 0.f;
-  load_block(0, cr0, cr1, cw);
-  if (nblk > 1) load_block(1, nr0, nr1, nw);
+  float cw, nw = 0.f, ct, nt = 0.f;
+  load_block(0, cr0, cr1, cw, ct);
+  if (nblk > 1) load_block(1, nr0, nr1, nw, nt);
   int64_t cblk = 0;
 
   for (int64_t st = 0; st < nst; ++st) {
     const bool tail = ragged && st == nst - 1;  // uniform
     const int64_t blk = st >> 1;
     if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
-      cr0 = nr0; cr1 = nr1; cw = nw;
+      cr0 = nr0; cr1 = nr1; cw = nw; ct = nt;
       cblk = blk;
-      if (blk + 1 < nblk) load_block(blk + 1, nr0, nr1, nw);
+      if (blk + 1 < nblk) load_block(blk + 1, nr0, nr1, nw, nt);
     }
     const int sb = 32 * (int)(st & 1) + kk;
     uint32_t r0[8], r1[8];
-    float w[8];
+    float w[8], tv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       r0[u] = __shfl(cr0, sb + 4 * u);
       r1[u] = __shfl(cr1, sb + 4 * u);
       w[u] = (WEIGHTED || tail) ? __shfl(cw, sb + 4 * u) : 1.f;
+      if (RHS) tv[u] = __shfl(ct, sb + 4 * u);  // 0 past the end
     }
     float a0[8][VW], a1[8][VW];
 #pragma unroll
@@ -276,6 +283,11 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
     __builtin_amdgcn_sched_barrier(0);
     // operand words: [class][part][word], word t holds substeps 2t, 2t + 1
     uint32_t opa[VW][PA][4], opb[VW][PB][4];
+    // fused right-hand side: the step's 8 terms per column in FP32, then one
+    // FP64 addition per step
+    float mstep[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) mstep[v] = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -285,6 +297,7 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
         for (int q = 0; q < 2; ++q) {
           const int u = 2 * t + q;
           float h = a0[u][v] * a1[u][v];
+          if constexpr (RHS) mstep[v] = fmaf(tv[u], h, mstep[v]);
           if constexpr (WEIGHTED) {
             split_bf16<PA>(h, pa[q]);
             split_bf16<PB>(w[u] * h, pb[q]);
@@ -300,6 +313,10 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
           for (int i = 0; i < PB; ++i) opb[v][i][t] = pack_bf16(pb[0][i], pb[1][i]);
         }
       }
+    if constexpr (RHS) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc.m[v] += (double)mstep[v];
+    }
     int q = 0;
 #pragma unroll
     for (int p = 0; p < VW; ++p)
@@ -348,7 +365,22 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, flo
 
 // Light tasks: one wave per task, four tasks per workgroup; tasks with more
 // than d.light nonzeros are left to k_gram_f32_heavy.
-template <class TR, int RP, bool VEC, bool WEIGHTED>
+// Fused right-hand side of one task: lanes l, l + 16, l + 32, l + 48 hold
+// the same columns for different nonzeros; their FP64 sums are added in a
+// fixed butterfly and lanes 0..15 store the task's RP partial entries.
+template <int RP>
+__device__ __forceinline__ void rhs_store(double *M, const GramAcc<RP> &acc, int lane) {
+  constexpr int VW = RP / 16;
+#pragma unroll
+  for (int v = 0; v < VW; ++v) {
+    double x = acc.m[v];
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    if (lane < 16) M[VW * lane + v] = x;
+  }
+}
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
 __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= d.task_end) return;
@@ -356,18 +388,21 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
   if (d.split_heavy && ne - nb > d.light) return;
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED>(d, nb, ne, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, nb, ne, acc);
   gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
                  d.w ? 1.f : (float)d.w_scale);
+  if constexpr (RHS) rhs_store<RP>(d.M + (t - d.task_base) * (int64_t)RP, acc, threadIdx.x & 63);
 }
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
-template <class TR, int RP, bool VEC, bool WEIGHTED, int NW>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, int NW>
 __global__ __launch_bounds__(64 * NW) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
+  constexpr int VW = RP / 16;
   __shared__ float buf[NV * 64];
+  __shared__ double mbuf[RHS ? VW * 64 : 1];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t t = heavy[blockIdx.x];
   const int64_t nb = d.task[t], ne = d.task[t + 1];
@@ -375,12 +410,17 @@ __global__ __launch_bounds__(64 * NW) void k_gram_f32_heavy(
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED>(d, b0, b1, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, b0, b1, acc);
   for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         buf[v * 64 + lane] = (q == 0 ? 0.f : buf[v * 64 + lane]) + acc.get(v);
+      if constexpr (RHS) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          mbuf[v * 64 + lane] = (q == 0 ? 0.0 : mbuf[v * 64 + lane]) + acc.m[v];
+      }
     }
     __syncthreads();
   }
@@ -389,7 +429,42 @@ __global__ __launch_bounds__(64 * NW) void k_gram_f32_heavy(
     for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
     gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
                  d.w ? 1.f : (float)d.w_scale);
+    if constexpr (RHS) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc.m[v] = mbuf[v * 64 + lane];
+      rhs_store<RP>(d.M + (t - d.task_base) * (int64_t)RP, acc, lane);
+    }
   }
+}
+
+// Rows with more than kReduceMin tasks: sum their tasks' fused right-hand
+// side partials in FP64 into the first task's slot.  The 256 threads take
+// the row's tasks in 4 strided sets of 64 lanes (lane = column), each with 4
+// independent partial sums, combined in a fixed order (deterministic).
+template <int RP>
+__global__ __launch_bounds__(256) void k_rhs_reduce(const int32_t *__restrict__ rows,
+                                                    const int32_t *__restrict__ row_task,
+                                                    int64_t task_base, double *M) {
+  __shared__ double part[4][64];
+  const int64_t row = rows[blockIdx.x];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int32_t t0 = row_task[row], t1 = row_task[row + 1];
+  double *m = M + ((int64_t)t0 - task_base) * RP;
+  const int n = t1 - t0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c < RP) {
+    int q = g;
+    for (; q + 12 < n; q += 16) {
+      s0 += m[(int64_t)q * RP + c];
+      s1 += m[(int64_t)(q + 4) * RP + c];
+      s2 += m[(int64_t)(q + 8) * RP + c];
+      s3 += m[(int64_t)(q + 12) * RP + c];
+    }
+    for (; q < n; q += 4) s0 += m[(int64_t)q * RP + c];
+  }
+  part[g][c] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && c < RP) m[c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
 }
 
 // Rows with more than kReduceMin tasks: sum their tasks' Grams entrywise
@@ -499,6 +574,7 @@ struct SolveDev {
   int R;
   double lambda;
   const void *rhs;           // I x R dense dtype
+  const double *M;           // fused right-hand side partials per task, or NULL
   void *X;                   // I x R in storage dtype, leading dim ldX
   int64_t ldX;
   int32_t *info;
@@ -721,7 +797,15 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   if (d.factor_only) return;
   double x = 0.0;
   if (info == 0) {
-    const double b = lane < R ? (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane] : 0.0;
+    double b = 0.0;
+    if (d.M) {
+      // fused right-hand side: the row's task partials (pre-reduced into the
+      // first task for rows with more than kReduceMin tasks), in task order
+      if (lane < R)
+        for (int32_t t = t0; t < t1; ++t) b += d.M[((int64_t)t - d.task_base) * RP + lane];
+    } else if (lane < R) {
+      b = (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane];
+    }
     x = bwd_lds<RP, double>(Lp, fwd_lds<RP, double>(Lp, b, rdiag, lane), rdiag, lane);
   }
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
@@ -780,7 +864,7 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
   return hipGetLastError();
 }
 
-template <class TR, int RP, bool VEC, bool WEIGHTED>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
 static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
                                double light_bytes, double light_flops, double heavy_bytes,
                                double heavy_flops, hipStream_t s) {
@@ -788,15 +872,15 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   d.split_heavy = 1;
   {
     ProfScope ps("gram_light", s, light_bytes, light_flops);
-    k_gram_f32<TR, RP, VEC, WEIGHTED><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+    k_gram_f32<TR, RP, VEC, WEIGHTED, RHS><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
   }
   if (nheavy > 0) {
     ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
     const dim3 g((unsigned)nheavy);
     switch (d.waves) {
-      case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 2><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
-      case 8: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 8><<<g, dim3(512), 0, s>>>(d, heavy, nheavy); break;
-      default: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, 4><<<g, dim3(256), 0, s>>>(d, heavy, nheavy); break;
+      case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 2><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
+      case 8: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 8><<<g, dim3(512), 0, s>>>(d, heavy, nheavy); break;
+      default: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 4><<<g, dim3(256), 0, s>>>(d, heavy, nheavy); break;
     }
   }
 }
@@ -811,12 +895,17 @@ static void launch_gram_f32_vec(const GramDev &d, const int32_t *heavy, int64_t 
   const bool vec = d.R % VW == 0 && d.ldA % VW == 0 &&
                    reinterpret_cast<uintptr_t>(d.A0) % al == 0 &&
                    reinterpret_cast<uintptr_t>(d.A1) % al == 0;
+  // weighted Grams (the Gauss-Newton preconditioner) never carry a fused
+  // right-hand side
   if (d.w) {
-    if (vec) launch_gram_f32_rp<TR, RP, true, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
-    else launch_gram_f32_rp<TR, RP, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    if (vec) launch_gram_f32_rp<TR, RP, true, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    else launch_gram_f32_rp<TR, RP, false, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+  } else if (d.M) {
+    if (vec) launch_gram_f32_rp<TR, RP, true, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    else launch_gram_f32_rp<TR, RP, false, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
   } else {
-    if (vec) launch_gram_f32_rp<TR, RP, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
-    else launch_gram_f32_rp<TR, RP, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    if (vec) launch_gram_f32_rp<TR, RP, true, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    else launch_gram_f32_rp<TR, RP, false, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
   }
 }
 
@@ -834,7 +923,8 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
   if (n <= 0) return hipSuccess;
   dim3 g((unsigned)((n + 3) / 4)), b(256);
   const double R = d.R, fb = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
-  const double gs = fdt == TT_F64 ? 8 : 4, pernz = 8 + (d.w ? gs : 0) + 2 * R * fb;
+  const double gs = fdt == TT_F64 ? 8 : 4,
+               pernz = 8 + (d.w ? gs : 0) + (d.M ? 4 : 0) + 2 * R * fb;
   const double tile = (double)gram_task_elems(RP) * gs;
   if (fdt == TT_F64) {
     ProfScope ps("gram_light", s, (wk.light_nnz + wk.heavy_nnz) * pernz + wk.light_tasks * tile,
@@ -881,6 +971,13 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
         case 32: k_gram_reduce<float, 32><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (float *)d.G); break;
         default: k_gram_reduce<float, 64><<<gr, 256, 0, s>>>(multi, row_task, d.task_base, (float *)d.G); break;
       }
+      if (d.M) {
+        switch (RP) {
+          case 16: k_rhs_reduce<16><<<dim3((unsigned)nmulti), 256, 0, s>>>(multi, row_task, d.task_base, d.M); break;
+          case 32: k_rhs_reduce<32><<<dim3((unsigned)nmulti), 256, 0, s>>>(multi, row_task, d.task_base, d.M); break;
+          default: k_rhs_reduce<64><<<dim3((unsigned)nmulti), 256, 0, s>>>(multi, row_task, d.task_base, d.M); break;
+        }
+      }
     }
   }
   return hipGetLastError();
@@ -897,6 +994,13 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   void *Gws = nullptr;
   tt_status st = ws_get(ix, "gram", (size_t)(wtasks * task_bytes), &Gws);
   if (st != TT_OK) return st;
+  double *Mws = nullptr;
+  if (c.fused_rhs) {
+    void *p = nullptr;
+    st = ws_get(ix, "gram_rhs", (size_t)(wtasks * RP * 8), &p);
+    if (st != TT_OK) return st;
+    Mws = (double *)p;
+  }
 
   int others[2], no = 0;
   for (int p = 0; p < ix->N; ++p)
@@ -917,6 +1021,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.split_heavy = 1;
   gd.light = ix->tune.gram_light;
   gd.waves = ix->tune.gram_waves;
+  gd.rhs_t = c.fused_rhs ? reinterpret_cast<const float *>(md.d_t) : nullptr;
+  gd.M = Mws;
 
   SolveDev sd;
   sd.row_task = md.d_row_task;
@@ -924,6 +1030,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   sd.R = c.R;
   sd.lambda = c.lambda;
   sd.rhs = c.rhs;
+  sd.M = Mws;
   sd.X = c.X;
   sd.ldX = c.ldA;
   sd.info = c.info;

@@ -20,6 +20,7 @@ ORDER_COO = -1
 ORDER_PER_MODE = -2
 INDEX_T = "t"          # selects the observed values held by the index
 TT_SYNC = 1
+RHS_MTTKRP = "mttkrp"  # solve_factor right-hand side = MTTKRP of the observed values
 RESERVE_GN = 1
 RESERVE_GN_POISSON = 2
 
@@ -274,7 +275,9 @@ def mttkrp(ix, s, A, mode, out=None, s_order=ORDER_COO, accumulate=False):
 
 def solve_factor(ix, w, A, mode, rhs, lam, X=None, info=None, w_order=ORDER_COO,
                  sync=False):
-    """Solve Factor (Section 3.4); returns (X, info)."""
+    """Solve Factor (Section 3.4); returns (X, info).  ``rhs`` is an I x R
+    array or RHS_MTTKRP (the ALS right-hand side MTTKRP(t), formed in the
+    Gram pass)."""
     fdt = fdt_of(A)
     R, ld = _rank_ld([a for n, a in enumerate(A) if n != mode])
     if X is None:
@@ -294,7 +297,8 @@ def solve_factor(ix, w, A, mode, rhs, lam, X=None, info=None, w_order=ORDER_COO,
     else:
         warr = None
         wp = _values(w)
-    _check(lib().solve_factor(ix.handle, wp, w_order, _ptrs(A), R, ld, fdt, mode, _ptr(rhs),
+    rp = ctypes.c_void_p(2) if isinstance(rhs, str) and rhs == RHS_MTTKRP else _ptr(rhs)
+    _check(lib().solve_factor(ix.handle, wp, w_order, _ptrs(A), R, ld, fdt, mode, rp,
                               float(lam), _ptr(X), _ptr(info), TT_SYNC if sync else 0,
                               _stream()))
     return X, info

@@ -290,6 +290,33 @@ def test_solve_factor_weighted_lowp(gpu_lib, form, R):
         assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"backward error {be:.3e} (mode {n})"
 
 
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [10, 21, 64])
+@pytest.mark.parametrize("kind", ["heavy", "zipf"])
+def test_solve_factor_fused_rhs(gpu_lib, form, R, kind):
+    """TT_RHS_MTTKRP: the ALS right-hand side MTTKRP(t) formed in the Gram
+    pass (FP32/BF16; a separate MTTKRP for FP64) solves the oracle's normal
+    equations (G + lambda I) x = MTTKRP(t)."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 800 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    s = stored_values(wl.t, form)
+    lam = 0.05
+    for n in range(3):
+        X, info = tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam)
+        assert (info.cpu().numpy() == 0).all()
+        G = O.gram(wl.idx, None, As, n, wl.dims[n])
+        M = O.mttkrp(wl.idx, s, As, n, wl.dims[n])
+        tau = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}[form]
+        be = backward_error(G, lam, host(X), M)
+        assert be <= tau, f"backward error {be:.3e} (mode {n})"
+        if form == "f64":
+            Xr, _ = O.solve_rows(G, M, lam)
+            np.testing.assert_allclose(host(X), Xr, rtol=1e-8, atol=1e-10)
+
+
 def test_solve_factor_weights_and_info(gpu_lib):
     tt = gpu_lib
     form = "f64"
@@ -433,3 +460,7 @@ def test_tuning_parity(gpu_lib, form, kind):
                 G = O.gram(wl.idx, None, As, n, wl.dims[n])
                 be = backward_error(G, 0.05, host(X), M)
                 assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"{tune} solve R={R} mode {n}"
+                X, info = tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, 0.05)
+                Mt = O.mttkrp(wl.idx, s, As, n, wl.dims[n])
+                be = backward_error(G, 0.05, host(X), Mt)
+                assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"{tune} fused R={R} mode {n}"
