@@ -164,7 +164,10 @@ def main():
     def step(record):
         run = timed if record else (lambda n, f: f())
         if not ratings:
-            run("tttp", lambda: tt.tttp(ix, None, A, out=out_m))
+            # model values for every nonzero, written in the index's mode-0
+            # order (the library's sparse layout; the caller's COO order would
+            # add a random scatter of m values)
+            run("tttp", lambda: tt.tttp(ix, None, A, out=out_m, out_order=0))
         for n in range(3):
             # ALS update of mode n: Solve Factor with the MTTKRP(t) right-hand
             # side formed in the same pass over the nonzeros as the Gram
@@ -272,8 +275,9 @@ def main():
                          f"planted rank 10 + N(0, 0.01^2)"),
             "step": ("ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand "
                      "side formed in the Gram pass) + Gauss-Newton step" if ratings else
-                     "TTTP + ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand "
-                     "side formed in the Gram pass)"),
+                     "TTTP (model values in the index's mode-0 order) + ALS sweep "
+                     "(3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed in "
+                     "the Gram pass)"),
             "R": R, "factor_storage": args.form, "lambda": lam, "loss": "least squares",
             "cg_iterations": args.cg if ratings else None, "nnz_passes_per_step": passes,
             "parallelism": "single GPU",
