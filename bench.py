@@ -214,7 +214,11 @@ def main():
     wname = (f"{'ratings' if ratings else 'uniform'}{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}"
              f"_m{m}_R{R}_{args.form}")
     traffic = traffic_from_profile(dom, wname, src_hash)
-    if dom.startswith("gram"):
+    # the Gram is a contraction: reported against the FP32 matrix-core peak
+    # when its algorithmic intensity (flops per algorithmic byte) is above the
+    # ridge point of that peak and the HBM bandwidth, else against HBM
+    intensity = rec["flops"] / max(rec["bytes"], 1.0)
+    if dom.startswith("gram") and intensity >= FP32_MFMA_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
         achieved = rec["flops"] / n_l / (per_ms / 1e3) / 1e12
         roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
                     "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
