@@ -75,8 +75,14 @@ def traffic(fetch_dir, write_dir, kernel, workload, src_hash, copy_bytes, out_md
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         disp = _per_dispatch(_counter_rows(d), counter)
-        copies = [v for (i, n), v in disp.items() if "copy" in n.lower() or
-                  "elementwise_kernel" in n.lower()]
+        # the calibration fill + copy are the program's first dispatches:
+        # take the runtime/torch copy kernels dispatched before the library's
+        # first kernel (later copies move the tensor's own data)
+        first_tt = min((int(i) for (i, n) in disp if n.startswith("tt::") or " tt::" in n),
+                       default=None)
+        copies = [v for (i, n), v in disp.items()
+                  if (first_tt is None or int(i) < first_tt) and "tt::" not in n
+                  and ("copy" in n.lower() or "elementwise_kernel" in n.lower())]
         if not copies:
             raise SystemExit(f"{counter}: no copy-kernel dispatch found")
         ref = max(copies)  # KiB read (or written) by the calibration copy
