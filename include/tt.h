@@ -116,7 +116,9 @@ tt_status tt_index_destroy(tt_index *ix);
  * made without it size the workspace on first use.  `flags` adds the
  * workspaces of tt_gn_step: TT_RESERVE_GN (PCG vectors and preconditioner
  * factors, least squares) and TT_RESERVE_GN_POISSON (also the per-mode
- * phi'' weights of the Poisson loss). */
+ * phi'' weights of the Poisson loss); either flag also builds the position
+ * map of gn_matvec (N x 4 bytes per nonzero, kept until the index is
+ * destroyed; built on the null stream, which is synchronized). */
 #define TT_RESERVE_GN 1u
 #define TT_RESERVE_GN_POISSON 2u
 tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
@@ -229,11 +231,19 @@ tt_status solve_factor(const tt_index *ix, const void *d_w, int w_order,
  * Appendix A first Hessian term):
  *     z_e = sum_p sum_r X_p[i_p(e), r] prod_{q != p} A_q[i_q(e), r]
  *     Y_d = MTTKRP_d(w .* z) + lambda2 * X_d          for every mode d
- * fused into one pass over each mode's sorted stream.
+ * w .* z is formed once, in the sorted order of the mode with the most rows,
+ * in the pass that also accumulates that mode's block (TTTP fused into
+ * MTTKRP); the other blocks are MTTKRPs of the stored w .* z, read through
+ * a position map of the index (mode-n sorted position -> that mode's sorted
+ * position), so no pass but the first gathers rows of X.
  *   d_w, w_order    per-nonzero weights (phi''); TT_ORDER_PER_MODE or a
  *                   mode order or COO; NULL = the constant w_const.
  *   d_X, d_Y        host arrays of N device pointers to dense-dtype I_d x R
  *                   blocks (contiguous); Y is overwritten.
+ * The first call on an index builds the position map (allocation, kernels
+ * on `stream`, one synchronization) unless tt_index_reserve built it; that
+ * call fails while `stream` is capturing a graph.  w .* z is kept in an
+ * index workspace of m values (value dtype).
  * ------------------------------------------------------------------------- */
 tt_status gn_matvec(const tt_index *ix, const void *d_w, int w_order,
                     double w_const, const void *const *d_A,

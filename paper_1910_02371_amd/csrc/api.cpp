@@ -196,6 +196,13 @@ static tt_status mttkrp_impl(tt_index *ix, const void *s, const int32_t *s_perm,
   return TT_OK;
 }
 
+// Gauss-Newton matvec (Section 2.5): Y_d = lambda2 X_d + J_d^T diag(w) J X for
+// every mode d.  The per-nonzero scalar w_e z_e (z = J X, the TTTP-shaped
+// Jacobian-vector product) is the same for every block, so it is formed once,
+// in the sorted order of the mode with the most rows (whose factor rows miss
+// the caches when gathered): that pass also accumulates its own block and
+// stores w_e z_e; the other blocks are MTTKRPs of those scalars, read through
+// the index's position map, which gather no direction rows at all.
 static tt_status gn_matvec_impl(tt_index *ix, const void *const *w, double w_const,
                                 const int32_t *const *w_perm, const void *const *d_A,
                                 const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
@@ -203,24 +210,45 @@ static tt_status gn_matvec_impl(tt_index *ix, const void *const *w, double w_con
                                 hipStream_t st) {
   double *carry = nullptr;
   TT_ST(carry_ws(ix, &carry));
+  const int zm = gn_zmode(ix);
+  const int32_t *zmap = nullptr;
+  TT_ST(zmap_get(ix, st, &zmap));
+  void *zbuf = nullptr;
+  TT_ST(ws_get(ix, "gn_z", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &zbuf));
   for (int d = 0; d < ix->N; ++d) {
     const ModeIndex &md = ix->mode[d];
     TT_LAUNCH(launch_scale_rows(d_Y[d], d_X[d], dense_of(fdt), R, md.I, R, lambda2,
                                 dense_of(fdt), st),
               "gn prefill");
-    StreamCall c = base_call(ix, d, R, ldA, fdt);
+  }
+  {
+    StreamCall c = base_call(ix, zm, R, ldA, fdt);
     for (int p = 0; p < ix->N; ++p) {
       c.A[p] = d_A[p];
       c.X[p] = d_X[p];
     }
-    c.s = w ? w[d] : nullptr;
-    c.s_perm = w_perm ? w_perm[d] : nullptr;
+    c.s = w ? w[zm] : nullptr;
+    c.s_perm = w_perm ? w_perm[zm] : nullptr;
     c.w_const = w_const;
+    c.out = d_Y[zm];
+    c.accumulate = 1;
+    c.carry = carry;
+    c.skip = skip;
+    c.zout = zbuf;
+    TT_LAUNCH(launch_stream(OP_GN, c, st), "gn kernel");
+  }
+  for (int d = 0; d < ix->N; ++d) {
+    if (d == zm) continue;
+    StreamCall c = base_call(ix, d, R, ldA, fdt);
+    for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+    c.s = zbuf;
+    c.s_perm = zmap + (int64_t)d * ix->m;
     c.out = d_Y[d];
     c.accumulate = 1;
     c.carry = carry;
     c.skip = skip;
-    TT_LAUNCH(launch_stream(OP_GN, c, st), "gn kernel");
+    c.prof_name = "gn_mttkrp";
+    TT_LAUNCH(launch_stream(OP_MTTKRP, c, st), "gn mttkrp kernel");
   }
   return TT_OK;
 }
@@ -388,6 +416,9 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags) {
     GnWs ws;
     TT_ST(gn_workspace(ix, R, fdt,
                        (flags & TT_RESERVE_GN_POISSON) ? TT_LOSS_POISSON_LOG : TT_LOSS_LS, &ws));
+    TT_ST(ws_get(ix, "gn_z", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &p));
+    const int32_t *zmap = nullptr;
+    TT_ST(zmap_get(ix, nullptr, &zmap));
   }
   return TT_OK;
 }

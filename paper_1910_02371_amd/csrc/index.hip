@@ -249,6 +249,17 @@ __global__ void k_iota_u32(uint32_t *__restrict__ dst, int64_t m) {
   for (; i < m; i += stride) dst[i] = (uint32_t)i;
 }
 
+// inv[perm[q]] = q: the inverse of a sorted-position -> COO-position map
+__global__ void k_inv_perm(const int32_t *__restrict__ perm, int64_t m,
+                           int32_t *__restrict__ inv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) {
+    const uint32_t q = (uint32_t)perm[i];
+    if (q < (uint64_t)m) inv[q] = (int32_t)i;
+  }
+}
+
 // ---------------------------------------------------------------------------
 static int grid_for(int64_t n, int threads, int cap = 65536) {
   int64_t g = (n + threads - 1) / threads;
@@ -556,6 +567,51 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
     if (he != hipSuccess) st = hip_fail(he, "tt_build_index");
   }
   return st;
+}
+
+}  // namespace tt
+
+namespace tt {
+
+int gn_zmode(const tt_index *ix) {
+  int b = 0;
+  for (int n = 1; n < ix->N; ++n)
+    if (ix->mode[n].I > ix->mode[b].I) b = n;
+  return b;
+}
+
+tt_status zmap_get(tt_index *ix, hipStream_t s, const int32_t **out) {
+  if (ix->d_zmap == nullptr) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s != nullptr && hipStreamIsCapturing(s, &cs) == hipSuccess &&
+        cs != hipStreamCaptureStatusNone) {
+      set_error("the Gauss-Newton position map is built on first use: reserve it with "
+                "tt_index_reserve(..., TT_RESERVE_GN) before capturing");
+      return TT_ERR_INVALID_ARG;
+    }
+    const int64_t m = ix->m;
+    const int zm = gn_zmode(ix);
+    int32_t *map = nullptr;
+    tt_status st = dev_alloc(ix, &map, (size_t)ix->N * (size_t)m);
+    if (st != TT_OK) return st;
+    if (m > 0) {
+      // slot zm: inverse of the mode-zm permutation; slot n: mode-n sorted
+      // position -> mode-zm sorted position
+      int32_t *inv = map + (int64_t)zm * m;
+      k_inv_perm<<<grid_for(m, 256), 256, 0, s>>>(ix->mode[zm].d_perm, m, inv);
+      for (int n = 0; n < ix->N; ++n)
+        if (n != zm)
+          k_gather_i32<<<grid_for(m, 256), 256, 0, s>>>(
+              inv, reinterpret_cast<const uint32_t *>(ix->mode[n].d_perm), m,
+              map + (int64_t)n * m);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "position map");
+    ix->d_zmap = map;
+  }
+  *out = ix->d_zmap;
+  return TT_OK;
 }
 
 }  // namespace tt

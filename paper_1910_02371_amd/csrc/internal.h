@@ -85,12 +85,21 @@ struct tt_index {
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
   tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
                     tt::kGramWavesDefault};
+  // Gauss-Newton position map (built on first use, N x m): slot n != zmode
+  // maps mode-n sorted positions to mode-zmode sorted positions
+  int32_t *d_zmap = nullptr;
 };
 
 namespace tt {
 
 // ----- index partitions (index.hip) ------------------------------------------
 tt_status build_partitions(tt_index *ix, int n, hipStream_t s);
+// Mode whose factor rows are the costliest to gather (the most rows): the
+// Gauss-Newton matvec evaluates its per-nonzero scalars in that mode's order.
+int gn_zmode(const tt_index *ix);
+// The index's Gauss-Newton position map, built (allocated, filled on stream s
+// and synchronized) on first use; fails while s is capturing a graph.
+tt_status zmap_get(tt_index *ix, hipStream_t s, const int32_t **out);
 
 // ----- error handling ------------------------------------------------------
 void set_error(const char *fmt, ...);
@@ -151,6 +160,9 @@ struct StreamCall {
   double *sum_parts;        // TTTP: per-chunk FP64 partial sums (or NULL)
   double *carry;            // segmented: carry workspace
   const double *skip;       // optional device flag: launches become no-ops
+  void *zout;               // GN: also store w_e * z_e per nonzero (value dtype,
+                            // this mode's sorted order) when non-NULL
+  const char *prof_name;    // profiler tag (NULL: named after the operation)
 };
 enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3 };
 hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s);

@@ -68,6 +68,7 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   d.sum_parts = c.sum_parts;
   d.carry = c.carry;
   d.skip = c.skip;
+  d.zout = op == OP_GN ? c.zout : nullptr;
   hipError_t e;
   {
     // algorithmic work of this launch (per-nonzero byte model: index
@@ -84,7 +85,8 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
       flops = m * R * given;
     } else if (op == OP_MTTKRP) {
       name = "mttkrp";
-      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (N - 1) * R * b) + I * R * xs;
+      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (c.s_perm ? 4 : 0) + (N - 1) * R * b) +
+              I * R * xs * (c.accumulate ? 2 : 1);
       flops = m * R * N;
     } else if (op == OP_GRAD) {
       name = "gradient";
@@ -92,9 +94,12 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
       flops = m * R * (N + 3);
     } else {
       name = "gn_matvec";
-      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (N - 1) * R * (b + xs)) + I * R * (b + 3 * xs);
+      bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (c.s_perm ? 4 : 0) + (c.zout ? v : 0) +
+                   (N - 1) * R * (b + xs)) +
+              I * R * (b + 3 * xs);
       flops = m * R * 10;
     }
+    if (c.prof_name) name = c.prof_name;
     ProfScope ps(name, s, bytes, flops);
     if (c.fdt == TT_F32)
       e = launch_stream_f32(op, d, md.nchunk, G, vec, ix->tune.chunk, s);

@@ -21,6 +21,8 @@
 //   OP_GRAD   Y[i] += phi'(t_e, <A_n[i], h_e>) * h_e
 //   OP_GN     Y[i] += w_e * z_e * h_e,  z_e = <X_n[i], h_e> + <A_n[i], dh_e>,
 //             dh_e = sum_{p != n} X_p[i_p(e)] * prod_{q != n, p} A_q[i_q(e)]
+//             (optionally also stores w_e * z_e per nonzero, for the other
+//             modes' blocks of the same product)
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -57,6 +59,7 @@ struct StreamDev {
   double *sum_parts;
   double *carry;
   const double *skip;       // when set and *skip != 0 the launch is a no-op
+  void *zout;               // OP_GN: per-nonzero w_e * z_e in sorted order, or NULL
 };
 
 template <class TR, int G, int CHUNK>
@@ -298,6 +301,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
             const AT wz = (AT)sm.val[e] * z;
 #pragma unroll
             for (int j = 0; j < V; ++j) acc[j] += wz * h[j];
+            if (a.zout != nullptr && c0 == 0) reinterpret_cast<VT *>(a.zout)[b + e] = (VT)wz;
           } else {  // OP_TTTP
             AT d = AT(0);
 #pragma unroll

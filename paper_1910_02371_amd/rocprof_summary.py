@@ -20,13 +20,14 @@ import sys
 
 # library profiler names -> substrings of the device kernel names
 KERNEL_MATCH = {
-    "tttp": ", 3, ", "mttkrp": None, "gradient": None, "gn_matvec": None,
+    "tttp": ", 3, ", "mttkrp": None, "gradient": None, "gn_matvec": None, "gn_mttkrp": None,
     "gram_heavy": "k_gram_f32_heavy", "gram_light": "k_gram_f32<",
     "gram_reduce": "k_gram_reduce", "cholesky_solve": "k_solve_rows",
     "cholesky_factor": "k_solve_rows", "precond_apply": "k_apply_rows",
     "heavy_fixup": "k_heavy_fixup",
 }
-STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3}
+# (the Gauss-Newton product's MTTKRP blocks run the MTTKRP kernel)
+STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3, "gn_mttkrp": 1}
 
 
 def matches(kernel, name):

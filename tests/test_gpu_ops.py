@@ -106,6 +106,11 @@ def test_index_empty(gpu_lib):
     assert torch.count_nonzero(Y).item() == 0
     _, s = tt.tttp(ix, tt.INDEX_T, A, out=False, epi="phi", want_sum=True)
     assert s.item() == 0.0
+    # no nonzeros: the Gauss-Newton product is lambda2 * X
+    X = [dev_factor(np.full((d, 4), 1.5), "f32") for d in (4, 5, 6)]
+    Y = tt.gn_matvec(ix, None, A, X, 0.5, w_const=2.0)
+    for y in Y:
+        assert torch.all(y == 0.75).item()
 
 
 # ----------------------------------------------------------------- TTTP ----
@@ -378,9 +383,13 @@ def test_gradient_and_objective(gpu_lib, form, loss, kind):
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("weights", ["const", "per_mode"])
-@pytest.mark.parametrize("kind", ["uniform", "heavy"])
+@pytest.mark.parametrize("weights", ["const", "per_mode", "coo"])
+@pytest.mark.parametrize("kind", ["uniform", "heavy", "zipf"])
 def test_gn_matvec_parity(gpu_lib, form, weights, kind):
+    """All three blocks of the product.  The scalar pass runs in the order of
+    the mode with the most rows: mode 1 for the uniform and heavy cases,
+    mode 0 for the Zipf case; the other blocks read its per-nonzero scalars
+    through the index's position map."""
     tt = gpu_lib
     wl, ix = get_index(tt, kind, form)
     R = 16
@@ -394,11 +403,14 @@ def test_gn_matvec_parity(gpu_lib, form, weights, kind):
     if weights == "const":
         w = np.full(wl.nnz, 2.0)
         Y = tt.gn_matvec(ix, None, A, Xd, lam2, w_const=2.0)
-    else:
+    elif weights == "per_mode":
         w = stored_values(rng.random(wl.nnz) + 0.5, form)
         ixs = O.build_index(wl.idx, wl.dims)
         wd = [dev_vals(w[ixs[d]["perm"]], form) for d in range(3)]
         Y = tt.gn_matvec(ix, wd, A, Xd, lam2)
+    else:
+        w = stored_values(rng.random(wl.nnz) + 0.5, form)
+        Y = tt.gn_matvec(ix, dev_vals(w, form), A, Xd, lam2, w_order=tt.ORDER_COO)
     Y = host(Y)
     ref = O.gn_matvec(wl.idx, w, As, X64, lam2, wl.dims)
     z_abs = O.jvp(wl.idx, [np.abs(a) for a in As], [np.abs(x) for x in X64])
