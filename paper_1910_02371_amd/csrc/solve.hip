@@ -653,13 +653,24 @@ __device__ __forceinline__ double bwd_lds(const LT *Lp, double b, double rdiag, 
   return b * rdiag;
 }
 
+// Panel buffer of the blocked Cholesky: four columns of PP doubles (column
+// c at c * PP, then 64 scratch slots).  PP is RP + 16 rounded so that
+// 2 PP = 32 (mod 64): the 16-lane groups of a half-wave that read
+// neighbouring columns fall on disjoint LDS bank halves.
+template <int RP>
+struct PanelBuf {
+  static constexpr int PP = RP == 16 ? 48 : RP + 16;
+  static constexpr int SCR = 4 * PP;
+  static constexpr int SIZE = 4 * PP + 64;
+};
+
 // Blocked Cholesky of one row's S = G + lambda I on the matrix cores.
 // S lives in NT accumulator tiles (lower tiles, layout of the Gram
 // workspace): lane l, register v of tile (I, J) holds
 // S(16 I + 4 v + l / 16, 16 J + l % 16).  For each panel of four columns
 // k0 .. k0 + 3 (inside column block J = k0 / 16):
 //   1. the lanes holding the panel's columns write them to the LDS panel
-//      buffer Pn (row-major, 4 per row);
+//      buffer Pn (column-major, PanelBuf);
 //   2. lane i reads row i of the panel and the panel is factored on the
 //      lanes (pivot from the diagonal lane, reciprocal square root, the
 //      three in-panel updates with broadcast multipliers);
@@ -672,10 +683,14 @@ __device__ __forceinline__ double bwd_lds(const LT *Lp, double b, double rdiag, 
 // read again.  The workgroup is one wave, whose LDS accesses complete in
 // program order, so the buffers need no barriers.  Returns info (LAPACK
 // potrf convention) and leaves 1 / L(i, i) in rdiag on lane i.
-template <class GT, int RP>
+// FWD: the forward substitution L y = b runs with the factorization (lane i
+// holds b_i; at pivot k, y_k = b_k / L(k, k) is broadcast and lanes i > k
+// subtract L(i, k) y_k, the multiplier they have just computed), so b
+// holds y on return.
+template <class GT, int RP, bool FWD>
 __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t t1,
                                           int lane, double *Lp, double *Pn,
-                                          double &rdiag) {
+                                          double &rdiag, double &b) {
   constexpr int NB = RP / 16;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int SZ = 256 * NT;
@@ -709,8 +724,8 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
         }
   }
   using P = Packed<RP>;
+  using PB = PanelBuf<RP>;
   const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
-  const int prow = lane < RP ? 4 * lane : 4 * RP;  // this lane's panel row (or scratch)
 #pragma unroll
   for (int p = 0; p < RP / 4; ++p) {
     const int k0 = 4 * p, J = k0 / 16, c0 = k0 % 16;
@@ -724,14 +739,17 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
       for (int I = J; I < NB; ++I)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int addr = mine ? 4 * (16 * I + 4 * v + rr) + (cc - c0) : 4 * RP + 4 + ln;
+          const int addr = mine ? (cc - c0) * PB::PP + 16 * I + 4 * v + rr : PB::SCR + ln;
           Pn[addr] = acc[I * (I + 1) / 2 + J][v];
         }
     }
     // 2. factor the panel on the lanes
     double x[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) x[c] = lane < RP ? Pn[prow + c] : 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const double xv = Pn[c * PB::PP + lane];  // in bounds for every lane
+      x[c] = lane < RP ? xv : 0.0;
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int k = k0 + c;
@@ -741,6 +759,10 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
       if (lane == k) rdiag = inv;
       const double lik = lane >= k ? x[c] * inv : 0.0;
       x[c] = lik;
+      if constexpr (FWD) {
+        const double yk = readlane_d(b, k) * inv;
+        b = lane == k ? yk : (lane > k ? fma(-lik, yk, b) : b);
+      }
 #pragma unroll
       for (int c2 = c + 1; c2 < 4; ++c2) x[c2] -= lik * readlane_d(lik, k0 + c2);
     }
@@ -749,7 +771,7 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
       const int ln = opaque_lane(lane);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        Pn[prow + c] = x[c];
+        Pn[ln < RP ? c * PB::PP + ln : PB::SCR + ln] = x[c];
         Lp[(k0 + c <= ln && ln < RP) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
       }
     }
@@ -757,7 +779,7 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
     if (k0 + 4 < RP) {
       double a[NB];
 #pragma unroll
-      for (int I = J; I < NB; ++I) a[I] = Pn[4 * (16 * I + (lane & 15)) + (lane >> 4)];
+      for (int I = J; I < NB; ++I) a[I] = Pn[(lane >> 4) * PB::PP + 16 * I + (lane & 15)];
 #pragma unroll
       for (int I = J; I < NB; ++I)
 #pragma unroll
@@ -773,7 +795,7 @@ template <class GT, class XT, class MT, int RP>
 __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   using P = Packed<RP>;
   __shared__ double Lp[P::LDS];
-  __shared__ double Pn[4 * RP + 4 + 64];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
   if (d.skip && *d.skip != 0.0) return;
   const int lane = threadIdx.x;
   const int64_t row = d.r0 + blockIdx.x;
@@ -783,7 +805,21 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   if (t1 - t0 > kReduceMin) t1 = t0 + 1;  // pre-reduced by k_gram_reduce
   if (lane == 0) Lp[P::ZERO] = 0.0;
   double rdiag = 1.0;
-  const int info = chol_tiles<GT, RP>(d, t0, t1, lane, Lp, Pn, rdiag);
+  // right-hand side (lane i holds b_i); the forward substitution runs inside
+  // the factorization
+  double b = 0.0;
+  if (!d.factor_only) {
+    if (d.M) {
+      // fused right-hand side: the row's task partials (pre-reduced into the
+      // first task for rows with more than kReduceMin tasks), in task order
+      if (lane < R)
+        for (int32_t t = t0; t < t1; ++t) b += d.M[((int64_t)t - d.task_base) * RP + lane];
+    } else if (lane < R) {
+      b = (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane];
+    }
+  }
+  const int info = d.factor_only ? chol_tiles<GT, RP, false>(d, t0, t1, lane, Lp, Pn, rdiag, b)
+                                 : chol_tiles<GT, RP, true>(d, t0, t1, lane, Lp, Pn, rdiag, b);
   if (d.info && lane == 0) d.info[row] = info;
   if (info && d.Lstore) {
     // failed rows keep the identity (no preconditioning for that block)
@@ -795,19 +831,8 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
     for (int q = lane; q < P::PS; q += 64) L[q] = (GT)Lp[q];
   }
   if (d.factor_only) return;
-  double x = 0.0;
-  if (info == 0) {
-    double b = 0.0;
-    if (d.M) {
-      // fused right-hand side: the row's task partials (pre-reduced into the
-      // first task for rows with more than kReduceMin tasks), in task order
-      if (lane < R)
-        for (int32_t t = t0; t < t1; ++t) b += d.M[((int64_t)t - d.task_base) * RP + lane];
-    } else if (lane < R) {
-      b = (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane];
-    }
-    x = bwd_lds<RP, double>(Lp, fwd_lds<RP, double>(Lp, b, rdiag, lane), rdiag, lane);
-  }
+  // b holds y = L^{-1} rhs; backward substitution L^T x = y
+  const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
 

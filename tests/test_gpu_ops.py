@@ -420,6 +420,35 @@ def test_gn_matvec_parity(gpu_lib, form, weights, kind):
         assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn mode {d}")
 
 
+@pytest.mark.parametrize("form", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("R", [1, 13, 21, 64])
+@pytest.mark.parametrize("kind", ["heavy", "zipf"])
+def test_gn_matvec_ranks(gpu_lib, form, R, kind):
+    """Ragged and full ranks (element and vector gather paths, one-lane
+    rows) with per-mode weights; two calls in a row on the same index reuse
+    its position map and scalar workspace."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 31 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(R)
+    ixs = O.build_index(wl.idx, wl.dims)
+    for call in range(2):
+        X64 = [stored_values(rng.standard_normal((d, R)), form) for d in wl.dims]
+        Xd = [dev_vals(x, form) for x in X64]
+        w = stored_values(rng.random(wl.nnz) + 0.5, form)
+        wd = [dev_vals(w[ixs[d]["perm"]], form) for d in range(3)]
+        lam2 = 0.1 * (call + 1)
+        Y = host(tt.gn_matvec(ix, wd, A, Xd, lam2))
+        ref = O.gn_matvec(wl.idx, w, As, X64, lam2, wl.dims)
+        z_abs = O.jvp(wl.idx, [np.abs(a) for a in As], [np.abs(x) for x in X64])
+        for d in range(3):
+            ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
+                lam2 * np.abs(X64[d])
+            assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn R={R} call {call} mode {d}")
+
+
 # --------------------------------------------------------------- tuning ----
 TUNINGS = [
     dict(chunk=512, gram_piece=2048, gram_light=256, gram_waves=2),
