@@ -135,10 +135,11 @@ def main():
         # work-partition autotuner (cached per shape class; outside the timing)
         from paper_1910_02371_amd import autotune
         t0 = time.time()
-        tuning = autotune.tune(tt, ix, A, R, lam)
+        tuning = autotune.tune(tt, ix, A, R, lam, gn=ratings)
         tuning["seconds"] = time.time() - t0
         log(f"tuning {tuning['tuning']} ({'cached' if tuning['from_cache'] else 'measured'})")
-    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls")
+    # the Gauss-Newton workspaces (and position map) only where the step has GN
+    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls" if ratings else None)
     m = wl.nnz
 
     stream = torch.cuda.current_stream()

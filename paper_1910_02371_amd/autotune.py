@@ -11,8 +11,9 @@ Search: coordinate descent over KNOBS starting from the index's current
 setting, one knob at a time in KNOBS order, keeping a candidate only if it
 beats the best time so far by more than `min_gain`.  Each evaluation rebuilds
 the index's partitions (tt_index_tune) and times `work`, a representative
-call sequence (by default one ALS sweep's MTTKRP and Solve Factor on every
-mode, plus one Gauss-Newton matvec), with HIP events on the current stream.
+call sequence (by default one ALS sweep's fused updates on every mode, plus
+one Gauss-Newton matvec unless gn=False), with HIP events on the current
+stream.
 
 Results are cached in a JSON file keyed by factor dtype, rank and a shape
 class of the tensor (log2 of the nonzero count and of the mean row degree of
@@ -81,23 +82,23 @@ def save_cache(path, cache):
     os.replace(tmp, path)
 
 
-def default_work(tt, ix, A, R, lam):
-    """One ALS sweep's MTTKRP + Solve Factor per mode and one GN matvec,
-    on scratch outputs (the factors are not changed)."""
+def default_work(tt, ix, A, R, lam, gn=True):
+    """One ALS sweep's updates (Solve Factor with the MTTKRP right-hand side
+    formed in the Gram pass) and (gn) one GN matvec, on scratch outputs (the
+    factors are not changed)."""
     import torch
     dev = A[0].device
-    M = [torch.empty((d, R), dtype=torch.float32 if A[0].dtype != torch.float64
-                     else torch.float64, device=dev) for d in ix.dims]
+    dense = torch.float32 if A[0].dtype != torch.float64 else torch.float64
     X = [torch.empty_like(a) for a in A]
     info = [torch.empty(d, dtype=torch.int32, device=dev) for d in ix.dims]
-    Y = [torch.empty_like(m) for m in M]
-    Xd = [m.clone() for m in M]
+    Y = [torch.empty((d, R), dtype=dense, device=dev) for d in ix.dims]
+    Xd = [torch.rand((d, R), dtype=dense, device=dev) for d in ix.dims]
 
     def work():
         for n in range(len(A)):
-            tt.mttkrp(ix, tt.INDEX_T, A, n, out=M[n])
-            tt.solve_factor(ix, None, A, n, M[n], lam, X=X[n], info=info[n])
-        tt.gn_matvec(ix, None, A, Xd, 2 * lam, Y=Y)
+            tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam, X=X[n], info=info[n])
+        if gn:
+            tt.gn_matvec(ix, None, A, Xd, 2 * lam, Y=Y)
     return work
 
 
@@ -114,8 +115,10 @@ def time_ms(work, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(tt, ix, A, R, lam=1e-5, work=None, reps=2, cache_path=DEFAULT_CACHE, retune=False):
-    """Pick the index's tuning (cached by shape class) and apply it.
+def tune(tt, ix, A, R, lam=1e-5, work=None, reps=2, cache_path=DEFAULT_CACHE, retune=False,
+         gn=True):
+    """Pick the index's tuning (cached by shape class) and apply it; the
+    default work includes a GN matvec when gn is set.
     Returns a report {"key", "tuning", "ms", "from_cache", "trials"}."""
     import torch
     dname = {torch.float64: "f64", torch.float32: "f32", torch.bfloat16: "bf16"}[A[0].dtype]
@@ -125,7 +128,7 @@ def tune(tt, ix, A, R, lam=1e-5, work=None, reps=2, cache_path=DEFAULT_CACHE, re
         ix.tune(**cache[key]["tuning"])
         return {"key": key, "tuning": cache[key]["tuning"], "ms": cache[key]["ms"],
                 "from_cache": True, "trials": []}
-    work = work or default_work(tt, ix, A, R, lam)
+    work = work or default_work(tt, ix, A, R, lam, gn=gn)
 
     def measure(t):
         ix.tune(**t)
