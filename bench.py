@@ -55,6 +55,8 @@ def parse():
                    help="skip the graph-replay vs plain-launch comparison")
     p.add_argument("--form-sweeps", type=int, default=5,
                    help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
+    p.add_argument("--gn-steps", type=int, default=3,
+                   help="Gauss-Newton steps after the ALS sweeps of the forms comparison")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this size first (counter calibration)")
     return p.parse_args()
@@ -117,7 +119,8 @@ def main():
     gen_s = time.time() - t0
     log(f"generated {wl.name}: {wl.nnz} nnz in {gen_s:.1f}s")
     R = args.R or (64 if ratings else 32)
-    lam = 1e-5
+    lam = 1e-5      # least-squares ALS regularization (Section 5.6)
+    lam_gn = 1e-3   # Gauss-Newton regularization of the paper's LS runs (Section 5.6)
     fdt_t = torch.float32 if args.form == "f32" else torch.bfloat16
     idx = [torch.as_tensor(i).to(dev) for i in wl.idx]
     t = torch.as_tensor(wl.t).to(dev)
@@ -175,7 +178,7 @@ def main():
             run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam,
                                                        X=A[n]))
         if ratings:
-            run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=args.cg,
+            run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam_gn, tol=5e-3, kmax=args.cg,
                                               stats=stats))
 
     for _ in range(args.warmup):
@@ -249,15 +252,16 @@ def main():
 
     batching = None
     if args.batching and ratings:
-        batching = compare_batching(tt, ix, A, M, R, lam, args.cg, stats, dev)
+        batching = compare_batching(tt, ix, A, M, R, lam, lam_gn, args.cg, stats, dev)
 
     forms = None
     if args.form_sweeps > 0:
-        forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev)
+        forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev,
+                              gn_steps=args.gn_steps if ratings else 0, lam_gn=lam_gn)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, A0, R, lam, args.cpu_sample, passes, gn=ratings)
+        cpu = cpu_baseline(wl, A0, R, lam, lam_gn, args.cpu_sample, passes, gn=ratings)
 
     out = {
         "metric": METRIC,
@@ -283,7 +287,8 @@ def main():
                      "TTTP (model values in the index's mode-0 order) + ALS sweep "
                      "(3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed in "
                      "the Gram pass)"),
-            "R": R, "factor_storage": args.form, "lambda": lam, "loss": "least squares",
+            "R": R, "factor_storage": args.form, "lambda": lam,
+            "lambda_gn": lam_gn if ratings else None, "loss": "least squares",
             "cg_iterations": args.cg if ratings else None, "nnz_passes_per_step": passes,
             "parallelism": "single GPU",
         },
@@ -302,7 +307,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def compare_batching(tt, ix, A, M, R, lam, cg, stats, dev, reps=3):
+def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
     """The step recorded once as a graph (tt_graph_begin/end) and replayed,
     against the same calls launched one by one; and the same comparison for
     one ALS sweep on the 200^3 cube (40,000 nonzeros, R = 10, FP64), where
@@ -325,7 +330,7 @@ def compare_batching(tt, ix, A, M, R, lam, cg, stats, dev, reps=3):
     def step():
         for n in range(3):
             tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam, X=A[n], info=info[n])
-        tt.gn_step(ix, A, "ls", lam, tol=5e-3, kmax=cg, stats=stats)
+        tt.gn_step(ix, A, "ls", lam_gn, tol=5e-3, kmax=cg, stats=stats)
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -359,36 +364,58 @@ def compare_batching(tt, ix, A, M, R, lam, cg, stats, dev, reps=3):
                                   "workload": "200^3, 40,000 nonzeros, R = 10, FP64"}}
 
 
-def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev):
+def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev, gn_steps=0, lam_gn=1e-3, kmax=30):
     """ALS from the same FP32 start with FP32 and with BF16 factor storage:
     per-sweep wall time (HIP events) and training RMSE (TTTP loss epilogue,
-    lambda = 0).  Equal RMSE means |RMSE_bf16 / RMSE_f32 - 1| <= 1% after the
-    same number of sweeps."""
+    lambda = 0); then, from each form's ALS result, `gn_steps` Gauss-Newton
+    steps (least squares, PCG with at most `kmax` iterations), timed the same
+    way.  Equal RMSE means |RMSE_bf16 / RMSE_f32 - 1| <= 1% after the same
+    number of sweeps (steps)."""
     import torch
     out = {}
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    def rmse(A):
+        return (tt.objective(ix, A, "ls", 0.0).item() / wl.nnz) ** 0.5
+
     for form, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
         A = [torch.as_tensor(a).to(dev).to(dt).contiguous() for a in A0]
         info = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
-        ms, rmse = [], []
+        rec = {"sweep_ms": [], "rmse": []}
         for _ in range(sweeps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            tt.als_sweep(ix, A, lam, info)
-            e1.record()
-            e1.synchronize()
-            ms.append(e0.elapsed_time(e1))
-            rmse.append((tt.objective(ix, A, "ls", 0.0).item() / wl.nnz) ** 0.5)
-        out[form] = {"sweep_ms": ms, "rmse": rmse}
+            rec["sweep_ms"].append(timed(lambda: tt.als_sweep(ix, A, lam, info)))
+            rec["rmse"].append(rmse(A))
+        if gn_steps:
+            stats = torch.zeros(4, dtype=torch.float64, device=dev)
+            rec["gn_ms"], rec["gn_rmse"] = [], []
+            for _ in range(gn_steps):
+                rec["gn_ms"].append(timed(lambda: tt.gn_step(ix, A, "ls", lam_gn, tol=5e-3,
+                                                             kmax=kmax, stats=stats)))
+                rec["gn_rmse"].append(rmse(A))
+        out[form] = rec
     r32, r16 = out["f32"]["rmse"][-1], out["bf16"]["rmse"][-1]
     out["rmse_ratio_bf16_over_f32"] = r16 / r32
     out["equal_rmse_within_1pct"] = abs(r16 / r32 - 1.0) <= 0.01
     out["sweep_speedup_bf16"] = (sum(out["f32"]["sweep_ms"][1:]) /
                                  max(1e-9, sum(out["bf16"]["sweep_ms"][1:])))
+    if gn_steps:
+        g32, g16 = out["f32"]["gn_rmse"][-1], out["bf16"]["gn_rmse"][-1]
+        out["gn_rmse_ratio_bf16_over_f32"] = g16 / g32
+        out["gn_equal_rmse_within_1pct"] = abs(g16 / g32 - 1.0) <= 0.01
+        out["gn_speedup_bf16"] = sum(out["f32"]["gn_ms"]) / max(1e-9, sum(out["bf16"]["gn_ms"]))
+        out["gn_kmax"] = kmax
     return out
 
 
-def cpu_baseline(wl, A0, R, lam, sample, passes, gn=True):
+def cpu_baseline(wl, A0, R, lam, lam_gn, sample, passes, gn=True):
     """The FP64 oracle, as it stands, on a bounded sample: the first `sample`
     nonzeros (COO order is draw order, i.e. random) of the same tensor, full
     dimensions, same step composition (ALS sweep over the sampled rows, then
@@ -417,13 +444,13 @@ def cpu_baseline(wl, A0, R, lam, sample, passes, gn=True):
             A[n] = A[n].copy()
             A[n][rows] = X
         if gn:
-            O.objective(idx, t, A, O.LOSS_LS, lam)
-            g = O.gradient(idx, t, A, O.LOSS_LS, lam, wl.dims)
+            O.objective(idx, t, A, O.LOSS_LS, lam_gn)
+            g = O.gradient(idx, t, A, O.LOSS_LS, lam_gn, wl.dims)
             for n in range(3):
                 O.gram(idx, np.full(sample, 2.0), A, n, wl.dims[n], rows=ixs[n]["rows"])
             w = np.full(sample, 2.0)
             for _ in range((passes - 13) // 3):
-                O.gn_matvec(idx, w, A, g, 2 * lam, wl.dims)
+                O.gn_matvec(idx, w, A, g, 2 * lam_gn, wl.dims)
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
