@@ -357,8 +357,27 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
   md.h_multi_row.clear();
   for (int64_t i = 0; i < md.I; ++i)
     if (row_task[i + 1] - row_task[i] > kReduceMin) md.h_multi_row.push_back((int32_t)i);
+  md.h_solo_row.clear();
+  md.h_rest_row.clear();
+  md.h_light_task.clear();
+  md.h_solo_nnz.assign(1, 0);
+  for (int64_t i = 0; i < md.I; ++i) {
+    const int32_t a = row_task[i], b = row_task[i + 1];
+    if (b - a == 1 && task[a + 1] - task[a] <= ix->tune.gram_light) {
+      md.h_solo_row.push_back((int32_t)i);
+      md.h_solo_nnz.push_back(md.h_solo_nnz.back() + task[a + 1] - task[a]);
+    } else {
+      md.h_rest_row.push_back((int32_t)i);
+      if (b - a > 1)
+        for (int32_t q = a; q < b; ++q)
+          if (task[q + 1] - task[q] <= ix->tune.gram_light) md.h_light_task.push_back(q);
+    }
+  }
   TT_ST(upload(L, &md.d_heavy_task, md.h_heavy_task, s));
   TT_ST(upload(L, &md.d_multi_row, md.h_multi_row, s));
+  TT_ST(upload(L, &md.d_solo_row, md.h_solo_row, s));
+  TT_ST(upload(L, &md.d_rest_row, md.h_rest_row, s));
+  TT_ST(upload(L, &md.d_light_task, md.h_light_task, s));
   // uploads are asynchronous from pageable vectors: wait before they go
   if ((he = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(he, "upload");
   ix->max_nchunk = ix->max_nslot = ix->max_nseg = 0;

@@ -63,6 +63,16 @@ struct ModeIndex {
   std::vector<int32_t> h_heavy_task;
   int32_t *d_multi_row = nullptr;   // rows with > kReduceMin tasks
   std::vector<int32_t> h_multi_row;
+  // rows whose only Gram task is light: their Gram is formed inside the
+  // solve kernel (no workspace); the other rows; the light tasks of rows
+  // with several tasks (all ascending)
+  int32_t *d_solo_row = nullptr;
+  std::vector<int32_t> h_solo_row;
+  std::vector<int64_t> h_solo_nnz;  // prefix sums of the solo rows' nonzeros
+  int32_t *d_rest_row = nullptr;
+  std::vector<int32_t> h_rest_row;
+  int32_t *d_light_task = nullptr;
+  std::vector<int32_t> h_light_task;
   double mean_row = 0.0;            // m / nrows
 };
 

@@ -363,8 +363,10 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, flo
     }
 }
 
-// Light tasks: one wave per task, four tasks per workgroup; tasks with more
-// than d.light nonzeros are left to k_gram_f32_heavy.
+// Light tasks of rows with several tasks (the `tasks` list): one wave per
+// task, four tasks per workgroup.  Rows whose only task is light form their
+// Gram inside k_solve_solo; tasks with more than d.light nonzeros go to
+// k_gram_f32_heavy.
 // Fused right-hand side of one task: lanes l, l + 16, l + 32, l + 48 hold
 // the same columns for different nonzeros; their FP64 sums are added in a
 // fixed butterfly and lanes 0..15 store the task's RP partial entries.
@@ -381,11 +383,12 @@ __device__ __forceinline__ void rhs_store(double *M, const GramAcc<RP> &acc, int
 }
 
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
-__global__ __launch_bounds__(256) void k_gram_f32(GramDev d) {
-  const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= d.task_end) return;
+__global__ __launch_bounds__(256) void k_gram_f32(GramDev d, const int32_t *tasks,
+                                                  int64_t ntasks) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= ntasks) return;
+  const int64_t t = tasks[q];
   const int64_t nb = d.task[t], ne = d.task[t + 1];
-  if (d.split_heavy && ne - nb > d.light) return;
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, nb, ne, acc);
@@ -567,6 +570,7 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 
 struct SolveDev {
+  const int32_t *rows;       // rows of the launch (NULL: r0 + block index)
   const int32_t *row_task;   // I + 1
   int64_t task_base;
   int64_t r0;                // first row of the batch
@@ -687,8 +691,10 @@ struct PanelBuf {
 // holds b_i; at pivot k, y_k = b_k / L(k, k) is broadcast and lanes i > k
 // subtract L(i, k) y_k, the multiplier they have just computed), so b
 // holds y on return.
+// The row's Gram is the sum of `ntask` consecutive tile-layout matrices at
+// gbase (task workspace, or the LDS copy of a Gram formed in the kernel).
 template <class GT, int RP, bool FWD>
-__device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t t1,
+__device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, int ntask,
                                           int lane, double *Lp, double *Pn,
                                           double &rdiag, double &b) {
   constexpr int NB = RP / 16;
@@ -698,13 +704,17 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, int32_t t0, int32_t
   f64x4 acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int32_t t = t0; t < t1; ++t) {
-    const GT *g = reinterpret_cast<const GT *>(d.G) + ((int64_t)t - d.task_base) * SZ + lane;
+  for (int t = 0; t < ntask; ++t) {
+    const GT *g = gbase + (int64_t)t * SZ + lane;
 #pragma unroll
     for (int q = 0; q < NT; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[q][v] += (double)g[256 * q + 64 * v];
   }
+  // the Gram may live in LDS that the factorization overwrites: no later
+  // memory access moves above these loads (a wave's LDS accesses complete in
+  // program order)
+  asm volatile("" ::: "memory");
   {
     // shift, identity on the padding, zero above the diagonal of the
     // diagonal tiles (those slots are not written by the Gram kernels)
@@ -798,7 +808,7 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   __shared__ double Pn[PanelBuf<RP>::SIZE];
   if (d.skip && *d.skip != 0.0) return;
   const int lane = threadIdx.x;
-  const int64_t row = d.r0 + blockIdx.x;
+  const int64_t row = d.rows ? (int64_t)d.rows[blockIdx.x] : d.r0 + blockIdx.x;
   const int R = d.R;
   const int32_t t0 = d.row_task[row];
   int32_t t1 = d.row_task[row + 1];
@@ -818,8 +828,11 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
       b = (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane];
     }
   }
-  const int info = d.factor_only ? chol_tiles<GT, RP, false>(d, t0, t1, lane, Lp, Pn, rdiag, b)
-                                 : chol_tiles<GT, RP, true>(d, t0, t1, lane, Lp, Pn, rdiag, b);
+  constexpr int SZ = gram_task_elems(RP);
+  const GT *gbase = reinterpret_cast<const GT *>(d.G) + ((int64_t)t0 - d.task_base) * SZ;
+  const int info = d.factor_only
+                       ? chol_tiles<GT, RP, false>(d, gbase, t1 - t0, lane, Lp, Pn, rdiag, b)
+                       : chol_tiles<GT, RP, true>(d, gbase, t1 - t0, lane, Lp, Pn, rdiag, b);
   if (d.info && lane == 0) d.info[row] = info;
   if (info && d.Lstore) {
     // failed rows keep the identity (no preconditioning for that block)
@@ -834,6 +847,63 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   // b holds y = L^{-1} rhs; backward substitution L^T x = y
   const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+}
+
+// Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
+// the row's Gram on the matrix cores (gram_accum), stores it in the
+// tile layout into the LDS that the factorization later reuses for L, and
+// factors and solves it there, so the Gram never goes to the workspace.
+// The fused right-hand side is reduced over the four nonzero groups with
+// the butterfly of rhs_store.  Otherwise as k_solve_rows.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
+__global__ __launch_bounds__(64) void k_solve_solo(GramDev g, SolveDev d) {
+  using P = Packed<RP>;
+  using XT = typename TR::T;
+  constexpr int VW = RP / 16;
+  static_assert(gram_task_elems(RP) <= 2 * P::PS, "the Gram fits below Lp[ZERO]");
+  __shared__ double Lp[P::LDS];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  if (d.skip && *d.skip != 0.0) return;
+  const int lane = threadIdx.x;
+  const int64_t row = d.rows[blockIdx.x];
+  const int R = d.R;
+  const int32_t t = d.row_task[row];
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, g.task[t], g.task[t + 1], acc);
+  float *Gl = reinterpret_cast<float *>(Lp);
+  gram_store<RP>(Gl, acc, g.w ? 1.f : (float)g.w_scale);
+  double b = 0.0;
+  if constexpr (RHS) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      double x = acc.m[v];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      if (lane < 16) Pn[VW * lane + v] = x;
+    }
+    const double bv = Pn[lane < RP ? lane : 0];
+    b = lane < R ? bv : 0.0;
+  } else if (!FO && lane < R) {
+    b = (double)reinterpret_cast<const float *>(d.rhs)[row * R + lane];
+  }
+  asm volatile("" ::: "memory");
+  if (lane == 0) Lp[P::ZERO] = 0.0;
+  double rdiag = 1.0;
+  const int info = chol_tiles<float, RP, !FO>(d, Gl, 1, lane, Lp, Pn, rdiag, b);
+  if (d.info && lane == 0) d.info[row] = info;
+  if (info && d.Lstore) {
+    for (int q = lane; q < P::PS; q += 64) Lp[q] = 0.0;
+    if (lane < RP) Lp[(lane * (lane + 3)) / 2] = 1.0;
+  }
+  if (d.Lstore) {
+    float *L = reinterpret_cast<float *>(d.Lstore) + row * (int64_t)P::PS;
+    for (int q = lane; q < P::PS; q += 64) L[q] = (float)Lp[q];
+  }
+  if constexpr (!FO) {
+    const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
+    if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+  }
 }
 
 // Apply stored factors to a right-hand side: X = (L L^T)^{-1} rhs.  The
@@ -889,18 +959,26 @@ static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipSt
   return hipGetLastError();
 }
 
+// One batch of the FP32 / BF16 forms: heavy tasks, the light tasks of
+// rows with several tasks, and (solo != NULL) the fused Gram + solve of the
+// rows whose only task is light.
+struct GramLists {
+  const int32_t *heavy, *light, *solo;
+  int64_t nheavy, nlight, nsolo;
+  double light_bytes, light_flops, heavy_bytes, heavy_flops, solo_bytes, solo_flops;
+};
+
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
-static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
-                               double light_bytes, double light_flops, double heavy_bytes,
-                               double heavy_flops, hipStream_t s) {
-  const int64_t n = d.task_end - d.task_base;
-  d.split_heavy = 1;
-  {
-    ProfScope ps("gram_light", s, light_bytes, light_flops);
-    k_gram_f32<TR, RP, VEC, WEIGHTED, RHS><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(d);
+static void launch_gram_f32_rp(GramDev d, const GramLists &gl, hipStream_t s) {
+  const int32_t *heavy = gl.heavy;
+  const int64_t nheavy = gl.nheavy;
+  if (gl.nlight > 0) {
+    ProfScope ps("gram_light", s, gl.light_bytes, gl.light_flops);
+    k_gram_f32<TR, RP, VEC, WEIGHTED, RHS><<<dim3((unsigned)((gl.nlight + 3) / 4)), dim3(256), 0, s>>>(
+        d, gl.light, gl.nlight);
   }
   if (nheavy > 0) {
-    ProfScope ps("gram_heavy", s, heavy_bytes, heavy_flops);
+    ProfScope ps("gram_heavy", s, gl.heavy_bytes, gl.heavy_flops);
     const dim3 g((unsigned)nheavy);
     switch (d.waves) {
       case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 2><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
@@ -910,28 +988,55 @@ static void launch_gram_f32_rp(GramDev d, const int32_t *heavy, int64_t nheavy,
   }
 }
 
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+static void launch_solo_rp(const GramDev &d, const SolveDev &sd, const GramLists &gl,
+                           hipStream_t s) {
+  if (gl.nsolo <= 0) return;
+  ProfScope ps(sd.factor_only ? "gram_factor_light" : "gram_solve_light", s, gl.solo_bytes,
+               gl.solo_flops);
+  SolveDev sd2 = sd;
+  sd2.rows = gl.solo;
+  const dim3 grid((unsigned)gl.nsolo), block(64);
+  if constexpr (RHS) {
+    // the fused right-hand side always comes with a solve
+    k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+  } else {
+    if (sd.factor_only)
+      k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, true><<<grid, block, 0, s>>>(d, sd2);
+    else
+      k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+  }
+}
+
 // Vector loads of VW = RP / 16 entries need R, ldA and both factor bases
-// aligned to VW elements.
+// aligned to VW elements.  sd == NULL: the Gram kernels only; otherwise the
+// fused solo-row kernel only.
 template <class TR, int RP>
-static void launch_gram_f32_vec(const GramDev &d, const int32_t *heavy, int64_t nheavy,
-                                double lb, double lf, double hb, double hf, hipStream_t s) {
+static void launch_gram_f32_vec(const GramDev &d, const SolveDev *sd, const GramLists &gl,
+                                hipStream_t s) {
   constexpr int VW = RP / 16;
   constexpr size_t al = VW * sizeof(typename TR::T);
   const bool vec = d.R % VW == 0 && d.ldA % VW == 0 &&
                    reinterpret_cast<uintptr_t>(d.A0) % al == 0 &&
                    reinterpret_cast<uintptr_t>(d.A1) % al == 0;
+#define TT_GRAM_CASE(V, W, H)                                    \
+  do {                                                           \
+    if (sd) launch_solo_rp<TR, RP, V, W, H>(d, *sd, gl, s);      \
+    else launch_gram_f32_rp<TR, RP, V, W, H>(d, gl, s);          \
+  } while (0)
   // weighted Grams (the Gauss-Newton preconditioner) never carry a fused
   // right-hand side
   if (d.w) {
-    if (vec) launch_gram_f32_rp<TR, RP, true, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
-    else launch_gram_f32_rp<TR, RP, false, true, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    if (vec) TT_GRAM_CASE(true, true, false);
+    else TT_GRAM_CASE(false, true, false);
   } else if (d.M) {
-    if (vec) launch_gram_f32_rp<TR, RP, true, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
-    else launch_gram_f32_rp<TR, RP, false, false, true>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    if (vec) TT_GRAM_CASE(true, false, true);
+    else TT_GRAM_CASE(false, false, true);
   } else {
-    if (vec) launch_gram_f32_rp<TR, RP, true, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
-    else launch_gram_f32_rp<TR, RP, false, false, false>(d, heavy, nheavy, lb, lf, hb, hf, s);
+    if (vec) TT_GRAM_CASE(true, false, false);
+    else TT_GRAM_CASE(false, false, false);
   }
+#undef TT_GRAM_CASE
 }
 
 // Gram of one batch of tasks [task_base, task_end): light tasks one wave
@@ -941,11 +1046,12 @@ struct GramWork {
   double light_nnz, heavy_nnz, light_tasks, reduce_tasks;
 };
 
-static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int32_t *heavy,
-                              int64_t nheavy, const int32_t *multi, int64_t nmulti,
+static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const GramLists &gl,
+                              const int32_t *multi, int64_t nmulti,
                               const int32_t *row_task, const GramWork &wk, hipStream_t s) {
   const int64_t n = d.task_end - d.task_base;
   if (n <= 0) return hipSuccess;
+  const int64_t nheavy = gl.nheavy;
   dim3 g((unsigned)((n + 3) / 4)), b(256);
   const double R = d.R, fb = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
   const double gs = fdt == TT_F64 ? 8 : 4,
@@ -962,21 +1068,22 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
       default: k_gram_f64<64><<<g, b, 0, s>>>(d2); break;
     }
   } else {
-    const double lb = wk.light_nnz * pernz + wk.light_tasks * tile;
-    const double lf = wk.light_nnz * R * (R + 1);
-    const double hb = wk.heavy_nnz * pernz + (double)nheavy * tile;
-    const double hf = wk.heavy_nnz * R * (R + 1);
+    GramLists g2 = gl;
+    g2.light_bytes = wk.light_nnz * pernz + wk.light_tasks * tile;
+    g2.light_flops = wk.light_nnz * R * (R + 1);
+    g2.heavy_bytes = wk.heavy_nnz * pernz + (double)nheavy * tile;
+    g2.heavy_flops = wk.heavy_nnz * R * (R + 1);
     if (fdt == TT_F32) {
       switch (RP) {
-        case 16: launch_gram_f32_vec<TrF32, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        case 32: launch_gram_f32_vec<TrF32, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        default: launch_gram_f32_vec<TrF32, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 16: launch_gram_f32_vec<TrF32, 16>(d, nullptr, g2, s); break;
+        case 32: launch_gram_f32_vec<TrF32, 32>(d, nullptr, g2, s); break;
+        default: launch_gram_f32_vec<TrF32, 64>(d, nullptr, g2, s); break;
       }
     } else {
       switch (RP) {
-        case 16: launch_gram_f32_vec<TrBF16, 16>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        case 32: launch_gram_f32_vec<TrBF16, 32>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
-        default: launch_gram_f32_vec<TrBF16, 64>(d, heavy, nheavy, lb, lf, hb, hf, s); break;
+        case 16: launch_gram_f32_vec<TrBF16, 16>(d, nullptr, g2, s); break;
+        case 32: launch_gram_f32_vec<TrBF16, 32>(d, nullptr, g2, s); break;
+        default: launch_gram_f32_vec<TrBF16, 64>(d, nullptr, g2, s); break;
       }
     }
   }
@@ -1003,6 +1110,26 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const int3
           default: k_rhs_reduce<64><<<dim3((unsigned)nmulti), 256, 0, s>>>(multi, row_task, d.task_base, d.M); break;
         }
       }
+    }
+  }
+  return hipGetLastError();
+}
+
+// Fused Gram + Cholesky of the solo rows of one batch (FP32 / BF16 forms).
+static hipError_t launch_solo(tt_dtype fdt, int RP, const GramDev &d, const SolveDev &sd,
+                              const GramLists &gl, hipStream_t s) {
+  if (gl.nsolo <= 0) return hipSuccess;
+  if (fdt == TT_F32) {
+    switch (RP) {
+      case 16: launch_gram_f32_vec<TrF32, 16>(d, &sd, gl, s); break;
+      case 32: launch_gram_f32_vec<TrF32, 32>(d, &sd, gl, s); break;
+      default: launch_gram_f32_vec<TrF32, 64>(d, &sd, gl, s); break;
+    }
+  } else {
+    switch (RP) {
+      case 16: launch_gram_f32_vec<TrBF16, 16>(d, &sd, gl, s); break;
+      case 32: launch_gram_f32_vec<TrBF16, 32>(d, &sd, gl, s); break;
+      default: launch_gram_f32_vec<TrBF16, 64>(d, &sd, gl, s); break;
     }
   }
   return hipGetLastError();
@@ -1050,6 +1177,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.M = Mws;
 
   SolveDev sd;
+  sd.rows = nullptr;
   sd.row_task = md.d_row_task;
   sd.G = Gws;
   sd.R = c.R;
@@ -1081,31 +1209,75 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     const int64_t h1 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r1]) - ht.begin();
     const int64_t q0 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r0) - mr.begin();
     const int64_t q1 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r1) - mr.begin();
+    const bool f64 = c.fdt == TT_F64;
+    // FP32 / BF16 forms: rows whose only task is light are solved by the
+    // fused kernel; the Gram kernels take the heavy tasks and the light tasks
+    // of rows with several tasks; the solve kernel takes the other rows
+    GramLists gl = {};
+    gl.heavy = md.d_heavy_task + h0;
+    gl.nheavy = h1 - h0;
+    int64_t p0 = 0, p1 = 0;
     GramWork wk;
     const std::vector<int64_t> &hn = md.h_heavy_nnz;
     wk.heavy_nnz = (double)(hn[h1] - hn[h0]);
-    wk.light_nnz = (double)(md.h_task[rt[r1]] - md.h_task[rt[r0]]) - wk.heavy_nnz;
-    wk.light_tasks = (double)(rt[r1] - rt[r0]) - (double)(h1 - h0);
     wk.reduce_tasks = 0;
     for (int64_t q = q0; q < q1; ++q) wk.reduce_tasks += rt[mr[q] + 1] - rt[mr[q]];
-    hipError_t e = launch_gram(c.fdt, RP, gd, md.d_heavy_task + h0, h1 - h0,
-                               md.d_multi_row + q0, q1 - q0, md.d_row_task, wk, s);
+    if (f64) {
+      wk.light_nnz = (double)(md.h_task[rt[r1]] - md.h_task[rt[r0]]) - wk.heavy_nnz;
+      wk.light_tasks = (double)(rt[r1] - rt[r0]) - (double)(h1 - h0);
+    } else {
+      const std::vector<int32_t> &lt = md.h_light_task, &so = md.h_solo_row,
+                                 &re = md.h_rest_row;
+      const int64_t l0 = std::lower_bound(lt.begin(), lt.end(), (int32_t)rt[r0]) - lt.begin();
+      const int64_t l1 = std::lower_bound(lt.begin(), lt.end(), (int32_t)rt[r1]) - lt.begin();
+      const int64_t s0 = std::lower_bound(so.begin(), so.end(), (int32_t)r0) - so.begin();
+      const int64_t s1 = std::lower_bound(so.begin(), so.end(), (int32_t)r1) - so.begin();
+      p0 = std::lower_bound(re.begin(), re.end(), (int32_t)r0) - re.begin();
+      p1 = std::lower_bound(re.begin(), re.end(), (int32_t)r1) - re.begin();
+      gl.light = md.d_light_task + l0;
+      gl.nlight = l1 - l0;
+      gl.solo = md.d_solo_row + s0;
+      gl.nsolo = s1 - s0;
+      wk.light_tasks = (double)(l1 - l0);
+      wk.light_nnz = 0;
+      for (int64_t q = l0; q < l1; ++q)
+        wk.light_nnz += (double)(md.h_task[lt[q] + 1] - md.h_task[lt[q]]);
+      // fused solo rows: gathers of their nonzeros, the solve's own traffic
+      const double Rd = c.R, fb = (double)dtype_size(c.fdt), nsolo = (double)gl.nsolo;
+      const double snnz = (double)(md.h_solo_nnz[s1] - md.h_solo_nnz[s0]);
+      gl.solo_bytes = snnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + 2 * Rd * fb) +
+                      nsolo * Rd * (4 + fb) +
+                      (c.Lstore ? nsolo * RP * (RP + 1) / 2 * 4.0 : 0.0);
+      gl.solo_flops = snnz * Rd * (Rd + 1) +
+                      nsolo * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd));
+    }
+    hipError_t e = launch_gram(c.fdt, RP, gd, gl, md.d_multi_row + q0, q1 - q0,
+                               md.d_row_task, wk, s);
     if (e != hipSuccess) return hip_fail(e, "gram kernel");
     sd.task_base = rt[r0];
     sd.r0 = r0;
-    const double Rd = c.R, nrow = (double)(r1 - r0);
-    ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
-                 (double)(rt[r1] - rt[r0]) * gram_task_elems(RP) * (double)gsz +
-                     nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
-                     (c.Lstore ? nrow * RP * (RP + 1) / 2 * (double)gsz : 0.0),
-                 nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
-    if (c.fdt == TT_F64)
-      e = launch_solve_rp<double, double, double>(RP, sd, r1 - r0, s);
-    else if (c.fdt == TT_F32)
-      e = launch_solve_rp<float, float, float>(RP, sd, r1 - r0, s);
-    else
-      e = launch_solve_rp<float, uint16_t, float>(RP, sd, r1 - r0, s);
+    const int64_t nrest = f64 ? r1 - r0 : p1 - p0;
+    sd.rows = f64 ? nullptr : md.d_rest_row + p0;
+    const double Rd = c.R, nrow = (double)nrest;
+    {
+      ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
+                   (double)(rt[r1] - rt[r0] - (f64 ? 0 : gl.nsolo)) * gram_task_elems(RP) *
+                           (double)gsz +
+                       nrow * Rd * (double)(gsz + dtype_size(c.fdt)) +
+                       (c.Lstore ? nrow * RP * (RP + 1) / 2 * (double)gsz : 0.0),
+                   nrow * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
+      if (c.fdt == TT_F64)
+        e = launch_solve_rp<double, double, double>(RP, sd, nrest, s);
+      else if (c.fdt == TT_F32)
+        e = launch_solve_rp<float, float, float>(RP, sd, nrest, s);
+      else
+        e = launch_solve_rp<float, uint16_t, float>(RP, sd, nrest, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
+    if (!f64) {
+      e = launch_solo(c.fdt, RP, gd, sd, gl, s);
+      if (e != hipSuccess) return hip_fail(e, "fused solve kernel");
+    }
     r0 = r1;
   }
   return TT_OK;
