@@ -587,21 +587,25 @@ struct SolveDev {
   const double *skip;
 };
 
-// Pivot of step k: 1 / sqrt(d) for d > 0.  The hardware reciprocal square
-// root estimate is refined by two Newton steps y <- y + y (1 - d y^2) / 2
-// (each squares the relative error, so the result is within a few ulp).
-// Pivots below 2^-900 are scaled by 2^960 first and the result by 2^480
-// (both exact), so d y^2 neither underflows nor overflows.
-__device__ __forceinline__ double rsqrt_pivot(double d) {
-  const bool tiny = d < 0x1p-900;
-  const double ds = tiny ? d * 0x1p960 : d;
-  double y = __builtin_amdgcn_rsq(ds);
+// Pivot of step k: 1 / sqrt(d) for d > 0 (d is the broadcast pivot, the
+// same on every lane, so the branch below is uniform).  The hardware
+// reciprocal square root estimate is refined by two Newton steps
+// y <- y + y (1 - d y^2) / 2 (each squares the relative error, so the result
+// is within a few ulp).  Pivots below 2^-900 are scaled by 2^960 first and
+// the result by 2^480 (both exact), so d y^2 neither underflows nor
+// overflows.
+__device__ __forceinline__ double rsqrt_newton(double d) {
+  double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    const double e = fma(-ds, y * y, 1.0);
+    const double e = fma(-d, y * y, 1.0);
     y = fma(0.5 * y, e, y);
   }
-  return tiny ? y * 0x1p480 : y;
+  return y;
+}
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+  if (__builtin_expect(d < 0x1p-900, 0)) return rsqrt_newton(d * 0x1p960) * 0x1p480;
+  return rsqrt_newton(d);
 }
 
 // A copy of the lane index that the compiler cannot identify with the
