@@ -92,6 +92,36 @@ def test_gn_step_f64_matches_oracle(gpu_lib, loss):
         np.testing.assert_allclose(host(A[d]), Ar[d], rtol=1e-7, atol=1e-9)
 
 
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+def test_gn_step_f32_matches_oracle(gpu_lib, loss):
+    """FP32 form (rows of one light Gram task: preconditioner factors formed
+    by the fused Gram + Cholesky kernel and stored in FP32): same PCG
+    iteration count as the FP64 oracle from the same FP32 inputs, and the
+    same step up to FP32 rounding."""
+    tt = gpu_lib
+    wl = W.random_tensor((12, 10, 14), 500, 21, rank=3, noise=0.0)
+    R = 4
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    t = stored_values(wl.t if loss == "ls" else np.round(np.exp(0.5 * wl.t)), "f32")
+    lam = 1e-3 if loss == "ls" else 0.1
+    mean_model = float(np.mean(t)) if loss == "ls" else float(np.log(np.mean(t) + 1))
+    A0 = stored_factors(W.init_factors(wl.dims, R, mean_model, 8, dtype=np.float64), "f32")
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f32"))
+    A = [dev_factor(a, "f32") for a in A0]
+    kmax = 30 if loss == "ls" else R
+    stats = tt.gn_step(ix, A, loss, lam, tol=5e-3, kmax=kmax)
+    Ar, it, rel = O.gn_step(wl.idx, t, A0, wl.dims, L, lam, 5e-3, kmax)
+    s = stats.cpu().numpy()
+    assert abs(int(s[0]) - it) <= 1, f"iterations {s[0]} vs {it}"
+    dx = np.concatenate([(host(A[d]) - A0[d]).ravel() for d in range(3)])
+    dr = np.concatenate([(Ar[d] - A0[d]).ravel() for d in range(3)])
+    if int(s[0]) == it:
+        assert abs(s[1] - rel) <= 1e-3 * max(rel, 1e-3)
+        assert np.linalg.norm(dx - dr) <= 1e-3 * np.linalg.norm(dr)
+    else:  # stopped one iteration apart at the tolerance: same direction
+        assert float(dx @ dr) >= 0.99 * np.linalg.norm(dx) * np.linalg.norm(dr)
+
+
 def test_gn_step_decreases_objective_f32(gpu_lib):
     tt = gpu_lib
     wl = W.random_tensor((40, 30, 35), 6000, 5, rank=3, noise=0.01)
