@@ -179,10 +179,12 @@ template <int NP>
 __device__ __forceinline__ void split_bf16(float x, uint32_t (&p)[NP]) {
   float r = x;
 #pragma unroll
-  for (int i = 0; i < NP; ++i) {
+  for (int i = 0; i + 1 < NP; ++i) {
     p[i] = bf16_head(r);
     r -= __uint_as_float(p[i]);
   }
+  // what remains has at most 8 significant bits: a bf16 value as it is
+  p[NP - 1] = __float_as_uint(r);
 }
 
 // Products of parts kept for h_a h_b^T: part i of the A side times part j of
@@ -256,8 +258,10 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   if (nblk > 1) load_block(1, nr0, nr1, nw, nt);
   int64_t cblk = 0;
 
-  for (int64_t st = 0; st < nst; ++st) {
-    const bool tail = ragged && st == nst - 1;  // uniform
+  // one step; only the last step of a ragged range (TAIL) has nonzeros past
+  // the end, so the others carry no validity code
+  auto step = [&](int64_t st, auto tail_tag) {
+    constexpr bool tail = decltype(tail_tag)::value;
     const int64_t blk = st >> 1;
     if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
       cr0 = nr0; cr1 = nr1; cw = nw; ct = nt;
@@ -337,8 +341,19 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
         ++q;
       }
     __builtin_amdgcn_sched_barrier(0);
-  }
+  };
+  const int64_t nfull = ragged ? nst - 1 : nst;
+  for (int64_t st = 0; st < nfull; ++st) step(st, std::false_type{});
+  if (ragged) step(nst - 1, std::true_type{});
 }
+
+// Waves per SIMD the Gram kernels are compiled for: at RP = 64 the
+// unweighted forms fit 3 (register-limited otherwise to 2), which hides
+// more of the gather latency of each 32-nonzero step.
+template <int RP, bool WEIGHTED>
+struct GramOcc {
+  static constexpr int value = (RP == 64 && !WEIGHTED) ? 3 : 1;
+};
 
 // Write G in the lower-tile layout from the accumulators (each unordered
 // column pair once).  v_mfma_f32_16x16x4f32 result: lane l, register v holds
@@ -383,8 +398,9 @@ __device__ __forceinline__ void rhs_store(double *M, const GramAcc<RP> &acc, int
 }
 
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
-__global__ __launch_bounds__(256) void k_gram_f32(GramDev d, const int32_t *tasks,
-                                                  int64_t ntasks) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32(
+    GramDev d, const int32_t *tasks, int64_t ntasks) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= ntasks) return;
   const int64_t t = tasks[q];
@@ -400,7 +416,8 @@ __global__ __launch_bounds__(256) void k_gram_f32(GramDev d, const int32_t *task
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, int NW>
-__global__ __launch_bounds__(64 * NW) void k_gram_f32_heavy(
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
   constexpr int NV = GramAcc<RP>::NV;
   constexpr int VW = RP / 16;
