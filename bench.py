@@ -309,7 +309,8 @@ def main():
 
 def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
     """The step recorded once as a graph (tt_graph_begin/end) and replayed,
-    against the same calls launched one by one; and the same comparison for
+    against the same calls launched one by one, each also with persistent
+    solve kernels (tuning solve_wgs = 8); and the same comparison for
     one ALS sweep on the 200^3 cube (40,000 nonzeros, R = 10, FP64), where
     launch overheads dominate.  Milliseconds per step / sweep (HIP events)."""
     import numpy as np
@@ -341,6 +342,23 @@ def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
         graph = timed_ms(g.launch, reps)
     torch.cuda.current_stream().wait_stream(side)
     g.close()
+    # persistent solve kernels (a grid of 8 workgroups per compute unit that
+    # strides over a batch's rows), launched one by one and as a graph
+    torch.cuda.synchronize()
+    t0 = ix.tuning()
+    ix.tune(solve_wgs=8)
+    ix.reserve(R, tt.fdt_of(A), gn="ls")
+    with torch.cuda.stream(side):
+        step()
+        pers = timed_ms(step, reps)
+        gp = tt.capture(step)
+        gp.launch()
+        pers_graph = timed_ms(gp.launch, reps)
+    torch.cuda.current_stream().wait_stream(side)
+    gp.close()
+    torch.cuda.synchronize()
+    ix.tune(**t0)
+    ix.reserve(R, tt.fdt_of(A), gn="ls")
 
     wl = W.cube()
     Rc = 10
@@ -359,7 +377,8 @@ def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
         graph_c = timed_ms(gc.launch, 20)
     torch.cuda.current_stream().wait_stream(side)
     gc.close()
-    return {"ratings_step_ms": {"plain": plain, "graph": graph},
+    return {"ratings_step_ms": {"plain": plain, "graph": graph, "persistent": pers,
+                                "persistent_graph": pers_graph},
             "cube_als_sweep_ms": {"plain": plain_c, "graph": graph_c,
                                   "workload": "200^3, 40,000 nonzeros, R = 10, FP64"}}
 

@@ -134,15 +134,20 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
  *   gram_light  Gram tasks with more nonzeros than this run on a workgroup
  *               of gram_waves waves, the others on one wave; 0 .. gram_piece
  *   gram_waves  2, 4 or 8
+ *   solve_wgs   0: the per-row solve kernels launch one workgroup per row;
+ *               1 .. 64: they run as persistent kernels, solve_wgs
+ *               workgroups per compute unit, each taking every grid-th row
+ *               of the batch in order
  * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
  * is not capturable); call tt_index_reserve again afterwards if the
- * workspace was reserved.  Defaults: 1024, 4096, 512, 4.
+ * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t chunk;
   int32_t gram_piece;
   int32_t gram_light;
   int32_t gram_waves;
+  int32_t solve_wgs;
 } tt_tuning;
 tt_status tt_index_tune(tt_index *ix, const tt_tuning *tuning, hipStream_t stream);
 tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out);

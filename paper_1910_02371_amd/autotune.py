@@ -28,6 +28,7 @@ KNOBS = {
     "gram_piece": (2048, 4096, 8192),
     "gram_light": (256, 512, 1024),
     "gram_waves": (2, 4, 8),
+    "solve_wgs": (0, 4, 8),
 }
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1910_02371_amd",

@@ -434,6 +434,8 @@ tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
            "gram_light %d outside [0, gram_piece]", t->gram_light);
   TT_CHECK(t->gram_waves == 2 || t->gram_waves == 4 || t->gram_waves == 8,
            "gram_waves %d is not 2, 4 or 8", t->gram_waves);
+  TT_CHECK(t->solve_wgs >= 0 && t->solve_wgs <= 64, "solve_wgs %d outside [0, 64]",
+           t->solve_wgs);
   ix->tune = *t;
   for (int n = 0; n < ix->N; ++n) TT_ST(build_partitions(ix, n, stream));
   return TT_OK;

@@ -464,6 +464,11 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
   ix->has_t = d_t != nullptr || m == 0;  // an empty value set is always available
   for (int n = 0; n < N; ++n) ix->dims[n] = dims[n];
   const size_t vsz = vdt == TT_F64 ? 8 : 4;
+  {
+    int dev = 0;
+    TT_HIP(hipGetDevice(&dev));
+    TT_HIP(hipDeviceGetAttribute(&ix->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  }
 
   // range check
   int *d_flag = nullptr;

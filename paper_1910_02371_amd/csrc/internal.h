@@ -20,6 +20,7 @@ constexpr int kChunkDefault = 1024;
 constexpr int kGramPieceDefault = 4096;
 constexpr int kGramLightDefault = 512;
 constexpr int kGramWavesDefault = 4;
+constexpr int kSolveWgsDefault = 0;
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
@@ -94,7 +95,8 @@ struct tt_index {
   std::map<std::string, tt::Buf> ws;         // named workspace buffers
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
   tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
-                    tt::kGramWavesDefault};
+                    tt::kGramWavesDefault, tt::kSolveWgsDefault};
+  int cu_count = 0;  // compute units of the device the index was built on
   // Gauss-Newton position map (built on first use, N x m): slot n != zmode
   // maps mode-n sorted positions to mode-zmode sorted positions
   int32_t *d_zmap = nullptr;

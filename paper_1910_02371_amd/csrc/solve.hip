@@ -587,7 +587,9 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 
 struct SolveDev {
-  const int32_t *rows;       // rows of the launch (NULL: r0 + block index)
+  const int32_t *rows;       // rows of the launch (NULL: r0 + position)
+  int64_t nrow;              // rows of the launch; the grid strides over them
+  int64_t grid_max;          // host side: 0, or the persistent grid size
   const int32_t *row_task;   // I + 1
   int64_t task_base;
   int64_t r0;                // first row of the batch
@@ -822,14 +824,11 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
   return 0;
 }
 
+// One row of k_solve_rows.
 template <class GT, class XT, class MT, int RP>
-__global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
+__device__ __forceinline__ void solve_row(const SolveDev &d, int64_t row, int lane, double *Lp,
+                                          double *Pn) {
   using P = Packed<RP>;
-  __shared__ double Lp[P::LDS];
-  __shared__ double Pn[PanelBuf<RP>::SIZE];
-  if (d.skip && *d.skip != 0.0) return;
-  const int lane = threadIdx.x;
-  const int64_t row = d.rows ? (int64_t)d.rows[blockIdx.x] : d.r0 + blockIdx.x;
   const int R = d.R;
   const int32_t t0 = d.row_task[row];
   int32_t t1 = d.row_task[row + 1];
@@ -870,28 +869,45 @@ __global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
 
-// Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
-// the row's Gram on the matrix cores (gram_accum), stores it in the
-// tile layout into the LDS that the factorization later reuses for L, and
-// factors and solves it there, so the Gram never goes to the workspace.
-// The fused right-hand side is reduced over the four nonzero groups with
-// the butterfly of rhs_store.  Otherwise as k_solve_rows.
+// PERSIST: a grid smaller than the row count, each workgroup taking every
+// gridDim.x-th row in order (one wave per workgroup, so the LDS is reused
+// across rows without barriers); otherwise one workgroup per row.
+template <class GT, class XT, class MT, int RP, bool PERSIST>
+__global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
+  using P = Packed<RP>;
+  __shared__ double Lp[P::LDS];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  if (d.skip && *d.skip != 0.0) return;
+  if constexpr (PERSIST) {
+    for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
+      // the lane index is re-derived per row (opaque), so the per-lane
+      // constants of the unrolled factorization are not held across rows
+      const int lane = opaque_lane(threadIdx.x);
+      solve_row<GT, XT, MT, RP>(d, d.rows ? (int64_t)d.rows[idx] : d.r0 + idx, lane, Lp, Pn);
+      asm volatile("" ::: "memory");
+    }
+  } else {
+    const int64_t idx = blockIdx.x;
+    solve_row<GT, XT, MT, RP>(d, d.rows ? (int64_t)d.rows[idx] : d.r0 + idx, threadIdx.x, Lp,
+                              Pn);
+  }
+}
+
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
-__global__ __launch_bounds__(64) void k_solve_solo(GramDev g, SolveDev d) {
+__device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev &d, int64_t row,
+                                               int lane, double *Lp, double *Pn) {
   using P = Packed<RP>;
   using XT = typename TR::T;
   constexpr int VW = RP / 16;
   static_assert(gram_task_elems(RP) <= 2 * P::PS, "the Gram fits below Lp[ZERO]");
-  __shared__ double Lp[P::LDS];
-  __shared__ double Pn[PanelBuf<RP>::SIZE];
-  if (d.skip && *d.skip != 0.0) return;
-  const int lane = threadIdx.x;
-  const int64_t row = d.rows[blockIdx.x];
   const int R = d.R;
   const int32_t t = d.row_task[row];
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, g.task[t], g.task[t + 1], acc);
+  // earlier LDS reads (a previous row's, one wave, program order) stay before
+  // these writes
+  asm volatile("" ::: "memory");
   float *Gl = reinterpret_cast<float *>(Lp);
   gram_store<RP>(Gl, acc, g.w ? 1.f : (float)g.w_scale);
   double b = 0.0;
@@ -924,6 +940,29 @@ __global__ __launch_bounds__(64) void k_solve_solo(GramDev g, SolveDev d) {
   if constexpr (!FO) {
     const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
     if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+  }
+}
+
+// Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
+// the row's Gram on the matrix cores (gram_accum), stores it in the tile
+// layout into the LDS that the factorization later reuses for L, and
+// factors and solves it there, so the Gram never goes to the workspace.
+// The fused right-hand side is reduced over the four nonzero groups with
+// the butterfly of rhs_store.  PERSIST as in k_solve_rows.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST>
+__global__ __launch_bounds__(64) void k_solve_solo(GramDev g, SolveDev d) {
+  using P = Packed<RP>;
+  __shared__ double Lp[P::LDS];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  if (d.skip && *d.skip != 0.0) return;
+  if constexpr (PERSIST) {
+    for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
+      const int lane = opaque_lane(threadIdx.x);  // per row (see k_solve_rows)
+      solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[idx], lane, Lp, Pn);
+      asm volatile("" ::: "memory");
+    }
+  } else {
+    solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[blockIdx.x], threadIdx.x, Lp, Pn);
   }
 }
 
@@ -968,14 +1007,30 @@ __global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore
 // ---------------------------------------------------------------------------
 static int rp_for(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
 
+// One workgroup per row, or a persistent grid of d.grid_max workgroups.
+static unsigned solve_grid(const SolveDev &d) {
+  return (unsigned)(d.grid_max > 0 ? std::min<int64_t>(d.nrow, d.grid_max) : d.nrow);
+}
+
 template <class GT, class XT, class MT>
-static hipError_t launch_solve_rp(int RP, const SolveDev &d, int64_t nrow, hipStream_t s) {
+static hipError_t launch_solve_rp(int RP, SolveDev d, int64_t nrow, hipStream_t s) {
   if (nrow <= 0) return hipSuccess;
-  dim3 g((unsigned)nrow), b(64);
+  d.nrow = nrow;
+  dim3 g(solve_grid(d)), b(64);
+  const bool pers = g.x < (unsigned)nrow;
   switch (RP) {
-    case 16: k_solve_rows<GT, XT, MT, 16><<<g, b, 0, s>>>(d); break;
-    case 32: k_solve_rows<GT, XT, MT, 32><<<g, b, 0, s>>>(d); break;
-    default: k_solve_rows<GT, XT, MT, 64><<<g, b, 0, s>>>(d); break;
+    case 16:
+      if (pers) k_solve_rows<GT, XT, MT, 16, true><<<g, b, 0, s>>>(d);
+      else k_solve_rows<GT, XT, MT, 16, false><<<g, b, 0, s>>>(d);
+      break;
+    case 32:
+      if (pers) k_solve_rows<GT, XT, MT, 32, true><<<g, b, 0, s>>>(d);
+      else k_solve_rows<GT, XT, MT, 32, false><<<g, b, 0, s>>>(d);
+      break;
+    default:
+      if (pers) k_solve_rows<GT, XT, MT, 64, true><<<g, b, 0, s>>>(d);
+      else k_solve_rows<GT, XT, MT, 64, false><<<g, b, 0, s>>>(d);
+      break;
   }
   return hipGetLastError();
 }
@@ -1017,16 +1072,22 @@ static void launch_solo_rp(const GramDev &d, const SolveDev &sd, const GramLists
                gl.solo_flops);
   SolveDev sd2 = sd;
   sd2.rows = gl.solo;
-  const dim3 grid((unsigned)gl.nsolo), block(64);
+  sd2.nrow = gl.nsolo;
+  const dim3 grid(solve_grid(sd2)), block(64);
+  const bool pers = grid.x < (unsigned)gl.nsolo;
+#define TT_SOLO(FO)                                                                    \
+  do {                                                                                 \
+    if (pers) k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, true><<<grid, block, 0, s>>>(d, sd2); \
+    else k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, false><<<grid, block, 0, s>>>(d, sd2); \
+  } while (0)
   if constexpr (RHS) {
     // the fused right-hand side always comes with a solve
-    k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+    TT_SOLO(false);
   } else {
-    if (sd.factor_only)
-      k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, true><<<grid, block, 0, s>>>(d, sd2);
-    else
-      k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+    if (sd.factor_only) TT_SOLO(true);
+    else TT_SOLO(false);
   }
+#undef TT_SOLO
 }
 
 // Vector loads of VW = RP / 16 entries need R, ldA and both factor bases
@@ -1211,6 +1272,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   sd.Lstore = c.Lstore;
   sd.factor_only = c.factor_only;
   sd.skip = nullptr;
+  sd.nrow = 0;
+  sd.grid_max = ix->tune.solve_wgs > 0 ? (int64_t)ix->tune.solve_wgs * std::max(ix->cu_count, 1) : 0;
 
   const std::vector<int32_t> &rt = md.h_row_task;
   const int64_t I = md.I;

@@ -8,7 +8,8 @@ from paper_1910_02371_amd import autotune as AT
 def test_descent_finds_separable_minimum():
     # separable cost with a known best setting; every evaluated candidate
     # must be valid, and no setting is evaluated twice
-    best = {"chunk": 512, "gram_piece": 8192, "gram_light": 1024, "gram_waves": 2}
+    best = {"chunk": 512, "gram_piece": 8192, "gram_light": 1024, "gram_waves": 2,
+            "solve_wgs": 8}
     seen = []
 
     def cost(t):
@@ -16,7 +17,8 @@ def test_descent_finds_separable_minimum():
         return 10.0 + sum(0.0 if t[k] == best[k] else 1.0 + AT.KNOBS[k].index(t[k])
                           for k in t)
 
-    start = {"chunk": 1024, "gram_piece": 4096, "gram_light": 512, "gram_waves": 4}
+    start = {"chunk": 1024, "gram_piece": 4096, "gram_light": 512, "gram_waves": 4,
+             "solve_wgs": 0}
     got, t, trials = AT.coordinate_descent(start, cost)
     assert got == best and t == 10.0
     assert all(AT.valid(dict(s)) for s in seen)
@@ -25,7 +27,8 @@ def test_descent_finds_separable_minimum():
 
 
 def test_descent_keeps_start_without_gain_and_respects_validity():
-    start = {"chunk": 1024, "gram_piece": 2048, "gram_light": 512, "gram_waves": 4}
+    start = {"chunk": 1024, "gram_piece": 2048, "gram_light": 512, "gram_waves": 4,
+             "solve_wgs": 0}
     got, _, trials = AT.coordinate_descent(start, lambda t: 5.0)
     assert got == start
     # gram_light 1024 > gram_piece 2048 is fine; gram_piece 2048 with light
@@ -51,7 +54,8 @@ def test_shape_key_and_cache(tmp_path):
 
 def test_knob_values_are_accepted_by_the_library_rules():
     # the C ABI accepts chunk 512/1024/2048, gram_piece 1024..65536,
-    # gram_waves 2/4/8 and 0 <= gram_light <= gram_piece
-    for c, p, l, w in itertools.product(*AT.KNOBS.values()):
+    # gram_waves 2/4/8, 0 <= gram_light <= gram_piece and solve_wgs 0..64
+    for c, p, l, w, sw in itertools.product(*AT.KNOBS.values()):
         assert c in (512, 1024, 2048) and 1024 <= p <= 65536 and w in (2, 4, 8)
+        assert 0 <= sw <= 64
         assert 0 <= l
