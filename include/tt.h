@@ -276,7 +276,10 @@ tt_status tt_objective(const tt_index *ix, const void *const *d_A, int R,
  * tt_als_sweep -- one alternating-least-squares sweep (Section 2.2 and its
  * Section 4 implementation): for n = 0..N-1, M = MTTKRP_n(t) and
  * A_n <- Solve Factor(Omega-hat, A, n, M, lambda).  Factors are updated in
- * place.  Requires t.  d_info: optional int32[sum_n I_n].
+ * place.  Requires t.  d_info: optional int32[sum_n I_n].  In the FP32 and
+ * BF16 forms M is formed in the Gram pass (solve_factor with
+ * TT_RHS_MTTKRP), so each mode reads its nonzeros once; the FP64 form runs
+ * the MTTKRP first.
  * ------------------------------------------------------------------------- */
 tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                        tt_dtype fdt, double lambda, int32_t *d_info,
@@ -296,6 +299,9 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * turns the remaining iterations into no-ops, so no host sync is needed.
  *   d_stats         optional device double[4]: iterations, final relative
  *                   residual, initial residual norm, objective before step.
+ * The products use gn_matvec's position map: built on first use (one
+ * allocation and synchronization) unless tt_index_reserve was called with
+ * TT_RESERVE_GN.
  * ------------------------------------------------------------------------- */
 tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                      tt_dtype fdt, tt_loss loss, double lambda, double tol,
