@@ -410,12 +410,15 @@ def test_als_cube_converges_to_noise_floor():
     A = W.init_factors(wl.dims, 10, float(np.mean(wl.t)), W.SEED_INIT + 1,
                        dtype=np.float64)
     r = []
-    for _ in range(8):
+    for _ in range(30):
         A, _ = O.als_sweep(wl.idx, wl.t, A, wl.dims, 1e-5)
         r.append(O.rmse(wl.idx, wl.t, A))
     assert all(b <= a * (1 + 1e-9) for a, b in zip(r, r[1:]))
-    # training RMSE falls toward sigma * sqrt(1 - dof / m) ~ 0.0092
-    assert r[-1] < 0.05
+    # a least-squares fit with dof = 3 * 200 * 10 free parameters to m noisy
+    # observations (sigma = 0.01) leaves a training residual of about
+    # sigma * sqrt(1 - dof / m) = 0.00922 once converged
+    floor = 0.01 * np.sqrt(1.0 - 3 * 200 * 10 / wl.nnz)
+    assert abs(r[-1] - floor) <= 0.05 * floor, (r[-1], floor)
 
 
 # ----------------------------------------------------------------- bf16 ----
