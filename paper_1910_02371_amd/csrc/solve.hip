@@ -54,8 +54,6 @@ struct GramDev {
   const int32_t *w_perm;
   double w_scale;
   void *G;                    // workspace: (task - task_base) * gram_task_elems(RP)
-  int split_heavy;            // light kernel skips tasks > light
-  int light;                  // light/heavy task threshold (nonzeros)
   int waves;                  // waves of a heavy-task workgroup (2, 4, 8)
   const float *rhs_t;         // fused right-hand side: observed values, stream order
   double *M;                  // fused right-hand side: (task - task_base) * RP partials
@@ -380,8 +378,8 @@ __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, flo
 
 // Light tasks of rows with several tasks (the `tasks` list): one wave per
 // task, four tasks per workgroup.  Rows whose only task is light form their
-// Gram inside k_solve_solo; tasks with more than d.light nonzeros go to
-// k_gram_f32_heavy.
+// Gram inside k_solve_solo; tasks above the light threshold (tuning
+// gram_light) go to k_gram_f32_heavy.
 // Fused right-hand side of one task: lanes l, l + 16, l + 32, l + 48 hold
 // the same columns for different nonzeros; their FP64 sums are added in a
 // fixed butterfly and lanes 0..15 store the task's RP partial entries.
@@ -1142,12 +1140,10 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const Gram
   if (fdt == TT_F64) {
     ProfScope ps("gram_light", s, (wk.light_nnz + wk.heavy_nnz) * pernz + wk.light_tasks * tile,
                  (wk.light_nnz + wk.heavy_nnz) * R * (R + 1));
-    GramDev d2 = d;
-    d2.split_heavy = 0;
     switch (RP) {
-      case 16: k_gram_f64<16><<<g, b, 0, s>>>(d2); break;
-      case 32: k_gram_f64<32><<<g, b, 0, s>>>(d2); break;
-      default: k_gram_f64<64><<<g, b, 0, s>>>(d2); break;
+      case 16: k_gram_f64<16><<<g, b, 0, s>>>(d); break;
+      case 32: k_gram_f64<32><<<g, b, 0, s>>>(d); break;
+      default: k_gram_f64<64><<<g, b, 0, s>>>(d); break;
     }
   } else {
     GramLists g2 = gl;
@@ -1252,8 +1248,6 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.w_perm = c.w_perm;
   gd.w_scale = c.w_scale;
   gd.G = Gws;
-  gd.split_heavy = 1;
-  gd.light = ix->tune.gram_light;
   gd.waves = ix->tune.gram_waves;
   gd.rhs_t = c.fused_rhs ? reinterpret_cast<const float *>(md.d_t) : nullptr;
   gd.M = Mws;
