@@ -741,22 +741,35 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
     // diagonal tiles (those slots are not written by the Gram kernels)
     const int ln = opaque_lane(lane);
     const int rr = ln >> 4, cc = ln & 15;
+    // the diagonal (and the unwritten upper slots) only occur in the
+    // diagonal tiles I == J
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
-      for (int J = 0; J <= I; ++J)
+      for (int v = 0; v < 4; ++v) {
+        double x = acc[I * (I + 1) / 2 + I][v];
+        x = (4 * v + rr < cc) ? 0.0 : x;
+        x += (4 * v + rr == cc) ? d.lambda : 0.0;
+        acc[I * (I + 1) / 2 + I][v] = x;
+      }
+    if (R < RP) {  // uniform: padding rows and columns become the identity
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * I + 4 * v + rr, c = 16 * J + cc;
-          double x = acc[I * (I + 1) / 2 + J][v];
-          if (I == J) x = (4 * v + rr < cc) ? 0.0 : x;
-          x += (r == c) ? d.lambda : 0.0;
-          acc[I * (I + 1) / 2 + J][v] = (r >= R || c >= R) ? (r == c ? 1.0 : 0.0) : x;
-        }
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + rr, c = 16 * J + cc;
+            const double x = acc[I * (I + 1) / 2 + J][v];
+            acc[I * (I + 1) / 2 + J][v] = (r >= R || c >= R) ? (r == c ? 1.0 : 0.0) : x;
+          }
+    }
   }
   using P = Packed<RP>;
   using PB = PanelBuf<RP>;
-  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+  // every lane of the wave is a row when RP = 64: the lane < RP tests fold
+  constexpr bool FULL = RP == 64;
+  const int base = (FULL || lane < RP) ? (lane * (lane + 1)) / 2 : 0;
 #pragma unroll
   for (int p = 0; p < RP / 4; ++p) {
     const int k0 = 4 * p, J = k0 / 16, c0 = k0 % 16;
@@ -779,7 +792,7 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double xv = Pn[c * PB::PP + lane];  // in bounds for every lane
-      x[c] = lane < RP ? xv : 0.0;
+      x[c] = (FULL || lane < RP) ? xv : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -791,8 +804,9 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
       const double lik = lane >= k ? x[c] * inv : 0.0;
       x[c] = lik;
       if constexpr (FWD) {
+        // lik is exactly 0 on the lanes above k, which keep their b
         const double yk = readlane_d(b, k) * inv;
-        b = lane == k ? yk : (lane > k ? fma(-lik, yk, b) : b);
+        b = lane == k ? yk : fma(-lik, yk, b);
       }
 #pragma unroll
       for (int c2 = c + 1; c2 < 4; ++c2) x[c2] -= lik * readlane_d(lik, k0 + c2);
@@ -802,8 +816,8 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
       const int ln = opaque_lane(lane);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        Pn[ln < RP ? c * PB::PP + ln : PB::SCR + ln] = x[c];
-        Lp[(k0 + c <= ln && ln < RP) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
+        Pn[(FULL || ln < RP) ? c * PB::PP + ln : PB::SCR + ln] = x[c];
+        Lp[(k0 + c <= ln && (FULL || ln < RP)) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
       }
     }
     // 4. trailing update on the matrix cores
@@ -948,7 +962,8 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
 // The fused right-hand side is reduced over the four nonzero groups with
 // the butterfly of rhs_store.  PERSIST as in k_solve_rows.
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST>
-__global__ __launch_bounds__(64) void k_solve_solo(GramDev g, SolveDev d) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_solo(
+    GramDev g, SolveDev d) {
   using P = Packed<RP>;
   __shared__ double Lp[P::LDS];
   __shared__ double Pn[PanelBuf<RP>::SIZE];
