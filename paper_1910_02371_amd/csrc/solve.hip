@@ -1012,8 +1012,36 @@ __global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
   const double dg = lane < RP ? (double)Lp[(lane * (lane + 3)) / 2] : 1.0;  // L(i, i)
   const double rdiag = 1.0 / dg;
-  const double y = fwd_lds<RP, MT>(Lp, b, rdiag, lane);
-  const double x = bwd_lds<RP, MT>(Lp, y, rdiag, lane);
+  double x;
+  if constexpr (sizeof(MT) == 4) {
+    // FP32 factors: lane i first copies its row L(i, k < i) and its column
+    // L(k > i, i) from LDS into registers (zeros elsewhere), so the two
+    // substitutions below touch no memory: each step is the broadcast of
+    // y_k (x_k) and one FMA per lane
+    MT lrow[RP], lcol[RP];
+    const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      lrow[k] = Lp[(lane > k && lane < RP) ? base + k : P::ZERO];
+      lcol[k] = Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+    }
+    double bb = b;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      const double yk = readlane_d(bb * rdiag, k);
+      bb = fma(-(double)lrow[k], yk, bb);
+    }
+    bb *= rdiag;
+#pragma unroll
+    for (int k = RP - 1; k >= 0; --k) {
+      const double xk = readlane_d(bb * rdiag, k);
+      bb = fma(-(double)lcol[k], xk, bb);
+    }
+    x = bb * rdiag;
+  } else {
+    const double y = fwd_lds<RP, MT>(Lp, b, rdiag, lane);
+    x = bwd_lds<RP, MT>(Lp, y, rdiag, lane);
+  }
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
 }
 
