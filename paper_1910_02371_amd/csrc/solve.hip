@@ -689,6 +689,23 @@ struct PanelBuf {
   static constexpr int SIZE = 4 * PP + 64;
 };
 
+// Backward substitution L^T x = y as bwd_lds, with lane i's column
+// L(k > i, i) copied from LDS into registers first (the factorization's
+// accumulator registers are free by then), so the steps touch no memory.
+template <int RP>
+__device__ __forceinline__ double bwd_regs(const double *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+  double lcol[RP];
+#pragma unroll
+  for (int k = 0; k < RP; ++k) lcol[k] = Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+#pragma unroll
+  for (int k = RP - 1; k >= 0; --k) {
+    const double xk = readlane_d(b * rdiag, k);
+    b = fma(-lcol[k], xk, b);
+  }
+  return b * rdiag;
+}
+
 // Blocked Cholesky of one row's S = G + lambda I on the matrix cores.
 // S lives in NT accumulator tiles (lower tiles, layout of the Gram
 // workspace): lane l, register v of tile (I, J) holds
@@ -877,7 +894,7 @@ __device__ __forceinline__ void solve_row(const SolveDev &d, int64_t row, int la
   }
   if (d.factor_only) return;
   // b holds y = L^{-1} rhs; backward substitution L^T x = y
-  const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
+  const double x = info == 0 ? bwd_regs<RP>(Lp, b, rdiag, lane) : 0.0;
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
 
@@ -950,7 +967,7 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
     for (int q = lane; q < P::PS; q += 64) L[q] = (float)Lp[q];
   }
   if constexpr (!FO) {
-    const double x = info == 0 ? bwd_lds<RP, double>(Lp, b, rdiag, lane) : 0.0;
+    const double x = info == 0 ? bwd_regs<RP>(Lp, b, rdiag, lane) : 0.0;
     if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
   }
 }
