@@ -11,7 +11,8 @@ float64 for arbitrary tensor order N:
 
 * ``cp``      -- index (stable counting sort), TTTP, loss maps, MTTKRP, Gram,
                  row solves, Solve Factor, objective, gradient, GN operator.
-* ``solvers`` -- ALS sweep, ALS fast-loss identity, PCG Gauss-Newton step.
+* ``solvers`` -- ALS sweep, ALS fast-loss identity, PCG Gauss-Newton step,
+                 generalized alternating-minimization sweep.
 * ``bf16``    -- round-to-nearest-even emulation of bfloat16 storage.
 
 Parity status of each function is listed in its docstring; every function here
@@ -23,5 +24,5 @@ from .cp import (  # noqa: F401
     solve_rows, solve_factor, objective, gradient, jvp, gn_matvec,
     rmse, cholesky_info, LOSS_LS, LOSS_POISSON_LOG,
 )
-from .solvers import als_sweep, als_fast_loss, pcg, gn_step  # noqa: F401
+from .solvers import als_sweep, als_fast_loss, pcg, gn_step, gam_sweep  # noqa: F401
 from .bf16 import bf16_round  # noqa: F401

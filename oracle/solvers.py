@@ -98,3 +98,38 @@ def gn_step(idx, t, A, dims, loss, lam, tol, kmax):
 
     dX, iters, rel = pcg(apply_H, apply_Pinv, B, tol, kmax)
     return [a + dx for a, dx in zip(A, dX)], iters, rel
+
+
+def gam_sweep(idx, t, A, dims, loss, lam, tol, max_inner):
+    """One generalized alternating-minimization sweep (Section 2.2, general
+    loss): modes in order 0..N-1; for mode n, Newton iterations on its rows
+    with the other factors fixed.  Each iteration recomputes the model
+    values m, phi'(t, m) and phi''(t, m), then for every row i solves
+        (G_phi''^(i) + 2 lam I) d_i = -(MTTKRP_n(phi')_i + 2 lam u_i)
+    (Hessian and gradient of Table 1 restricted to row i; the objective's
+    regularizer lam ||A||^2 gives the 2 lam terms) and sets u_i <- u_i + d_i.
+    A mode stops after ``max_inner`` iterations or once
+    ||D||_F <= tol ||A_n||_F with D the whole step of that iteration and A_n
+    the updated factor (Section 5.7's relative step tolerance, read over the
+    factor matrix).  tol <= 0 always runs ``max_inner`` iterations.
+    Returns the new factors, the inner iteration count per mode and the
+    solve info of each mode's last iteration.
+    Pinned by: least squares, where one Newton step from any start is the
+    ALS solve; Poisson rows after converged inner iterations against a
+    general-purpose minimizer of the row's objective written from phi."""
+    A = [np.array(a, dtype=np.float64) for a in A]
+    counts, infos = [], []
+    for n in range(len(A)):
+        k, info = 0, np.zeros(dims[n], dtype=np.int64)
+        while k < max_inner:
+            m = cp.model_values(idx, A)
+            g = cp.mttkrp(idx, cp.dphi(t, m, loss), A, n, dims[n]) + 2.0 * lam * A[n]
+            G = cp.gram(idx, cp.d2phi(t, m, loss), A, n, dims[n])
+            D, info = cp.solve_rows(G, -g, 2.0 * lam)
+            A[n] = A[n] + D
+            k += 1
+            if tol > 0 and np.linalg.norm(D) <= tol * np.linalg.norm(A[n]):
+                break
+        counts.append(k)
+        infos.append(info)
+    return A, counts, infos

@@ -421,6 +421,83 @@ def test_als_cube_converges_to_noise_floor():
     assert abs(r[-1] - floor) <= 0.05 * floor, (r[-1], floor)
 
 
+# ------------------------------------------------------------------ GAM ----
+def test_gam_least_squares_is_als():
+    """Least squares: the row subproblem is quadratic, so one Newton step
+    from any start lands on its minimizer, the ALS solve (Section 2.2).  The
+    GAM sweep (gradient, phi'' Gram, shift 2 lam) must equal the ALS sweep
+    (MTTKRP of t, Omega-hat Gram, shift lam) from a random start, and a
+    second inner iteration must not move it."""
+    wl = W.random_tensor((9, 10, 8), 200, 55, rank=3)
+    lam = 1e-3
+    A = W.init_factors(wl.dims, 4, float(np.mean(wl.t)), 3, dtype=np.float64)
+    Aa, _ = O.als_sweep(wl.idx, wl.t, A, wl.dims, lam)
+    Ag, counts, infos = O.gam_sweep(wl.idx, wl.t, A, wl.dims, O.LOSS_LS, lam, 0.0, 1)
+    assert counts == [1, 1, 1] and all((i == 0).all() for i in infos)
+    for d in range(3):
+        np.testing.assert_allclose(Ag[d], Aa[d], rtol=1e-9, atol=1e-12)
+    # the stop rule: the second Newton step of each mode is ~0
+    Ag2, counts2, _ = O.gam_sweep(wl.idx, wl.t, A, wl.dims, O.LOSS_LS, lam, 1e-6, 5)
+    assert counts2 == [2, 2, 2]
+    for d in range(3):
+        np.testing.assert_allclose(Ag2[d], Aa[d], rtol=1e-8, atol=1e-11)
+
+
+def test_gam_poisson_rows_minimize_their_objective():
+    """Poisson log link: after converged inner iterations on mode 0, every
+    row of A_0 minimizes its own objective
+        sum_{e in row i} [exp(m_e) - t_e m_e] + lam ||u_i||^2,
+    found here by scipy's BFGS from the loss phi alone (no phi' or phi'' of
+    the oracle), and the objective does not increase mode by mode."""
+    import scipy.optimize
+    wl = W.random_tensor((7, 6, 5), 90, 31, rank=2, noise=0.0)
+    t = np.round(np.exp(0.5 * wl.t))
+    lam = 0.1
+    A = W.init_factors(wl.dims, 3, float(np.log(np.mean(t) + 1)), 4, dtype=np.float64)
+    f_prev = O.objective(wl.idx, t, A, O.LOSS_POISSON_LOG, lam)
+    A1, counts, _ = O.gam_sweep(wl.idx, t, A, wl.dims, O.LOSS_POISSON_LOG, lam, 0.0, 25)
+    # mode 0 was solved first, with A[1], A[2] still the initial factors
+    B = [A1[0], A[1], A[2]]
+    idx = [np.asarray(a) for a in wl.idx]
+    for i in range(wl.dims[0]):
+        sel = np.nonzero(idx[0] == i)[0]
+        H = A[1][idx[1][sel]] * A[2][idx[2][sel]]
+
+        def f(u):
+            mv = H @ u
+            return float(np.sum(O.phi(t[sel], mv, O.LOSS_POISSON_LOG)) + lam * u @ u)
+
+        res = scipy.optimize.minimize(f, np.zeros(3), method="BFGS",
+                                      options=dict(gtol=1e-11, maxiter=2000))
+        np.testing.assert_allclose(B[0][i], res.x, rtol=1e-5, atol=1e-6)
+        assert f(B[0][i]) <= res.fun + 1e-9 * abs(res.fun)
+    # block minimization: the objective after the sweep is below the start
+    assert O.objective(wl.idx, t, A1, O.LOSS_POISSON_LOG, lam) < f_prev
+
+
+def test_gam_stop_rule():
+    """tol > 0 stops a mode at the first iteration whose step is at most
+    tol times the updated factor's norm; tol = 0 runs max_inner."""
+    wl = W.random_tensor((7, 6, 5), 90, 31, rank=2, noise=0.0)
+    t = np.round(np.exp(0.5 * wl.t))
+    A = W.init_factors(wl.dims, 3, float(np.log(np.mean(t) + 1)), 4, dtype=np.float64)
+    _, c0, _ = O.gam_sweep(wl.idx, t, A, wl.dims, O.LOSS_POISSON_LOG, 0.1, 0.0, 4)
+    assert c0 == [4, 4, 4]
+    _, c1, _ = O.gam_sweep(wl.idx, t, A, wl.dims, O.LOSS_POISSON_LOG, 0.1, 1e-3, 25)
+    assert all(1 <= c < 25 for c in c1)
+    # replay mode 0 by hand to check the count
+    An = [a.copy() for a in A]
+    k = 0
+    while True:
+        B, _, _ = O.gam_sweep(wl.idx, t, An, wl.dims, O.LOSS_POISSON_LOG, 0.1, 0.0, 1)
+        D = B[0] - An[0]
+        An[0] = B[0]
+        k += 1
+        if np.linalg.norm(D) <= 1e-3 * np.linalg.norm(B[0]):
+            break
+    assert k == c1[0]
+
+
 # ----------------------------------------------------------------- bf16 ----
 def test_bf16_rne():
     exact = np.array([0.0, 1.0, -2.5, 0.15625, 2.0 ** 127 * 1.5, 2.0 ** -120])
