@@ -308,6 +308,33 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                      int kmax, double *d_stats, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * tt_gam_sweep -- one generalized alternating-minimization sweep (Section
+ * 2.2 for a general loss; stop rule of Section 5.7): for n = 0..N-1, Newton
+ * iterations on the rows of A_n with the other factors fixed.  Iteration:
+ *     g = MTTKRP_n(phi'(t, m)) + 2 lambda A_n       (one fused pass)
+ *     w = phi''(t, m) in mode n's order             (one TTTP pass; the
+ *                                                    constant 2 for LS)
+ *     (G_w^(i) + 2 lambda I) d_i = -g_i per row     (Solve Factor)
+ *     A_n <- A_n + D
+ * until ||D||_F <= tol ||A_n||_F (A_n after the update) or max_inner
+ * iterations.  For least squares one iteration is the ALS update.  Factors
+ * are updated in place; D is held in the factor dtype (rounded to BF16 in
+ * the BF16 form) and added in FP64.
+ *   tol             > 0: after each iteration but a mode's last, the two
+ *                   norms are copied to the host (one stream synchronization
+ *                   per iteration); <= 0: exactly max_inner iterations per
+ *                   mode, no synchronization.
+ *   d_info          optional int32[sum_n I_n]: Solve Factor info of each
+ *                   mode's last iteration.
+ *   h_iters         optional host int32[N]: iterations run per mode.
+ * Workspaces are allocated on first use (not capturable).  Requires t.
+ * ------------------------------------------------------------------------- */
+tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
+                       tt_dtype fdt, tt_loss loss, double lambda, double tol,
+                       int max_inner, int32_t *d_info, int32_t *h_iters,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batching (graph capture).  The ALS sweep and the Gauss-Newton step
  * enqueue many kernels (per-mode streams, row batches of Gram and solve
  * kernels, and kmax fixed PCG iterations whose early exit is a device flag);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -790,6 +791,93 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   for (int d = 0; d < N; ++d)
     TT_LAUNCH(launch_add_to_factor(d_A[d], fdt, ldA, ix->mode[d].I, R, blk(X, d), st), "step");
   if (d_stats) TT_LAUNCH(launch_pcg_stats(sc, sc + 10, d_stats, st), "stats");
+  return TT_OK;
+}
+
+tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+                       tt_loss loss, double lambda, double tol, int max_inner,
+                       int32_t *d_info, int32_t *h_iters, hipStream_t st) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(loss == TT_LOSS_LS || loss == TT_LOSS_POISSON_LOG, "bad loss %d", (int)loss);
+  TT_CHECK(max_inner >= 0, "max_inner < 0");
+  TT_CHECK(d_A != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
+  const int N = ix->N;
+  const tt_dtype dn = dense_of(fdt);
+  const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
+  // workspace: -gradient rows (dense), the Newton step (factor dtype, ldA),
+  // phi'' in one mode's order (Poisson), step and factor norms
+  void *vg = nullptr, *vd = nullptr, *vw = nullptr, *vparts = nullptr, *vsc = nullptr;
+  TT_ST(ws_get(ix, "gam_g", (size_t)ix->max_I * R * value_size(fdt), &vg));
+  const size_t fsz = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
+  TT_ST(ws_get(ix, "gam_d", (size_t)ix->max_I * ldA * fsz, &vd));
+  if (loss == TT_LOSS_POISSON_LOG)
+    TT_ST(ws_get(ix, "gam_w", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &vw));
+  int64_t need = 0;
+  for (int n = 0; n < N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
+  TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &vparts));
+  TT_ST(ws_get(ix, "gam_sc", 2 * 8, &vsc));
+  double *carry = nullptr;
+  TT_ST(carry_ws(ix, &carry));
+  double *sc = (double *)vsc, *parts = (double *)vparts;
+  int64_t off = 0;
+  for (int n = 0; n < N; ++n) {
+    const ModeIndex &md = ix->mode[n];
+    int k = 0;
+    while (k < max_inner) {
+      // -(MTTKRP_n(phi') + 2 lambda A_n): the row gradients (Table 1), negated
+      TT_LAUNCH(launch_scale_rows(vg, d_A[n], fdt, ldA, md.I, R, 2.0 * lambda, dn, st),
+                "gam prefill");
+      StreamCall c = base_call(ix, n, R, ldA, fdt);
+      for (int p = 0; p < N; ++p) c.A[p] = A[p];
+      c.s = md.d_t;
+      c.loss = loss;
+      c.out = vg;
+      c.accumulate = 1;
+      c.carry = carry;
+      TT_LAUNCH(launch_stream(OP_GRAD, c, st), "gam gradient kernel");
+      TT_LAUNCH(launch_scale_rows(vg, vg, dn, R, md.I, R, -1.0, dn, st), "gam negate");
+      // phi'' in mode n's order (the constant 2 for least squares)
+      if (loss == TT_LOSS_POISSON_LOG)
+        TT_ST(tttp_mode(ix, n, md.d_t, nullptr, A, R, ldA, fdt, TT_EPI_D2PHI, loss, vw,
+                        nullptr, nullptr, nullptr, st));
+      // per row: (G_phi'' + 2 lambda I) d_i = -g_i  (Solve Factor)
+      SolveCall sc_call;
+      memset(&sc_call, 0, sizeof(sc_call));
+      sc_call.ix = ix;
+      sc_call.mode = n;
+      sc_call.R = R;
+      sc_call.ldA = ldA;
+      sc_call.fdt = fdt;
+      for (int p = 0; p < N; ++p) sc_call.A[p] = A[p];
+      sc_call.w = vw;
+      sc_call.w_scale = vw ? 1.0 : 2.0;
+      sc_call.lambda = 2.0 * lambda;
+      sc_call.rhs = vg;
+      sc_call.X = vd;
+      sc_call.info = d_info ? d_info + off : nullptr;
+      TT_ST(run_solve_factor(ix, sc_call, st));
+      TT_LAUNCH(launch_add_rows(d_A[n], ldA, vd, ldA, fdt, md.I, R, st), "gam step");
+      ++k;
+      if (tol > 0.0 && k < max_inner) {
+        int64_t np = 0;
+        TT_LAUNCH(launch_sumsq_rows(vd, fdt, ldA, md.I, R, 1.0, parts, &np, st), "gam norm");
+        TT_LAUNCH(launch_sum_doubles(parts, np, sc, 0, st), "gam norm");
+        TT_LAUNCH(launch_sumsq_rows(d_A[n], fdt, ldA, md.I, R, 1.0, parts, &np, st),
+                  "gam norm");
+        TT_LAUNCH(launch_sum_doubles(parts, np, sc + 1, 0, st), "gam norm");
+        double h[2] = {0.0, 0.0};
+        TT_LAUNCH(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, st), "gam norm copy");
+        TT_LAUNCH(hipStreamSynchronize(st), "gam norm sync");
+        if (std::sqrt(h[0]) <= tol * std::sqrt(h[1])) break;
+      }
+    }
+    if (h_iters) h_iters[n] = k;
+    off += md.I;
+  }
   return TT_OK;
 }
 

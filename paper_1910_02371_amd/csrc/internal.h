@@ -232,5 +232,8 @@ hipError_t launch_pcg_scalar(double *sc, int stage, double tol, hipStream_t s);
 hipError_t launch_pcg_stats(const double *sc, const double *f0, double *stats, hipStream_t s);
 hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
                                 const void *dx, hipStream_t s);
+// A += D, both I x R in the factor dtype fdt with leading dimensions ldA, ldD.
+hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
+                           int64_t I, int R, hipStream_t s);
 
 }  // namespace tt

@@ -276,4 +276,33 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
   return hipGetLastError();
 }
 
+// A[i, r] += D[i, r] over I rows, both in the factor dtype with their own
+// leading dimensions; the sum is formed in FP64 and rounded once.
+template <class T>
+__global__ void k_add_rows(T *A, int64_t ldA, const T *D, int64_t ldD, int64_t I, int R) {
+  const int64_t n = I * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / R;
+    const int r = (int)(i - row * R);
+    T *p = A + row * ldA + r;
+    *p = from_double<T>(to_double<T>(*p) + to_double<T>(D[row * ldD + r]));
+  }
+}
+
+hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
+                           int64_t I, int R, hipStream_t s) {
+  const int64_t n = I * R;
+  if (n <= 0) return hipSuccess;
+  const int g = grid_cap(n, 8192);
+  if (fdt == TT_F64)
+    k_add_rows<double><<<g, VT_THREADS, 0, s>>>((double *)A, ldA, (const double *)D, ldD, I, R);
+  else if (fdt == TT_F32)
+    k_add_rows<float><<<g, VT_THREADS, 0, s>>>((float *)A, ldA, (const float *)D, ldD, I, R);
+  else
+    k_add_rows<uint16_t><<<g, VT_THREADS, 0, s>>>((uint16_t *)A, ldA, (const uint16_t *)D, ldD,
+                                                  I, R);
+  return hipGetLastError();
+}
+
 }  // namespace tt

@@ -53,6 +53,7 @@ SIGNATURES = {
     "tt_objective": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _P, _P]),
     "tt_als_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
     "tt_gn_step": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P]),
+    "tt_gam_sweep": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P, _P]),
     "tt_graph_begin": (_I, [_P]),
     "tt_graph_end": (_I, [_P, ctypes.POINTER(_P)]),
     "tt_graph_launch": (_I, [_P, _P]),
@@ -366,6 +367,18 @@ def gn_step(ix, A, loss, lam, tol=5e-3, kmax=30, stats=None):
     _check(lib().tt_gn_step(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
                             float(tol), int(kmax), _ptr(stats), _stream()))
     return stats
+
+
+def gam_sweep(ix, A, loss, lam, tol=1e-3, max_inner=5, info=None):
+    """One generalized alternating-minimization sweep (Section 2.2, general
+    loss; Section 5.7 inner stop rule), factors updated in place.  Returns
+    the Newton iterations run per mode (host list)."""
+    fdt = fdt_of(A)
+    R, ld = _rank_ld(A)
+    iters = (ctypes.c_int32 * len(A))()
+    _check(lib().tt_gam_sweep(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
+                              float(tol), int(max_inner), _ptr(info), iters, _stream()))
+    return list(iters)
 
 
 class Graph:

@@ -205,3 +205,96 @@ def test_graph_replay_matches_eager(gpu_lib, form, loss):
         assert torch.equal(info_e, info_g)
     assert np.isfinite(host(Ag[0])).all()
     g.close()
+
+
+# ------------------------------------------ generalized alternating min. ----
+GAM_CASES = {
+    # rows of a few dozen nonzeros
+    "small": ((12, 10, 14), 500, 3),
+    # mode-0 rows of ~5000 nonzeros: several streaming chunks and Gram tasks
+    "heavy": ((3, 300, 200), 15000, 2),
+    # most mode-0 rows empty: those rows go to the regularizer's minimum, 0
+    "empty_rows": ((40, 10, 14), 60, 3),
+}
+
+
+def gam_problem(case, loss, seed=21):
+    dims, m, rank = GAM_CASES[case]
+    wl = W.random_tensor(dims, m, seed, rank=rank, noise=0.0)
+    if loss == "ls":
+        t, lam = wl.t, 1e-3
+        mean_model = float(np.mean(t))
+    else:
+        t = W.rng_for(seed + 1).poisson(np.exp(1.5 * wl.t)).astype(np.float64)
+        lam = 0.1
+        mean_model = float(np.log(np.mean(t) + 1))
+    return wl, t, lam, mean_model
+
+
+@pytest.mark.parametrize("case", list(GAM_CASES))
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+def test_gam_sweep_f64_matches_oracle(gpu_lib, loss, case):
+    """FP64 form: inner iteration counts under the 1e-3 relative step rule
+    (at most 5) equal the oracle's, and so do the factors and solve info."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem(case, loss)
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    A0 = W.init_factors(wl.dims, 4, mm, 8, dtype=np.float64)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f64"))
+    A = [dev_factor(a, "f64") for a in A0]
+    info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
+    counts = tt.gam_sweep(ix, A, loss, lam, tol=1e-3, max_inner=5, info=info)
+    Ar, cr, infr = O.gam_sweep(wl.idx, t, A0, wl.dims, L, lam, 1e-3, 5)
+    assert counts == cr, f"inner iterations {counts} vs {cr}"
+    np.testing.assert_array_equal(info.cpu().numpy(), np.concatenate(infr))
+    for d in range(3):
+        np.testing.assert_allclose(host(A[d]), Ar[d], rtol=1e-7, atol=1e-9)
+    f = tt.objective(ix, A, loss, lam).item()
+    assert f < O.objective(wl.idx, t, A0, L, lam)
+
+
+@pytest.mark.parametrize("case", ["small", "heavy"])
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_gam_sweep_low_precision_forms(gpu_lib, form, loss, case):
+    """FP32 / BF16 storage, three Newton iterations per mode (tol = 0, so
+    the count is fixed): each factor within the form's tolerance of the
+    oracle run from the same stored inputs (relative Frobenius error; the
+    BF16 form rounds every step and every updated factor to BF16)."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem(case, loss)
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    t = stored_values(t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 4, mm, 8, dtype=np.float64), form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    A = [dev_factor(a, form) for a in A0]
+    counts = tt.gam_sweep(ix, A, loss, lam, tol=0.0, max_inner=3)
+    assert counts == [3, 3, 3]
+    Ar, _, _ = O.gam_sweep(wl.idx, t, A0, wl.dims, L, lam, 0.0, 3)
+    tau = 1e-4 if form == "f32" else 2e-2
+    for d in range(3):
+        err = np.linalg.norm(host(A[d]) - Ar[d]) / np.linalg.norm(Ar[d])
+        assert err <= tau, f"{form} {loss} {case} mode {d}: relative error {err:.2e}"
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_gam_least_squares_one_iteration_is_als(gpu_lib, form):
+    """Least squares: one Newton iteration per mode is the ALS update, so
+    the GAM sweep and the ALS sweep agree from the same start; max_inner = 0
+    leaves the factors untouched."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem("small", "ls")
+    t = stored_values(t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 4, mm, 8, dtype=np.float64), form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    A = [dev_factor(a, form) for a in A0]
+    assert tt.gam_sweep(ix, A, "ls", lam, tol=0.0, max_inner=0) == [0, 0, 0]
+    for d in range(3):
+        np.testing.assert_array_equal(host(A[d]), A0[d])
+    B = [dev_factor(a, form) for a in A0]
+    assert tt.gam_sweep(ix, A, "ls", lam, tol=0.0, max_inner=1) == [1, 1, 1]
+    tt.als_sweep(ix, B, lam)
+    tau = 1e-10 if form == "f64" else 1e-5
+    for d in range(3):
+        a, b = host(A[d]), host(B[d])
+        assert np.linalg.norm(a - b) <= tau * np.linalg.norm(b), f"mode {d}"
