@@ -55,6 +55,9 @@ def parse():
                    help="skip the graph-replay vs plain-launch comparison")
     p.add_argument("--form-sweeps", type=int, default=5,
                    help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
+    p.add_argument("--poisson-iters", type=int, default=3,
+                   help="ratings: GAM sweeps and GN steps of the Poisson log-link "
+                        "comparison (0: skip)")
     p.add_argument("--gn-steps", type=int, default=3,
                    help="Gauss-Newton steps after the ALS sweeps of the forms comparison")
     p.add_argument("--calib-copy-mib", type=int, default=0,
@@ -259,6 +262,10 @@ def main():
         forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev,
                               gn_steps=args.gn_steps if ratings else 0, lam_gn=lam_gn)
 
+    poisson = None
+    if args.poisson_iters > 0 and ratings:
+        poisson = compare_poisson(tt, ix, wl, dev, args.poisson_iters)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, A0, R, lam, lam_gn, args.cpu_sample, passes, gn=ratings)
@@ -296,6 +303,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
         "batching": batching,
+        "poisson": poisson,
         "tuning": tuning,
         "calls": calls,
         "step_kernels": step_prof,
@@ -431,6 +439,56 @@ def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev, gn_steps=0, lam_gn=1e-3, 
         out["gn_equal_rmse_within_1pct"] = abs(g16 / g32 - 1.0) <= 0.01
         out["gn_speedup_bf16"] = sum(out["f32"]["gn_ms"]) / max(1e-9, sum(out["bf16"]["gn_ms"]))
         out["gn_kmax"] = kmax
+    return out
+
+
+def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5):
+    """Poisson log-link completion of the same tensor, its values 1..5 read as
+    counts, with Section 5.7's settings (R = 10, lambda = 0.1; alternating
+    minimization inner Newton iterations to a relative step of 1e-3 or at
+    most 5; PCG to 5e-3 or at most R iterations): from one start, `iters`
+    generalized alternating-minimization sweeps and, separately, `iters`
+    Gauss-Newton steps, each timed with HIP events, with the normalized loss
+    (1/m) sum phi after each.  A first untimed call of each method on a copy
+    allocates its workspaces."""
+    import numpy as np
+    import torch
+    from paper_1910_02371_amd import workloads as W
+    A0 = W.init_factors(wl.dims, R, float(np.log(np.mean(wl.t))), W.SEED_INIT + 3,
+                        dtype=np.float32)
+    m = wl.nnz
+
+    def loss(A):
+        v = tt.objective(ix, A, "poisson", 0.0).item() / m
+        return v if np.isfinite(v) else None  # a diverged run stays valid JSON
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1), r
+
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    run = {
+        "gam": lambda A: tt.gam_sweep(ix, A, "poisson", lam, tol=tol, max_inner=max_inner),
+        "gn": lambda A: tt.gn_step(ix, A, "poisson", lam, tol=5e-3, kmax=R, stats=stats),
+    }
+    out = {"R": R, "lambda": lam, "inner_tol": tol, "max_inner": max_inner, "cg_tol": 5e-3,
+           "cg_kmax": R}
+    for meth, fn in run.items():
+        fn([torch.as_tensor(a).to(dev).contiguous() for a in A0])
+        A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+        rec = {"ms": [], "loss": [loss(A)], "iterations": []}
+        for _ in range(iters):
+            ms, it = timed(lambda: fn(A))
+            rec["ms"].append(ms)
+            # GAM: Newton iterations per mode; GN: PCG iterations
+            rec["iterations"].append(it if meth == "gam" else int(it[0].item()))
+            rec["loss"].append(loss(A))
+        out[meth] = rec
     return out
 
 

@@ -311,8 +311,8 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * tt_gam_sweep -- one generalized alternating-minimization sweep (Section
  * 2.2 for a general loss; stop rule of Section 5.7): for n = 0..N-1, Newton
  * iterations on the rows of A_n with the other factors fixed.  Iteration:
- *     g = MTTKRP_n(phi'(t, m)) + 2 lambda A_n       (one fused pass)
- *     w = phi''(t, m) in mode n's order             (one TTTP pass; the
+ *     g = MTTKRP_n(phi'(t, m)) + 2 lambda A_n       (one pass, TTTP fused;
+ *     w = phi''(t, m) in mode n's order              it also stores w, the
  *                                                    constant 2 for LS)
  *     (G_w^(i) + 2 lambda I) d_i = -g_i per row     (Solve Factor)
  *     A_n <- A_n + D

@@ -828,7 +828,8 @@ tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
     const ModeIndex &md = ix->mode[n];
     int k = 0;
     while (k < max_inner) {
-      // -(MTTKRP_n(phi') + 2 lambda A_n): the row gradients (Table 1), negated
+      // -(MTTKRP_n(phi') + 2 lambda A_n): the row gradients (Table 1), negated;
+      // the same pass stores phi'' in mode n's order (the constant 2 for LS)
       TT_LAUNCH(launch_scale_rows(vg, d_A[n], fdt, ldA, md.I, R, 2.0 * lambda, dn, st),
                 "gam prefill");
       StreamCall c = base_call(ix, n, R, ldA, fdt);
@@ -838,12 +839,9 @@ tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
       c.out = vg;
       c.accumulate = 1;
       c.carry = carry;
+      c.zout = vw;
       TT_LAUNCH(launch_stream(OP_GRAD, c, st), "gam gradient kernel");
       TT_LAUNCH(launch_scale_rows(vg, vg, dn, R, md.I, R, -1.0, dn, st), "gam negate");
-      // phi'' in mode n's order (the constant 2 for least squares)
-      if (loss == TT_LOSS_POISSON_LOG)
-        TT_ST(tttp_mode(ix, n, md.d_t, nullptr, A, R, ldA, fdt, TT_EPI_D2PHI, loss, vw,
-                        nullptr, nullptr, nullptr, st));
       // per row: (G_phi'' + 2 lambda I) d_i = -g_i  (Solve Factor)
       SolveCall sc_call;
       memset(&sc_call, 0, sizeof(sc_call));

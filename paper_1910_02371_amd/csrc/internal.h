@@ -172,8 +172,8 @@ struct StreamCall {
   double *sum_parts;        // TTTP: per-chunk FP64 partial sums (or NULL)
   double *carry;            // segmented: carry workspace
   const double *skip;       // optional device flag: launches become no-ops
-  void *zout;               // GN: also store w_e * z_e per nonzero (value dtype,
-                            // this mode's sorted order) when non-NULL
+  void *zout;               // when non-NULL, also store per nonzero (value dtype, this
+                            // mode's sorted order): GN w_e * z_e, gradient phi''(t_e, m_e)
   const char *prof_name;    // profiler tag (NULL: named after the operation)
 };
 enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3 };

@@ -68,7 +68,7 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   d.sum_parts = c.sum_parts;
   d.carry = c.carry;
   d.skip = c.skip;
-  d.zout = op == OP_GN ? c.zout : nullptr;
+  d.zout = (op == OP_GN || op == OP_GRAD) ? c.zout : nullptr;
   hipError_t e;
   {
     // algorithmic work of this launch (per-nonzero byte model: index
@@ -90,7 +90,8 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
       flops = m * R * N;
     } else if (op == OP_GRAD) {
       name = "gradient";
-      bytes = m * (4 * (N - 1) + v + (N - 1) * R * b) + I * R * (b + 2 * xs);
+      bytes = m * (4 * (N - 1) + v + (c.zout ? v : 0) + (N - 1) * R * b) +
+              I * R * (b + 2 * xs);
       flops = m * R * (N + 3);
     } else {
       name = "gn_matvec";

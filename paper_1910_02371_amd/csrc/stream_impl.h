@@ -18,7 +18,7 @@
 // gradient, Section 2.5 Gauss-Newton matvec):
 //   OP_TTTP   out_e = epilogue(s_e or t_e, sum_r prod_n A_n[i_n(e), r])
 //   OP_MTTKRP Y[i] += s_e * h_e,            h_e = prod_{p != n} A_p[i_p(e)]
-//   OP_GRAD   Y[i] += phi'(t_e, <A_n[i], h_e>) * h_e
+//   OP_GRAD   Y[i] += phi'(t_e, <A_n[i], h_e>) * h_e  (optionally storing phi'')
 //   OP_GN     Y[i] += w_e * z_e * h_e,  z_e = <X_n[i], h_e> + <A_n[i], dh_e>,
 //             dh_e = sum_{p != n} X_p[i_p(e)] * prod_{q != n, p} A_q[i_q(e)]
 //             (optionally also stores w_e * z_e per nonzero, for the other
@@ -59,7 +59,8 @@ struct StreamDev {
   double *sum_parts;
   double *carry;
   const double *skip;       // when set and *skip != 0 the launch is a no-op
-  void *zout;               // OP_GN: per-nonzero w_e * z_e in sorted order, or NULL
+  void *zout;               // per nonzero in sorted order, or NULL: OP_GN w_e * z_e,
+                            // OP_GRAD phi''(t_e, m_e)
 };
 
 template <class TR, int G, int CHUNK>
@@ -285,6 +286,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
             const AT dp = loss_eval<AT>(EPI_DPHI, a.loss, (AT)sm.val[e], mval);
 #pragma unroll
             for (int j = 0; j < V; ++j) acc[j] += dp * h[j];
+            if (a.zout != nullptr && c0 == 0)
+              reinterpret_cast<VT *>(a.zout)[b + e] =
+                  (VT)loss_eval<AT>(EPI_D2PHI, a.loss, (AT)sm.val[e], mval);
           } else if constexpr (OP == OP_GN) {
             AT zz = AT(0);
 #pragma unroll
