@@ -10,7 +10,8 @@ Every function is the plain definition from the paper, written out in NumPy
 float64 for arbitrary tensor order N:
 
 * ``cp``      -- index (stable counting sort), TTTP, loss maps, MTTKRP, Gram,
-                 row solves, Solve Factor, objective, gradient, GN operator.
+                 row solves, Solve Factor, objective, gradient, GN operator,
+                 full Hessian-vector product.
 * ``solvers`` -- ALS sweep, ALS fast-loss identity, PCG Gauss-Newton step,
                  generalized alternating-minimization sweep.
 * ``bf16``    -- round-to-nearest-even emulation of bfloat16 storage.
@@ -21,7 +22,7 @@ is pinned by ``tests/test_oracle_*.py`` except where a docstring says
 """
 from .cp import (  # noqa: F401
     build_index, tttp, phi, dphi, d2phi, mttkrp, row_design, gram,
-    solve_rows, solve_factor, objective, gradient, jvp, gn_matvec,
+    solve_rows, solve_factor, objective, gradient, jvp, gn_matvec, newton_matvec,
     rmse, cholesky_info, LOSS_LS, LOSS_POISSON_LOG,
 )
 from .solvers import als_sweep, als_fast_loss, pcg, gn_step, gam_sweep  # noqa: F401

@@ -294,3 +294,26 @@ def gn_matvec(idx, w, A, X, lam2, dims):
     wz = _f64(w) * z
     return [mttkrp(idx, wz, A, d, dims[d]) + lam2 * _f64(X[d])
             for d in range(len(A))]
+
+
+def newton_matvec(idx, t, A, X, lam2, dims, loss):
+    """Full Hessian-vector product of the objective (Section 2.5 with the
+    phi' terms of the off-diagonal blocks; Appendix A): the Gauss-Newton
+    operator with w = phi'' plus, for every block d,
+        sum_e phi'_e * sum_{p != d} X_p[i_p] * prod_{q != d, p} A_q[i_q],
+    i.e. the MTTKRP of phi' with the factor of one other mode p replaced by
+    the direction X_p, summed over p.  lam2 is the regularizer's Hessian
+    (2 lambda).
+    Pinned by: central differences of the oracle gradient in the direction
+    X, symmetry, and equality with the GN operator where phi' = 0."""
+    m = model_values(idx, A)
+    y = gn_matvec(idx, d2phi(t, m, loss), A, X, lam2, dims)
+    d1 = dphi(t, m, loss)
+    for d in range(len(A)):
+        for p in range(len(A)):
+            if p == d:
+                continue
+            Ap = list(A)
+            Ap[p] = X[p]
+            y[d] = y[d] + mttkrp(idx, d1, Ap, d, dims[d])
+    return y

@@ -339,6 +339,50 @@ def test_gn_matvec_explicit_jacobian_symmetry_psd():
                                    rtol=1e-11, atol=1e-12)
 
 
+@pytest.mark.parametrize("loss", [O.LOSS_LS, O.LOSS_POISSON_LOG])
+def test_newton_matvec_is_gradient_derivative(loss):
+    """The full Hessian-vector product equals the central difference of the
+    gradient in the direction X (error O(eps^2)); the GN operator differs
+    from it by the phi' terms, so it must not match."""
+    wl = W.random_tensor((6, 5, 7), 80, 13, rank=2)
+    rng = np.random.default_rng(4)
+    A = [0.5 * rng.standard_normal((d, 3)) for d in wl.dims]
+    X = [rng.standard_normal((d, 3)) for d in wl.dims]
+    t = wl.t if loss == O.LOSS_LS else np.round(np.exp(wl.t))
+    lam, eps = 0.05, 1e-5
+    gp = O.gradient(wl.idx, t, [a + eps * x for a, x in zip(A, X)], loss, lam, wl.dims)
+    gm = O.gradient(wl.idx, t, [a - eps * x for a, x in zip(A, X)], loss, lam, wl.dims)
+    fd = [(p - q) / (2 * eps) for p, q in zip(gp, gm)]
+    Y = O.newton_matvec(wl.idx, t, A, X, 2 * lam, wl.dims, loss)
+    scale = max(np.abs(f).max() for f in fd)
+    for d in range(3):
+        np.testing.assert_allclose(Y[d], fd[d], rtol=0, atol=1e-7 * scale)
+    m = O.tttp(wl.idx, None, A)
+    G = O.gn_matvec(wl.idx, O.d2phi(t, m, loss), A, X, 2 * lam, wl.dims)
+    assert max(np.abs(g - f).max() for g, f in zip(G, fd)) > 1e-3 * scale
+
+
+def test_newton_matvec_symmetric_and_gn_at_zero_residual():
+    wl = W.random_tensor((6, 5, 7), 80, 17, rank=2)
+    rng = np.random.default_rng(5)
+    A = [rng.standard_normal((d, 3)) for d in wl.dims]
+    X1 = [rng.standard_normal((d, 3)) for d in wl.dims]
+    X2 = [rng.standard_normal((d, 3)) for d in wl.dims]
+    t = np.round(np.exp(0.3 * wl.t))
+    L = O.LOSS_POISSON_LOG
+    Y1 = O.newton_matvec(wl.idx, t, A, X1, 0.2, wl.dims, L)
+    Y2 = O.newton_matvec(wl.idx, t, A, X2, 0.2, wl.dims, L)
+    a = sum(np.sum(y * x) for y, x in zip(Y1, X2))
+    b = sum(np.sum(y * x) for y, x in zip(Y2, X1))
+    assert np.isclose(a, b, rtol=1e-11)
+    # least squares with t equal to the model: phi' = 0, so Newton = GN
+    tm = O.tttp(wl.idx, None, A)
+    Yn = O.newton_matvec(wl.idx, tm, A, X1, 0.2, wl.dims, O.LOSS_LS)
+    Yg = O.gn_matvec(wl.idx, np.full(len(tm), 2.0), A, X1, 0.2, wl.dims)
+    for d in range(3):
+        np.testing.assert_allclose(Yn[d], Yg[d], rtol=1e-12, atol=1e-12)
+
+
 def test_jvp_matches_fd_of_model():
     wl, A = small((4, 5, 3), 20, 41, R=3)
     rng = np.random.default_rng(8)
