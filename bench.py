@@ -489,6 +489,17 @@ def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5
             rec["iterations"].append(it if meth == "gam" else int(it[0].item()))
             rec["loss"].append(loss(A))
         out[meth] = rec
+    # one Gauss-Newton product and one full Hessian product (the GN product
+    # plus the phi' terms of the off-diagonal blocks, Section 2.5) at the
+    # start point, with phi'' and phi' in each mode's order
+    A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+    X = [torch.randn(d, R, device=dev) for d in wl.dims]
+    w = [tt.tttp(ix, tt.INDEX_T, A, out_order=d, epi="d2phi", loss="poisson") for d in range(3)]
+    g = [tt.tttp(ix, tt.INDEX_T, A, out_order=d, epi="dphi", loss="poisson") for d in range(3)]
+    tt.newton_matvec(ix, w, g, A, X, 2 * lam)
+    for name, fn in (("gn_matvec_ms", lambda: tt.gn_matvec(ix, w, A, X, 2 * lam)),
+                     ("newton_matvec_ms", lambda: tt.newton_matvec(ix, w, g, A, X, 2 * lam))):
+        out[name] = timed(fn)[0]
     return out
 
 

@@ -256,6 +256,28 @@ tt_status gn_matvec(const tt_index *ix, const void *d_w, int w_order,
                     double lambda2, void *const *d_Y, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * newton_matvec -- full Hessian-vector product of the objective (Section 2.5
+ * with the phi' terms of the off-diagonal blocks; Appendix A):
+ *     Y_d = gn_matvec_d(w, X) + sum_e g_e dh_e^(d),
+ *     dh_e^(d) = sum_{p != d} X_p[i_p(e)] * prod_{q != d, p} A_q[i_q(e)]
+ * with w = phi'' and g = phi' per nonzero, lambda2 = 2 lambda for the
+ * objective's regularizer.  The GN part runs as in gn_matvec (and shares its
+ * position map and w .* z workspace); the phi' terms take one more pass per
+ * mode, which gathers the rows of both A and X of the other modes.
+ *   d_w, w_order    as in gn_matvec.
+ *   d_g, g_order    phi' per nonzero: TT_ORDER_PER_MODE (host array of N
+ *                   device pointers, each in that mode's sorted order) or
+ *                   TT_ORDER_COO; not NULL.
+ * The product is symmetric but, unlike the GN operator, not necessarily
+ * positive semidefinite.
+ * ------------------------------------------------------------------------- */
+tt_status newton_matvec(const tt_index *ix, const void *d_w, int w_order,
+                        double w_const, const void *d_g, int g_order,
+                        const void *const *d_A, const void *const *d_X, int R,
+                        int64_t ldA, tt_dtype fdt, double lambda2,
+                        void *const *d_Y, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * tt_gradient -- hand-written adjoint of the objective (Table 1 gradient
  * row; Appendix A):  grad_d = MTTKRP_d(phi'(t, m)) + 2 lambda A_d, with m
  * recomputed inside each mode's pass (TTTP fused into MTTKRP).

@@ -620,6 +620,54 @@ tt_status gn_matvec(const tt_index *cix, const void *d_w, int w_order, double w_
                         fdt, lambda2, d_Y, nullptr, stream);
 }
 
+tt_status newton_matvec(const tt_index *cix, const void *d_w, int w_order, double w_const,
+                        const void *d_g, int g_order, const void *const *d_A,
+                        const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
+                        double lambda2, void *const *d_Y, hipStream_t stream) {
+  g_err.clear();
+  tt_index *ix = const_cast<tt_index *>(cix);
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(d_A != nullptr && d_X != nullptr && d_Y != nullptr && d_g != nullptr,
+           "NULL argument");
+  for (int p = 0; p < ix->N; ++p)
+    TT_CHECK(d_A[p] && d_X[p] && d_Y[p], "block %d is NULL", p);
+  TT_CHECK(d_g != TT_INDEX_T, "newton_matvec: phi' cannot be the index values");
+  TT_CHECK(g_order == TT_ORDER_PER_MODE || g_order == TT_ORDER_COO,
+           "newton_matvec phi' must be per-mode or COO");
+  const void *w[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  const int32_t *wp[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  const void *g[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  const int32_t *gp[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+  if (d_w != nullptr) {
+    TT_CHECK(w_order == TT_ORDER_PER_MODE || w_order == TT_ORDER_COO || d_w == TT_INDEX_T,
+             "newton_matvec weights must be per-mode, COO or the index values");
+    for (int d = 0; d < ix->N; ++d)
+      TT_ST(resolve_values(ix, d_w, w_order, d, fdt, &w[d], &wp[d], "newton_matvec weights"));
+  }
+  for (int d = 0; d < ix->N; ++d)
+    TT_ST(resolve_values(ix, d_g, g_order, d, fdt, &g[d], &gp[d], "newton_matvec phi'"));
+  // the Gauss-Newton part (phi'' terms and lambda2 X) ...
+  TT_ST(gn_matvec_impl(ix, d_w ? w : nullptr, w_const, d_w ? wp : nullptr, d_A, d_X, R, ldA,
+                       fdt, lambda2, d_Y, nullptr, stream));
+  // ... plus, per block, the phi' terms of the off-diagonal Hessian blocks
+  double *carry = nullptr;
+  TT_ST(carry_ws(ix, &carry));
+  for (int d = 0; d < ix->N; ++d) {
+    StreamCall c = base_call(ix, d, R, ldA, fdt);
+    for (int p = 0; p < ix->N; ++p) {
+      c.A[p] = d_A[p];
+      c.X[p] = d_X[p];
+    }
+    c.s = g[d];
+    c.s_perm = gp[d];
+    c.out = d_Y[d];
+    c.accumulate = 1;
+    c.carry = carry;
+    TT_LAUNCH(launch_stream(OP_NEWTON, c, stream), "newton kernel");
+  }
+  return TT_OK;
+}
+
 tt_status tt_gradient(const tt_index *cix, const void *const *d_A, int R, int64_t ldA,
                       tt_dtype fdt, tt_loss loss, double lambda, void *const *d_G,
                       hipStream_t stream) {

@@ -176,7 +176,7 @@ struct StreamCall {
                             // mode's sorted order): GN w_e * z_e, gradient phi''(t_e, m_e)
   const char *prof_name;    // profiler tag (NULL: named after the operation)
 };
-enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3 };
+enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3, OP_NEWTON = 4 };
 hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s);
 int stream_group_width(tt_dtype fdt, int R);
 int stream_rp(tt_dtype fdt, int R);

@@ -93,6 +93,11 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
       bytes = m * (4 * (N - 1) + v + (c.zout ? v : 0) + (N - 1) * R * b) +
               I * R * (b + 2 * xs);
       flops = m * R * (N + 3);
+    } else if (op == OP_NEWTON) {
+      name = "newton_terms";
+      bytes = m * (4 * (N - 1) + v + (c.s_perm ? 4 : 0) + (N - 1) * R * (b + xs)) +
+              I * R * xs * 2;
+      flops = m * R * (2 * (N - 1) + 2);
     } else {
       name = "gn_matvec";
       bytes = m * (4 * (N - 1) + (c.s ? v : 0) + (c.s_perm ? 4 : 0) + (c.zout ? v : 0) +

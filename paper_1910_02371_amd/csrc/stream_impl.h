@@ -23,6 +23,8 @@
 //             dh_e = sum_{p != n} X_p[i_p(e)] * prod_{q != n, p} A_q[i_q(e)]
 //             (optionally also stores w_e * z_e per nonzero, for the other
 //             modes' blocks of the same product)
+//   OP_NEWTON Y[i] += s_e * dh_e   (the phi' terms of the full Hessian
+//             product, Section 2.5 / Appendix A, with s = phi')
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
           } else {
             gather_frag<TR, VEC>(Ao[p], ldA, ip, c0, R, ra[u][p]);
           }
-          if constexpr (OP == OP_GN)
+          if constexpr (OP == OP_GN || OP == OP_NEWTON)
             gather_frag<DenseTr<AT>, VEC>(Xo[p], R, ip, c0, R, rx[u][p]);
         }
       }
@@ -254,7 +256,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
           } else {
             widen_frag<TR, VEC>(ra[u][p], c0, R, fa[p]);
           }
-          if constexpr (OP == OP_GN) widen_frag<DenseTr<AT>, VEC>(rx[u][p], c0, R, fx[p]);
+          if constexpr (OP == OP_GN || OP == OP_NEWTON)
+            widen_frag<DenseTr<AT>, VEC>(rx[u][p], c0, R, fx[p]);
         }
         if (e < e1) {
           const int row = sm.key[e + 1];
@@ -306,6 +309,18 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
 #pragma unroll
             for (int j = 0; j < V; ++j) acc[j] += wz * h[j];
             if (a.zout != nullptr && c0 == 0) reinterpret_cast<VT *>(a.zout)[b + e] = (VT)wz;
+          } else if constexpr (OP == OP_NEWTON) {
+            const AT sv = (AT)sm.val[e];
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+              AT dh;
+              if constexpr (NO == 1) {
+                dh = fx[0][j];
+              } else {
+                dh = fx[0][j] * fa[1][j] + fa[0][j] * fx[1][j];
+              }
+              acc[j] += sv * dh;
+            }
           } else {  // OP_TTTP
             AT d = AT(0);
 #pragma unroll
@@ -459,6 +474,7 @@ hipError_t launch_stream_t(StreamOp op, const StreamDev &d, int64_t nchunk,
     case OP_MTTKRP: k_stream<TR, N, G, VEC, OP_MTTKRP, CHUNK><<<grid, block, 0, s>>>(d); break;
     case OP_GRAD: k_stream<TR, N, G, VEC, OP_GRAD, CHUNK><<<grid, block, 0, s>>>(d); break;
     case OP_GN: k_stream<TR, N, G, VEC, OP_GN, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_NEWTON: k_stream<TR, N, G, VEC, OP_NEWTON, CHUNK><<<grid, block, 0, s>>>(d); break;
   }
   return hipGetLastError();
 }

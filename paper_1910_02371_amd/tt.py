@@ -49,6 +49,7 @@ SIGNATURES = {
     "mttkrp": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _I, _P]),
     "solve_factor": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _D, _P, _P, _U32, _P]),
     "gn_matvec": (_I, [_P, _P, _I, _D, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
+    "newton_matvec": (_I, [_P, _P, _I, _D, _P, _I, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
     "tt_gradient": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _PP, _P]),
     "tt_objective": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _P, _P]),
     "tt_als_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
@@ -322,6 +323,31 @@ def gn_matvec(ix, w, A, X, lam2, Y=None, w_order=ORDER_PER_MODE, w_const=2.0):
         wp = _values(w)
     _check(lib().gn_matvec(ix.handle, wp, w_order, float(w_const), _ptrs(A), _ptrs(X), R, ld,
                            fdt, float(lam2), _ptrs(Y), _stream()))
+    return Y
+
+
+def newton_matvec(ix, w, g, A, X, lam2, Y=None, w_order=ORDER_PER_MODE,
+                  g_order=ORDER_PER_MODE, w_const=2.0):
+    """Full Hessian-vector product (Section 2.5 with the phi' terms): the GN
+    product with weights ``w`` (as in gn_matvec) plus the phi' terms with
+    ``g`` = phi', a list of per-mode arrays or one COO array."""
+    fdt = fdt_of(A)
+    R, ld = _rank_ld(A)
+    if Y is None:
+        Y = [torch.empty((d, R), dtype=value_dtype(fdt), device="cuda") for d in ix.dims]
+    keep = []
+
+    def marshal(v, order):
+        if isinstance(v, (list, tuple)):
+            arr = _ptrs(v)
+            keep.append(arr)
+            return ctypes.cast(arr, ctypes.c_void_p), ORDER_PER_MODE
+        return _values(v), order
+
+    wp, w_order = marshal(w, w_order)
+    gp, g_order = marshal(g, g_order)
+    _check(lib().newton_matvec(ix.handle, wp, w_order, float(w_const), gp, g_order, _ptrs(A),
+                               _ptrs(X), R, ld, fdt, float(lam2), _ptrs(Y), _stream()))
     return Y
 
 

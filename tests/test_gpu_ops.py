@@ -421,6 +421,57 @@ def test_gn_matvec_parity(gpu_lib, form, weights, kind):
 
 
 @pytest.mark.parametrize("form", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("R", [16, 21])
+@pytest.mark.parametrize("kind", ["uniform", "heavy", "zipf"])
+@pytest.mark.parametrize("g_order", ["per_mode", "coo"])
+def test_newton_matvec_parity(gpu_lib, form, R, kind, g_order):
+    """Full Hessian-vector product (GN product + phi' terms) for the Poisson
+    log link at a random point: w = phi'' and g = phi' of the oracle's model
+    values, stored at the value precision, against the oracle's product
+    computed from t and the loss."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 41 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    rng = np.random.default_rng(6)
+    X64 = [stored_values(rng.standard_normal((d, R)), form) for d in wl.dims]
+    Xd = [dev_vals(x, form) for x in X64]
+    L = O.LOSS_POISSON_LOG
+    t = np.round(np.exp(np.abs(wl.t)))
+    m = O.tttp(wl.idx, None, As)
+    w = stored_values(O.d2phi(t, m, L), form)
+    g = stored_values(O.dphi(t, m, L), form)
+    ixs = O.build_index(wl.idx, wl.dims)
+    wd = [dev_vals(w[ixs[d]["perm"]], form) for d in range(3)]
+    if g_order == "per_mode":
+        Y = tt.newton_matvec(ix, wd, [dev_vals(g[ixs[d]["perm"]], form) for d in range(3)],
+                             A, Xd, 0.2)
+    else:
+        Y = tt.newton_matvec(ix, wd, dev_vals(g, form), A, Xd, 0.2, g_order=tt.ORDER_COO)
+    Y = host(Y)
+    # reference from the same stored w and g (t enters only through them)
+    ref = O.gn_matvec(wl.idx, w, As, X64, 0.2, wl.dims)
+    Aa, Xa = [np.abs(a) for a in As], [np.abs(x) for x in X64]
+    z_abs = O.jvp(wl.idx, Aa, Xa)
+    for d in range(3):
+        ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, Aa, d, wl.dims[d]) + 0.2 * Xa[d]
+        for p in range(3):
+            if p == d:
+                continue
+            Ap, Apa = list(As), list(Aa)
+            Ap[p], Apa[p] = X64[p], Xa[p]
+            ref[d] = ref[d] + O.mttkrp(wl.idx, g, Ap, d, wl.dims[d])
+            ra = ra + O.mttkrp(wl.idx, np.abs(g), Apa, d, wl.dims[d])
+        assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"newton mode {d}")
+    if form == "f64" and R == 16 and g_order == "per_mode":
+        # the same product from t and the loss, as the oracle defines it
+        full = O.newton_matvec(wl.idx, t, As, X64, 0.2, wl.dims, L)
+        for d in range(3):
+            np.testing.assert_allclose(Y[d], full[d], rtol=1e-9, atol=1e-9 * np.abs(full[d]).max())
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16", "f64"])
 @pytest.mark.parametrize("R", [1, 13, 21, 64])
 @pytest.mark.parametrize("kind", ["heavy", "zipf"])
 def test_gn_matvec_ranks(gpu_lib, form, R, kind):
