@@ -13,7 +13,7 @@ float64 for arbitrary tensor order N:
                  row solves, Solve Factor, objective, gradient, GN operator,
                  full Hessian-vector product.
 * ``solvers`` -- ALS sweep, ALS fast-loss identity, PCG Gauss-Newton step,
-                 generalized alternating-minimization sweep.
+                 generalized alternating-minimization sweep, CCD++ sweep.
 * ``bf16``    -- round-to-nearest-even emulation of bfloat16 storage.
 
 Parity status of each function is listed in its docstring; every function here
@@ -25,5 +25,7 @@ from .cp import (  # noqa: F401
     solve_rows, solve_factor, objective, gradient, jvp, gn_matvec, newton_matvec,
     rmse, cholesky_info, LOSS_LS, LOSS_POISSON_LOG,
 )
-from .solvers import als_sweep, als_fast_loss, pcg, gn_step, gam_sweep  # noqa: F401
+from .solvers import (  # noqa: F401
+    als_sweep, als_fast_loss, pcg, gn_step, gam_sweep, ccd_sweep,
+)
 from .bf16 import bf16_round  # noqa: F401

@@ -133,3 +133,34 @@ def gam_sweep(idx, t, A, dims, loss, lam, tol, max_inner):
         counts.append(k)
         infos.append(info)
     return A, counts, infos
+
+
+def ccd_sweep(idx, t, A, dims, lam):
+    """One least-squares coordinate-minimization sweep in the CCD++ order
+    (Section 2.3): for each column r, for each mode n in turn, every entry
+    u_ir of that column is set to its exact minimizer with all else fixed,
+        u_ir = sum_e rho_e h_er / (lam + sum_e h_er^2)    (e in row i),
+    with h_er the product of the other modes' column-r entries and
+    rho = t - model + (column r's own rank-1 term), the residual without
+    column r (it does not change while column r is updated).  After the
+    column, rho drops the new rank-1 term.  Returns the new factors and the
+    final residual t - model kept incrementally.
+    Pinned by: R = 1 equals the ALS sweep; the objective never increases;
+    the last updated column has zero partial derivatives; the incremental
+    residual equals the recomputed one."""
+    A = [np.array(a, dtype=np.float64) for a in A]
+    N, R = len(A), A[0].shape[1]
+    t = np.asarray(t, dtype=np.float64)
+    rho = t - cp.model_values(idx, A)
+    for r in range(R):
+        cols = [a[:, r:r + 1] for a in A]
+        rho = rho + cp.tttp(idx, None, cols)
+        for n in range(N):
+            cols = [a[:, r:r + 1] for a in A]
+            num = cp.mttkrp(idx, rho, cols, n, dims[n])[:, 0]
+            sq = [c * c for c in cols]
+            den = lam + cp.mttkrp(idx, None, sq, n, dims[n])[:, 0]
+            A[n][:, r] = num / den
+        cols = [a[:, r:r + 1] for a in A]
+        rho = rho - cp.tttp(idx, None, cols)
+    return A, rho

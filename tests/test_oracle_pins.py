@@ -542,6 +542,40 @@ def test_gam_stop_rule():
     assert k == c1[0]
 
 
+# ------------------------------------------------------------------ CCD ----
+def test_ccd_rank1_is_als():
+    """Rank 1: coordinate minimization of the single column is the ALS
+    update of each mode (Section 2.3), so one CCD++ sweep equals one ALS
+    sweep from the same start (different arithmetic: residual contractions
+    against the Omega-hat Gram and Cholesky solve)."""
+    wl = W.random_tensor((9, 10, 8), 200, 55, rank=1)
+    lam = 1e-3
+    A = W.init_factors(wl.dims, 1, float(np.mean(wl.t)), 3, dtype=np.float64)
+    Aa, _ = O.als_sweep(wl.idx, wl.t, A, wl.dims, lam)
+    Ac, _ = O.ccd_sweep(wl.idx, wl.t, A, wl.dims, lam)
+    for d in range(3):
+        np.testing.assert_allclose(Ac[d], Aa[d], rtol=1e-10, atol=1e-13)
+
+
+def test_ccd_monotone_stationary_and_residual():
+    """Each coordinate update minimizes exactly, so the objective
+    (sum (t - m)^2 + lam sum ||A||^2) never increases; right after a sweep
+    the last updated column (r = R-1 of the last mode) has zero partial
+    derivatives; the incrementally kept residual equals t - model."""
+    wl = W.random_tensor((9, 10, 8), 200, 56, rank=3)
+    lam = 1e-3
+    A = W.init_factors(wl.dims, 4, float(np.mean(wl.t)), 5, dtype=np.float64)
+    f_prev = O.objective(wl.idx, wl.t, A, O.LOSS_LS, lam)
+    for _ in range(3):
+        A, rho = O.ccd_sweep(wl.idx, wl.t, A, wl.dims, lam)
+        f = O.objective(wl.idx, wl.t, A, O.LOSS_LS, lam)
+        assert f <= f_prev * (1 + 1e-12)
+        f_prev = f
+        g = O.gradient(wl.idx, wl.t, A, O.LOSS_LS, lam, wl.dims)[2][:, 3]
+        assert np.abs(g).max() < 1e-10 * max(1.0, np.abs(wl.t).max())
+        np.testing.assert_allclose(rho, wl.t - O.tttp(wl.idx, None, A), rtol=0, atol=1e-12)
+
+
 # ----------------------------------------------------------------- bf16 ----
 def test_bf16_rne():
     exact = np.array([0.0, 1.0, -2.5, 0.15625, 2.0 ** 127 * 1.5, 2.0 ** -120])
