@@ -55,6 +55,8 @@ def parse():
                    help="skip the graph-replay vs plain-launch comparison")
     p.add_argument("--form-sweeps", type=int, default=5,
                    help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
+    p.add_argument("--no-ccd", dest="ccd", action="store_false",
+                   help="ratings: skip the ALS-vs-CCD++ sweep comparison")
     p.add_argument("--poisson-iters", type=int, default=3,
                    help="ratings: GAM sweeps and GN steps of the Poisson log-link "
                         "comparison (0: skip)")
@@ -266,6 +268,10 @@ def main():
     if args.poisson_iters > 0 and ratings:
         poisson = compare_poisson(tt, ix, wl, dev, args.poisson_iters)
 
+    ccd = None
+    if args.ccd and ratings:
+        ccd = compare_ccd(tt, ix, A0, wl, lam, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, A0, R, lam, lam_gn, args.cpu_sample, passes, gn=ratings)
@@ -304,6 +310,7 @@ def main():
         "forms": forms,
         "batching": batching,
         "poisson": poisson,
+        "ccd": ccd,
         "tuning": tuning,
         "calls": calls,
         "step_kernels": step_prof,
@@ -500,6 +507,38 @@ def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5
     for name, fn in (("gn_matvec_ms", lambda: tt.gn_matvec(ix, w, A, X, 2 * lam)),
                      ("newton_matvec_ms", lambda: tt.newton_matvec(ix, w, g, A, X, 2 * lam))):
         out[name] = timed(fn)[0]
+    return out
+
+
+def compare_ccd(tt, ix, A0, wl, lam, dev):
+    """One ALS sweep and one CCD++ sweep (Section 2.3: column-wise exact
+    coordinate minimization, rank-1 MTTKRP + Solve Factor per column and
+    mode) from the same FP32 start: time (HIP events) and training RMSE
+    after the sweep.  A first untimed CCD++ sweep on a copy allocates its
+    workspaces."""
+    import torch
+
+    def fresh():
+        return [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+
+    def rmse(A):
+        return (tt.objective(ix, A, "ls", 0.0).item() / wl.nnz) ** 0.5
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1)
+
+    tt.ccd_sweep(ix, fresh(), lam)
+    out = {"rmse_start": rmse(fresh())}
+    for name, fn in (("als", tt.als_sweep), ("ccd", tt.ccd_sweep)):
+        A = fresh()
+        out[f"{name}_ms"] = timed(lambda: fn(ix, A, lam))
+        out[f"{name}_rmse"] = rmse(A)
     return out
 
 

@@ -330,6 +330,26 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                      int kmax, double *d_stats, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * tt_ccd_sweep -- one least-squares coordinate-minimization sweep in the
+ * CCD++ order (Section 2.3 and its Section 4 implementation): for each
+ * column r, for each mode n in turn, every entry of column r of A_n is set
+ * to its exact minimizer
+ *     u_ir = sum_e rho_e h_e / (lambda + sum_e h_e^2),   e in row i,
+ * h_e the product of the other modes' column-r entries and rho the
+ * residual t - model without column r's rank-1 term.  Each column update
+ * is mttkrp of rho at rank 1 followed by Solve Factor at rank 1 (the
+ * column is a strided view: rank 1, leading dimension ldA).  rho is kept
+ * incrementally in COO order (two rank-1 TTTP passes per column).  Factors
+ * are updated in place.  Requires t.
+ *   d_info          optional int32[sum_n I_n]: Solve Factor info of the
+ *                   last column's solves.
+ * Workspaces (2 m values and I_max values) are allocated on first use.
+ * ------------------------------------------------------------------------- */
+tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
+                       tt_dtype fdt, double lambda, int32_t *d_info,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * tt_gam_sweep -- one generalized alternating-minimization sweep (Section
  * 2.2 for a general loss; stop rule of Section 5.7): for n = 0..N-1, Newton
  * iterations on the rows of A_n with the other factors fixed.  Iteration:

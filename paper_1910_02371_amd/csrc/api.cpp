@@ -842,6 +842,70 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
   return TT_OK;
 }
 
+tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
+                       double lambda, int32_t *d_info, hipStream_t st) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  TT_CHECK(d_A != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
+  const int N = ix->N;
+  const tt_dtype dn = dense_of(fdt);
+  const size_t vsz = value_size(fdt);
+  const size_t esz = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
+  const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
+  // workspace: the residual rho and one rank-1 term (COO order), one column
+  // of right-hand sides
+  void *vrho = nullptr, *vterm = nullptr, *vm = nullptr;
+  TT_ST(ws_get(ix, "ccd_rho", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vrho));
+  TT_ST(ws_get(ix, "ccd_term", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vterm));
+  TT_ST(ws_get(ix, "ccd_m", (size_t)std::max<int64_t>(ix->max_I, 1) * vsz, &vm));
+  // rho = t - model, in COO order (streamed in mode 0)
+  const int32_t *coo0 = ix->mode[0].d_perm;
+  if (ix->m > 0)
+    TT_ST(tttp_mode(ix, 0, ix->mode[0].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID,
+                    TT_LOSS_LS, vrho, coo0, nullptr, nullptr, st));
+  for (int r = 0; r < R; ++r) {
+    const void *cols[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
+    for (int p = 0; p < N; ++p) cols[p] = (const char *)d_A[p] + (size_t)r * esz;
+    // rho <- rho + u_r o v_r o w_r: the residual without column r
+    if (ix->m > 0) {
+      TT_ST(tttp_mode(ix, 0, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
+                      vterm, coo0, nullptr, nullptr, st));
+      TT_LAUNCH(launch_axpy_values(vrho, vterm, 1.0, ix->m, dn, st), "ccd residual");
+    }
+    int64_t off = 0;
+    for (int n = 0; n < N; ++n) {
+      // column r of A_n: (lambda + sum_e h_e^2) x_i = sum_e rho_e h_e, h_e the
+      // other modes' column-r entries (Solve Factor at rank 1)
+      TT_ST(mttkrp_impl(ix, vrho, ix->mode[n].d_perm, 1.0, cols, 1, ldA, fdt, n, vm, 0, st));
+      SolveCall c;
+      memset(&c, 0, sizeof(c));
+      c.ix = ix;
+      c.mode = n;
+      c.R = 1;
+      c.ldA = ldA;
+      c.fdt = fdt;
+      for (int p = 0; p < N; ++p) c.A[p] = cols[p];
+      c.w_scale = 1.0;
+      c.lambda = lambda;
+      c.rhs = vm;
+      c.X = const_cast<void *>(cols[n]);
+      c.info = d_info ? d_info + off : nullptr;
+      TT_ST(run_solve_factor(ix, c, st));
+      off += ix->mode[n].I;
+    }
+    // rho <- rho - (new rank-1 term)
+    if (ix->m > 0) {
+      TT_ST(tttp_mode(ix, 0, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
+                      vterm, coo0, nullptr, nullptr, st));
+      TT_LAUNCH(launch_axpy_values(vrho, vterm, -1.0, ix->m, dn, st), "ccd residual");
+    }
+  }
+  return TT_OK;
+}
+
 tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
                        tt_loss loss, double lambda, double tol, int max_inner,
                        int32_t *d_info, int32_t *h_iters, hipStream_t st) {

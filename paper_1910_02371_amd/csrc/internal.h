@@ -235,5 +235,8 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
 // A += D, both I x R in the factor dtype fdt with leading dimensions ldA, ldD.
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
                            int64_t I, int R, hipStream_t s);
+// y += a x over n values of the dense dtype.
+hipError_t launch_axpy_values(void *y, const void *x, double a, int64_t n, tt_dtype dense,
+                              hipStream_t s);
 
 }  // namespace tt

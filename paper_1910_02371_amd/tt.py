@@ -55,6 +55,7 @@ SIGNATURES = {
     "tt_als_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
     "tt_gn_step": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P]),
     "tt_gam_sweep": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _D, _I, _P, _P, _P]),
+    "tt_ccd_sweep": (_I, [_P, _PP, _I, _I64, _I, _D, _P, _P]),
     "tt_graph_begin": (_I, [_P]),
     "tt_graph_end": (_I, [_P, ctypes.POINTER(_P)]),
     "tt_graph_launch": (_I, [_P, _P]),
@@ -393,6 +394,15 @@ def gn_step(ix, A, loss, lam, tol=5e-3, kmax=30, stats=None):
     _check(lib().tt_gn_step(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
                             float(tol), int(kmax), _ptr(stats), _stream()))
     return stats
+
+
+def ccd_sweep(ix, A, lam, info=None):
+    """One least-squares CCD++ sweep (Section 2.3), factors updated in place."""
+    fdt = fdt_of(A)
+    R, ld = _rank_ld(A)
+    _check(lib().tt_ccd_sweep(ix.handle, _ptrs(A), R, ld, fdt, float(lam), _ptr(info),
+                              _stream()))
+    return A
 
 
 def gam_sweep(ix, A, loss, lam, tol=1e-3, max_inner=5, info=None):

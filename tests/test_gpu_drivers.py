@@ -298,3 +298,65 @@ def test_gam_least_squares_one_iteration_is_als(gpu_lib, form):
     for d in range(3):
         a, b = host(A[d]), host(B[d])
         assert np.linalg.norm(a - b) <= tau * np.linalg.norm(b), f"mode {d}"
+
+
+# ------------------------------------------------------------------ CCD++ ----
+@pytest.mark.parametrize("case", list(GAM_CASES))
+@pytest.mark.parametrize("R", [1, 4, 7])
+def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R):
+    """FP64 form: two CCD++ sweeps equal the oracle's (column views of rank
+    1 with the factors' leading dimension; ragged R; empty rows), and the
+    objective does not increase."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem(case, "ls")
+    A0 = W.init_factors(wl.dims, R, mm, 8, dtype=np.float64)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f64"))
+    A = [dev_factor(a, "f64") for a in A0]
+    info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
+    Ar = A0
+    f_prev = O.objective(wl.idx, t, A0, O.LOSS_LS, lam)
+    for _ in range(2):
+        tt.ccd_sweep(ix, A, lam, info)
+        Ar, _ = O.ccd_sweep(wl.idx, t, Ar, wl.dims, lam)
+        assert (info.cpu().numpy() == 0).all()
+        for d in range(3):
+            np.testing.assert_allclose(host(A[d]), Ar[d], rtol=1e-7, atol=1e-9)
+        f = tt.objective(ix, A, "ls", lam).item()
+        assert f <= f_prev * (1 + 1e-12)
+        f_prev = f
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("case", ["small", "heavy"])
+def test_ccd_sweep_low_precision_forms(gpu_lib, form, case):
+    """FP32 / BF16 storage: one CCD++ sweep at R = 8 within the form's
+    tolerance of the oracle run from the same stored inputs (relative
+    Frobenius error per factor)."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem(case, "ls")
+    t = stored_values(t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 8, mm, 8, dtype=np.float64), form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    A = [dev_factor(a, form) for a in A0]
+    tt.ccd_sweep(ix, A, lam)
+    Ar, _ = O.ccd_sweep(wl.idx, t, A0, wl.dims, lam)
+    tau = 1e-4 if form == "f32" else 2e-2
+    for d in range(3):
+        err = np.linalg.norm(host(A[d]) - Ar[d]) / np.linalg.norm(Ar[d])
+        assert err <= tau, f"{form} {case} mode {d}: relative error {err:.2e}"
+
+
+def test_ccd_rank1_is_als_f32(gpu_lib):
+    """Rank 1: a CCD++ sweep is the ALS sweep (Section 2.3)."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem("small", "ls")
+    t = stored_values(t, "f32")
+    A0 = stored_factors(W.init_factors(wl.dims, 1, mm, 8, dtype=np.float64), "f32")
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f32"))
+    A = [dev_factor(a, "f32") for a in A0]
+    B = [dev_factor(a, "f32") for a in A0]
+    tt.ccd_sweep(ix, A, lam)
+    tt.als_sweep(ix, B, lam)
+    for d in range(3):
+        a, b = host(A[d]), host(B[d])
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b), f"mode {d}"
