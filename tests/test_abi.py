@@ -24,7 +24,8 @@ def test_header_parses():
     names = declared_functions()
     for n in ["tt_build_index", "tt_index_destroy", "tt_index_view", "tttp", "mttkrp",
               "solve_factor", "gn_matvec", "tt_gradient", "tt_objective", "tt_als_sweep",
-              "tt_gn_step", "tt_last_error"]:
+              "tt_gn_step", "tt_gam_sweep", "tt_ccd_sweep", "newton_matvec",
+              "tt_last_error"]:
         assert n in names
 
 
@@ -74,3 +75,12 @@ def test_host_argument_checks(lib):
     assert L.tt_graph_launch(None, None) == -1
     assert L.tt_graph_destroy(None) == 0
     assert L.tt_index_reserve(None, 8, 1, 0) == -1
+    # the sweep drivers and the full Hessian product check their index first
+    it = (ctypes.c_int32 * 3)()
+    assert L.tt_gam_sweep(None, None, 4, 4, 1, 1, 0.1, 1e-3, 5, None, it, None) == -1
+    assert b"index" in L.tt_last_error()
+    assert L.tt_ccd_sweep(None, None, 4, 4, 1, 1e-5, None, None) == -1
+    assert b"index" in L.tt_last_error()
+    assert L.newton_matvec(None, None, -2, 2.0, None, -2, None, None, 4, 4, 1, 0.2,
+                           None, None) == -1
+    assert b"index" in L.tt_last_error()
