@@ -27,7 +27,8 @@ KERNEL_MATCH = {
     "heavy_fixup": "k_heavy_fixup",
 }
 # (the Gauss-Newton product's MTTKRP blocks run the MTTKRP kernel)
-STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3, "gn_mttkrp": 1}
+STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3, "gn_mttkrp": 1,
+             "newton_terms": 4}
 
 
 # fused Gram + Cholesky of rows with one light task:
