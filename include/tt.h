@@ -339,8 +339,11 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * residual t - model without column r's rank-1 term.  Each column update
  * is mttkrp of rho at rank 1 followed by Solve Factor at rank 1 (the
  * column is a strided view: rank 1, leading dimension ldA).  rho is kept
- * incrementally in COO order (two rank-1 TTTP passes per column).  Factors
- * are updated in place.  Requires t.
+ * incrementally (two rank-1 TTTP passes per column) in the sorted order of
+ * the mode with the most rows, and the other modes read it through the
+ * index's position map (built on first use, with one synchronization,
+ * unless tt_index_reserve built it).  Factors are updated in place.
+ * Requires t.
  *   d_info          optional int32[sum_n I_n]: Solve Factor info of the
  *                   last column's solves.
  * Workspaces (2 m values and I_max values) are allocated on first use.

@@ -861,25 +861,31 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   TT_ST(ws_get(ix, "ccd_rho", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vrho));
   TT_ST(ws_get(ix, "ccd_term", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vterm));
   TT_ST(ws_get(ix, "ccd_m", (size_t)std::max<int64_t>(ix->max_I, 1) * vsz, &vm));
-  // rho = t - model, in COO order (streamed in mode 0)
-  const int32_t *coo0 = ix->mode[0].d_perm;
-  if (ix->m > 0)
-    TT_ST(tttp_mode(ix, 0, ix->mode[0].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID,
-                    TT_LOSS_LS, vrho, coo0, nullptr, nullptr, st));
+  // rho = t - model, kept in the sorted order of the mode with the most rows
+  // (written and updated with unit stride); the other modes read it through
+  // the index's position map
+  const int zm = gn_zmode(ix);
+  const int32_t *zmap = nullptr;
+  if (ix->m > 0) {
+    TT_ST(zmap_get(ix, st, &zmap));
+    TT_ST(tttp_mode(ix, zm, ix->mode[zm].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID,
+                    TT_LOSS_LS, vrho, nullptr, nullptr, nullptr, st));
+  }
   for (int r = 0; r < R; ++r) {
     const void *cols[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
     for (int p = 0; p < N; ++p) cols[p] = (const char *)d_A[p] + (size_t)r * esz;
     // rho <- rho + u_r o v_r o w_r: the residual without column r
     if (ix->m > 0) {
-      TT_ST(tttp_mode(ix, 0, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
-                      vterm, coo0, nullptr, nullptr, st));
+      TT_ST(tttp_mode(ix, zm, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
+                      vterm, nullptr, nullptr, nullptr, st));
       TT_LAUNCH(launch_axpy_values(vrho, vterm, 1.0, ix->m, dn, st), "ccd residual");
     }
     int64_t off = 0;
     for (int n = 0; n < N; ++n) {
       // column r of A_n: (lambda + sum_e h_e^2) x_i = sum_e rho_e h_e, h_e the
       // other modes' column-r entries (Solve Factor at rank 1)
-      TT_ST(mttkrp_impl(ix, vrho, ix->mode[n].d_perm, 1.0, cols, 1, ldA, fdt, n, vm, 0, st));
+      const int32_t *rperm = (n == zm || ix->m == 0) ? nullptr : zmap + (int64_t)n * ix->m;
+      TT_ST(mttkrp_impl(ix, vrho, rperm, 1.0, cols, 1, ldA, fdt, n, vm, 0, st));
       SolveCall c;
       memset(&c, 0, sizeof(c));
       c.ix = ix;
@@ -898,8 +904,8 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
     }
     // rho <- rho - (new rank-1 term)
     if (ix->m > 0) {
-      TT_ST(tttp_mode(ix, 0, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
-                      vterm, coo0, nullptr, nullptr, st));
+      TT_ST(tttp_mode(ix, zm, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
+                      vterm, nullptr, nullptr, nullptr, st));
       TT_LAUNCH(launch_axpy_values(vrho, vterm, -1.0, ix->m, dn, st), "ccd residual");
     }
   }
