@@ -422,6 +422,118 @@ def test_gn_step_decreases_objective():
     assert it >= 1
 
 
+def _gn_problem(loss, seed):
+    """A tiny tensor for the Gauss-Newton composition pins: least squares
+    with planted values, or Poisson counts drawn at a planted log rate."""
+    wl = W.random_tensor((4, 5, 3), 26, seed, rank=2, noise=0.05)
+    rng = np.random.default_rng(seed + 1)
+    A = [0.7 * rng.random((I, 2)) + 0.2 for I in wl.dims]
+    t = np.asarray(wl.t, dtype=np.float64)
+    if loss == O.LOSS_POISSON_LOG:
+        t = rng.poisson(np.exp(0.5 * t)).astype(np.float64)
+    return wl, t, A
+
+
+def _gn_explicit(wl, t, A, loss, lam):
+    """H = J^T diag(phi'') J + 2 lam I, the gradient J^T phi' + 2 lam vec(A)
+    and the block-diagonal preconditioner (each mode's diagonal block of H),
+    all from the explicit Jacobian and the closed-form loss derivatives."""
+    J = jacobian(wl.idx, A, wl.dims)
+    a = np.concatenate([x.ravel() for x in A])
+    m = J.shape[0]
+    # model values from the Jacobian: each nonzero's row of J dotted with the
+    # factors counts every rank-1 term N times (once per mode)
+    mv = (J @ a) / len(A)
+    if loss == O.LOSS_LS:
+        d1, d2 = 2.0 * (mv - t), np.full(m, 2.0)
+    else:
+        d1, d2 = np.exp(mv) - t, np.exp(mv)
+    n = J.shape[1]
+    H = J.T @ (d2[:, None] * J) + 2.0 * lam * np.eye(n)
+    g = J.T @ d1 + 2.0 * lam * a
+    P = np.zeros_like(H)
+    off = 0
+    for I in wl.dims:
+        sl = slice(off, off + I * A[0].shape[1])
+        P[sl, sl] = H[sl, sl]
+        off += I * A[0].shape[1]
+    return H, g, P
+
+
+def _step(A1, A):
+    return np.concatenate([(x1 - x).ravel() for x1, x in zip(A1, A)])
+
+
+@pytest.mark.parametrize("loss", [O.LOSS_LS, O.LOSS_POISSON_LOG])
+def test_gn_step_converged_is_newton_system_solution(loss):
+    """Section 2.5: with a tight tolerance and enough iterations the step is
+    -(J^T diag(phi'') J + 2 lam I)^{-1} grad f, the full Gauss-Newton step
+    (fails for lam instead of 2 lam in the operator, or for 2 instead of
+    phi'' as the operator weights)."""
+    lam = 0.05
+    wl, t, A = _gn_problem(loss, 91)
+    H, g, _ = _gn_explicit(wl, t, A, loss, lam)
+    A1, it, rel = O.gn_step(wl.idx, t, A, wl.dims, loss, lam, 1e-14, 4 * H.shape[0])
+    np.testing.assert_allclose(_step(A1, A), -np.linalg.solve(H, g), rtol=1e-8, atol=1e-10)
+    assert rel <= 1e-14
+
+
+@pytest.mark.parametrize("loss", [O.LOSS_LS, O.LOSS_POISSON_LOG])
+def test_gn_step_one_iteration_is_preconditioned_steepest_descent(loss):
+    """One PCG iteration from x0 = 0 gives alpha P^{-1} r0 with r0 = -grad f,
+    P the block diagonal of J^T diag(phi'') J + 2 lam I and
+    alpha = (r0 . P^{-1} r0) / (z0 . H z0): pins the preconditioner's weights
+    (phi'') and shift (2 lam) separately from the operator's."""
+    lam = 0.05
+    wl, t, A = _gn_problem(loss, 92)
+    H, g, P = _gn_explicit(wl, t, A, loss, lam)
+    r0 = -g
+    z0 = np.linalg.solve(P, r0)
+    alpha = (r0 @ z0) / (z0 @ H @ z0)
+    A1, it, _ = O.gn_step(wl.idx, t, A, wl.dims, loss, lam, 0.0, 1)
+    assert it == 1
+    np.testing.assert_allclose(_step(A1, A), alpha * z0, rtol=1e-10, atol=1e-12)
+
+
+def test_gn_step_stops_on_unpreconditioned_residual():
+    """The PCG stop rule (Sections 5.6/5.7) compares the unpreconditioned
+    residual norm ||b - H x_k|| / ||b|| with the tolerance.  A tolerance is
+    chosen at which that norm and the preconditioned one sqrt(r.P^{-1}r)
+    (relative to its initial value) first fall below it at different
+    iterations; the step must stop at the unpreconditioned crossing and
+    equal that iterate."""
+    lam = 0.05
+    loss = O.LOSS_POISSON_LOG
+    wl, t, A = _gn_problem(loss, 93)
+    H, g, P = _gn_explicit(wl, t, A, loss, lam)
+    b = -g
+    Pi = np.linalg.inv(P)
+    xs, un, pre = [], [], []
+    for k in range(1, 12):
+        A1, it, _ = O.gn_step(wl.idx, t, A, wl.dims, loss, lam, 0.0, k)
+        assert it == k
+        x = _step(A1, A)
+        r = b - H @ x
+        xs.append(x)
+        un.append(np.linalg.norm(r) / np.linalg.norm(b))
+        pre.append(np.sqrt(r @ Pi @ r) / np.sqrt(b @ Pi @ b))
+
+    def first(seq, tol):
+        return next((k + 1 for k, v in enumerate(seq) if v <= tol), None)
+
+    tol = None
+    for cand in np.geomspace(0.5, 1e-6, 200):
+        ku, kp = first(un, cand), first(pre, cand)
+        if ku is not None and kp is not None and ku != kp:
+            tol = float(cand)
+            break
+    assert tol is not None, "no tolerance separates the two residual measures"
+    ku = first(un, tol)
+    A1, it, rel = O.gn_step(wl.idx, t, A, wl.dims, loss, lam, tol, 50)
+    assert it == ku and it != first(pre, tol)
+    np.testing.assert_allclose(_step(A1, A), xs[ku - 1], rtol=1e-9, atol=1e-12)
+
+
 # ------------------------------------------------------------------ ALS ----
 def test_als_monotone_gradient_and_fast_loss():
     wl = W.random_tensor((9, 10, 8), 200, 55, rank=3)
