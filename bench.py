@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the completion hot path on one MI355X.
 
-One step = one pass of the whole hot path over the resident tensor:
-  * one ALS sweep: per mode MTTKRP of t (right-hand sides) and Solve Factor
-    (Gram on matrix cores + FP64 Cholesky) -- Sections 2.2, 3.2, 3.4;
-  * one preconditioned Gauss-Newton step with ``--cg`` CG iterations: the
-    objective through the TTTP loss epilogue, the fused gradient adjoint,
-    the block-diagonal preconditioner factorization, and per CG iteration one
-    fused implicit GN matvec plus one preconditioner application -- Sections
-    2.5 and 3.3.
+Headline workload (``--workload uniform``, the default): the 2^20-cubed
+tensor with 1.5 x 10^9 uniformly random nonzeros (one GPU's share of a
+10^10-nonzero least-squares completion, Section 5.6), rank 32, FP32 factors.
+One step = one TTTP over every nonzero (model values) + one ALS sweep, each
+mode updated by Solve Factor with the MTTKRP(t) right-hand side formed in
+the Gram pass (Sections 2.2, 3.2-3.4).  The BF16 factor-storage form is
+compared with the FP32 form by ALS sweeps from the same start, at equal
+training RMSE.
+
+Secondary workload (``--secondary``, on by default; ``--workload ratings``
+makes it the headline): the 10^8-nonzero Zipf ratings tensor at rank 64,
+one step = one ALS sweep + one preconditioned Gauss-Newton step (Section
+2.5), with the batching, BF16-form, Poisson (Section 5.7) and CCD++
+(Section 2.3) comparison legs.
+
 The index (per-mode stable sort) is built once before timing and reported
 separately.  ``value`` counts nonzero-rank products: m * R for every pass
-over the nonzeros (TTTP, MTTKRP, gradient and GN-matvec passes, Gram passes)
-divided by the step time.
+over the nonzeros the unfused method makes, divided by the step time.
 
 Prints ONE JSON line.  Single GPU only.
 """
@@ -29,26 +35,45 @@ sys.path.insert(0, ROOT)
 METRIC = "MTTKRP+TTTP nnz·R/s, %HBM peak; ALS/GN sweep s, BF16 vs FP32 @ equal RMSE"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_TFLOPS = 157.3
+# counters say the algorithmic bytes reach HBM when the measured traffic is at
+# least this fraction of them
+HBM_BINDS_FRAC = 0.8
+
+# device code each profiled kernel is built from (the counters recorded in
+# profiles/ are valid while these files are unchanged)
+KERNEL_SOURCES = {
+    "gram": ["solve.hip", "common.h"],
+    "cholesky": ["solve.hip", "common.h"],
+    "precond": ["solve.hip", "common.h"],
+    "stream": ["stream_impl.h", "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip",
+               "common.h"],
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", choices=["ratings", "uniform"], default="ratings",
-                   help="ratings: 100M-nonzero Zipf ratings tensor, ALS sweep + GN step; "
-                        "uniform: 1.5B-nonzero 2^20-cubed tensor, TTTP + ALS sweep")
-    p.add_argument("--R", type=int, default=None, help="rank (64 ratings, 32 uniform)")
+    p.add_argument("--workload", choices=["ratings", "uniform"], default="uniform",
+                   help="uniform: 1.5B-nonzero 2^20-cubed tensor, TTTP + ALS sweep (headline); "
+                        "ratings: 100M-nonzero Zipf ratings tensor, ALS sweep + GN step")
+    p.add_argument("--R", type=int, default=None, help="rank (32 uniform, 64 ratings)")
     p.add_argument("--form", choices=["f32", "bf16"], default="f32")
-    p.add_argument("--cg", type=int, default=2, help="CG iterations in the GN step")
+    p.add_argument("--cg", type=int, default=2, help="CG iterations in the ratings GN step")
     p.add_argument("--nnz", type=int, default=None)
+    p.add_argument("--no-secondary", dest="secondary", action="store_false",
+                   help="uniform headline: skip the ratings-workload legs")
+    p.add_argument("--secondary-steps", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=1 << 19)
+    p.add_argument("--cpu-sample", type=int, default=None,
+                   help="nonzeros of the oracle's sample (default 2^16 uniform, 2^18 ratings)")
+    p.add_argument("--cpu-reps", type=int, default=3,
+                   help="timed oracle runs per thread setting (after one warm-up run)")
     p.add_argument("--no-tune", dest="tune", action="store_false",
                    help="keep the default work partitions (no autotuner)")
     p.add_argument("--no-batching", dest="batching", action="store_false",
@@ -64,41 +89,259 @@ def parse():
                    help="Gauss-Newton steps after the ALS sweeps of the forms comparison")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this size first (counter calibration)")
-    return p.parse_args()
+    return p.parse_args(argv)
 
 
-def kernel_source_hash():
+def kernel_family(kernel):
+    if kernel.startswith("gram"):
+        return "gram"
+    if kernel.startswith("cholesky"):
+        return "cholesky"
+    if kernel == "precond_apply":
+        return "precond"
+    return "stream"
+
+
+def kernel_source_hash(kernel=None):
+    """Hash of the device sources of `kernel` (all of csrc/ when None)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1910_02371_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    files = sorted(os.listdir(d)) if kernel is None else KERNEL_SOURCES[kernel_family(kernel)]
+    for f in files:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel, workload, src_hash):
-    """HBM traffic per launch measured with rocprofv3 counters, if a committed
-    summary for this kernel, workload and kernel source exists."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def profile_record(db_name, kernel, workload):
+    """A committed counter record (profiles/<db_name>) for this kernel and
+    workload, if it was measured on the current device sources."""
+    path = os.path.join(ROOT, "profiles", db_name)
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path)).get(f"{kernel}|{workload}")
     except Exception:
         return None
-    if not rec or rec.get("src_hash") != src_hash:
+    if not rec or rec.get("src_hash") != kernel_source_hash(kernel):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
-def main():
-    args = parse()
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, copy-kernel calibrated), or None."""
+    rec = profile_record("traffic.json", kernel, workload)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def price_roofline(kernel, rec, workload, peak_gbs=HBM_PEAK_GBS, peak_tf=FP32_MFMA_TFLOPS):
+    """Roofline entry of one kernel from the library profiler's record
+    (launches, total ms, algorithmic bytes and flops over the timed steps).
+
+    The bound is the one that binds: HBM when the kernel is a streaming
+    (gather) kernel, or a Gram contraction whose measured HBM traffic is
+    close to its algorithmic bytes; the FP32 matrix-core peak for a Gram
+    whose gathers the caches serve (measured traffic well below the
+    algorithmic bytes, or, unmeasured, an algorithmic byte rate above the
+    HBM peak).  `frac` never exceeds what the bound allows: an algorithmic
+    byte rate above the HBM peak is reported as `effective_GBps`, and the
+    streaming kernels are then priced by their measured traffic."""
+    n_l = rec["launches"]
+    per_ms = rec["ms"] / n_l
+    t = per_ms / 1e3
+    alg_b = rec["bytes"] / n_l
+    alg_f = rec["flops"] / n_l
+    traffic = traffic_from_profile(kernel, workload)
+    alg_rate = alg_b / t / 1e9
+    out = {"kernel": kernel, "traffic": traffic, "alg_bytes_per_launch": alg_b,
+           "alg_flops_per_launch": alg_f, "launch_ms": per_ms, "launches": n_l}
+    if traffic is not None:
+        out["hbm_frac_measured"] = traffic / t / 1e9 / peak_gbs
+    contraction = kernel_family(kernel) == "gram"
+    if traffic is not None:
+        hbm_binds = traffic >= HBM_BINDS_FRAC * alg_b
+    else:
+        hbm_binds = alg_rate <= peak_gbs
+    if contraction and not hbm_binds:
+        ach = alg_f / t / 1e12
+        out.update({"bound": "mfma", "achieved": ach, "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": ach / peak_tf, "effective_GBps": alg_rate})
+        cnt = profile_record("counters.json", kernel, workload)
+        if cnt and "mfma_busy" in cnt:
+            out["mfma_busy_measured"] = cnt["mfma_busy"]
+        return out
+    if alg_rate <= peak_gbs:
+        out.update({"bound": "hbm", "achieved": alg_rate, "peak": peak_gbs, "unit": "GB/s",
+                    "frac": alg_rate / peak_gbs, "effective": False})
+        return out
+    # algorithmic gathers beyond what HBM can deliver: most are cache hits
+    meas = traffic / t / 1e9 if traffic is not None else None
+    out.update({"bound": "hbm", "achieved": meas, "peak": peak_gbs, "unit": "GB/s",
+                "frac": meas / peak_gbs if meas is not None else None, "effective": True,
+                "effective_GBps": alg_rate})
+    return out
+
+
+def step_stats(ms):
+    """Median, mean and the paper's 95% interval half-width (2 sigma) of
+    per-step times (warm-up steps already dropped)."""
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    sd = float(a.std(ddof=1)) if len(a) > 1 else 0.0
+    return {"median": float(np.median(a)), "mean": float(a.mean()), "ci2sigma": 2.0 * sd,
+            "min": float(a.min()), "max": float(a.max()), "n": int(len(a))}
+
+
+def time_steps(tt, step, steps, warmup):
+    """`warmup` untimed steps, then exactly `steps` timed ones bracketed by
+    device synchronizations (wall clock), with HIP events on the launch
+    stream between consecutive steps and the library profiler on."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    tt.profile_enable(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.time()
+    ev[0].record(stream)
+    for k in range(steps):
+        step(True)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    tt.profile_enable(False)
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return 1000.0 * wall / steps, per, tt.profile_report()
+
+
+def kernel_table(prof, steps):
+    return {k: {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps,
+                "GBps_alg": v["bytes"] / v["ms"] / 1e6 if v["ms"] else None,
+                "TFLOPs_alg": v["flops"] / v["ms"] / 1e9 if v["ms"] else None}
+            for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+
+
+class Leg:
+    """One workload resident on the GPU: inputs, index (built once), tuned
+    partitions and the step of the hot path timed on it."""
+
+    def __init__(self, tt, W, workload, args, R=None, form="f32", tune=True, nnz=None):
+        import numpy as np
+        import torch
+        self.tt, self.W, self.args = tt, W, args
+        self.ratings = workload == "ratings"
+        self.form = form
+        dev = torch.device("cuda:0")
+        self.dev = dev
+        t0 = time.time()
+        wl = W.ratings(m=nnz or 100_000_000) if self.ratings else \
+            W.uniform(m=nnz or 1_500_000_000)
+        self.gen_s = time.time() - t0
+        log(f"generated {wl.name}: {wl.nnz} nnz in {self.gen_s:.1f}s")
+        self.wl = wl
+        self.R = R or (64 if self.ratings else 32)
+        self.lam = 1e-5      # least-squares ALS regularization (Section 5.6)
+        self.lam_gn = 1e-3   # Gauss-Newton regularization of the paper's LS runs (Section 5.6)
+        self.fdt_t = torch.float32 if form == "f32" else torch.bfloat16
+        idx = [torch.as_tensor(i).to(dev) for i in wl.idx]
+        t = torch.as_tensor(wl.t).to(dev)
+        self.A0 = W.init_factors(wl.dims, self.R, float(np.mean(wl.t)), W.SEED_INIT + 2,
+                                 dtype=np.float32)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        self.ix = tt.build_index(idx, wl.dims, t)
+        torch.cuda.synchronize()
+        self.index_s = time.time() - t0
+        log(f"index built in {self.index_s:.2f}s")
+        del idx, t  # the index holds its own sorted copies
+        self.A = [torch.as_tensor(a).to(dev).to(self.fdt_t).contiguous() for a in self.A0]
+        self.tuning = None
+        if tune:
+            # work-partition autotuner (cached per shape class; outside the timing)
+            from paper_1910_02371_amd import autotune
+            t0 = time.time()
+            self.tuning = autotune.tune(tt, self.ix, self.A, self.R, self.lam, gn=self.ratings)
+            self.tuning["seconds"] = time.time() - t0
+            log(f"tuning {self.tuning['tuning']} "
+                f"({'cached' if self.tuning['from_cache'] else 'measured'})")
+        # the Gauss-Newton workspaces (and position map) only where the step has GN
+        self.ix.reserve(self.R, tt.fdt_of([torch.empty(1, 1, dtype=self.fdt_t)]),
+                        gn="ls" if self.ratings else None)
+        self.stats = torch.zeros(4, dtype=torch.float64, device=dev)
+        self.out_m = None if self.ratings else torch.empty(wl.nnz, dtype=torch.float32,
+                                                           device=dev)
+        self.calls = {}
+        # nonzero passes of one step: ALS 3 MTTKRP + 3 Gram; GN step 1 TTTP +
+        # 3 gradient + 3 Gram (preconditioner) + 3 GN-matvec per CG iteration;
+        # the uniform workload: 1 TTTP + ALS
+        self.passes = (6 + 1 + 3 + 3 + 3 * args.cg) if self.ratings else 7
+        self.wname = (f"{'ratings' if self.ratings else 'uniform'}"
+                      f"{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}_m{wl.nnz}_R{self.R}_{form}")
+
+    def step(self, record):
+        import torch
+        tt, ix, A = self.tt, self.ix, self.A
+        stream = torch.cuda.current_stream()
+
+        def run(name, fn):
+            if not record:
+                fn()
+                return
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            self.calls.setdefault(name, []).append((e0, e1))
+
+        if not self.ratings:
+            # model values for every nonzero, written in the index's mode-0
+            # order (the library's sparse layout; the caller's COO order would
+            # add a random scatter of m values)
+            run("tttp", lambda: tt.tttp(ix, None, A, out=self.out_m, out_order=0))
+        for n in range(3):
+            # ALS update of mode n: Solve Factor with the MTTKRP(t) right-hand
+            # side formed in the same pass over the nonzeros as the Gram
+            run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP,
+                                                       self.lam, X=A[n]))
+        if self.ratings:
+            run("gn_step", lambda: tt.gn_step(ix, A, "ls", self.lam_gn, tol=5e-3,
+                                              kmax=self.args.cg, stats=self.stats))
+
+    def measure(self, steps, warmup):
+        import numpy as np
+        self.calls = {}
+        ms, per, prof = time_steps(self.tt, self.step, steps, warmup)
+        m = self.wl.nnz
+        value = m * self.R * self.passes / (ms / 1000.0)
+        calls = {k: {"ms": float(np.mean([a.elapsed_time(b) for a, b in v]))}
+                 for k, v in self.calls.items()}
+        # dominant kernel: the library kernel with the largest total time over
+        # the timed steps (library profiler: HIP events on the launch stream
+        # around every launch, tagged with algorithmic bytes / flops)
+        dom, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+        return {"ms_per_step": ms, "value": value, "step_ms": step_stats(per),
+                "roofline": price_roofline(dom, rec, self.wname), "calls": calls,
+                "step_kernels": kernel_table(prof, steps)}
+
+    def close(self):
+        import torch
+        self.ix.close()
+        self.A = None
+        self.out_m = None
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+
+def main(argv=None):
+    args = parse(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path is measured on a single "
               "MI355X (multi-GPU sharding is a design note, not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1910_02371_amd import tt, workloads as W
 
@@ -115,211 +358,129 @@ def main():
         xb.copy_(xa)
         torch.cuda.synchronize()
         del xa, xb
-    t0 = time.time()
-    ratings = args.workload == "ratings"
-    if ratings:
-        wl = W.ratings(m=args.nnz or 100_000_000)
-    else:
-        wl = W.uniform(m=args.nnz or 1_500_000_000)
-    gen_s = time.time() - t0
-    log(f"generated {wl.name}: {wl.nnz} nnz in {gen_s:.1f}s")
-    R = args.R or (64 if ratings else 32)
-    lam = 1e-5      # least-squares ALS regularization (Section 5.6)
-    lam_gn = 1e-3   # Gauss-Newton regularization of the paper's LS runs (Section 5.6)
-    fdt_t = torch.float32 if args.form == "f32" else torch.bfloat16
-    idx = [torch.as_tensor(i).to(dev) for i in wl.idx]
-    t = torch.as_tensor(wl.t).to(dev)
-    A0 = W.init_factors(wl.dims, R, float(np.mean(wl.t)), W.SEED_INIT + 2, dtype=np.float32)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    ix = tt.build_index(idx, wl.dims, t)
-    torch.cuda.synchronize()
-    index_s = time.time() - t0
-    log(f"index built in {index_s:.2f}s")
-    del idx, t  # the index holds its own sorted copies
-    A = [torch.as_tensor(a).to(dev).to(fdt_t).contiguous() for a in A0]
-    tuning = None
-    if args.tune:
-        # work-partition autotuner (cached per shape class; outside the timing)
-        from paper_1910_02371_amd import autotune
-        t0 = time.time()
-        tuning = autotune.tune(tt, ix, A, R, lam, gn=ratings)
-        tuning["seconds"] = time.time() - t0
-        log(f"tuning {tuning['tuning']} ({'cached' if tuning['from_cache'] else 'measured'})")
-    # the Gauss-Newton workspaces (and position map) only where the step has GN
-    ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=fdt_t)]), gn="ls" if ratings else None)
-    m = wl.nnz
 
-    stream = torch.cuda.current_stream()
-    names = []
-    events = []
+    leg = Leg(tt, W, args.workload, args, R=args.R, form=args.form, tune=args.tune,
+              nnz=args.nnz)
+    res = leg.measure(args.steps, args.warmup)
+    log(f"{args.workload}: {res['ms_per_step']:.2f} ms per step "
+        f"(median {res['step_ms']['median']:.2f})")
+    wl, R = leg.wl, leg.R
 
-    def timed(name, fn):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        names.append(name)
-        events.append((e0, e1))
-
-    # per-mode right-hand sides and direction blocks for the separately timed
-    # kernels of the step
-    M = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in wl.dims]
-    stats = torch.zeros(4, dtype=torch.float64, device=dev)
-
-    out_m = None if ratings else torch.empty(m, dtype=torch.float32, device=dev)
-
-    def step(record):
-        run = timed if record else (lambda n, f: f())
-        if not ratings:
-            # model values for every nonzero, written in the index's mode-0
-            # order (the library's sparse layout; the caller's COO order would
-            # add a random scatter of m values)
-            run("tttp", lambda: tt.tttp(ix, None, A, out=out_m, out_order=0))
-        for n in range(3):
-            # ALS update of mode n: Solve Factor with the MTTKRP(t) right-hand
-            # side formed in the same pass over the nonzeros as the Gram
-            run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam,
-                                                       X=A[n]))
-        if ratings:
-            run("gn_step", lambda: tt.gn_step(ix, A, "ls", lam_gn, tol=5e-3, kmax=args.cg,
-                                              stats=stats))
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    tt.profile_enable(True)
-    t0 = time.time()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    wall = time.time() - t0
-    tt.profile_enable(False)
-    prof = tt.profile_report()
-    ms_per_step = 1000.0 * wall / args.steps
-
-    per = {}
-    for nme, (e0, e1) in zip(names, events):
-        per.setdefault(nme, []).append(e0.elapsed_time(e1))
-    avg = {k: float(np.mean(v)) for k, v in per.items()}
-
-    # nonzero passes of one step: ALS 3 MTTKRP + 3 Gram; GN step 1 TTTP +
-    # 3 gradient + 3 Gram (preconditioner) + 3 GN-matvec per CG iteration;
-    # the uniform workload: 1 TTTP + ALS
-    passes = (6 + 1 + 3 + 3 + 3 * args.cg) if ratings else 7
-    value = m * R * passes / (ms_per_step / 1000.0)
-
-    # C-ABI calls of the step (HIP events on the launch stream)
-    calls = {k: {"ms": v} for k, v in avg.items()}
-
-    # dominant kernel: the library kernel with the largest total time over the
-    # timed steps (library profiler: HIP events on the launch stream around
-    # every launch, tagged with algorithmic bytes / flops per launch)
-    dom, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    n_l = rec["launches"]
-    per_ms = rec["ms"] / n_l
-    src_hash = kernel_source_hash()
-    wname = (f"{'ratings' if ratings else 'uniform'}{wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}"
-             f"_m{m}_R{R}_{args.form}")
-    traffic = traffic_from_profile(dom, wname, src_hash)
-    # the Gram is a contraction: reported against the FP32 matrix-core peak
-    # when its algorithmic intensity (flops per algorithmic byte) is above the
-    # ridge point of that peak and the HBM bandwidth, else against HBM
-    intensity = rec["flops"] / max(rec["bytes"], 1.0)
-    if dom.startswith("gram") and intensity >= FP32_MFMA_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9):
-        achieved = rec["flops"] / n_l / (per_ms / 1e3) / 1e12
-        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
-                    "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_MFMA_TFLOPS, "traffic": traffic,
-                    "alg_flops_per_launch": rec["flops"] / n_l,
-                    "alg_bytes_per_launch": rec["bytes"] / n_l, "launch_ms": per_ms,
-                    "launches": n_l}
-    else:
-        achieved = rec["bytes"] / n_l / (per_ms / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": traffic, "alg_bytes_per_launch": rec["bytes"] / n_l,
-                    "launch_ms": per_ms, "launches": n_l}
-        # algorithmic bytes count every factor-row gather; when most of them
-        # are served by L2 / Infinity Cache (measured HBM traffic below half
-        # the algorithmic bytes, or a rate above the HBM peak) the rate is an
-        # effective one
-        roofline["effective"] = achieved > HBM_PEAK_GBS or (
-            traffic is not None and traffic < 0.5 * rec["bytes"] / n_l)
-    if traffic is not None:
-        roofline["hbm_frac_measured"] = traffic / (per_ms / 1e3) / 1e9 / HBM_PEAK_GBS
-    step_prof = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step":
-                     v["launches"] / args.steps,
-                     "GBps_alg": v["bytes"] / v["ms"] / 1e6 if v["ms"] else None,
-                     "TFLOPs_alg": v["flops"] / v["ms"] / 1e9 if v["ms"] else None}
-                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
-
-    batching = None
-    if args.batching and ratings:
-        batching = compare_batching(tt, ix, A, M, R, lam, lam_gn, args.cg, stats, dev)
-
-    forms = None
+    extra = {}
     if args.form_sweeps > 0:
-        forms = compare_forms(tt, ix, A0, wl, R, lam, args.form_sweeps, dev,
-                              gn_steps=args.gn_steps if ratings else 0, lam_gn=lam_gn)
-
-    poisson = None
-    if args.poisson_iters > 0 and ratings:
-        poisson = compare_poisson(tt, ix, wl, dev, args.poisson_iters)
-
-    ccd = None
-    if args.ccd and ratings:
-        ccd = compare_ccd(tt, ix, A0, wl, lam, dev)
+        extra["forms"] = compare_forms(tt, leg.ix, leg.A0, wl, R, leg.lam, args.form_sweeps,
+                                       dev, gn_steps=args.gn_steps if leg.ratings else 0,
+                                       lam_gn=leg.lam_gn)
+        log("forms leg done")
+    if leg.ratings:
+        extra.update(ratings_extras(tt, leg, args, dev))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, A0, R, lam, lam_gn, args.cpu_sample, passes, gn=ratings)
+        sample = args.cpu_sample or (1 << 18 if leg.ratings else 1 << 16)
+        cpu = cpu_baseline(wl, leg.A0, R, leg.lam, leg.lam_gn, sample, leg.passes,
+                           gn=leg.ratings, reps=args.cpu_reps)
+        log("cpu baseline done")
+
+    secondary = None
+    if args.secondary and not leg.ratings:
+        head_meta = (leg.tuning, leg.index_s, leg.gen_s, leg.wname)
+        leg.close()
+        del leg
+        sec = Leg(tt, W, "ratings", args, R=64, form="f32", tune=args.tune)
+        r2 = sec.measure(args.secondary_steps, 2)
+        log(f"ratings: {r2['ms_per_step']:.2f} ms per step")
+        if args.form_sweeps > 0:
+            r2["forms"] = compare_forms(tt, sec.ix, sec.A0, sec.wl, sec.R, sec.lam,
+                                        args.form_sweeps, dev, gn_steps=args.gn_steps,
+                                        lam_gn=sec.lam_gn)
+        r2.update(ratings_extras(tt, sec, args, dev))
+        r2.update({"workload": ratings_desc(sec), "step": step_desc(sec), "R": sec.R,
+                   "nnz_passes_per_step": sec.passes, "steps": args.secondary_steps,
+                   "warmup": 2, "tuning": sec.tuning, "index_build_s": sec.index_s,
+                   "generate_s": sec.gen_s, "workload_key": sec.wname})
+        secondary = {"ratings": r2}
+        sec.close()
+        tuning, index_s, gen_s, wname = head_meta
+        cfg_leg = None
+    else:
+        tuning, index_s, gen_s, wname = leg.tuning, leg.index_s, leg.gen_s, leg.wname
+        cfg_leg = leg
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": res["value"],
         "unit": "nnz*R/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.form,
         "data": "synthetic",
         "config": {
-            "workload": (f"ratings-shaped {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, "
-                         f"{m} distinct nonzeros, Zipf(1.1) mode degrees, values 1..5"
-                         if ratings else
-                         f"uniform {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, {m} nonzeros, "
+            "workload": (ratings_desc(cfg_leg) if cfg_leg is not None and cfg_leg.ratings else
+                         f"uniform {wl.dims[0]}x{wl.dims[1]}x{wl.dims[2]}, {wl.nnz} nonzeros, "
                          f"planted rank 10 + N(0, 0.01^2)"),
-            "step": ("ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand "
-                     "side formed in the Gram pass) + Gauss-Newton step" if ratings else
+            "step": (step_desc(cfg_leg) if cfg_leg is not None else
                      "TTTP (model values in the index's mode-0 order) + ALS sweep "
                      "(3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed in "
                      "the Gram pass)"),
-            "R": R, "factor_storage": args.form, "lambda": lam,
-            "lambda_gn": lam_gn if ratings else None, "loss": "least squares",
-            "cg_iterations": args.cg if ratings else None, "nnz_passes_per_step": passes,
+            "R": R, "factor_storage": args.form, "lambda": 1e-5,
+            "lambda_gn": 1e-3 if args.workload == "ratings" else None,
+            "loss": "least squares",
+            "cg_iterations": args.cg if args.workload == "ratings" else None,
+            "nnz_passes_per_step": 7 if args.workload == "uniform" else 6 + 1 + 9 + 3 * args.cg,
             "parallelism": "single GPU",
         },
-        "roofline": roofline,
+        "step_ms": res["step_ms"],
+        "roofline": res["roofline"],
         "cpu_baseline": cpu,
-        "forms": forms,
-        "batching": batching,
-        "poisson": poisson,
-        "ccd": ccd,
         "tuning": tuning,
-        "calls": calls,
-        "step_kernels": step_prof,
+        "calls": res["calls"],
+        "step_kernels": res["step_kernels"],
         "index_build_s": index_s,
         "generate_s": gen_s,
-        "src_hash": src_hash,
+        "src_hash": kernel_source_hash(),
         "workload_key": wname,
     }
+    out.update(extra)
+    if secondary is not None:
+        out["secondary"] = secondary
     print(json.dumps(out), flush=True)
+
+
+def ratings_desc(leg):
+    d = leg.wl.dims
+    return (f"ratings-shaped {d[0]}x{d[1]}x{d[2]}, {leg.wl.nnz} distinct nonzeros, "
+            f"Zipf(1.1) mode degrees, values 1..5")
+
+
+def step_desc(leg):
+    if leg.ratings:
+        return ("ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed "
+                f"in the Gram pass) + Gauss-Newton step ({leg.args.cg} CG iterations)")
+    return ("TTTP (model values in the index's mode-0 order) + ALS sweep (3 x [MTTKRP + "
+            "Solve Factor], the MTTKRP right-hand side formed in the Gram pass)")
+
+
+def ratings_extras(tt, leg, args, dev):
+    """Comparison legs run on the ratings tensor: launch batching, Poisson
+    GAM vs GN, ALS vs CCD++."""
+    out = {}
+    if args.batching:
+        out["batching"] = compare_batching(tt, leg.ix, leg.A, None, leg.R, leg.lam, leg.lam_gn,
+                                           args.cg, leg.stats, dev)
+        log("batching leg done")
+    if args.poisson_iters > 0:
+        out["poisson"] = compare_poisson(tt, leg.ix, leg.wl, dev, args.poisson_iters)
+        log("poisson leg done")
+    if args.ccd:
+        out["ccd"] = compare_ccd(tt, leg.ix, leg.A0, leg.wl, leg.lam, dev)
+        log("ccd leg done")
+    return out
 
 
 def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
@@ -440,6 +601,8 @@ def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev, gn_steps=0, lam_gn=1e-3, 
     out["equal_rmse_within_1pct"] = abs(r16 / r32 - 1.0) <= 0.01
     out["sweep_speedup_bf16"] = (sum(out["f32"]["sweep_ms"][1:]) /
                                  max(1e-9, sum(out["bf16"]["sweep_ms"][1:])))
+    out["time_to_rmse"] = time_to_rmse(out["f32"]["sweep_ms"], out["f32"]["rmse"],
+                                       out["bf16"]["sweep_ms"], out["bf16"]["rmse"])
     if gn_steps:
         g32, g16 = out["f32"]["gn_rmse"][-1], out["bf16"]["gn_rmse"][-1]
         out["gn_rmse_ratio_bf16_over_f32"] = g16 / g32
@@ -447,6 +610,28 @@ def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev, gn_steps=0, lam_gn=1e-3, 
         out["gn_speedup_bf16"] = sum(out["f32"]["gn_ms"]) / max(1e-9, sum(out["bf16"]["gn_ms"]))
         out["gn_kmax"] = kmax
     return out
+
+
+def time_to_rmse(ms32, rmse32, ms16, rmse16, slack=0.01):
+    """Time each storage form takes to reach the FP32 form's final training
+    RMSE within `slack` (equal RMSE): the summed sweep times up to the first
+    sweep whose RMSE is at or below (1 + slack) * final FP32 RMSE; None if a
+    form never reaches it."""
+    target = (1.0 + slack) * rmse32[-1]
+
+    def reach(ms, rm):
+        acc = 0.0
+        for k, (a, r) in enumerate(zip(ms, rm)):
+            acc += a
+            if r is not None and r <= target:
+                return acc, k + 1
+        return None, None
+
+    t32, k32 = reach(ms32, rmse32)
+    t16, k16 = reach(ms16, rmse16)
+    return {"target_rmse": target, "f32_ms": t32, "f32_sweeps": k32, "bf16_ms": t16,
+            "bf16_sweeps": k16,
+            "speedup_bf16": (t32 / t16) if (t32 and t16) else None}
 
 
 def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5):
@@ -542,11 +727,34 @@ def compare_ccd(tt, ix, A0, wl, lam, dev):
     return out
 
 
-def cpu_baseline(wl, A0, R, lam, lam_gn, sample, passes, gn=True):
+def cpu_info():
+    """Host CPU model name and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    # the box grants this process a CPU share; OMP_NUM_THREADS states it
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return model, avail, (min(share, avail) if share > 0 else avail)
+
+
+def cpu_baseline(wl, A0, R, lam, lam_gn, sample, passes, gn=True, reps=3):
     """The FP64 oracle, as it stands, on a bounded sample: the first `sample`
     nonzeros (COO order is draw order, i.e. random) of the same tensor, full
-    dimensions, same step composition (ALS sweep over the sampled rows, then
-    objective, gradient, GN preconditioner Grams and CG matvecs)."""
+    dimensions, same step composition (uniform: TTTP + ALS sweep; ratings:
+    ALS sweep, then objective, gradient, GN preconditioner Grams and CG
+    matvecs).  One warm-up run, then `reps` timed runs (mean +- 2 sigma, the
+    paper's convention), once with the BLAS/OpenMP pools on every CPU of the
+    process's share and once on one thread."""
     import numpy as np
     try:
         from threadpoolctl import threadpool_limits
@@ -556,10 +764,9 @@ def cpu_baseline(wl, A0, R, lam, lam_gn, sample, passes, gn=True):
 
     idx = [i[:sample].astype(np.int64) for i in wl.idx]
     t = wl.t[:sample].astype(np.float64)
-    A = [np.asarray(a, dtype=np.float64) for a in A0]
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    t0 = time.time()
-    try:
+
+    def one_step():
+        A = [np.asarray(a, dtype=np.float64) for a in A0]
         ixs = O.build_index(idx, wl.dims)
         if not gn:
             O.tttp(idx, None, A)
@@ -578,14 +785,36 @@ def cpu_baseline(wl, A0, R, lam, lam_gn, sample, passes, gn=True):
             w = np.full(sample, 2.0)
             for _ in range((passes - 13) // 3):
                 O.gn_matvec(idx, w, A, g, 2 * lam_gn, wl.dims)
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    dt = time.time() - t0
-    return {"value": sample * R * passes / dt, "unit": "nnz*R/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {sample} nonzeros (COO draw order) of the same tensor, full "
-                      f"dimensions, one full step of the FP64 NumPy oracle; {dt:.1f}s"}
+
+    def timed(threads):
+        ctx = threadpool_limits(threads) if threadpool_limits else None
+        ts = []
+        try:
+            for _ in range(reps + 1):
+                t0 = time.time()
+                one_step()
+                ts.append(time.time() - t0)
+        finally:
+            if ctx is not None:
+                ctx.__exit__(None, None, None)
+        ts = np.asarray(ts[1:])  # warm-up run dropped
+        sd = float(ts.std(ddof=1)) if len(ts) > 1 else 0.0
+        mean = float(ts.mean())
+        return {"value": sample * R * passes / mean, "mean_s": mean, "ci2sigma_s": 2.0 * sd,
+                "runs_s": [float(x) for x in ts]}
+
+    model, avail, share = cpu_info()
+    allc = timed(share)
+    one = timed(1)
+    return {"value": allc["value"], "unit": "nnz*R/s", "cores": share, "kind": "oracle",
+            "sample": (f"first {sample} nonzeros (COO draw order) of the same tensor, full "
+                       f"dimensions, one full step of the FP64 NumPy oracle; 1 warm-up + "
+                       f"{reps} timed runs, mean {allc['mean_s']:.2f} s +- "
+                       f"{allc['ci2sigma_s']:.2f} s (2 sigma) with the BLAS pool on {share} "
+                       f"threads (its row loops are single-threaded NumPy)"),
+            "mean_s": allc["mean_s"], "ci2sigma_s": allc["ci2sigma_s"], "runs_s": allc["runs_s"],
+            "cpu_model": model, "cpus_visible": avail,
+            "one_core": one}
 
 
 if __name__ == "__main__":

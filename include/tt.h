@@ -139,7 +139,8 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
  *               workgroups per compute unit, each taking every grid-th row
  *               of the batch in order
  * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
- * is not capturable); call tt_index_reserve again afterwards if the
+ * is not capturable, and fails with TT_ERR_INVALID_ARG while an instantiated
+ * graph is alive); call tt_index_reserve again afterwards if the
  * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -191,13 +192,15 @@ tt_status tttp(const tt_index *ix, const void *d_s, int s_order,
  *   d_A             host array of N device pointers; entry [mode] ignored.
  *   d_out           I_mode x R, dense dtype; overwritten, or added to when
  *                   accumulate != 0.
- * Segments are reduced with FP32 chains of at most 128 terms (FP64 for
- * TT_F64) and partials of rows longer than one work chunk are combined in
- * FP64 in a fixed order, so results are deterministic.
+ * Segments are reduced with FP32 chains of at most 144 terms (a lane
+ * group's share of a work chunk, then the in-order combination of the
+ * groups' pieces; FP64 for TT_F64) and partials of rows longer than one work
+ * chunk are combined in FP64 in a fixed order, so results are deterministic.
  * ------------------------------------------------------------------------- */
 tt_status mttkrp(const tt_index *ix, const void *d_s, int s_order,
                  const void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
                  int mode, void *d_out, int accumulate, hipStream_t stream);
+
 
 /* ---------------------------------------------------------------------------
  * solve_factor -- Solve Factor (Section 3.4): for every row i of `mode`
@@ -395,6 +398,14 @@ tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  *                   (library-owned until tt_graph_destroy).
  *   tt_graph_launch replays the recorded work on `stream`; pointers and
  *                   scalars are those of the captured calls.
+ * Lifetime: a graph replays kernels on the device addresses recorded at
+ * capture, including the index's workspaces and work partitions.  While any
+ * instantiated graph is alive (from tt_graph_end until tt_graph_destroy;
+ * counted process-wide), a call that would reallocate a workspace (a larger
+ * rank, the Poisson loss after least squares, a new Gauss-Newton form) and
+ * tt_index_tune fail with TT_ERR_INVALID_ARG and enqueue nothing; reserve
+ * for the largest call before capturing.  Every index a graph used must
+ * outlive the graph (tt_index_destroy does not check).
  * ------------------------------------------------------------------------- */
 typedef struct tt_graph tt_graph;
 tt_status tt_graph_begin(hipStream_t stream);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,9 +33,24 @@ tt_status hip_fail(hipError_t e, const char *what) {
   return TT_ERR_HIP;
 }
 
+// Instantiated graphs alive in the process (tt_graph_end .. tt_graph_destroy).
+// A graph replays its kernels on the device addresses recorded at capture,
+// so while any is alive no workspace may be reallocated and no partition
+// rebuilt.
+static std::atomic<int> g_live_graphs{0};
+
+int live_graphs() { return g_live_graphs.load(); }
+
 tt_status ws_get(tt_index *ix, const char *name, size_t bytes, void **out) {
   Buf &b = ix->ws[name];
   if (b.bytes < bytes) {
+    if (b.p && live_graphs() > 0) {
+      set_error("workspace '%s' would grow from %zu to %zu bytes while %d instantiated "
+                "graph(s) replay kernels on it: destroy the graphs first, or reserve the "
+                "workspaces (tt_index_reserve) for the largest call before capturing",
+                name, b.bytes, bytes, live_graphs());
+      return TT_ERR_INVALID_ARG;
+    }
     if (b.p) {
       hipError_t e = hipDeviceSynchronize();
       if (e != hipSuccess) return hip_fail(e, "workspace resize");
@@ -181,18 +197,24 @@ static int best_mode(const tt_index *ix) {
 
 static tt_status mttkrp_impl(tt_index *ix, const void *s, const int32_t *s_perm, double w_const,
                              const void *const *d_A, int R, int64_t ldA, tt_dtype fdt, int mode,
-                             void *out, int accumulate, hipStream_t st) {
+                             void *out, int accumulate, hipStream_t st,
+                             double *carry = nullptr) {
   const ModeIndex &md = ix->mode[mode];
+  StreamCall c = base_call(ix, mode, R, ldA, fdt);
+  if (carry) {
+    c.carry = carry;
+    c.carry_partial = carry + md.nslot * (int64_t)stream_rp(fdt, R);
+  } else {
+    TT_ST(carry_ws(ix, &c.carry));
+  }
   if (!accumulate && md.nrows < md.I)
     TT_LAUNCH(launch_fill(out, md.I * R, dense_of(fdt), 0.0, st), "fill");
-  StreamCall c = base_call(ix, mode, R, ldA, fdt);
   for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
   c.s = s;
   c.s_perm = s_perm;
   c.w_const = w_const;
   c.out = out;
   c.accumulate = accumulate;
-  TT_ST(carry_ws(ix, &c.carry));
   TT_LAUNCH(launch_stream(OP_MTTKRP, c, st), "mttkrp kernel");
   return TT_OK;
 }
@@ -437,6 +459,9 @@ tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
            "gram_waves %d is not 2, 4 or 8", t->gram_waves);
   TT_CHECK(t->solve_wgs >= 0 && t->solve_wgs <= 64, "solve_wgs %d outside [0, 64]",
            t->solve_wgs);
+  TT_CHECK(live_graphs() == 0,
+           "%d instantiated graph(s) are alive: retuning rebuilds the work partitions "
+           "their kernels read; destroy the graphs first", live_graphs());
   ix->tune = *t;
   for (int n = 0; n < ix->N; ++n) TT_ST(build_partitions(ix, n, stream));
   return TT_OK;
@@ -517,7 +542,17 @@ tt_status mttkrp(const tt_index *cix, const void *d_s, int s_order, const void *
                  int R, int64_t ldA, tt_dtype fdt, int mode, void *d_out, int accumulate,
                  hipStream_t stream) {
   g_err.clear();
-  tt_index *ix = const_cast<tt_index *>(cix);
+  return mttkrp_checked(const_cast<tt_index *>(cix), d_s, s_order, d_A, R, ldA, fdt, mode,
+                        d_out, accumulate, stream, nullptr);
+}
+
+}  // extern "C"
+
+namespace tt {
+
+tt_status mttkrp_checked(tt_index *ix, const void *d_s, int s_order, const void *const *d_A,
+                         int R, int64_t ldA, tt_dtype fdt, int mode, void *d_out,
+                         int accumulate, hipStream_t stream, double *carry) {
   TT_ST(check_common(ix, R, ldA, fdt));
   TT_CHECK(mode >= 0 && mode < ix->N, "bad mode %d", mode);
   TT_CHECK(d_A != nullptr && d_out != nullptr, "NULL argument");
@@ -526,8 +561,13 @@ tt_status mttkrp(const tt_index *cix, const void *d_s, int s_order, const void *
   const void *s = nullptr;
   const int32_t *s_perm = nullptr;
   TT_ST(resolve_values(ix, d_s, s_order, mode, fdt, &s, &s_perm, "mttkrp values"));
-  return mttkrp_impl(ix, s, s_perm, 1.0, d_A, R, ldA, fdt, mode, d_out, accumulate, stream);
+  return mttkrp_impl(ix, s, s_perm, 1.0, d_A, R, ldA, fdt, mode, d_out, accumulate, stream,
+                     carry);
 }
+
+}  // namespace tt
+
+extern "C" {
 
 }  // extern "C"
 
@@ -543,6 +583,7 @@ static tt_status als_rhs(tt_index *ix, const void *const *A, int R, int64_t ldA,
   }
   void *M = nullptr;
   TT_ST(ws_get(ix, "rhs", (size_t)ix->max_I * R * value_size(fdt), &M));
+  TT_ST(solve_workspace(ix, mode, R, fdt, false, nullptr, nullptr));
   TT_ST(mttkrp_impl(ix, ix->mode[mode].d_t, nullptr, 1.0, A, R, ldA, fdt, mode, M, 0, stream));
   c->rhs = M;
   return TT_OK;
@@ -1030,6 +1071,7 @@ tt_status tt_graph_end(hipStream_t stream, tt_graph **out) {
     return hip_fail(e, "graph instantiate");
   }
   *out = new tt_graph{g, ex};
+  g_live_graphs.fetch_add(1);
   return TT_OK;
 }
 
@@ -1046,6 +1088,7 @@ tt_status tt_graph_destroy(tt_graph *graph) {
   hipGraphExecDestroy(graph->exec);
   hipGraphDestroy(graph->graph);
   delete graph;
+  g_live_graphs.fetch_sub(1);
   return TT_OK;
 }
 

@@ -129,8 +129,11 @@ tt_status hip_fail(hipError_t e, const char *what);
     }                                                          \
   } while (0)
 
-// Workspace buffer `name` of at least `bytes`, grown (never shrunk) on demand.
+// Workspace buffer `name` of at least `bytes`, grown (never shrunk) on demand;
+// growth fails with TT_ERR_INVALID_ARG while an instantiated graph is alive.
 tt_status ws_get(tt_index *ix, const char *name, size_t bytes, void **out);
+// Number of instantiated graphs not yet destroyed (process-wide).
+int live_graphs();
 
 inline size_t dtype_size(tt_dtype d) { return d == TT_F64 ? 8 : (d == TT_F32 ? 4 : 2); }
 inline size_t value_size(tt_dtype fdt) { return fdt == TT_F64 ? 8 : 4; }
@@ -171,6 +174,7 @@ struct StreamCall {
   int accumulate;
   double *sum_parts;        // TTTP: per-chunk FP64 partial sums (or NULL)
   double *carry;            // segmented: carry workspace
+  double *carry_partial;    // heavy-row partials (NULL: after the index-wide carry slots)
   const double *skip;       // optional device flag: launches become no-ops
   void *zout;               // when non-NULL, also store per nonzero (value dtype, this
                             // mode's sorted order): GN w_e * z_e, gradient phi''(t_e, m_e)
@@ -180,6 +184,13 @@ enum StreamOp { OP_TTTP = 0, OP_MTTKRP = 1, OP_GRAD = 2, OP_GN = 3, OP_NEWTON = 
 hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s);
 int stream_group_width(tt_dtype fdt, int R);
 int stream_rp(tt_dtype fdt, int R);
+
+// MTTKRP after argument checks (api.cpp).  `carry` = NULL takes the carry
+// slots from the index workspace; otherwise `carry` holds this mode's slots
+// (nslot x stream_rp) followed by its heavy-row partials (nseg x stream_rp).
+tt_status mttkrp_checked(tt_index *ix, const void *d_s, int s_order, const void *const *d_A,
+                         int R, int64_t ldA, tt_dtype fdt, int mode, void *d_out,
+                         int accumulate, hipStream_t stream, double *carry);
 
 // solve.hip: Gram on matrix cores + batched FP64 Cholesky.
 struct SolveCall {
@@ -202,6 +213,11 @@ struct SolveCall {
   int factor_only;          // 1: factor and store, no solve
 };
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);
+// The Gram (and fused right-hand-side) workspaces of one row batch of
+// Solve Factor on `mode`; acquiring them first lets a call fail before it
+// enqueues anything.
+tt_status solve_workspace(tt_index *ix, int mode, int R, tt_dtype fdt, bool fused_rhs,
+                          void **G, double **M);
 // Apply stored factors: X = (L L^T)^{-1} rhs, X dense dtype (not fdt).
 hipError_t launch_apply_factor(const tt_index *ix, int mode, int R, tt_dtype fdt,
                                const void *Lstore, const void *rhs, void *X,

@@ -8,11 +8,13 @@
 // With H the task's rows h_e stacked, G = H^T diag(w) H is a K x R by K x R
 // contraction over the nonzeros, mapped onto MFMA with the nonzero index as
 // the reduction dimension: A-operand = h (R on the M index), B-operand = w h.
-//   FP32/BF16 storage: v_mfma_f32_16x16x4f32 tiles, four nonzeros per step,
-//                      each lane reading RP / 16 consecutive columns of a row
-//                      (RP (RP / 16 + 1) / 32 tiles cover the upper triangle).
-//   BF16 factors are widened exactly to FP32 (a product of two bf16 values
-//   is exact in FP32), so the BF16 form accumulates like the FP32 form.
+//   FP32/BF16 storage: v_mfma_f32_16x16x32_bf16 tiles over steps of 32
+//                      nonzeros, each lane reading RP / 16 consecutive
+//                      columns of a row (RP (RP / 16 + 1) / 32 tiles cover
+//                      the upper triangle).  Each FP32 product h is split
+//                      exactly into bf16 parts (three for FP32 factors; two
+//                      for BF16 factors, whose products have 16 significant
+//                      bits) and the parts' products accumulate in FP32.
 //   FP64 storage: v_mfma_f64_16x16x4f64 tiles (lower triangle only).
 // Each task writes its G to a batch workspace in the lower-tile layout: the
 // NB (NB + 1) / 2 lower 16 x 16 tiles (NB = RP / 16), tile (I, J) at
@@ -90,14 +92,15 @@ __device__ __forceinline__ VT weight_at(const GramDev &d, int64_t pos) {
   return (VT)d.w_scale * reinterpret_cast<const VT *>(d.w)[q];
 }
 
-// FP32 / BF16 storage, FP32 accumulation on v_mfma_f32_16x16x4f32.
-// Vector-fragment layout: lane l = 16 k + i takes nonzero k of a step (four
-// nonzeros per step) and columns VW*i .. VW*i + VW - 1 of its two factor rows
-// (VW = RP / 16), read as one vector load.  Register v of lane (i, k) then
-// holds column VW*i + v, so the register-class pair (p, q) is one 16x16x4
-// MFMA whose tile entry (r, c) is G[VW*r + p][VW*c + q].  The classes
-// p <= q (VW (VW + 1) / 2 tiles) cover every unordered column pair: once when
-// p < q, twice when p == q (only r <= c is stored).
+// FP32 / BF16 storage, FP32 accumulation on v_mfma_f32_16x16x32_bf16.
+// Vector-fragment layout: lane l = 16 k + i takes nonzero k of each substep
+// of four nonzeros and columns VW*i .. VW*i + VW - 1 of its two factor rows
+// (VW = RP / 16), read as one vector load.  Register class v of lane (i, k)
+// then holds column VW*i + v, so the class pair (p, q) is one 16 x 16 MFMA
+// tile (K = 32 nonzeros per step) whose entry (r, c) is
+// G[VW*r + p][VW*c + q].  The classes p <= q (VW (VW + 1) / 2 tiles) cover
+// every unordered column pair: once when p < q, twice when p == q (only
+// r <= c is stored).
 template <int RP>
 struct GramAcc {
   static constexpr int VW = RP / 16;
@@ -354,8 +357,8 @@ struct GramOcc {
 };
 
 // Write G in the lower-tile layout from the accumulators (each unordered
-// column pair once).  v_mfma_f32_16x16x4f32 result: lane l, register v holds
-// D[4 (l / 16) + v][l % 16].
+// column pair once).  v_mfma_f32_16x16x32_bf16 result: lane l, register v
+// holds D[4 (l / 16) + v][l % 16].
 template <int RP>
 __device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, float scale) {
   constexpr int VW = RP / 16;
@@ -1273,24 +1276,43 @@ static hipError_t launch_solo(tt_dtype fdt, int RP, const GramDev &d, const Solv
   return hipGetLastError();
 }
 
+// Gram tasks whose workspaces one row batch holds (at least a row's tasks).
+static int64_t batch_tasks(const ModeIndex &md, int64_t task_bytes) {
+  int64_t wtasks = std::max<int64_t>(kGramBatchBytes / task_bytes, md.max_task_per_row);
+  wtasks = std::max<int64_t>(wtasks, 1);
+  if (wtasks > md.ntask) wtasks = std::max<int64_t>(md.ntask, 1);
+  return wtasks;
+}
+
+tt_status solve_workspace(tt_index *ix, int mode, int R, tt_dtype fdt, bool fused_rhs,
+                          void **G, double **M) {
+  const int RP = rp_for(R);
+  const int64_t task_bytes = (int64_t)gram_task_elems(RP) * (fdt == TT_F64 ? 8 : 4);
+  const int64_t wtasks = batch_tasks(ix->mode[mode], task_bytes);
+  void *g = nullptr;
+  tt_status st = ws_get(ix, "gram", (size_t)(wtasks * task_bytes), &g);
+  if (st != TT_OK) return st;
+  if (G) *G = g;
+  if (M) *M = nullptr;
+  if (fused_rhs) {
+    void *p = nullptr;
+    st = ws_get(ix, "gram_rhs", (size_t)(wtasks * RP * 8), &p);
+    if (st != TT_OK) return st;
+    if (M) *M = (double *)p;
+  }
+  return TT_OK;
+}
+
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   const ModeIndex &md = ix->mode[c.mode];
   const int RP = rp_for(c.R);
   const size_t gsz = c.fdt == TT_F64 ? 8 : 4;
   const int64_t task_bytes = (int64_t)gram_task_elems(RP) * gsz;
-  int64_t wtasks = std::max<int64_t>(kGramBatchBytes / task_bytes, md.max_task_per_row);
-  wtasks = std::max<int64_t>(wtasks, 1);
-  if (wtasks > md.ntask) wtasks = std::max<int64_t>(md.ntask, 1);
+  const int64_t wtasks = batch_tasks(md, task_bytes);
   void *Gws = nullptr;
-  tt_status st = ws_get(ix, "gram", (size_t)(wtasks * task_bytes), &Gws);
-  if (st != TT_OK) return st;
   double *Mws = nullptr;
-  if (c.fused_rhs) {
-    void *p = nullptr;
-    st = ws_get(ix, "gram_rhs", (size_t)(wtasks * RP * 8), &p);
-    if (st != TT_OK) return st;
-    Mws = (double *)p;
-  }
+  tt_status st = solve_workspace(ix, c.mode, c.R, c.fdt, c.fused_rhs != 0, &Gws, &Mws);
+  if (st != TT_OK) return st;
 
   int others[2], no = 0;
   for (int p = 0; p < ix->N; ++p)

@@ -79,9 +79,13 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
     double bytes = 0, flops = 0;
     const char *name = "tttp";
     if (op == OP_TTTP) {
+      // the pass runs in this mode's sorted order: the own factor row is
+      // read once per nonzero row (segment), the others once per nonzero
       int given = 0;
       for (int p = 0; p < ix->N; ++p) given += c.A[p] != nullptr;
-      bytes = m * (4 * N + (c.s ? v : 0) + (c.out ? v : 0) + given * R * b);
+      const bool own = c.A[c.mode] != nullptr;
+      bytes = m * (4 * N + (c.s ? v : 0) + (c.out ? v : 0) + (given - own) * R * b) +
+              (own ? (double)md.nrows * R * b : 0.0);
       flops = m * R * given;
     } else if (op == OP_MTTKRP) {
       name = "mttkrp";
@@ -117,7 +121,8 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   if (e != hipSuccess) return e;
   if (op != OP_TTTP && md.nheavy > 0) {
     const int RP = G * V;
-    double *partial = c.carry + (int64_t)ix->max_nslot * 64;  // after the slots
+    double *partial = c.carry_partial ? c.carry_partial
+                                      : c.carry + (int64_t)ix->max_nslot * 64;  // after the slots
     ProfScope ps("heavy_fixup", s,
                  (double)md.nslot * RP * 8 + (double)md.nseg * RP * 16 +
                      (double)md.nheavy * c.R * 4,

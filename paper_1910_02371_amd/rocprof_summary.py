@@ -5,6 +5,10 @@
         <kernel> <workload> <src_hash> <copy_bytes> <out.md> <cmd>
 
 ``stats`` renders the per-kernel table of a ``--kernel-trace --stats`` run.
+``counters`` (``counters <kernel> <workload> <src_hash> <out.md> <cmd> <pmc_dir>...``)
+averages every counter of ``kernel``'s dispatches over one or more ``--pmc``
+runs and records derived utilisation and request-size figures in
+profiles/counters.json.
 ``traffic`` reads two ``--pmc`` runs (FETCH_SIZE, then WRITE_SIZE; KiB per
 dispatch), scales each by what the same counter reads for the plain copy
 kernel of ``copy_bytes`` bytes that the profiled program runs first (a copy
@@ -125,10 +129,80 @@ def traffic(fetch_dir, write_dir, kernel, workload, src_hash, copy_bytes, out_md
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def _per_dispatch_all(rows):
+    """{(dispatch id, kernel name): {counter: value}} of a --pmc run."""
+    out = {}
+    for r in rows:
+        key = (r["Dispatch_Id"], r["Kernel_Name"])
+        d = out.setdefault(key, {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def counters(kernel, workload, src_hash, out_md, cmd, *pmc_dirs):
+    """Per-launch averages of every counter recorded for `kernel` in the
+    given --pmc runs, with the derived figures used in the design notes:
+      mfma_busy      MfmaUtil / 100 (matrix-core busy cycles per SIMD over
+                     the dispatch's GPU-active cycles)
+      valu_busy      VALUBusy / 100
+      bf16_mfma_flops, f64_mfma_flops   executed matrix-core operations
+                     (SQ_INSTS_VALU_MFMA_MOPS_* x 512)
+      read_req_bytes 32/64/128-byte L2->fabric read requests weighted by
+                     their size (TCC_EA0_RDREQ_{32B,64B,128B}), and the
+                     fraction of requests of each size.
+    Records the result in profiles/counters.json keyed by kernel and
+    workload, tagged with the kernel-source hash."""
+    acc, n_l = {}, {}
+    for d in pmc_dirs:
+        disp = _per_dispatch_all(_counter_rows(d))
+        for (i, name), vals in disp.items():
+            if not matches(kernel, name):
+                continue
+            for c, v in vals.items():
+                acc[c] = acc.get(c, 0.0) + v
+                n_l[c] = n_l.get(c, 0) + 1
+    if not acc:
+        raise SystemExit(f"no dispatch of {kernel}")
+    avg = {c: acc[c] / n_l[c] for c in acc}
+    rec = {"src_hash": src_hash, "per_launch": avg, "launches": max(n_l.values())}
+    if "MfmaUtil" in avg:
+        rec["mfma_busy"] = avg["MfmaUtil"] / 100.0
+    if "VALUBusy" in avg:
+        rec["valu_busy"] = avg["VALUBusy"] / 100.0
+    for dt in ("BF16", "F64", "F32"):
+        k = f"SQ_INSTS_VALU_MFMA_MOPS_{dt}"
+        if k in avg:
+            rec[f"{dt.lower()}_mfma_flops"] = avg[k] * 512.0
+    sizes = {32: "TCC_EA0_RDREQ_32B_sum", 64: "TCC_EA0_RDREQ_64B_sum",
+             128: "TCC_EA0_RDREQ_128B_sum"}
+    if all(v in avg for v in sizes.values()):
+        nreq = sum(avg[v] for v in sizes.values())
+        rec["read_req_bytes"] = sum(b * avg[v] for b, v in sizes.items())
+        rec["read_req_mix"] = {f"{b}B": (avg[v] / nreq if nreq else 0.0)
+                               for b, v in sizes.items()}
+        rec["read_requests"] = nreq
+    path = os.path.join(os.path.dirname(out_md), "counters.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    db[f"{kernel}|{workload}"] = rec
+    json.dump(db, open(path, "w"), indent=1, sort_keys=True)
+    lines = [f"# Counters of `{kernel}` on {workload}\n", f"Command: `{cmd}`\n",
+             f"Kernel source hash: {src_hash}\n", "| counter | per launch |", "|---|---|"]
+    for c in sorted(avg):
+        lines.append(f"| {c} | {avg[c]:.6g} |")
+    lines.append("")
+    for k in ("mfma_busy", "valu_busy", "bf16_mfma_flops", "f64_mfma_flops",
+              "read_req_bytes", "read_requests", "read_req_mix"):
+        if k in rec:
+            lines.append(f"* {k}: {rec[k]}")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:10])
+    elif sys.argv[1] == "counters":
+        counters(*sys.argv[2:])
     else:
         raise SystemExit(__doc__)

@@ -74,3 +74,36 @@ def backward_error(G, lam, X, M):
         den = np.linalg.norm(S, 2) * np.linalg.norm(X[i]) + np.linalg.norm(M[i])
         worst = max(worst, num / den if den > 0 else num)
     return worst
+
+
+def loss_abs(t, m, m_abs, loss, what):
+    """The absolute-value form of an elementwise loss map at the model value
+    m, against which its rounding error is measured: each operation of the
+    map evaluated on absolute values, with the model value's own error
+    (bounded relative to m_abs, the model on absolute factors) carried
+    through the map's slope.
+      least squares: resid |t| + m_abs, phi (|t| + m_abs)^2,
+                     phi' 2 (|t| + m_abs), phi'' 2;
+      Poisson log link (e = exp(m)): resid |t| + m_abs,
+                     phi e (1 + m_abs) + |t| m_abs, phi' e (1 + m_abs) + |t|,
+                     phi'' e (1 + m_abs)."""
+    t = np.abs(np.asarray(t, dtype=np.float64))
+    m = np.asarray(m, dtype=np.float64)
+    m_abs = np.asarray(m_abs, dtype=np.float64)
+    if what == "resid":
+        return t + m_abs
+    if loss == O.LOSS_LS:
+        return {"phi": (t + m_abs) ** 2, "dphi": 2.0 * (t + m_abs),
+                "d2phi": np.full(np.broadcast(t, m).shape, 2.0)}[what]
+    e = np.exp(m) * (1.0 + m_abs)
+    return {"phi": e + t * m_abs, "dphi": e + t, "d2phi": e}[what]
+
+
+def rounded_abs(ref, ref_abs, tau, rel_round):
+    """Absolute expression for a result within tau * ref_abs that is then
+    rounded with relative error rel_round (e.g. 2^-8 for bf16 RNE): the
+    bound tau * ref_abs + rel_round * (|ref| + tau * ref_abs), written as
+    tau * (returned value)."""
+    ref = np.abs(np.asarray(ref, dtype=np.float64))
+    ref_abs = np.asarray(ref_abs, dtype=np.float64)
+    return ref_abs * (1.0 + rel_round) + ref * (rel_round / tau)

@@ -88,3 +88,71 @@ def test_ccd_leg(fake):
     json.loads(json.dumps(out, allow_nan=False))
     assert set(out) == {"rmse_start", "als_ms", "als_rmse", "ccd_ms", "ccd_rmse"}
     assert calls.count("ccd_sweep") == 2 and calls.count("als_sweep") == 1
+
+
+def _rec(ms, launches, nbytes, flops):
+    return {"launches": launches, "ms": ms, "bytes": nbytes, "flops": flops}
+
+
+def test_roofline_prices_cache_served_gram_on_matrix_cores(monkeypatch):
+    """A Gram launch whose algorithmic byte rate exceeds the HBM peak is a
+    contraction bound by the matrix cores: frac is its flop rate over the
+    FP32 peak, never an HBM fraction above 1."""
+    monkeypatch.setattr(bench, "traffic_from_profile", lambda k, w: None)
+    # 6.66 GB and 5.3e10 flop per launch in 0.478 ms
+    r = bench.price_roofline("gram_heavy", _rec(0.478 * 10, 10, 6.66e10, 5.3e11), "w")
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert abs(r["achieved"] - 5.3e10 / 0.478e-3 / 1e12) < 1e-6
+    assert 0 < r["frac"] <= 1 and r["effective_GBps"] > 8000
+
+
+def test_roofline_measured_traffic_decides_the_bound(monkeypatch):
+    rec = _rec(4.4 * 39, 39, 39 * 3.117e10, 39 * 1.2e11)
+    # traffic equal to the algorithmic bytes: HBM binds
+    monkeypatch.setattr(bench, "traffic_from_profile", lambda k, w: 3.13e10)
+    r = bench.price_roofline("gram_heavy", rec, "w")
+    assert r["bound"] == "hbm" and 0.85 < r["frac"] < 0.9 and r["traffic"] == 3.13e10
+    # a quarter of them reach HBM: the matrix cores bind
+    monkeypatch.setattr(bench, "traffic_from_profile", lambda k, w: 0.25 * 3.117e10)
+    r = bench.price_roofline("gram_heavy", rec, "w")
+    assert r["bound"] == "mfma" and r["frac"] <= 1
+
+
+def test_roofline_streaming_kernel_above_peak_uses_measured_traffic(monkeypatch):
+    rec = _rec(2.76, 1, 7.86e10, 1e10)  # 28 TB/s algorithmic: cache-served gathers
+    monkeypatch.setattr(bench, "traffic_from_profile", lambda k, w: 1.78e10)
+    r = bench.price_roofline("tttp", rec, "w")
+    assert r["bound"] == "hbm" and r["effective"] and r["frac"] <= 1
+    assert abs(r["achieved"] - 1.78e10 / 2.76e-3 / 1e9) < 1e-6
+    monkeypatch.setattr(bench, "traffic_from_profile", lambda k, w: None)
+    r = bench.price_roofline("tttp", rec, "w")
+    assert r["frac"] is None and r["effective_GBps"] > 8000
+
+
+def test_step_stats_and_time_to_rmse():
+    s = bench.step_stats([10.0, 12.0, 11.0, 13.0])
+    assert s["median"] == 11.5 and s["mean"] == 11.5 and s["n"] == 4
+    assert abs(s["ci2sigma"] - 2 * np.std([10, 12, 11, 13], ddof=1)) < 1e-12
+    t = bench.time_to_rmse([5, 5, 5], [0.3, 0.2, 0.1], [4, 4, 4], [0.3, 0.2, 0.1009])
+    assert abs(t["target_rmse"] - 0.101) < 1e-12
+    assert t["f32_ms"] == 15 and t["bf16_ms"] == 12 and t["bf16_sweeps"] == 3
+    assert t["speedup_bf16"] == 15 / 12
+    t = bench.time_to_rmse([5, 5], [0.3, 0.1], [4, 4], [0.3, 0.2])
+    assert t["bf16_ms"] is None and t["speedup_bf16"] is None
+
+
+def test_cpu_baseline_reports_both_thread_settings(monkeypatch):
+    wl = W.random_tensor((30, 20, 10), 400, 5)
+    A0 = W.init_factors(wl.dims, 4, 1.0, 3)
+    out = bench.cpu_baseline(wl, A0, 4, 1e-5, 1e-3, 200, 7, gn=False, reps=2)
+    json.loads(json.dumps(out, allow_nan=False))
+    assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
+    assert len(out["runs_s"]) == 2 and out["one_core"]["value"] > 0
+    assert "mean" in out["sample"] and out["mean_s"] > 0
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr

@@ -16,7 +16,8 @@ import torch
 
 import oracle as O
 from paper_1910_02371_amd import workloads as W
-from gpu_helpers import TAU, TAU_BF16_VS_F32, assert_close_abs, host, stored_factors
+from gpu_helpers import (TAU, TAU_BF16_VS_F32, assert_close_abs, host, loss_abs, rounded_abs,
+                         stored_factors)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -163,6 +164,55 @@ def test_ratings_solve_sampled_rows(gpu_lib, ratings64):
         assert be <= 1e-5, f"mode {n}: backward error {be:.2e} rows {cnt[rows]}"
 
 
+def row_oracle(c, n, i, chunk=1 << 20):
+    """The oracle's MTTKRP_n(t) row, its absolute form and the Gram of row i
+    of mode n, summed over chunks of the row's nonzeros (each chunk is the
+    sub-tensor of row i alone, its mode-n index mapped to 0)."""
+    sel = np.flatnonzero(c.wl.idx[n] == i)
+    R = c.R
+    M, Ma, G = np.zeros(R), np.zeros(R), np.zeros((R, R))
+    Aa = [np.abs(a) for a in c.As]
+    for k in range(0, len(sel), chunk):
+        part = sel[k:k + chunk]
+        sub = [np.zeros(len(part), np.int64) if p == n else c.wl.idx[p][part]
+               for p in range(3)]
+        ts = c.t[part]
+        M += O.mttkrp(sub, ts, c.As, n, 1)[0]
+        Ma += O.mttkrp(sub, np.abs(ts), Aa, n, 1)[0]
+        G += O.gram(sub, None, c.As, n, 1)[0]
+    return M, Ma, G, len(sel)
+
+
+def test_ratings_heaviest_rows(gpu_lib, ratings64):
+    """Each mode's heaviest row (millions of nonzeros: hundreds of streaming
+    pieces through the FP64 carries, thousands of Gram tasks through the
+    FP64 task reductions): MTTKRP elementwise at tau, and Solve Factor with
+    the given right-hand side and with the fused one (MTTKRP(t) formed in
+    the Gram pass) by backward error against the oracle's Gram and
+    MTTKRP."""
+    from gpu_helpers import backward_error
+    tt = gpu_lib
+    c = ratings64
+    lam = 1e-5
+    for n in range(3):
+        cnt = np.bincount(c.wl.idx[n], minlength=c.wl.dims[n])
+        i = int(np.argmax(cnt))
+        t0 = time.time()
+        M, Ma, G, nz = row_oracle(c, n, i)
+        say(f"mode {n} row {i}: {nz} nonzeros, oracle {time.time() - t0:.1f}s")
+        Y = tt.mttkrp(c.ix, tt.INDEX_T, c.A, n)
+        assert_close_abs(host(Y)[i], M, Ma, TAU["f32"], f"heaviest mttkrp mode {n} ({nz} nnz)")
+        X, info = tt.solve_factor(c.ix, None, c.A, n, Y, lam)
+        assert int(info[i].item()) == 0
+        be = backward_error(G[None], lam, host(X)[i][None], host(Y)[i][None])
+        assert be <= 1e-5, f"heaviest solve mode {n}: {be:.2e}"
+        Xf, info = tt.solve_factor(c.ix, None, c.A, n, tt.RHS_MTTKRP, lam)
+        assert int(info[i].item()) == 0
+        be = backward_error(G[None], lam, host(Xf)[i][None], M[None])
+        assert be <= 1e-5, f"heaviest fused solve mode {n}: {be:.2e}"
+        del Y, X, Xf, info
+
+
 def test_ratings_gradient_gn_sampled_rows(gpu_lib, ratings64):
     tt = gpu_lib
     c = ratings64
@@ -181,15 +231,16 @@ def test_ratings_gradient_gn_sampled_rows(gpu_lib, ratings64):
         m_abs = O.tttp(sidx, None, [np.abs(a) for a in c.As])
         g = O.mttkrp(sidx, O.dphi(ts, m, O.LOSS_LS), c.As, d, c.wl.dims[d])[rows] + \
             2 * lam * c.As[d][rows]
-        gabs = O.mttkrp(sidx, 2 * np.abs(m - ts) + 2 * m_abs, [np.abs(a) for a in c.As], d,
-                        c.wl.dims[d])[rows] + 2 * lam * np.abs(c.As[d][rows])
-        assert_close_abs(G[d][rows], g, gabs, 4 * TAU["f32"], f"gradient mode {d}")
+        gabs = O.mttkrp(sidx, loss_abs(ts, m, m_abs, O.LOSS_LS, "dphi"),
+                        [np.abs(a) for a in c.As], d, c.wl.dims[d])[rows] + \
+            2 * lam * np.abs(c.As[d][rows])
+        assert_close_abs(G[d][rows], g, gabs, TAU["f32"], f"gradient mode {d}")
         z = O.jvp(sidx, c.As, Xh)
         zabs = O.jvp(sidx, [np.abs(a) for a in c.As], [np.abs(x) for x in Xh])
         y = O.mttkrp(sidx, 2.0 * z, c.As, d, c.wl.dims[d])[rows] + 2 * lam * Xh[d][rows]
         yabs = O.mttkrp(sidx, 2.0 * zabs, [np.abs(a) for a in c.As], d, c.wl.dims[d])[rows] + \
             2 * lam * np.abs(Xh[d][rows])
-        assert_close_abs(Y[d][rows], y, yabs, 4 * TAU["f32"], f"gn mode {d}")
+        assert_close_abs(Y[d][rows], y, yabs, TAU["f32"], f"gn mode {d}")
 
 
 def test_ratings_als_sweep_objective(gpu_lib, ratings64):
@@ -255,16 +306,18 @@ def test_ratings_bf16_r64_autograd_and_fd(gpu_lib, ratings_data):
             rows, cnt = sample_rows(c.wl.idx[d], c.wl.dims[d], rng, max_nnz=200_000, k=3)
             sidx, sel = subset(c.wl, d, rows)
             ts = c.t[sel]
-            for As, tau in ((c.As, 4 * TAU["bf16"]), (c.A0, TAU_BF16_VS_F32)):
+            for As, tau in ((c.As, TAU["bf16"]), (c.A0, TAU_BF16_VS_F32)):
                 m = O.tttp(sidx, None, As)
                 m_abs = O.tttp(sidx, None, [np.abs(a) for a in As])
                 g = O.mttkrp(sidx, O.dphi(ts, m, O.LOSS_LS), As, d, c.wl.dims[d])[rows] + \
                     2 * lam * As[d][rows]
-                gabs = O.mttkrp(sidx, 2 * np.abs(m - ts) + 2 * m_abs, [np.abs(a) for a in As],
-                                d, c.wl.dims[d])[rows] + 2 * lam * np.abs(As[d][rows])
+                gabs = O.mttkrp(sidx, loss_abs(ts, m, m_abs, O.LOSS_LS, "dphi"),
+                                [np.abs(a) for a in As], d, c.wl.dims[d])[rows] + \
+                    2 * lam * np.abs(As[d][rows])
                 gd = A[d].grad.float().double().cpu().numpy()[rows]
-                # the returned gradient is cast to the factors' dtype (bf16)
-                assert_close_abs(gd, g, gabs + np.abs(g) * 2.0 ** -8, tau + 2.0 ** -8,
+                # the returned gradient is rounded to the factors' dtype
+                # (bf16 RNE: 2^-8 of the FP32 value, itself within tau*gabs)
+                assert_close_abs(gd, g, rounded_abs(g, gabs, tau, 2.0 ** -8), tau,
                                  f"bf16 grad mode {d}")
         # finite differences on a 1,000-nonzero subsample (FP64 form)
         rfd = W.rng_for(W.SEED_FD + 3)
@@ -313,8 +366,8 @@ def test_counts_poisson_gn(gpu_lib):
         sidx = [i[pos] for i in wl.idx]
         m = O.tttp(sidx, None, c.As)
         m_abs = O.tttp(sidx, None, [np.abs(a) for a in c.As])
-        assert_close_abs(host(w)[pos], np.exp(m), np.exp(m) * (1 + m_abs), 4 * TAU["f32"],
-                         "phi''")
+        assert_close_abs(host(w)[pos], np.exp(m), loss_abs(0.0, m, m_abs, O.LOSS_POISSON_LOG,
+                                                           "d2phi"), TAU["f32"], "phi''")
         wd = [tt.tttp(c.ix, tt.INDEX_T, c.A, epi="d2phi", loss="poisson", out_order=d)
               for d in range(3)]
         Xd = [torch.as_tensor(rng.standard_normal((dd, 32)).astype(np.float32)).cuda()
@@ -330,9 +383,39 @@ def test_counts_poisson_gn(gpu_lib):
             z = O.jvp(sidx, c.As, Xh)
             zabs = O.jvp(sidx, [np.abs(a) for a in c.As], [np.abs(x) for x in Xh])
             y = O.mttkrp(sidx, ww * z, c.As, d, wl.dims[d])[rows] + 2 * lam * Xh[d][rows]
-            ya = O.mttkrp(sidx, ww * (zabs + np.abs(z) * m_abs), [np.abs(a) for a in c.As], d,
+            # w = phi'' as the GPU stored it carries the model value's error
+            # through exp: its absolute form e^m (1 + m_abs) weights z_abs
+            wa = loss_abs(0.0, m, m_abs, O.LOSS_POISSON_LOG, "d2phi")
+            ya = O.mttkrp(sidx, wa * zabs, [np.abs(a) for a in c.As], d,
                           wl.dims[d])[rows] + 2 * lam * np.abs(Xh[d][rows])
-            assert_close_abs(Y[d][rows], y, ya, 8 * TAU["f32"], f"poisson gn mode {d}")
+            assert_close_abs(Y[d][rows], y, ya, TAU["f32"], f"poisson gn mode {d}")
+        # BF16 factor storage: phi'' through the TTTP epilogue and the GN
+        # product with w = phi'' on sampled rows, against the oracle on the
+        # RNE-rounded factors (FP32 accumulation: tau)
+        Ab = [a.to(torch.bfloat16).contiguous() for a in c.A]
+        Abs = stored_factors(c.As, "bf16")
+        wb = [tt.tttp(c.ix, tt.INDEX_T, Ab, epi="d2phi", loss="poisson", out_order=d)
+              for d in range(3)]
+        Yb = host(tt.gn_matvec(c.ix, wb, Ab, Xd, 2 * lam))
+        w0 = host(tt.tttp(c.ix, tt.INDEX_T, Ab, epi="d2phi", loss="poisson"))[pos]
+        sidx = [i[pos] for i in wl.idx]
+        m = O.tttp(sidx, None, Abs)
+        m_abs = O.tttp(sidx, None, [np.abs(a) for a in Abs])
+        assert_close_abs(w0, np.exp(m), loss_abs(0.0, m, m_abs, O.LOSS_POISSON_LOG, "d2phi"),
+                         TAU["bf16"], "bf16 phi''")
+        for d in range(3):
+            rows, cnt = sample_rows(wl.idx[d], wl.dims[d], rng, k=3)
+            sidx, sel = subset(wl, d, rows)
+            m = O.tttp(sidx, None, Abs)
+            m_abs = O.tttp(sidx, None, [np.abs(a) for a in Abs])
+            z = O.jvp(sidx, Abs, Xh)
+            zabs = O.jvp(sidx, [np.abs(a) for a in Abs], [np.abs(x) for x in Xh])
+            y = O.mttkrp(sidx, np.exp(m) * z, Abs, d, wl.dims[d])[rows] + 2 * lam * Xh[d][rows]
+            wa = loss_abs(0.0, m, m_abs, O.LOSS_POISSON_LOG, "d2phi")
+            ya = O.mttkrp(sidx, wa * zabs, [np.abs(a) for a in Abs], d,
+                          wl.dims[d])[rows] + 2 * lam * np.abs(Xh[d][rows])
+            assert_close_abs(Yb[d][rows], y, ya, TAU["bf16"], f"bf16 poisson gn mode {d}")
+        del Ab, wb
         # one GN step (full step, as written in Section 2.5): PCG from dx = 0
         # guarantees a descent direction and a decrease of the quadratic
         # model q(dx) = g.dx + dx.H dx / 2 at any size; the full step itself
@@ -400,6 +483,42 @@ def test_uniform_1p5b(gpu_lib):
             be = backward_error(G, lam, host(X)[rows], ref)
             assert be <= 1e-5, f"solve 1.5B mode {n}: {be:.2e}"
             del M, X, info
+        # BF16 factor storage on the same index: TTTP on sampled nonzeros,
+        # MTTKRP on sampled rows (FP32 accumulation: tau against the oracle on
+        # the RNE-rounded factors) and the fused ALS update (Gram and
+        # right-hand side in one pass, FP64 Cholesky, solved rows rounded to
+        # BF16: backward error within 2e-2 of the rounded and the unrounded
+        # factors' normal equations)
+        Ab = [a.to(torch.bfloat16).contiguous() for a in c.A]
+        Abs = [a.float().double().cpu().numpy() for a in Ab]
+        assert all(np.array_equal(x, y) for x, y in zip(Abs, stored_factors(c.As, "bf16")))
+        x = tt.tttp(c.ix, c.t_dev, Ab)
+        xs = x[torch.as_tensor(pos).cuda()].double().cpu().numpy()
+        del x
+        sidx = [i[pos] for i in wl.idx]
+        assert_close_abs(xs, O.tttp(sidx, c.t[pos], Abs),
+                         O.tttp(sidx, np.abs(c.t[pos]), [np.abs(a) for a in Abs]),
+                         TAU["bf16"], "bf16 tttp 1.5B")
+        for n in range(3):
+            sel = np.flatnonzero(np.isin(wl.idx[n], rows))
+            sidx = [i[sel] for i in wl.idx]
+            M = host(tt.mttkrp(c.ix, tt.INDEX_T, Ab, n))[rows]
+            ref = O.mttkrp(sidx, c.t[sel], Abs, n, wl.dims[n])[rows]
+            ra = O.mttkrp(sidx, np.abs(c.t[sel]), [np.abs(a) for a in Abs], n,
+                          wl.dims[n])[rows]
+            assert_close_abs(M, ref, ra, TAU["bf16"], f"bf16 mttkrp 1.5B mode {n}")
+            X, info = tt.solve_factor(c.ix, None, Ab, n, tt.RHS_MTTKRP, lam)
+            assert int((info != 0).sum().item()) == 0
+            Xh = host(X)[rows]
+            G = O.gram(sidx, None, Abs, n, wl.dims[n], rows=rows)
+            be = backward_error(G, lam, Xh, ref)
+            assert be <= TAU_BF16_VS_F32, f"bf16 fused update 1.5B mode {n}: {be:.2e}"
+            G0 = O.gram(sidx, None, c.A0, n, wl.dims[n], rows=rows)
+            M0 = O.mttkrp(sidx, c.t[sel], c.A0, n, wl.dims[n])[rows]
+            be0 = backward_error(G0, lam, Xh, M0)
+            assert be0 <= TAU_BF16_VS_F32, f"bf16 vs fp32 factors mode {n}: {be0:.2e}"
+            del X, info
+        del Ab
     finally:
         c.ix.close()
         del c

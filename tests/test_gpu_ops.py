@@ -8,7 +8,7 @@ import torch
 import oracle as O
 from paper_1910_02371_amd import workloads as W
 from gpu_helpers import (TAU, TAU_BF16_VS_F32, assert_close_abs, backward_error, dev_factor,
-                         dev_idx, dev_vals, host, stored_factors, stored_values)
+                         dev_idx, dev_vals, host, loss_abs, stored_factors, stored_values)
 
 pytestmark = pytest.mark.gpu
 
@@ -190,12 +190,11 @@ def test_tttp_epilogues(gpu_lib, form, loss, epi):
     L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
     f = {"resid": lambda: t - m, "phi": lambda: O.phi(t, m, L),
          "dphi": lambda: O.dphi(t, m, L), "d2phi": lambda: O.d2phi(t, m, L)}[epi]()
-    # error in m propagates through the epilogue's slope
-    slope = {"resid": np.ones_like(m), "phi": np.abs(O.dphi(t, m, L)),
-             "dphi": np.abs(O.d2phi(t, m, L)), "d2phi": np.abs(O.d2phi(t, m, L))}[epi]
-    fabs = np.abs(f) + slope * m_abs + (np.abs(t) if epi in ("resid", "phi", "dphi") else 0)
-    assert_close_abs(host(x), f, fabs, 4 * TAU[form], f"epi {epi}")
-    assert abs(tot.item() - f.sum()) <= 4 * TAU[form] * fabs.sum()
+    # the map on absolute values, the model value's error carried through
+    # its slope (FP32 chain: model value <= 10 roundings, map <= 3)
+    fabs = loss_abs(t, m, m_abs, L, epi)
+    assert_close_abs(host(x), f, fabs, TAU[form], f"epi {epi}")
+    assert abs(tot.item() - f.sum()) <= TAU[form] * fabs.sum()
 
 
 # --------------------------------------------------------------- MTTKRP ----
@@ -370,16 +369,15 @@ def test_gradient_and_objective(gpu_lib, form, loss, kind):
     ref = O.gradient(wl.idx, t, As, L, lam, wl.dims)
     m = O.tttp(wl.idx, None, As)
     m_abs = O.tttp(wl.idx, None, [np.abs(a) for a in As])
-    d1 = np.abs(O.dphi(t, m, L)) + np.abs(O.d2phi(t, m, L)) * m_abs
+    d1 = loss_abs(t, m, m_abs, L, "dphi")
     for d in range(3):
         ra = O.mttkrp(wl.idx, d1, [np.abs(a) for a in As], d, wl.dims[d]) + \
             2 * lam * np.abs(As[d])
-        assert_close_abs(G[d], ref[d], ra, 4 * TAU[form], f"gradient mode {d}")
+        assert_close_abs(G[d], ref[d], ra, TAU[form], f"gradient mode {d}")
     f = tt.objective(ix, A, loss, lam).item()
     fr = O.objective(wl.idx, t, As, L, lam)
-    fabs = np.sum(np.abs(O.phi(t, m, L)) + np.abs(O.dphi(t, m, L)) * m_abs) + \
-        lam * sum(np.sum(a * a) for a in As)
-    assert abs(f - fr) <= 4 * TAU[form] * fabs
+    fabs = np.sum(loss_abs(t, m, m_abs, L, "phi")) + lam * sum(np.sum(a * a) for a in As)
+    assert abs(f - fr) <= TAU[form] * fabs
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
@@ -417,7 +415,7 @@ def test_gn_matvec_parity(gpu_lib, form, weights, kind):
     for d in range(3):
         ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
             lam2 * np.abs(X64[d])
-        assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn mode {d}")
+        assert_close_abs(Y[d], ref[d], ra, TAU[form], f"gn mode {d}")
 
 
 @pytest.mark.parametrize("form", ["f32", "bf16", "f64"])
@@ -463,7 +461,7 @@ def test_newton_matvec_parity(gpu_lib, form, R, kind, g_order):
             Ap[p], Apa[p] = X64[p], Xa[p]
             ref[d] = ref[d] + O.mttkrp(wl.idx, g, Ap, d, wl.dims[d])
             ra = ra + O.mttkrp(wl.idx, np.abs(g), Apa, d, wl.dims[d])
-        assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"newton mode {d}")
+        assert_close_abs(Y[d], ref[d], ra, TAU[form], f"newton mode {d}")
     if form == "f64" and R == 16 and g_order == "per_mode":
         # the same product from t and the loss, as the oracle defines it
         full = O.newton_matvec(wl.idx, t, As, X64, 0.2, wl.dims, L)
@@ -497,7 +495,7 @@ def test_gn_matvec_ranks(gpu_lib, form, R, kind):
         for d in range(3):
             ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
                 lam2 * np.abs(X64[d])
-            assert_close_abs(Y[d], ref[d], ra, 4 * TAU[form], f"gn R={R} call {call} mode {d}")
+            assert_close_abs(Y[d], ref[d], ra, TAU[form], f"gn R={R} call {call} mode {d}")
 
 
 # --------------------------------------------------------------- tuning ----
@@ -545,7 +543,7 @@ def test_tuning_parity(gpu_lib, form, kind):
             for d in range(3):
                 ra = O.mttkrp(wl.idx, 2.0 * z_abs, [np.abs(a) for a in As], d, wl.dims[d]) + \
                     0.1 * np.abs(X64[d])
-                assert_close_abs(Yg[d], refg[d], ra, 4 * TAU[form], f"{tune} gn R={R} mode {d}")
+                assert_close_abs(Yg[d], refg[d], ra, TAU[form], f"{tune} gn R={R} mode {d}")
             for n in range(3):
                 M = stored_values(rng.standard_normal((wl.dims[n], R)), form)
                 X, info = tt.solve_factor(ix, None, A, n, dev_vals(M, form), 0.05)
