@@ -201,6 +201,25 @@ tt_status mttkrp(const tt_index *ix, const void *d_s, int s_order,
                  const void *const *d_A, int R, int64_t ldA, tt_dtype fdt,
                  int mode, void *d_out, int accumulate, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * mttkrp_noalloc -- mttkrp for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as mttkrp; it calls no
+ * allocator.  The FP64 carry slots of rows longer than one work chunk and
+ * their partials live in a fixed 32 MiB array per device, held from the
+ * first call on that device until the process ends.  A mode needs
+ * (pieces + segments) x RP x 8 bytes, RP being the rank rounded up to a power
+ * of two of at least 8 elements (4 for TT_F64); a call that needs more fails
+ * with TT_ERR_UNSUPPORTED and enqueues nothing.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialized by the caller.
+ * The array's contents are fully rewritten by each call before they are
+ * read.  The index must already hold its partitions (tt_build_index); call
+ * on the device the index was built on.
+ * ------------------------------------------------------------------------- */
+tt_status mttkrp_noalloc(const tt_index *ix, const void *d_s, int s_order,
+                         const void *const *d_A, int R, int64_t ldA, tt_dtype fdt, int mode,
+                         void *d_out, int accumulate, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * solve_factor -- Solve Factor (Section 3.4): for every row i of `mode`

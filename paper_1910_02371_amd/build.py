@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = [
     "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip", "solve.hip",
-    "index.hip", "stream_host.hip", "vec.hip", "api.cpp",
+    "index.hip", "stream_host.hip", "vec.hip", "api.cpp", "noalloc.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -47,6 +47,7 @@ SIGNATURES = {
     "tt_index_other": (_I, [_P, _I, _I, ctypes.POINTER(_P)]),
     "tttp": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _I, _P, _I, _P, _P]),
     "mttkrp": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _I, _P]),
+    "mttkrp_noalloc": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _I, _P]),
     "solve_factor": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _D, _P, _P, _U32, _P]),
     "gn_matvec": (_I, [_P, _P, _I, _D, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
     "newton_matvec": (_I, [_P, _P, _I, _D, _P, _I, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
@@ -274,6 +275,17 @@ def mttkrp(ix, s, A, mode, out=None, s_order=ORDER_COO, accumulate=False):
         out = torch.empty((ix.dims[mode], R), dtype=value_dtype(fdt), device="cuda")
     _check(lib().mttkrp(ix.handle, _values(s), s_order, _ptrs(A), R, ld, fdt, mode, _ptr(out),
                         1 if accumulate else 0, _stream()))
+    return out
+
+
+def mttkrp_noalloc(ix, s, A, mode, out, s_order=ORDER_COO, accumulate=False):
+    """MTTKRP of mode ``mode`` into the caller's ``out`` without any device
+    allocation (carry scratch in the library's fixed per-device array);
+    calls that overlap on one GPU race on that array."""
+    fdt = fdt_of(A)
+    R, ld = _rank_ld([a for n, a in enumerate(A) if n != mode])
+    _check(lib().mttkrp_noalloc(ix.handle, _values(s), s_order, _ptrs(A), R, ld, fdt, mode,
+                                _ptr(out), 1 if accumulate else 0, _stream()))
     return out
 
 
