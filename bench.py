@@ -664,15 +664,28 @@ def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5
         return e0.elapsed_time(e1), r
 
     stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    # factors stored with their leading dimension padded to the 4-element
+    # lane fragment (12 at R = 10), so the streaming kernels read whole
+    # fragments
+    ld = (R + 3) // 4 * 4
+
+    def factors():
+        out = []
+        for a in A0:
+            buf = torch.zeros((a.shape[0], ld), dtype=torch.float32, device=dev)
+            buf[:, :R] = torch.as_tensor(a).to(dev)
+            out.append(buf[:, :R])
+        return out
+
     run = {
         "gam": lambda A: tt.gam_sweep(ix, A, "poisson", lam, tol=tol, max_inner=max_inner),
         "gn": lambda A: tt.gn_step(ix, A, "poisson", lam, tol=5e-3, kmax=R, stats=stats),
     }
-    out = {"R": R, "lambda": lam, "inner_tol": tol, "max_inner": max_inner, "cg_tol": 5e-3,
-           "cg_kmax": R}
+    out = {"R": R, "ldA": ld, "lambda": lam, "inner_tol": tol, "max_inner": max_inner,
+           "cg_tol": 5e-3, "cg_kmax": R}
     for meth, fn in run.items():
-        fn([torch.as_tensor(a).to(dev).contiguous() for a in A0])
-        A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+        fn(factors())
+        A = factors()
         rec = {"ms": [], "loss": [loss(A)], "iterations": []}
         for _ in range(iters):
             ms, it = timed(lambda: fn(A))
@@ -684,7 +697,7 @@ def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5
     # one Gauss-Newton product and one full Hessian product (the GN product
     # plus the phi' terms of the off-diagonal blocks, Section 2.5) at the
     # start point, with phi'' and phi' in each mode's order
-    A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+    A = factors()
     X = [torch.randn(d, R, device=dev) for d in wl.dims]
     w = [tt.tttp(ix, tt.INDEX_T, A, out_order=d, epi="d2phi", loss="poisson") for d in range(3)]
     g = [tt.tttp(ix, tt.INDEX_T, A, out_order=d, epi="dphi", loss="poisson") for d in range(3)]

@@ -72,8 +72,10 @@ __device__ __forceinline__ double to_double<uint16_t>(uint16_t v) {
 
 // ---------------------------------------------------------------------------
 // Factor-row fragment loads: lane `c0 / V` of a group reads elements
-// [c0, c0 + V) of row `row`.  VEC: one vector load (requires R % V == 0,
-// 16-byte aligned rows); otherwise element loads.  Elements at or beyond R
+// [c0, c0 + V) of row `row`.  VEC: one vector load (requires 16-byte (BF16:
+// 8-byte) aligned rows and a leading dimension of at least R rounded up to
+// V; with R % V != 0 the caller masks per element, PARTIAL); otherwise
+// element loads.  Elements at or beyond R
 // read as 0.  The loads are unconditional (out-of-range lanes read column 0
 // or R - 1 of the row and select 0 afterwards), so no branch separates a
 // load from its use and the compiler can keep many gathers in flight.
@@ -142,11 +144,19 @@ __device__ __forceinline__ void gather_frag(const typename TR::T *__restrict__ A
   }
 }
 
-template <class TR, bool VEC>
+// PARTIAL (vector fragments only): R need not be a multiple of V; the
+// fragment holding column R - 1 reads past it (inside the row's leading
+// dimension) and each element is masked on its own column.
+template <class TR, bool VEC, bool PARTIAL = false>
 __device__ __forceinline__ void widen_frag(const FragRaw<TR, VEC> &f, int c0, int R,
                                            typename TR::AT (&o)[TR::V]) {
   using AT = typename TR::AT;
-  if constexpr (VEC) {
+  if constexpr (VEC && PARTIAL) {
+    AT w[TR::V];
+    widen_frag<TR, true, false>(f, c0, R, w);
+#pragma unroll
+    for (int j = 0; j < TR::V; ++j) o[j] = c0 + j < R ? w[j] : AT(0);
+  } else if constexpr (VEC) {
     const bool ok = c0 < R;
     if constexpr (std::is_same<TR, TrF32>::value) {
       o[0] = ok ? f.v.x : 0.f; o[1] = ok ? f.v.y : 0.f;
@@ -165,13 +175,13 @@ __device__ __forceinline__ void widen_frag(const FragRaw<TR, VEC> &f, int c0, in
   }
 }
 
-template <class TR, bool VEC>
+template <class TR, bool VEC, bool PARTIAL = false>
 __device__ __forceinline__ void load_frag(const typename TR::T *__restrict__ A,
                                           int64_t ldA, int64_t row, int c0, int R,
                                           typename TR::AT (&o)[TR::V]) {
   FragRaw<TR, VEC> f;
   gather_frag<TR, VEC>(A, ldA, row, c0, R, f);
-  widen_frag<TR, VEC>(f, c0, R, o);
+  widen_frag<TR, VEC, PARTIAL>(f, c0, R, o);
 }
 
 // Dense (accumulation-type) row fragment with row stride R: V elements

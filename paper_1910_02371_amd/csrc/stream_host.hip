@@ -10,11 +10,11 @@
 namespace tt {
 
 hipError_t launch_stream_f32(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                             bool vec, int chunk, hipStream_t s);
+                             int vm, int chunk, hipStream_t s);
 hipError_t launch_stream_bf16(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                              bool vec, int chunk, hipStream_t s);
+                              int vm, int chunk, hipStream_t s);
 hipError_t launch_stream_f64(StreamOp op, const StreamDev &d, int64_t nchunk, int G,
-                             bool vec, int chunk, hipStream_t s);
+                             int vm, int chunk, hipStream_t s);
 
 static int frag_elems(tt_dtype fdt) { return fdt == TT_F64 ? 2 : 4; }
 
@@ -30,6 +30,14 @@ int stream_rp(tt_dtype fdt, int R) { return stream_group_width(fdt, R) * frag_el
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Factor rows are read as whole fragments (V elements: 16 bytes, 8 for
+// BF16) when the bases are fragment-aligned and the leading dimension is a
+// multiple of V that holds R rounded up to V (the last fragment then stays
+// inside the row even when R is not a multiple of V).
+static bool frag_aligned(const void *p, tt_dtype fdt) {
+  return ((uintptr_t)p & (fdt == TT_BF16 ? 7u : 15u)) == 0;
+}
+
 hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   const tt_index *ix = c.ix;
   const ModeIndex &md = ix->mode[c.mode];
@@ -39,22 +47,27 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   d.chunk = md.d_chunk;
   d.chunk_slot = md.d_chunk_slot;
   d.key = md.d_key;
-  bool vec = (c.R % V == 0) && (c.ldA % V == 0);
+  // factor rows as fragments (va), dense blocks (row stride R) as
+  // fragments too (vd)
+  const int64_t Rv = (c.R + V - 1) / V * V;
+  bool va = (c.ldA % V == 0) && c.ldA >= Rv;
+  bool vd = va && (c.R % V == 0);
   int q = 0;
   for (int p = 0; p < ix->N; ++p) {
     if (p == c.mode) continue;
     d.oidx[q] = md.d_oidx[p];
     d.A_oth[q] = c.A[p];
     d.X_oth[q] = c.X[p];
-    if (c.A[p] && !aligned16(c.A[p])) vec = false;
-    if (c.X[p] && !aligned16(c.X[p])) vec = false;
+    if (c.A[p] && !frag_aligned(c.A[p], c.fdt)) va = false;
+    if (c.X[p] && !aligned16(c.X[p])) vd = false;
     ++q;
   }
   d.A_own = c.A[c.mode];
   d.X_own = c.X[c.mode];
-  if (d.A_own && !aligned16(d.A_own)) vec = false;
-  if (d.X_own && !aligned16(d.X_own)) vec = false;
-  if (op != OP_TTTP && !aligned16(c.out)) vec = false;
+  if (d.A_own && !frag_aligned(d.A_own, c.fdt)) va = false;
+  if (d.X_own && !aligned16(d.X_own)) vd = false;
+  if (op != OP_TTTP && !aligned16(c.out)) vd = false;
+  const int vm = !va ? 0 : (vd ? 2 : 1);
   d.s = c.s;
   d.s_perm = c.s_perm;
   d.w_const = c.w_const;
@@ -112,11 +125,11 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
     if (c.prof_name) name = c.prof_name;
     ProfScope ps(name, s, bytes, flops);
     if (c.fdt == TT_F32)
-      e = launch_stream_f32(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
+      e = launch_stream_f32(op, d, md.nchunk, G, vm, ix->tune.chunk, s);
     else if (c.fdt == TT_BF16)
-      e = launch_stream_bf16(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
+      e = launch_stream_bf16(op, d, md.nchunk, G, vm, ix->tune.chunk, s);
     else
-      e = launch_stream_f64(op, d, md.nchunk, G, vec, ix->tune.chunk, s);
+      e = launch_stream_f64(op, d, md.nchunk, G, vm, ix->tune.chunk, s);
   }
   if (e != hipSuccess) return e;
   if (op != OP_TTTP && md.nheavy > 0) {

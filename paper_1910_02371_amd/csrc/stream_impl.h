@@ -131,12 +131,19 @@ __device__ __forceinline__ typename TR::VT load_value(const StreamDev &a, int64_
   return reinterpret_cast<const VT *>(a.s)[q];
 }
 
-template <class TR, int N, int G, bool VEC, int OP, int CHUNK>
+// VM selects the loads: 0 element loads everywhere; 1 factor rows as vector
+// fragments masked per element (R not a multiple of V, leading dimension
+// padded to one) with element loads of the dense blocks (row stride R);
+// 2 vector fragments everywhere (R a multiple of V).
+template <class TR, int N, int G, int VM, int OP, int CHUNK>
 __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   using T = typename TR::T;
   using VT = typename TR::VT;
   using AT = typename TR::AT;
   constexpr int V = TR::V;
+  constexpr bool VA = VM >= 1;              // factor rows as fragments
+  constexpr bool VD = VM == 2;              // dense blocks as fragments
+  constexpr bool PART = VA && !VD;          // per-element masks on factor rows
   constexpr int NO = N - 1;
   constexpr int NG = ST_THREADS / G;
   static_assert(NO <= 2, "order 3 streams");
@@ -190,20 +197,20 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   auto load_own = [&](int row) {
     if constexpr (OP == OP_TTTP || OP == OP_GRAD || OP == OP_GN) {
       if (Aown) {
-        load_frag<TR, VEC>(Aown, ldA, row, c0, R, own);
+        load_frag<TR, VA, PART>(Aown, ldA, row, c0, R, own);
       } else {
 #pragma unroll
         for (int j = 0; j < V; ++j) own[j] = (c0 + j < R) ? AT(1) : AT(0);
       }
     }
-    if constexpr (OP == OP_GN) load_dense<AT, V, VEC>(Xown, row, c0, R, xown);
+    if constexpr (OP == OP_GN) load_dense<AT, V, VD>(Xown, row, c0, R, xown);
   };
 
   bool first_piece = true;
   auto emit = [&](int row, bool ol, bool orr) {
     if constexpr (OP != OP_TTTP) {
       if (!ol && !orr && slot < 0) {
-        store_row<TR, G, VEC>(a.out, row, c0, R, a.accumulate, acc);
+        store_row<TR, G, VD>(a.out, row, c0, R, a.accumulate, acc);
       } else {
         int which = first_piece ? 0 : 1;
 #pragma unroll
@@ -225,8 +232,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
       // gathers of ST_UNROLL nonzeros, issued back to back and kept raw until
       // used; slots past the end of the sub-range reload its last nonzero and
       // are skipped below
-      FragRaw<TR, VEC> ra[ST_UNROLL][2];
-      FragRaw<DenseTr<AT>, VEC> rx[ST_UNROLL][2];
+      FragRaw<TR, VA> ra[ST_UNROLL][2];
+      FragRaw<DenseTr<AT>, VD> rx[ST_UNROLL][2];
 #pragma unroll
       for (int u = 0; u < ST_UNROLL; ++u) {
         const int e = min(eb + u, e1 - 1);
@@ -235,13 +242,13 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
           const int ip = sm.oi[p][e];
           if constexpr (OP == OP_TTTP) {
             const bool skip = Ao[p] == nullptr;
-            gather_frag<TR, VEC>(skip ? reinterpret_cast<const T *>(g_skip_row) : Ao[p], ldA,
+            gather_frag<TR, VA>(skip ? reinterpret_cast<const T *>(g_skip_row) : Ao[p], ldA,
                                  skip ? 0 : ip, c0, R, ra[u][p]);
           } else {
-            gather_frag<TR, VEC>(Ao[p], ldA, ip, c0, R, ra[u][p]);
+            gather_frag<TR, VA>(Ao[p], ldA, ip, c0, R, ra[u][p]);
           }
           if constexpr (OP == OP_GN || OP == OP_NEWTON)
-            gather_frag<DenseTr<AT>, VEC>(Xo[p], R, ip, c0, R, rx[u][p]);
+            gather_frag<DenseTr<AT>, VD>(Xo[p], R, ip, c0, R, rx[u][p]);
         }
       }
 #pragma unroll
@@ -254,10 +261,10 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
 #pragma unroll
             for (int j = 0; j < V; ++j) fa[p][j] = (c0 + j < R) ? AT(1) : AT(0);
           } else {
-            widen_frag<TR, VEC>(ra[u][p], c0, R, fa[p]);
+            widen_frag<TR, VA, PART>(ra[u][p], c0, R, fa[p]);
           }
           if constexpr (OP == OP_GN || OP == OP_NEWTON)
-            widen_frag<DenseTr<AT>, VEC>(rx[u][p], c0, R, fx[p]);
+            widen_frag<DenseTr<AT>, VD>(rx[u][p], c0, R, fx[p]);
         }
         if (e < e1) {
           const int row = sm.key[e + 1];
@@ -376,7 +383,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
 #pragma unroll
           for (int j = 0; j < V; ++j) cs[j] = (double)run[j];
         } else {
-          store_row<TR, G, VEC>(a.out, run_row, c0, R, a.accumulate, run);
+          store_row<TR, G, VD>(a.out, run_row, c0, R, a.accumulate, run);
         }
         active = false;
       };
@@ -464,33 +471,40 @@ __global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__
   }
 }
 
-template <class TR, int N, int G, bool VEC, int CHUNK>
+template <class TR, int N, int G, int VM, int CHUNK>
 hipError_t launch_stream_t(StreamOp op, const StreamDev &d, int64_t nchunk,
                            hipStream_t s) {
   if (nchunk <= 0) return hipSuccess;
   dim3 grid((unsigned)nchunk), block(ST_THREADS);
   switch (op) {
-    case OP_TTTP: k_stream<TR, N, G, VEC, OP_TTTP, CHUNK><<<grid, block, 0, s>>>(d); break;
-    case OP_MTTKRP: k_stream<TR, N, G, VEC, OP_MTTKRP, CHUNK><<<grid, block, 0, s>>>(d); break;
-    case OP_GRAD: k_stream<TR, N, G, VEC, OP_GRAD, CHUNK><<<grid, block, 0, s>>>(d); break;
-    case OP_GN: k_stream<TR, N, G, VEC, OP_GN, CHUNK><<<grid, block, 0, s>>>(d); break;
-    case OP_NEWTON: k_stream<TR, N, G, VEC, OP_NEWTON, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_TTTP: k_stream<TR, N, G, VM, OP_TTTP, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_MTTKRP: k_stream<TR, N, G, VM, OP_MTTKRP, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_GRAD: k_stream<TR, N, G, VM, OP_GRAD, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_GN: k_stream<TR, N, G, VM, OP_GN, CHUNK><<<grid, block, 0, s>>>(d); break;
+    case OP_NEWTON: k_stream<TR, N, G, VM, OP_NEWTON, CHUNK><<<grid, block, 0, s>>>(d); break;
   }
   return hipGetLastError();
 }
 
-// The vector path has one instantiation per supported chunk size (the LDS
-// footprint sets the occupancy); the element path, for unaligned ranks, uses
-// the largest, which serves every chunk size.
-template <class TR, int G>
-hipError_t launch_stream_g(StreamOp op, const StreamDev &d, int64_t nchunk, bool vec,
-                           int chunk, hipStream_t s) {
-  if (!vec) return launch_stream_t<TR, 3, G, false, 2048>(op, d, nchunk, s);
+// The vector paths have one instantiation per supported chunk size (the LDS
+// footprint sets the occupancy); the element path, for unaligned factors,
+// uses the largest, which serves every chunk size.
+template <class TR, int G, int VM>
+hipError_t launch_stream_vm(StreamOp op, const StreamDev &d, int64_t nchunk, int chunk,
+                            hipStream_t s) {
   switch (chunk) {
-    case 512: return launch_stream_t<TR, 3, G, true, 512>(op, d, nchunk, s);
-    case 1024: return launch_stream_t<TR, 3, G, true, 1024>(op, d, nchunk, s);
-    default: return launch_stream_t<TR, 3, G, true, 2048>(op, d, nchunk, s);
+    case 512: return launch_stream_t<TR, 3, G, VM, 512>(op, d, nchunk, s);
+    case 1024: return launch_stream_t<TR, 3, G, VM, 1024>(op, d, nchunk, s);
+    default: return launch_stream_t<TR, 3, G, VM, 2048>(op, d, nchunk, s);
   }
+}
+
+template <class TR, int G>
+hipError_t launch_stream_g(StreamOp op, const StreamDev &d, int64_t nchunk, int vm,
+                           int chunk, hipStream_t s) {
+  if (vm == 2) return launch_stream_vm<TR, G, 2>(op, d, nchunk, chunk, s);
+  if (vm == 1) return launch_stream_vm<TR, G, 1>(op, d, nchunk, chunk, s);
+  return launch_stream_t<TR, 3, G, 0, 2048>(op, d, nchunk, s);
 }
 
 }  // namespace tt

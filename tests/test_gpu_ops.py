@@ -498,6 +498,91 @@ def test_gn_matvec_ranks(gpu_lib, form, R, kind):
             assert_close_abs(Y[d], ref[d], ra, TAU[form], f"gn R={R} call {call} mode {d}")
 
 
+# ------------------------------------------- padded leading dimension ----
+def _padded(a, ld):
+    """The factor `a` (device, I x R) stored in an I x ld buffer whose extra
+    columns hold garbage (never read as part of the row)."""
+    buf = torch.full((a.shape[0], ld), 3.0e4, dtype=a.dtype, device=a.device)
+    buf[:, :a.shape[1]] = a
+    return buf[:, :a.shape[1]]
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16", "f64"])
+@pytest.mark.parametrize("R", [10, 13, 21])
+@pytest.mark.parametrize("kind", ["heavy", "zipf"])
+def test_padded_ld_vector_path(gpu_lib, form, R, kind):
+    """A rank that is not a multiple of the lane fragment (4 elements; 2 for
+    FP64) with the factors' leading dimension padded to one: the streaming
+    kernels read factor rows as whole fragments masked per column (the
+    padding holds garbage), so TTTP, MTTKRP, the gradient, the GN product
+    and the full Hessian product equal, bit for bit, the same calls on
+    contiguous factors (element loads), and the oracle at tau."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    V = 2 if form == "f64" else 4
+    ld = (R + V - 1) // V * V
+    A64 = factors(wl.dims, R, 61 + R, positive=True)
+    A64 = [0.6 * a for a in A64]
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    Ap = [_padded(a, ld) for a in A]
+    assert Ap[0].stride(0) == ld
+    rng = np.random.default_rng(R)
+    X64 = [stored_values(rng.standard_normal((d, R)), form) for d in wl.dims]
+    Xd = [dev_vals(x, form) for x in X64]
+    ixs = O.build_index(wl.idx, wl.dims)
+    w = stored_values(rng.random(wl.nnz) + 0.5, form)
+    wd = [dev_vals(w[ixs[d]["perm"]], form) for d in range(3)]
+    g = stored_values(rng.standard_normal(wl.nnz), form)
+    gd = [dev_vals(g[ixs[d]["perm"]], form) for d in range(3)]
+    calls = {
+        "tttp": lambda F: [tt.tttp(ix, tt.INDEX_T, F)],
+        "mttkrp": lambda F: [tt.mttkrp(ix, tt.INDEX_T, F, n) for n in range(3)],
+        "gradient": lambda F: tt.gradient(ix, F, "ls", 0.1),
+        "gn": lambda F: tt.gn_matvec(ix, wd, F, Xd, 0.2),
+        "newton": lambda F: tt.newton_matvec(ix, wd, gd, F, Xd, 0.2),
+    }
+    out = {}
+    for name, fn in calls.items():
+        a = [host(y) for y in fn(A)]
+        b = [host(y) for y in fn(Ap)]
+        for k, (ya, yb) in enumerate(zip(a, b)):
+            assert np.array_equal(ya, yb), f"{name} block {k}: padded differs from contiguous"
+        out[name] = b
+    s = stored_values(wl.t, form)
+    Aa = [np.abs(a) for a in As]
+    m = O.tttp(wl.idx, None, As)
+    m_abs = O.tttp(wl.idx, None, Aa)
+    assert_close_abs(out["tttp"][0], s * m, np.abs(s) * m_abs, TAU[form], "padded tttp")
+    for n in range(3):
+        assert_close_abs(out["mttkrp"][n], O.mttkrp(wl.idx, s, As, n, wl.dims[n]),
+                         O.mttkrp(wl.idx, np.abs(s), Aa, n, wl.dims[n]), TAU[form],
+                         f"padded mttkrp mode {n}")
+    ref = O.gn_matvec(wl.idx, w, As, X64, 0.2, wl.dims)
+    z_abs = O.jvp(wl.idx, Aa, [np.abs(x) for x in X64])
+    for d in range(3):
+        ra = O.mttkrp(wl.idx, np.abs(w) * z_abs, Aa, d, wl.dims[d]) + 0.2 * np.abs(X64[d])
+        assert_close_abs(out["gn"][d], ref[d], ra, TAU[form], f"padded gn mode {d}")
+    ref = O.gradient(wl.idx, s, As, O.LOSS_LS, 0.1, wl.dims)
+    d1 = loss_abs(s, m, m_abs, O.LOSS_LS, "dphi")
+    for d in range(3):
+        ra = O.mttkrp(wl.idx, d1, Aa, d, wl.dims[d]) + 0.2 * Aa[d]
+        assert_close_abs(out["gradient"][d], ref[d], ra, TAU[form], f"padded gradient {d}")
+    # the drivers on padded factors: one Gauss-Newton step and one
+    # alternating-minimization sweep equal the contiguous runs bit for bit
+    for drv in ("gn", "gam"):
+        Ac = [a.clone() for a in A]
+        Ad = [_padded(a, ld) for a in A]
+        for F in (Ac, Ad):
+            if drv == "gn":
+                tt.gn_step(ix, F, "ls", 0.05, tol=1e-3, kmax=3)
+            else:
+                tt.gam_sweep(ix, F, "ls", 0.05, tol=0.0, max_inner=2)
+        torch.cuda.synchronize()
+        for d in range(3):
+            assert torch.equal(Ac[d], Ad[d]), f"{drv} on padded factors, mode {d}"
+
+
 # --------------------------------------------------------------- tuning ----
 TUNINGS = [
     dict(chunk=512, gram_piece=2048, gram_light=256, gram_waves=2, solve_wgs=0),
