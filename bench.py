@@ -41,10 +41,12 @@ HBM_BINDS_FRAC = 0.8
 
 # device code each profiled kernel is built from (the counters recorded in
 # profiles/ are valid while these files are unchanged)
+_SOLVE = ["solve_impl.h", "solve.hip", "solve_fused_f32.hip", "solve_fused_bf16.hip",
+          "common.h"]
 KERNEL_SOURCES = {
-    "gram": ["solve.hip", "common.h"],
-    "cholesky": ["solve.hip", "common.h"],
-    "precond": ["solve.hip", "common.h"],
+    "gram": _SOLVE,
+    "cholesky": _SOLVE,
+    "precond": _SOLVE,
     "stream": ["stream_impl.h", "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip",
                "common.h"],
 }

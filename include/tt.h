@@ -378,23 +378,32 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * tt_gam_sweep -- one generalized alternating-minimization sweep (Section
  * 2.2 for a general loss; stop rule of Section 5.7): for n = 0..N-1, Newton
  * iterations on the rows of A_n with the other factors fixed.  Iteration:
- *     g = MTTKRP_n(phi'(t, m)) + 2 lambda A_n       (one pass, TTTP fused;
- *     w = phi''(t, m) in mode n's order              it also stores w, the
- *                                                    constant 2 for LS)
- *     (G_w^(i) + 2 lambda I) d_i = -g_i per row     (Solve Factor)
+ *     g_i = sum_e phi'(t_e, m_e) h_e + 2 lambda u_i  (row gradient, Table 1)
+ *     G_i = sum_e phi''(t_e, m_e) h_e h_e^T           (row Hessian; phi'' = 2
+ *                                                    for least squares)
+ *     (G_i + 2 lambda I) d_i = -g_i per row          (Solve Factor)
  *     A_n <- A_n + D
  * until ||D||_F <= tol ||A_n||_F (A_n after the update) or max_inner
  * iterations.  For least squares one iteration is the ALS update.  Factors
  * are updated in place; D is held in the factor dtype (rounded to BF16 in
  * the BF16 form) and added in FP64.
- *   tol             > 0: after each iteration but a mode's last, the two
- *                   norms are copied to the host (one stream synchronization
- *                   per iteration); <= 0: exactly max_inner iterations per
- *                   mode, no synchronization.
+ *   FP32 and BF16 forms: g and G of a mode are formed in one pass over its
+ *   nonzeros (the Gram pass evaluates the model value m_e = <u_i, h_e>,
+ *   phi' and phi''), and the stop rule runs on the device: after each
+ *   iteration but a mode's last the two norms are reduced on the device and
+ *   a flag turns the mode's remaining launches into no-ops.  With h_iters
+ *   NULL the call never synchronizes and can be captured in a graph once an
+ *   uncaptured call has sized its workspaces.
+ *   FP64 form: a gradient pass (TTTP fused, storing phi'' per nonzero)
+ *   then the Gram pass; with tol > 0 the norms are copied to the host after
+ *   each iteration but a mode's last (one synchronization each).
+ *   tol             > 0: relative step tolerance; <= 0: exactly max_inner
+ *                   iterations per mode.
  *   d_info          optional int32[sum_n I_n]: Solve Factor info of each
  *                   mode's last iteration.
- *   h_iters         optional host int32[N]: iterations run per mode.
- * Workspaces are allocated on first use (not capturable).  Requires t.
+ *   h_iters         optional host int32[N]: iterations run per mode (one
+ *                   synchronization at the end of the sweep).
+ * Workspaces are allocated on first use.  Requires t.
  * ------------------------------------------------------------------------- */
 tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                        tt_dtype fdt, tt_loss loss, double lambda, double tol,

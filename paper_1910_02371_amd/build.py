@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libtt.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = [
-    "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip", "solve.hip",
+    "solve.hip", "solve_fused_f32.hip", "solve_fused_bf16.hip",
+    "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip",
     "index.hip", "stream_host.hip", "vec.hip", "api.cpp", "noalloc.hip",
 ]
 

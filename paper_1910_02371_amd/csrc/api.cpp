@@ -970,18 +970,78 @@ tt_status tt_gam_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   // workspace: -gradient rows (dense), the Newton step (factor dtype, ldA),
   // phi'' in one mode's order (Poisson), step and factor norms
   void *vg = nullptr, *vd = nullptr, *vw = nullptr, *vparts = nullptr, *vsc = nullptr;
-  TT_ST(ws_get(ix, "gam_g", (size_t)ix->max_I * R * value_size(fdt), &vg));
   const size_t fsz = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
   TT_ST(ws_get(ix, "gam_d", (size_t)ix->max_I * ldA * fsz, &vd));
-  if (loss == TT_LOSS_POISSON_LOG)
-    TT_ST(ws_get(ix, "gam_w", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &vw));
   int64_t need = 0;
   for (int n = 0; n < N; ++n) need = std::max(need, sumsq_parts_needed(ix->mode[n].I, R));
   TT_ST(ws_get(ix, "sumsq", (size_t)need * 8, &vparts));
-  TT_ST(ws_get(ix, "gam_sc", 2 * 8, &vsc));
+  TT_ST(ws_get(ix, "gam_sc", (3 + TT_MAX_ORDER) * 8, &vsc));
   double *carry = nullptr;
-  TT_ST(carry_ws(ix, &carry));
+  if (fdt == TT_F64) {
+    // the FP64 form's separate gradient pass: row gradients, phi'' per
+    // nonzero (Poisson), carries of its segmented reduction
+    TT_ST(ws_get(ix, "gam_g", (size_t)ix->max_I * R * value_size(fdt), &vg));
+    if (loss == TT_LOSS_POISSON_LOG)
+      TT_ST(ws_get(ix, "gam_w", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &vw));
+    TT_ST(carry_ws(ix, &carry));
+  }
   double *sc = (double *)vsc, *parts = (double *)vparts;
+  if (fdt != TT_F64) {
+    // FP32 and BF16 forms: the Newton system of a mode is formed in one
+    // pass per iteration -- the Gram pass evaluates the model value, phi'
+    // and phi'' of each nonzero (no separate gradient pass) -- and the stop
+    // rule is a device flag: once a mode has converged, its remaining
+    // iterations' launches return at once.  sc: [||D||^2, ||A_n||^2, flag,
+    // iterations of mode 0 .. N-1].
+    for (int n = 0; n < N; ++n) TT_ST(solve_workspace(ix, n, R, fdt, true, nullptr, nullptr));
+    TT_LAUNCH(launch_fill(sc, 3 + N, TT_F64, 0.0, st), "gam counters");
+    int64_t off = 0;
+    for (int n = 0; n < N; ++n) {
+      const ModeIndex &md = ix->mode[n];
+      TT_LAUNCH(launch_fill(sc + 2, 1, TT_F64, 0.0, st), "gam flag");
+      for (int k = 0; k < max_inner; ++k) {
+        SolveCall c;
+        memset(&c, 0, sizeof(c));
+        c.ix = ix;
+        c.mode = n;
+        c.R = R;
+        c.ldA = ldA;
+        c.fdt = fdt;
+        for (int p = 0; p < N; ++p) c.A[p] = A[p];
+        c.w_scale = 1.0;
+        c.lambda = 2.0 * lambda;
+        c.fused_rhs = 1;
+        c.newton = 1;
+        c.loss = loss;
+        c.own_coef = 2.0 * lambda;
+        c.X = vd;
+        c.info = d_info ? d_info + off : nullptr;
+        c.skip = sc + 2;
+        TT_ST(run_solve_factor(ix, c, st));
+        TT_LAUNCH(launch_add_rows(d_A[n], ldA, vd, ldA, fdt, md.I, R, st, sc + 2), "gam step");
+        const bool check = tol > 0.0 && k + 1 < max_inner;
+        if (check) {
+          int64_t np = 0;
+          TT_LAUNCH(launch_sumsq_rows(vd, fdt, ldA, md.I, R, 1.0, parts, &np, st, sc + 2),
+                    "gam norm");
+          TT_LAUNCH(launch_sum_doubles(parts, np, sc, 0, st, sc + 2), "gam norm");
+          TT_LAUNCH(launch_sumsq_rows(d_A[n], fdt, ldA, md.I, R, 1.0, parts, &np, st, sc + 2),
+                    "gam norm");
+          TT_LAUNCH(launch_sum_doubles(parts, np, sc + 1, 0, st, sc + 2), "gam norm");
+        }
+        TT_LAUNCH(launch_gam_flag(sc, tol, 3 + n, check ? 1 : 0, st), "gam flag");
+      }
+      off += md.I;
+    }
+    if (h_iters) {
+      double h[TT_MAX_ORDER] = {0, 0, 0, 0};
+      TT_LAUNCH(hipMemcpyAsync(h, sc + 3, N * sizeof(double), hipMemcpyDeviceToHost, st),
+                "gam iterations copy");
+      TT_LAUNCH(hipStreamSynchronize(st), "gam iterations sync");
+      for (int n = 0; n < N; ++n) h_iters[n] = (int32_t)h[n];
+    }
+    return TT_OK;
+  }
   int64_t off = 0;
   for (int n = 0; n < N; ++n) {
     const ModeIndex &md = ix->mode[n];

@@ -346,36 +346,53 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
   TT_ST(upload(L, &md.d_task, task, s));
   TT_ST(upload(L, &md.d_row_task, row_task, s));
   md.h_row_task = row_task;
-  md.h_heavy_task.clear();
-  md.h_heavy_nnz.assign(1, 0);
-  for (int64_t q = 0; q + 1 < (int64_t)task.size(); ++q)
-    if (task[q + 1] - task[q] > ix->tune.gram_light) {
-      md.h_heavy_task.push_back((int32_t)q);
-      md.h_heavy_nnz.push_back(md.h_heavy_nnz.back() + task[q + 1] - task[q]);
-    }
   md.h_task = task;
   md.h_multi_row.clear();
   for (int64_t i = 0; i < md.I; ++i)
     if (row_task[i + 1] - row_task[i] > kReduceMin) md.h_multi_row.push_back((int32_t)i);
+  // rows by their tasks: one light task (solo), one heavy task (heavy
+  // solo), the others (several tasks, or none); the heavy and the light
+  // tasks of the rows with several tasks
+  const int64_t light = ix->tune.gram_light;
   md.h_solo_row.clear();
+  md.h_hsolo_row.clear();
   md.h_rest_row.clear();
   md.h_light_task.clear();
+  md.h_heavy_task.clear();
+  std::vector<int32_t> hsolo_task;
   md.h_solo_nnz.assign(1, 0);
+  md.h_hsolo_nnz.assign(1, 0);
+  md.h_heavy_nnz.assign(1, 0);
   for (int64_t i = 0; i < md.I; ++i) {
     const int32_t a = row_task[i], b = row_task[i + 1];
-    if (b - a == 1 && task[a + 1] - task[a] <= ix->tune.gram_light) {
-      md.h_solo_row.push_back((int32_t)i);
-      md.h_solo_nnz.push_back(md.h_solo_nnz.back() + task[a + 1] - task[a]);
-    } else {
-      md.h_rest_row.push_back((int32_t)i);
-      if (b - a > 1)
-        for (int32_t q = a; q < b; ++q)
-          if (task[q + 1] - task[q] <= ix->tune.gram_light) md.h_light_task.push_back(q);
+    if (b - a == 1) {
+      const int64_t nz = task[a + 1] - task[a];
+      if (nz <= light) {
+        md.h_solo_row.push_back((int32_t)i);
+        md.h_solo_nnz.push_back(md.h_solo_nnz.back() + nz);
+      } else {
+        md.h_hsolo_row.push_back((int32_t)i);
+        hsolo_task.push_back(a);
+        md.h_hsolo_nnz.push_back(md.h_hsolo_nnz.back() + nz);
+      }
+      continue;
+    }
+    md.h_rest_row.push_back((int32_t)i);
+    for (int32_t q = a; q < b; ++q) {
+      const int64_t nz = task[q + 1] - task[q];
+      if (nz <= light) {
+        md.h_light_task.push_back(q);
+      } else {
+        md.h_heavy_task.push_back(q);
+        md.h_heavy_nnz.push_back(md.h_heavy_nnz.back() + nz);
+      }
     }
   }
   TT_ST(upload(L, &md.d_heavy_task, md.h_heavy_task, s));
   TT_ST(upload(L, &md.d_multi_row, md.h_multi_row, s));
   TT_ST(upload(L, &md.d_solo_row, md.h_solo_row, s));
+  TT_ST(upload(L, &md.d_hsolo_row, md.h_hsolo_row, s));
+  TT_ST(upload(L, &md.d_hsolo_task, hsolo_task, s));
   TT_ST(upload(L, &md.d_rest_row, md.h_rest_row, s));
   TT_ST(upload(L, &md.d_light_task, md.h_light_task, s));
   // uploads are asynchronous from pageable vectors: wait before they go

@@ -60,8 +60,8 @@ struct ModeIndex {
   std::vector<int64_t> h_task;      // host copy of task boundaries
   std::vector<int64_t> h_heavy_nnz; // prefix sums of heavy-task sizes
   int32_t max_task_per_row = 0;
-  int32_t *d_heavy_task = nullptr;  // tasks with > gram_light nonzeros
-  std::vector<int32_t> h_heavy_task;
+  int32_t *d_heavy_task = nullptr;  // tasks with > gram_light nonzeros of rows with
+  std::vector<int32_t> h_heavy_task;  // several tasks
   int32_t *d_multi_row = nullptr;   // rows with > kReduceMin tasks
   std::vector<int32_t> h_multi_row;
   // rows whose only Gram task is light: their Gram is formed inside the
@@ -72,6 +72,11 @@ struct ModeIndex {
   std::vector<int64_t> h_solo_nnz;  // prefix sums of the solo rows' nonzeros
   int32_t *d_rest_row = nullptr;
   std::vector<int32_t> h_rest_row;
+  // rows whose only Gram task is heavy, and that task of each (ascending)
+  int32_t *d_hsolo_row = nullptr;
+  std::vector<int32_t> h_hsolo_row;
+  int32_t *d_hsolo_task = nullptr;
+  std::vector<int64_t> h_hsolo_nnz;  // prefix sums of the heavy solo rows' nonzeros
   int32_t *d_light_task = nullptr;
   std::vector<int32_t> h_light_task;
   double mean_row = 0.0;            // m / nrows
@@ -211,6 +216,14 @@ struct SolveCall {
   void *Lstore;             // when non-NULL: keep the Cholesky factors (I x RP(RP+1)/2),
                             // FP64 for the FP64 form, FP32 otherwise
   int factor_only;          // 1: factor and store, no solve
+  // Newton form of alternating minimization (FP32 and BF16 forms; needs
+  // fused_rhs, w NULL, w_scale 1): one pass forms G = sum phi''(t, m) h h^T
+  // and M = sum phi'(t, m) h with m the model value from A[mode], and the
+  // rows solve (G + lambda I) x = -(M + own_coef A[mode][i])
+  int newton;
+  int loss;
+  double own_coef;
+  const double *skip;       // optional device flag: every launch becomes a no-op
 };
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);
 // The Gram (and fused right-hand-side) workspaces of one row batch of
@@ -229,10 +242,10 @@ hipError_t launch_fill(void *p, int64_t n, tt_dtype dense, double v, hipStream_t
 hipError_t launch_scale_rows(void *y, const void *x, tt_dtype xdt, int64_t ldx,
                              int64_t I, int R, double a, tt_dtype ydt, hipStream_t s);
 hipError_t launch_sum_doubles(const double *parts, int64_t n, double *out,
-                              int accumulate, hipStream_t s);
+                              int accumulate, hipStream_t s, const double *skip = nullptr);
 hipError_t launch_sumsq_rows(const void *A, tt_dtype fdt, int64_t ldA, int64_t I,
                              int R, double scale, double *parts, int64_t *nparts,
-                             hipStream_t s);
+                             hipStream_t s, const double *skip = nullptr);
 int64_t sumsq_parts_needed(int64_t I, int R);
 
 // PCG vector kernels (blocks concatenated into one contiguous dense array).
@@ -250,7 +263,9 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
                                 const void *dx, hipStream_t s);
 // A += D, both I x R in the factor dtype fdt with leading dimensions ldA, ldD.
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
-                           int64_t I, int R, hipStream_t s);
+                           int64_t I, int R, hipStream_t s, const double *skip = nullptr);
+// Alternating-minimization Newton bookkeeping on the device (see vec.hip).
+hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.
 hipError_t launch_axpy_values(void *y, const void *x, double a, int64_t n, tt_dtype dense,
                               hipStream_t s);

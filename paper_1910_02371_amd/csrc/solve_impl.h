@@ -1,0 +1,1306 @@
+// Device code of Solve Factor (Section 3.4), shared by the translation
+// units that instantiate its kernels: the Gram accumulation on the matrix
+// cores, the FP64 blocked Cholesky and triangular solves, the kernels, and
+// the host-side launch helpers of the fused Gram + solve rows (instantiated
+// per factor dtype in solve_fused_f32.hip and solve_fused_bf16.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "common.h"
+#include "internal.h"
+
+namespace tt {
+
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct GramDev {
+  const int64_t *task;        // task boundaries in the sorted stream
+  int64_t task_base, task_end;
+  const int32_t *oidx0, *oidx1;
+  const void *A0, *A1;        // other modes' factors (order of the streams)
+  int64_t ldA;
+  int R;
+  const void *w;              // weights in stream order (value dtype) or NULL
+  const int32_t *w_perm;
+  double w_scale;
+  void *G;                    // workspace: (task - task_base) * gram_task_elems(RP)
+  int waves;                  // waves of a heavy-task workgroup (2, 4, 8)
+  const float *rhs_t;         // fused right-hand side: observed values, stream order
+  double *M;                  // fused right-hand side: (task - task_base) * RP partials
+  // Newton form of alternating minimization (WEIGHTED and RHS together):
+  // the weights phi''(t, m) and the right-hand-side values phi'(t, m) are
+  // evaluated in the pass from the model value m = <A_own[i], h_e> of each
+  // nonzero of row i = key[e]
+  const void *A_own;          // the updated mode's factor (leading dim ldA)
+  const int32_t *key;         // sorted mode index of each nonzero
+  int loss;
+  const double *skip;         // when set and *skip != 0 the launch is a no-op
+};
+
+// Slot of the lower element (r, c), r >= c, in the lower-tile layout.
+__device__ __forceinline__ int lower_slot(int r, int c) {
+  const int I = r >> 4, J = c >> 4;
+  return 256 * (I * (I + 1) / 2 + J) + 16 * (r & 15) + (c & 15);
+}
+
+template <class TR>
+__device__ __forceinline__ float elem_f(const typename TR::T *A, int64_t off);
+template <>
+__device__ __forceinline__ float elem_f<TrF32>(const float *A, int64_t off) { return A[off]; }
+template <>
+__device__ __forceinline__ float elem_f<TrBF16>(const uint16_t *A, int64_t off) {
+  return bf16_to_f32(A[off]);
+}
+// Same load with a 32-bit element offset (factor matrices below 2^32 bytes),
+// which lets the address be a scalar base plus a 32-bit vector offset.
+template <class TR>
+__device__ __forceinline__ float elem_f32off(const typename TR::T *A, uint32_t off) {
+  const typename TR::T *p = reinterpret_cast<const typename TR::T *>(
+      reinterpret_cast<const char *>(A) + (uint32_t)(off * (uint32_t)sizeof(typename TR::T)));
+  if constexpr (sizeof(typename TR::T) == 4) return *p;
+  else return bf16_to_f32(*p);
+}
+
+template <class VT>
+__device__ __forceinline__ VT weight_at(const GramDev &d, int64_t pos) {
+  if (d.w == nullptr) return (VT)d.w_scale;
+  int64_t q = d.w_perm ? (int64_t)d.w_perm[pos] : pos;
+  return (VT)d.w_scale * reinterpret_cast<const VT *>(d.w)[q];
+}
+
+// FP32 / BF16 storage, FP32 accumulation on v_mfma_f32_16x16x32_bf16.
+// Vector-fragment layout: lane l = 16 k + i takes nonzero k of each substep
+// of four nonzeros and columns VW*i .. VW*i + VW - 1 of its two factor rows
+// (VW = RP / 16), read as one vector load.  Register class v of lane (i, k)
+// then holds column VW*i + v, so the class pair (p, q) is one 16 x 16 MFMA
+// tile (K = 32 nonzeros per step) whose entry (r, c) is
+// G[VW*r + p][VW*c + q].  The classes p <= q (VW (VW + 1) / 2 tiles) cover
+// every unordered column pair: once when p < q, twice when p == q (only
+// r <= c is stored).
+template <int RP>
+struct GramAcc {
+  static constexpr int VW = RP / 16;
+  static constexpr int NT = VW * (VW + 1) / 2;
+  static constexpr int NV = 4 * NT;
+  f32x4 c[NT];
+  double m[VW];  // fused right-hand side: sum of t_e h_e over this lane's nonzeros
+  __device__ void zero() {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) c[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < VW; ++v) m[v] = 0.0;
+  }
+  __device__ float get(int v) const { return c[v / 4][v % 4]; }
+  __device__ void set(int v, float x) { c[v / 4][v % 4] = x; }
+};
+
+
+// VW consecutive factor entries starting at element `off`, widened to FP32.
+// VEC: one aligned vector load (the caller guarantees alignment and that
+// the whole vector lies inside the row); otherwise element loads.
+template <class TR, int VW, bool VEC>
+__device__ __forceinline__ void load_cols(const typename TR::T *A, uint32_t off, int cb,
+                                          int R, float (&o)[VW]) {
+  if constexpr (VEC) {
+    const uint32_t e = off + (uint32_t)(cb < R ? cb : 0);
+    if constexpr (std::is_same<TR, TrF32>::value) {
+      if constexpr (VW == 4) {
+        const float4 x = *reinterpret_cast<const float4 *>(at32(A, e));
+        o[0] = x.x; o[1] = x.y; o[2] = x.z; o[3] = x.w;
+      } else if constexpr (VW == 2) {
+        const float2 x = *reinterpret_cast<const float2 *>(at32(A, e));
+        o[0] = x.x; o[1] = x.y;
+      } else {
+        o[0] = *at32(A, e);
+      }
+    } else {
+      if constexpr (VW == 4) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(at32(A, e));
+        o[0] = __uint_as_float(x.x << 16); o[1] = __uint_as_float(x.x & 0xffff0000u);
+        o[2] = __uint_as_float(x.y << 16); o[3] = __uint_as_float(x.y & 0xffff0000u);
+      } else if constexpr (VW == 2) {
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(at32(A, e));
+        o[0] = __uint_as_float(x << 16); o[1] = __uint_as_float(x & 0xffff0000u);
+      } else {
+        o[0] = bf16_to_f32(*at32(A, e));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      const int c = cb + v;
+      const uint32_t e = off + (uint32_t)(c < R ? c : 0);
+      if constexpr (std::is_same<TR, TrF32>::value) o[v] = *at32(A, e);
+      else o[v] = bf16_to_f32(*at32(A, e));
+    }
+  }
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Bits of the leading bf16 part of x (truncation): x minus this part is
+// exact in FP32.
+__device__ __forceinline__ uint32_t bf16_head(float x) { return __float_as_uint(x) & 0xffff0000u; }
+
+// Two bf16 parts (in the upper halves of a and b) packed as elements
+// 2t (a) and 2t + 1 (b) of an MFMA operand word.
+__device__ __forceinline__ uint32_t pack_bf16(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+
+// Exact split of x into NP bf16 parts (NP = 3 for any FP32 value; NP = 2 is
+// exact for a product of two bf16 values, which has at most 16 significant
+// bits): x = sum of the parts, largest first.
+template <int NP>
+__device__ __forceinline__ void split_bf16(float x, uint32_t (&p)[NP]) {
+  float r = x;
+#pragma unroll
+  for (int i = 0; i + 1 < NP; ++i) {
+    p[i] = bf16_head(r);
+    r -= __uint_as_float(p[i]);
+  }
+  // what remains has at most 8 significant bits: a bf16 value as it is
+  p[NP - 1] = __float_as_uint(r);
+}
+
+// Products of parts kept for h_a h_b^T: part i of the A side times part j of
+// the B side, for i + j <= 4 (1-based; the dropped terms are below 2^-24 of
+// the product).  With two parts on both sides all four products are kept,
+// which is exact.
+template <int PA, int PB>
+struct PartPairs {
+  static constexpr int N = (PA == 2 && PB == 2) ? 4 : (PA == 2 ? 5 : 6);
+  __device__ static constexpr int a(int k) {
+    return (PA == 2 && PB == 2) ? (k < 2 ? 0 : 1) : (k == 0 ? 0 : k == 1 ? 0 : k == 2 ? 1 : k == 3 ? 0 : k == 4 ? (PA == 3 ? 2 : 1) : 1);
+  }
+  __device__ static constexpr int b(int k) {
+    return (PA == 2 && PB == 2) ? (k % 2) : (k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 0 : k == 3 ? 2 : k == 4 ? (PA == 3 ? 0 : 1) : 1);
+  }
+};
+
+// Nonzeros [nb, ne) of one row into acc, on v_mfma_f32_16x16x32_bf16.  The
+// range is walked in blocks of 64 nonzeros (lane l loads the row offsets of
+// the two gathered factor rows and the weight of nonzero base + l,
+// coalesced, one block ahead) and steps of 32: a step is 8 substeps of 4
+// nonzeros in the vector-fragment layout, so lane (i, k) holds, for column
+// class p, the values h_e[VW i + p] of the 8 nonzeros e = 4 s + k
+// (s = 0..7).  Those 8 values are exactly the lane's K-run of an MFMA
+// operand (lanes 16 g + i take K = 8 g .. 8 g + 7), so the operands are
+// built in registers with no transposition.  Each FP32 value is split
+// exactly into bf16 parts (three for FP32 factors, two for BF16 factors,
+// whose products have 16 significant bits) and the parts' products are
+// accumulated in FP32 (PartPairs).  Without per-nonzero weights both
+// operands are the parts of h; with weights the B operand is the parts of
+// w h.  Columns at or beyond R read a clamped address and hold finite values
+// that only reach padding entries of G, which the solve replaces by the
+// identity.  Nonzeros past the end of the range (only in the last step)
+// read row 0 and are zeroed by their weight or validity.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+__device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
+                                           GramAcc<RP> &acc) {
+  using T = typename TR::T;
+  constexpr int VW = RP / 16;
+  constexpr bool F32 = std::is_same<TR, TrF32>::value;
+  constexpr int PA = F32 ? 3 : 2;
+  constexpr int PB = WEIGHTED ? 3 : PA;
+  // weights and right-hand-side values from the loss at the model value
+  constexpr bool NEWTON = WEIGHTED && RHS;
+  using PP = PartPairs<PA, PB>;
+  const int lane = threadIdx.x & 63;
+  const T *A0 = reinterpret_cast<const T *>(d.A0);
+  const T *A1 = reinterpret_cast<const T *>(d.A1);
+  const int R = d.R;
+  const uint32_t ldA = (uint32_t)d.ldA;
+  const int kk = lane >> 4;
+  const int cb = VW * (lane & 15);
+  const int64_t n = ne - nb;
+  if (n <= 0) return;
+  // NEWTON: this lane's columns of the row's own factor row (0 beyond R)
+  float own[VW];
+  if constexpr (NEWTON) {
+    const uint32_t row = (uint32_t)d.key[nb];
+    load_cols<TR, VW, VEC>(reinterpret_cast<const T *>(d.A_own), row * ldA, cb, R, own);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) own[v] = cb + v < R ? own[v] : 0.f;
+  }
+  const int64_t nblk = (n + 63) / 64;
+  const int64_t nst = (n + 31) / 32;
+  const bool ragged = (n & 31) != 0;  // the last step has nonzeros past the end
+
+  auto load_block = [&](int64_t blk, uint32_t &r0, uint32_t &r1, float &w, float &tv) {
+    const int64_t e = nb + blk * 64 + lane;
+    if (e < ne) {
+      r0 = (uint32_t)d.oidx0[e] * ldA;
+      r1 = (uint32_t)d.oidx1[e] * ldA;
+      w = WEIGHTED ? weight_at<float>(d, e) : 1.f;
+      tv = RHS ? d.rhs_t[e] : 0.f;
+    } else {
+      r0 = 0; r1 = 0; w = 0.f; tv = 0.f;
+    }
+  };
+  uint32_t cr0, cr1, nr0 = 0, nr1 = 0;
+  float cw, nw = 0.f, ct, nt = 0.f;
+  load_block(0, cr0, cr1, cw, ct);
+  if (nblk > 1) load_block(1, nr0, nr1, nw, nt);
+  int64_t cblk = 0;
+
+  // one step; only the last step of a ragged range (TAIL) has nonzeros past
+  // the end, so the others carry no validity code
+  auto step = [&](int64_t st, auto tail_tag) {
+    constexpr bool tail = decltype(tail_tag)::value;
+    const int64_t blk = st >> 1;
+    if (blk != cblk) {  // advance cur to blk (== cblk + 1), prefetch the next
+      cr0 = nr0; cr1 = nr1; cw = nw; ct = nt;
+      cblk = blk;
+      if (blk + 1 < nblk) load_block(blk + 1, nr0, nr1, nw, nt);
+    }
+    const int sb = 32 * (int)(st & 1) + kk;
+    uint32_t r0[8], r1[8];
+    float w[8], tv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      r0[u] = __shfl(cr0, sb + 4 * u);
+      r1[u] = __shfl(cr1, sb + 4 * u);
+      w[u] = (WEIGHTED || tail) ? __shfl(cw, sb + 4 * u) : 1.f;
+      if (RHS) tv[u] = __shfl(ct, sb + 4 * u);  // 0 past the end
+    }
+    float a0[8][VW], a1[8][VW];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      load_cols<TR, VW, VEC>(A0, r0[u], cb, R, a0[u]);
+      load_cols<TR, VW, VEC>(A1, r1[u], cb, R, a1[u]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // NEWTON: model value of each substep's nonzero (the 16 lanes of a DPP
+    // row hold its columns), then phi'' as the weight and phi' as the
+    // right-hand-side value; both vanish past the end of the range
+    if constexpr (NEWTON) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        float dsum = 0.f;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) dsum = fmaf(own[v], a0[u][v] * a1[u][v], dsum);
+        const float m = group_sum<16>(dsum);
+        const float ok = w[u];  // 1 inside the range, 0 past its end
+        const float t = tv[u];
+        tv[u] = ok * loss_eval<float>(EPI_DPHI, d.loss, t, m);
+        w[u] = ok * loss_eval<float>(EPI_D2PHI, d.loss, t, m);
+      }
+    }
+    // operand words: [class][part][word], word t holds substeps 2t, 2t + 1
+    uint32_t opa[VW][PA][4], opb[VW][PB][4];
+    // fused right-hand side: the step's 8 terms per column in FP32, then one
+    // FP64 addition per step
+    float mstep[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) mstep[v] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < VW; ++v) {
+        uint32_t pa[2][PA], pb[2][PB];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int u = 2 * t + q;
+          float h = a0[u][v] * a1[u][v];
+          if constexpr (RHS) mstep[v] = fmaf(tv[u], h, mstep[v]);
+          if constexpr (WEIGHTED) {
+            split_bf16<PA>(h, pa[q]);
+            split_bf16<PB>(w[u] * h, pb[q]);
+          } else {
+            if (tail) h *= w[u];  // validity (1 or 0)
+            split_bf16<PA>(h, pa[q]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < PA; ++i) opa[v][i][t] = pack_bf16(pa[0][i], pa[1][i]);
+        if constexpr (WEIGHTED) {
+#pragma unroll
+          for (int i = 0; i < PB; ++i) opb[v][i][t] = pack_bf16(pb[0][i], pb[1][i]);
+        }
+      }
+    if constexpr (RHS) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc.m[v] += (double)mstep[v];
+    }
+    int q = 0;
+#pragma unroll
+    for (int p = 0; p < VW; ++p)
+#pragma unroll
+      for (int pp = p; pp < VW; ++pp) {
+#pragma unroll
+        for (int k = 0; k < PP::N; ++k) {
+          const int ia = PP::a(k), ib = PP::b(k);
+          const u32x4 wa = {opa[p][ia][0], opa[p][ia][1], opa[p][ia][2], opa[p][ia][3]};
+          u32x4 wb;
+          if constexpr (WEIGHTED)
+            wb = (u32x4){opb[pp][ib][0], opb[pp][ib][1], opb[pp][ib][2], opb[pp][ib][3]};
+          else
+            wb = (u32x4){opa[pp][ib][0], opa[pp][ib][1], opa[pp][ib][2], opa[pp][ib][3]};
+          acc.c[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, wa), __builtin_bit_cast(bf16x8, wb), acc.c[q], 0, 0, 0);
+        }
+        ++q;
+      }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  const int64_t nfull = ragged ? nst - 1 : nst;
+  for (int64_t st = 0; st < nfull; ++st) step(st, std::false_type{});
+  if (ragged) step(nst - 1, std::true_type{});
+}
+
+// Waves per SIMD the Gram kernels are compiled for: at RP = 64 the
+// unweighted forms fit 3 (register-limited otherwise to 2), which hides
+// more of the gather latency of each 32-nonzero step.
+template <int RP, bool WEIGHTED>
+struct GramOcc {
+  static constexpr int value = (RP == 64 && !WEIGHTED) ? 3 : 1;
+};
+
+// Write G in the lower-tile layout from the accumulators (each unordered
+// column pair once).  v_mfma_f32_16x16x32_bf16 result: lane l, register v
+// holds D[4 (l / 16) + v][l % 16].
+template <int RP>
+__device__ __forceinline__ void gram_store(float *G, const GramAcc<RP> &acc, float scale) {
+  constexpr int VW = RP / 16;
+  const int lane = threadIdx.x & 63;
+  const int c = lane & 15;
+  int q = 0;
+#pragma unroll
+  for (int p = 0; p < VW; ++p)
+#pragma unroll
+    for (int pp = p; pp < VW; ++pp) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 4 * (lane >> 4) + v;
+        const int a = VW * r + p, b = VW * c + pp;
+        if (p < pp || r <= c) G[lower_slot(max(a, b), min(a, b))] = acc.c[q][v] * scale;
+      }
+      ++q;
+    }
+}
+
+// Light tasks of rows with several tasks (the `tasks` list): one wave per
+// task, four tasks per workgroup.  Rows whose only task is light form their
+// Gram inside k_solve_solo; tasks above the light threshold (tuning
+// gram_light) go to k_gram_f32_heavy.
+// Fused right-hand side of one task: lanes l, l + 16, l + 32, l + 48 hold
+// the same columns for different nonzeros; their FP64 sums are added in a
+// fixed butterfly and lanes 0..15 store the task's RP partial entries.
+template <int RP>
+__device__ __forceinline__ void rhs_store(double *M, const GramAcc<RP> &acc, int lane) {
+  constexpr int VW = RP / 16;
+#pragma unroll
+  for (int v = 0; v < VW; ++v) {
+    double x = acc.m[v];
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    if (lane < 16) M[VW * lane + v] = x;
+  }
+}
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32(
+    GramDev d, const int32_t *tasks, int64_t ntasks) {
+  if (d.skip && *d.skip != 0.0) return;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= ntasks) return;
+  const int64_t t = tasks[q];
+  const int64_t nb = d.task[t], ne = d.task[t + 1];
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, nb, ne, acc);
+  gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
+                 d.w ? 1.f : (float)d.w_scale);
+  if constexpr (RHS) rhs_store<RP>(d.M + (t - d.task_base) * (int64_t)RP, acc, threadIdx.x & 63);
+}
+
+// Heavy tasks: the waves of a workgroup split the task's nonzeros and add
+// their accumulators through LDS in wave order (deterministic).
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, int NW>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32_heavy(
+    GramDev d, const int32_t *heavy, int64_t nheavy) {
+  constexpr int NV = GramAcc<RP>::NV;
+  constexpr int VW = RP / 16;
+  __shared__ float buf[NV * 64];
+  __shared__ double mbuf[RHS ? VW * 64 : 1];
+  if (d.skip && *d.skip != 0.0) return;  // uniform over the workgroup
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t t = heavy[blockIdx.x];
+  const int64_t nb = d.task[t], ne = d.task[t + 1];
+  const int64_t per = (((ne - nb) + NW - 1) / NW + 3) & ~(int64_t)3;
+  const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, b0, b1, acc);
+  for (int q = 0; q < NW; ++q) {
+    if (w == q) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        buf[v * 64 + lane] = (q == 0 ? 0.f : buf[v * 64 + lane]) + acc.get(v);
+      if constexpr (RHS) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          mbuf[v * 64 + lane] = (q == 0 ? 0.0 : mbuf[v * 64 + lane]) + acc.m[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
+    gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
+                 d.w ? 1.f : (float)d.w_scale);
+    if constexpr (RHS) {
+#pragma unroll
+      for (int v = 0; v < VW; ++v) acc.m[v] = mbuf[v * 64 + lane];
+      rhs_store<RP>(d.M + (t - d.task_base) * (int64_t)RP, acc, lane);
+    }
+  }
+}
+
+// Rows with more than kReduceMin tasks: sum their tasks' fused right-hand
+// side partials in FP64 into the first task's slot.  The 256 threads take
+// the row's tasks in 4 strided sets of 64 lanes (lane = column), each with 4
+// independent partial sums, combined in a fixed order (deterministic).
+template <int RP>
+__global__ __launch_bounds__(256) void k_rhs_reduce(const int32_t *__restrict__ rows,
+                                                    const int32_t *__restrict__ row_task,
+                                                    int64_t task_base, double *M,
+                                                    const double *skip) {
+  __shared__ double part[4][64];
+  if (skip && *skip != 0.0) return;
+  const int64_t row = rows[blockIdx.x];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int32_t t0 = row_task[row], t1 = row_task[row + 1];
+  double *m = M + ((int64_t)t0 - task_base) * RP;
+  const int n = t1 - t0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (c < RP) {
+    int q = g;
+    for (; q + 12 < n; q += 16) {
+      s0 += m[(int64_t)q * RP + c];
+      s1 += m[(int64_t)(q + 4) * RP + c];
+      s2 += m[(int64_t)(q + 8) * RP + c];
+      s3 += m[(int64_t)(q + 12) * RP + c];
+    }
+    for (; q < n; q += 4) s0 += m[(int64_t)q * RP + c];
+  }
+  part[g][c] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && c < RP) m[c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+}
+
+// Rows with more than kReduceMin tasks: sum their tasks' Grams entrywise
+// (lower-tile layout) in FP64, in task order, into the row's first task slot.
+template <class GT, int RP>
+__global__ __launch_bounds__(256) void k_gram_reduce(const int32_t *__restrict__ rows,
+                                                     const int32_t *__restrict__ row_task,
+                                                     int64_t task_base, GT *G,
+                                                     const double *skip) {
+  constexpr int SZ = 128 * (RP / 16) * (RP / 16 + 1);
+  if (skip && *skip != 0.0) return;
+  const int64_t row = rows[blockIdx.x];
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= SZ) return;
+  const int32_t t0 = row_task[row], t1 = row_task[row + 1];
+  const GT *g = G + ((int64_t)t0 - task_base) * SZ + e;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int n = t1 - t0;
+  int q = 0;
+  for (; q + 4 <= n; q += 4) {
+    s0 += (double)g[(int64_t)q * SZ];
+    s1 += (double)g[(int64_t)(q + 1) * SZ];
+    s2 += (double)g[(int64_t)(q + 2) * SZ];
+    s3 += (double)g[(int64_t)(q + 3) * SZ];
+  }
+  for (; q < n; ++q) s0 += (double)g[(int64_t)q * SZ];
+  G[((int64_t)t0 - task_base) * SZ + e] = (GT)((s0 + s1) + (s2 + s3));
+}
+
+// FP64 storage and accumulation: 16x16x4 FP64 tiles of the upper triangle.
+template <int RP>
+__global__ __launch_bounds__(256) void k_gram_f64(GramDev d) {
+  constexpr int TB = RP / 16;
+  constexpr int NT = TB * (TB + 1) / 2;
+  if (d.skip && *d.skip != 0.0) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = d.task_base + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= d.task_end) return;
+  const int64_t nb = d.task[t], ne = d.task[t + 1];
+  const double *A0 = reinterpret_cast<const double *>(d.A0);
+  const double *A1 = reinterpret_cast<const double *>(d.A1);
+  const int R = d.R;
+  const int i = lane % 16, kk = lane / 16;
+  f64x4 c[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) c[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t base = nb; base < ne; base += 64) {
+    const int cnt = (int)min((int64_t)64, ne - base);
+    int my0 = 0, my1 = 0;
+    double myw = 0.0;
+    if (lane < cnt) {
+      my0 = d.oidx0[base + lane];
+      my1 = d.oidx1[base + lane];
+      myw = weight_at<double>(d, base + lane);
+    }
+    const int steps = (cnt + 3) / 4;
+    for (int st = 0; st < steps; ++st) {
+      const int src = st * 4 + kk;
+      const int j0 = __shfl(my0, src);
+      const int j1 = __shfl(my1, src);
+      const double w = __shfl(myw, src);
+      double h[TB];
+#pragma unroll
+      for (int a = 0; a < TB; ++a) {
+        const int col = 16 * a + i;
+        h[a] = col < R ? A0[(int64_t)j0 * d.ldA + col] * A1[(int64_t)j1 * d.ldA + col] : 0.0;
+      }
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < TB; ++a)
+#pragma unroll
+        for (int bb = a; bb < TB; ++bb) {
+          c[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(h[a], w * h[bb], c[q], 0, 0, 0);
+          ++q;
+        }
+    }
+  }
+  double *G = reinterpret_cast<double *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP);
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < TB; ++a)
+#pragma unroll
+    for (int bb = a; bb < TB; ++bb) {
+      // v_mfma_f64_16x16x4f64 result: D[row][col] at col = lane % 16,
+      // row = 4 * v + lane / 16 (checked on the device); tile (a, bb) is
+      // block (a, bb) of the upper triangle, stored transposed as the lower
+      // element (16 bb + col, 16 a + row)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 4 * v + lane / 16, col = lane % 16;
+        if (a < bb || col >= row) G[lower_slot(16 * bb + col, 16 * a + row)] = c[q][v];
+      }
+      ++q;
+    }
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  long long b = __double_as_longlong(x);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+struct SolveDev {
+  const int32_t *rows;       // rows of the launch (NULL: r0 + position)
+  int64_t nrow;              // rows of the launch; the grid strides over them
+  int64_t grid_max;          // host side: 0, or the persistent grid size
+  const int32_t *row_task;   // I + 1
+  int64_t task_base;
+  int64_t r0;                // first row of the batch
+  const void *G;             // Gram workspace (float or double per dtype)
+  int R;
+  double lambda;
+  const void *rhs;           // I x R dense dtype
+  const double *M;           // fused right-hand side partials per task, or NULL
+  void *X;                   // I x R in storage dtype, leading dim ldX
+  int64_t ldX;
+  int32_t *info;
+  void *Lstore;              // I x RP (RP + 1) / 2 packed factors, Gram dtype (optional)
+  int factor_only;
+  const double *skip;
+  // Newton form of alternating minimization: the fused right-hand side M
+  // holds the row gradients' loss part, and the system is solved for
+  // -(M_i + own_coef * own[i]) (own: the updated factor, leading dim ldX)
+  const void *own;
+  double own_coef;
+};
+
+// Right-hand side of lane i (< R) in the Newton form: -(m + c own[row, i]).
+template <class XT>
+__device__ __forceinline__ double newton_rhs(const SolveDev &d, int64_t row, int lane, double m) {
+  const XT u = reinterpret_cast<const XT *>(d.own)[row * d.ldX + lane];
+  return -(m + d.own_coef * to_double<XT>(u));
+}
+
+// Pivot of step k: 1 / sqrt(d) for d > 0 (d is the broadcast pivot, the
+// same on every lane, so the branch below is uniform).  The hardware
+// reciprocal square root estimate is refined by two Newton steps
+// y <- y + y (1 - d y^2) / 2 (each squares the relative error, so the result
+// is within a few ulp).  Pivots below 2^-900 are scaled by 2^960 first and
+// the result by 2^480 (both exact), so d y^2 neither underflows nor
+// overflows.
+__device__ __forceinline__ double rsqrt_newton(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d, y * y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ double rsqrt_pivot(double d) {
+  if (__builtin_expect(d < 0x1p-900, 0)) return rsqrt_newton(d * 0x1p960) * 0x1p480;
+  return rsqrt_newton(d);
+}
+
+// A copy of the lane index that the compiler cannot identify with the
+// original (an empty asm statement owns it), so lane comparisons in different
+// phases of a kernel are not merged and kept alive as masks across them.
+__device__ __forceinline__ int opaque_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+
+// Row-packed lower triangle: row i of L at i (i + 1) / 2 .. i (i + 1) / 2 + i.
+// The LDS copy holds PS = RP (RP + 1) / 2 entries, a zero at PS and one
+// scratch slot per lane after it, so that every lane can issue the same
+// loads and stores (no lane-dependent branches around memory operations).
+template <int RP>
+struct Packed {
+  static constexpr int PS = RP * (RP + 1) / 2;
+  static constexpr int ZERO = PS;
+  static constexpr int LDS = PS + 1 + 64;
+};
+
+// Triangular solves with L read from the LDS copy; b on lane i is b_i and
+// rdiag on lane i is 1 / L(i, i).  At step k every lane subtracts its
+// multiplier times the broadcast pivot value; the multiplier is read from
+// Lp[ZERO] (= 0) on the pivot lane and on lanes already solved, so those
+// lanes keep their value and the result is b * rdiag at the end.  The
+// loops are only partly unrolled: their bodies index nothing by k except
+// through LDS addresses.
+// Forward substitution L y = b (LT: the LDS copy's element type).
+template <int RP, class LT>
+__device__ __forceinline__ double fwd_lds(const LT *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+  const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+#pragma unroll 8
+  for (int k = 0; k < RP; ++k) {
+    const double yk = readlane_d(b * rdiag, k);
+    const double lik = (double)Lp[(lane > k && lane < RP) ? base + k : P::ZERO];
+    b = fma(-lik, yk, b);
+  }
+  return b * rdiag;
+}
+
+// Backward substitution L^T x = y (lane i takes L(k, i), i < k, from row k).
+template <int RP, class LT>
+__device__ __forceinline__ double bwd_lds(const LT *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+#pragma unroll 8
+  for (int k = RP - 1; k >= 0; --k) {
+    const double xk = readlane_d(b * rdiag, k);
+    const double lki = (double)Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+    b = fma(-lki, xk, b);
+  }
+  return b * rdiag;
+}
+
+// Panel buffer of the blocked Cholesky: four columns of PP doubles (column
+// c at c * PP, then 64 scratch slots).  PP is RP + 16 rounded so that
+// 2 PP = 32 (mod 64): the 16-lane groups of a half-wave that read
+// neighbouring columns fall on disjoint LDS bank halves.
+template <int RP>
+struct PanelBuf {
+  static constexpr int PP = RP == 16 ? 48 : RP + 16;
+  static constexpr int SCR = 4 * PP;
+  static constexpr int SIZE = 4 * PP + 64;
+};
+
+// Backward substitution L^T x = y as bwd_lds, with lane i's column
+// L(k > i, i) copied from LDS into registers first (the factorization's
+// accumulator registers are free by then), so the steps touch no memory.
+template <int RP>
+__device__ __forceinline__ double bwd_regs(const double *Lp, double b, double rdiag, int lane) {
+  using P = Packed<RP>;
+  double lcol[RP];
+#pragma unroll
+  for (int k = 0; k < RP; ++k) lcol[k] = Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+#pragma unroll
+  for (int k = RP - 1; k >= 0; --k) {
+    const double xk = readlane_d(b * rdiag, k);
+    b = fma(-lcol[k], xk, b);
+  }
+  return b * rdiag;
+}
+
+// Blocked Cholesky of one row's S = G + lambda I on the matrix cores.
+// S lives in NT accumulator tiles (lower tiles, layout of the Gram
+// workspace): lane l, register v of tile (I, J) holds
+// S(16 I + 4 v + l / 16, 16 J + l % 16).  For each panel of four columns
+// k0 .. k0 + 3 (inside column block J = k0 / 16):
+//   1. the lanes holding the panel's columns write them to the LDS panel
+//      buffer Pn (column-major, PanelBuf);
+//   2. lane i reads row i of the panel and the panel is factored on the
+//      lanes (pivot from the diagonal lane, reciprocal square root, the
+//      three in-panel updates with broadcast multipliers);
+//   3. the factored panel L_p goes back to Pn and into the row-packed LDS
+//      copy Lp of L;
+//   4. the trailing update S(I, J') -= L_p(I) L_p(J')^T for J <= J' <= I
+//      runs as v_mfma_f64_16x16x4f64 with K = the panel's four columns,
+//      operand L_p(I) read from Pn (lane l: L(16 I + l % 16, k0 + l / 16)).
+// Entries of already factored columns in a tile are updated too but never
+// read again.  The workgroup is one wave, whose LDS accesses complete in
+// program order, so the buffers need no barriers.  Returns info (LAPACK
+// potrf convention) and leaves 1 / L(i, i) in rdiag on lane i.
+// FWD: the forward substitution L y = b runs with the factorization (lane i
+// holds b_i; at pivot k, y_k = b_k / L(k, k) is broadcast and lanes i > k
+// subtract L(i, k) y_k, the multiplier they have just computed), so b
+// holds y on return.
+// The row's Gram is the sum of `ntask` consecutive tile-layout matrices at
+// gbase (task workspace, or the LDS copy of a Gram formed in the kernel).
+template <class GT, int RP, bool FWD>
+__device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, int ntask,
+                                          int lane, double *Lp, double *Pn,
+                                          double &rdiag, double &b) {
+  constexpr int NB = RP / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int SZ = 256 * NT;
+  const int R = d.R;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < ntask; ++t) {
+    const GT *g = gbase + (int64_t)t * SZ + lane;
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[q][v] += (double)g[256 * q + 64 * v];
+  }
+  // the Gram may live in LDS that the factorization overwrites: no later
+  // memory access moves above these loads (a wave's LDS accesses complete in
+  // program order)
+  asm volatile("" ::: "memory");
+  {
+    // shift, identity on the padding, zero above the diagonal of the
+    // diagonal tiles (those slots are not written by the Gram kernels)
+    const int ln = opaque_lane(lane);
+    const int rr = ln >> 4, cc = ln & 15;
+    // the diagonal (and the unwritten upper slots) only occur in the
+    // diagonal tiles I == J
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = acc[I * (I + 1) / 2 + I][v];
+        x = (4 * v + rr < cc) ? 0.0 : x;
+        x += (4 * v + rr == cc) ? d.lambda : 0.0;
+        acc[I * (I + 1) / 2 + I][v] = x;
+      }
+    if (R < RP) {  // uniform: padding rows and columns become the identity
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + rr, c = 16 * J + cc;
+            const double x = acc[I * (I + 1) / 2 + J][v];
+            acc[I * (I + 1) / 2 + J][v] = (r >= R || c >= R) ? (r == c ? 1.0 : 0.0) : x;
+          }
+    }
+  }
+  using P = Packed<RP>;
+  using PB = PanelBuf<RP>;
+  // every lane of the wave is a row when RP = 64: the lane < RP tests fold
+  constexpr bool FULL = RP == 64;
+  const int base = (FULL || lane < RP) ? (lane * (lane + 1)) / 2 : 0;
+#pragma unroll
+  for (int p = 0; p < RP / 4; ++p) {
+    const int k0 = 4 * p, J = k0 / 16, c0 = k0 % 16;
+    {
+      // 1. panel columns to Pn (lanes whose column is outside the panel
+      // write to their scratch slot)
+      const int ln = opaque_lane(lane);
+      const int cc = ln & 15, rr = ln >> 4;
+      const bool mine = (unsigned)(cc - c0) < 4u;
+#pragma unroll
+      for (int I = J; I < NB; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int addr = mine ? (cc - c0) * PB::PP + 16 * I + 4 * v + rr : PB::SCR + ln;
+          Pn[addr] = acc[I * (I + 1) / 2 + J][v];
+        }
+    }
+    // 2. factor the panel on the lanes
+    double x[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double xv = Pn[c * PB::PP + lane];  // in bounds for every lane
+      x[c] = (FULL || lane < RP) ? xv : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = k0 + c;
+      const double dkk = readlane_d(x[c], k);
+      if (!(dkk > 0.0)) return k + 1;
+      const double inv = rsqrt_pivot(dkk);
+      if (lane == k) rdiag = inv;
+      const double lik = lane >= k ? x[c] * inv : 0.0;
+      x[c] = lik;
+      if constexpr (FWD) {
+        // lik is exactly 0 on the lanes above k, which keep their b
+        const double yk = readlane_d(b, k) * inv;
+        b = lane == k ? yk : fma(-lik, yk, b);
+      }
+#pragma unroll
+      for (int c2 = c + 1; c2 < 4; ++c2) x[c2] -= lik * readlane_d(lik, k0 + c2);
+    }
+    // 3. the factored panel to Pn and to the row-packed copy of L
+    {
+      const int ln = opaque_lane(lane);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Pn[(FULL || ln < RP) ? c * PB::PP + ln : PB::SCR + ln] = x[c];
+        Lp[(k0 + c <= ln && (FULL || ln < RP)) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
+      }
+    }
+    // 4. trailing update on the matrix cores
+    if (k0 + 4 < RP) {
+      double a[NB];
+#pragma unroll
+      for (int I = J; I < NB; ++I) a[I] = Pn[(lane >> 4) * PB::PP + 16 * I + (lane & 15)];
+#pragma unroll
+      for (int I = J; I < NB; ++I)
+#pragma unroll
+        for (int J2 = J; J2 <= I; ++J2)
+          acc[I * (I + 1) / 2 + J2] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              -a[I], a[J2], acc[I * (I + 1) / 2 + J2], 0, 0, 0);
+    }
+  }
+  return 0;
+}
+
+// One row of k_solve_rows.
+template <class GT, class XT, class MT, int RP>
+__device__ __forceinline__ void solve_row(const SolveDev &d, int64_t row, int lane, double *Lp,
+                                          double *Pn) {
+  using P = Packed<RP>;
+  const int R = d.R;
+  const int32_t t0 = d.row_task[row];
+  int32_t t1 = d.row_task[row + 1];
+  if (t1 - t0 > kReduceMin) t1 = t0 + 1;  // pre-reduced by k_gram_reduce
+  if (lane == 0) Lp[P::ZERO] = 0.0;
+  double rdiag = 1.0;
+  // right-hand side (lane i holds b_i); the forward substitution runs inside
+  // the factorization
+  double b = 0.0;
+  if (!d.factor_only) {
+    if (d.M) {
+      // fused right-hand side: the row's task partials (pre-reduced into the
+      // first task for rows with more than kReduceMin tasks), in task order
+      if (lane < R) {
+        for (int32_t t = t0; t < t1; ++t) b += d.M[((int64_t)t - d.task_base) * RP + lane];
+        if (d.own) b = newton_rhs<XT>(d, row, lane, b);
+      }
+    } else if (lane < R) {
+      b = (double)reinterpret_cast<const MT *>(d.rhs)[row * R + lane];
+    }
+  }
+  constexpr int SZ = gram_task_elems(RP);
+  const GT *gbase = reinterpret_cast<const GT *>(d.G) + ((int64_t)t0 - d.task_base) * SZ;
+  const int info = d.factor_only
+                       ? chol_tiles<GT, RP, false>(d, gbase, t1 - t0, lane, Lp, Pn, rdiag, b)
+                       : chol_tiles<GT, RP, true>(d, gbase, t1 - t0, lane, Lp, Pn, rdiag, b);
+  if (d.info && lane == 0) d.info[row] = info;
+  if (info && d.Lstore) {
+    // failed rows keep the identity (no preconditioning for that block)
+    for (int q = lane; q < P::PS; q += 64) Lp[q] = 0.0;
+    if (lane < RP) Lp[(lane * (lane + 3)) / 2] = 1.0;
+  }
+  if (d.Lstore) {
+    GT *L = reinterpret_cast<GT *>(d.Lstore) + row * (int64_t)P::PS;
+    for (int q = lane; q < P::PS; q += 64) L[q] = (GT)Lp[q];
+  }
+  if (d.factor_only) return;
+  // b holds y = L^{-1} rhs; backward substitution L^T x = y
+  const double x = info == 0 ? bwd_regs<RP>(Lp, b, rdiag, lane) : 0.0;
+  if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+}
+
+// PERSIST: a grid smaller than the row count, each workgroup taking every
+// gridDim.x-th row in order (one wave per workgroup, so the LDS is reused
+// across rows without barriers); otherwise one workgroup per row.
+template <class GT, class XT, class MT, int RP, bool PERSIST>
+__global__ __launch_bounds__(64) void k_solve_rows(SolveDev d) {
+  using P = Packed<RP>;
+  __shared__ double Lp[P::LDS];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  if (d.skip && *d.skip != 0.0) return;
+  if constexpr (PERSIST) {
+    for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
+      // the lane index is re-derived per row (opaque), so the per-lane
+      // constants of the unrolled factorization are not held across rows
+      const int lane = opaque_lane(threadIdx.x);
+      solve_row<GT, XT, MT, RP>(d, d.rows ? (int64_t)d.rows[idx] : d.r0 + idx, lane, Lp, Pn);
+      asm volatile("" ::: "memory");
+    }
+  } else {
+    const int64_t idx = blockIdx.x;
+    solve_row<GT, XT, MT, RP>(d, d.rows ? (int64_t)d.rows[idx] : d.r0 + idx, threadIdx.x, Lp,
+                              Pn);
+  }
+}
+
+// The tail of a fused Gram + solve: the row's whole Gram (and fused
+// right-hand side) is in one wave's accumulators; store the Gram in the tile
+// layout into the LDS that the factorization later reuses for L, factor,
+// and solve or store the factors.
+template <class TR, int RP, bool RHS, bool FO>
+__device__ __forceinline__ void solve_from_acc(const GramDev &g, const SolveDev &d, int64_t row,
+                                               int lane, double *Lp, double *Pn,
+                                               const GramAcc<RP> &acc) {
+  using P = Packed<RP>;
+  using XT = typename TR::T;
+  constexpr int VW = RP / 16;
+  static_assert(gram_task_elems(RP) <= 2 * P::PS, "the Gram fits below Lp[ZERO]");
+  const int R = d.R;
+  // earlier LDS reads (a previous row's, one wave, program order) stay before
+  // these writes
+  asm volatile("" ::: "memory");
+  float *Gl = reinterpret_cast<float *>(Lp);
+  gram_store<RP>(Gl, acc, g.w ? 1.f : (float)g.w_scale);
+  double b = 0.0;
+  if constexpr (RHS) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      double x = acc.m[v];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      if (lane < 16) Pn[VW * lane + v] = x;
+    }
+    const double bv = Pn[lane < RP ? lane : 0];
+    b = lane < R ? bv : 0.0;
+    if (d.own && lane < R) b = newton_rhs<XT>(d, row, lane, b);
+  } else if (!FO && lane < R) {
+    b = (double)reinterpret_cast<const float *>(d.rhs)[row * R + lane];
+  }
+  asm volatile("" ::: "memory");
+  if (lane == 0) Lp[P::ZERO] = 0.0;
+  double rdiag = 1.0;
+  const int info = chol_tiles<float, RP, !FO>(d, Gl, 1, lane, Lp, Pn, rdiag, b);
+  if (d.info && lane == 0) d.info[row] = info;
+  if (info && d.Lstore) {
+    for (int q = lane; q < P::PS; q += 64) Lp[q] = 0.0;
+    if (lane < RP) Lp[(lane * (lane + 3)) / 2] = 1.0;
+  }
+  if (d.Lstore) {
+    float *L = reinterpret_cast<float *>(d.Lstore) + row * (int64_t)P::PS;
+    for (int q = lane; q < P::PS; q += 64) L[q] = (float)Lp[q];
+  }
+  if constexpr (!FO) {
+    const double x = info == 0 ? bwd_regs<RP>(Lp, b, rdiag, lane) : 0.0;
+    if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+  }
+}
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
+__device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev &d, int64_t row,
+                                               int lane, double *Lp, double *Pn) {
+  const int32_t t = d.row_task[row];
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, g.task[t], g.task[t + 1], acc);
+  solve_from_acc<TR, RP, RHS, FO>(g, d, row, lane, Lp, Pn, acc);
+}
+
+// Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
+// the row's Gram on the matrix cores (gram_accum), stores it in the tile
+// layout into the LDS that the factorization later reuses for L, and
+// factors and solves it there, so the Gram never goes to the workspace.
+// The fused right-hand side is reduced over the four nonzero groups with
+// the butterfly of rhs_store.  PERSIST as in k_solve_rows.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_solo(
+    GramDev g, SolveDev d) {
+  using P = Packed<RP>;
+  __shared__ double Lp[P::LDS];
+  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  if (d.skip && *d.skip != 0.0) return;
+  if constexpr (PERSIST) {
+    for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
+      const int lane = opaque_lane(threadIdx.x);  // per row (see k_solve_rows)
+      solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[idx], lane, Lp, Pn);
+      asm volatile("" ::: "memory");
+    }
+  } else {
+    solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[blockIdx.x], threadIdx.x, Lp, Pn);
+  }
+}
+
+// Rows whose only Gram task is heavy (FP32 and BF16 forms): the task's
+// nonzeros are split over the workgroup's four waves as in
+// k_gram_f32_heavy and their accumulators are added in LDS in wave order;
+// then wave 0 factors and solves (or stores the factors of) the row from
+// the summed accumulators, so neither the Gram nor the right-hand side
+// passes through the workspace.  While wave 0 factors, the other waves have
+// left and the compute unit's other workgroups keep gathering.  The LDS of
+// the wave reduction is reused for the factorization.
+template <int RP>
+struct HeavySoloLds {
+  static constexpr int NV = GramAcc<RP>::NV;
+  static constexpr int RED = NV * 64 * 4 + (RP / 16) * 64 * 8;  // floats, then doubles
+  static constexpr int FAC = (Packed<RP>::LDS + PanelBuf<RP>::SIZE) * 8;
+  static constexpr int DOUBLES = ((RED > FAC ? RED : FAC) + 7) / 8;
+};
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(RP == 64 ? 2 : 4))) void k_gram_solve_heavy(GramDev g,
+                                                                               SolveDev d) {
+  using L = HeavySoloLds<RP>;
+  constexpr int NW = 4;
+  constexpr int NV = L::NV;
+  constexpr int VW = RP / 16;
+  __shared__ double lds[L::DOUBLES];
+  float *buf = reinterpret_cast<float *>(lds);
+  double *mbuf = lds + NV * 64 / 2;
+  if (d.skip && *d.skip != 0.0) return;  // uniform over the workgroup
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t row = d.rows[blockIdx.x];
+  const int32_t t = d.row_task[row];
+  const int64_t nb = g.task[t], ne = g.task[t + 1];
+  const int64_t per = (((ne - nb) + NW - 1) / NW + 3) & ~(int64_t)3;
+  const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
+  GramAcc<RP> acc;
+  acc.zero();
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, b0, b1, acc);
+  for (int q = 0; q < NW; ++q) {
+    if (w == q) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        buf[v * 64 + lane] = (q == 0 ? 0.f : buf[v * 64 + lane]) + acc.get(v);
+      if constexpr (RHS) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+          mbuf[v * 64 + lane] = (q == 0 ? 0.0 : mbuf[v * 64 + lane]) + acc.m[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (w != 0) return;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc.set(v, buf[v * 64 + lane]);
+  if constexpr (RHS) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc.m[v] = mbuf[v * 64 + lane];
+  }
+  // the factorization reuses the reduction buffers (one wave from here on:
+  // its LDS accesses complete in program order)
+  double *Lp = lds;
+  double *Pn = lds + Packed<RP>::LDS;
+  solve_from_acc<TR, RP, RHS, FO>(g, d, row, lane, Lp, Pn, acc);
+}
+
+// Apply stored factors to a right-hand side: X = (L L^T)^{-1} rhs.  The
+// factors (row-packed, RP (RP + 1) / 2 per row) are stored in the dense
+// dtype MT (FP64 for the FP64 form, FP32 otherwise: they only precondition);
+// they are copied into LDS in that dtype with coalesced loads and both
+// triangular solves run in FP64 from there.
+template <class MT, int RP>
+__global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore,
+                                                   const void *rhs, void *X, int R,
+                                                   const double *skip) {
+  using P = Packed<RP>;
+  __shared__ MT Lp[P::LDS];
+  if (skip && *skip != 0.0) return;
+  const int lane = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const MT *L = Lstore + row * (int64_t)P::PS;
+  // all loads of the row's factor are issued before the first LDS write
+  constexpr int NIT = (P::PS + 63) / 64;
+  MT v[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = lane + 64 * it;
+    v[it] = L[q < P::PS ? q : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int q = lane + 64 * it;
+    if (q < P::PS) Lp[q] = v[it];
+  }
+  if (lane == 0) Lp[P::ZERO] = MT(0);
+  __syncthreads();
+  const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
+  const double dg = lane < RP ? (double)Lp[(lane * (lane + 3)) / 2] : 1.0;  // L(i, i)
+  const double rdiag = 1.0 / dg;
+  double x;
+  if constexpr (sizeof(MT) == 4) {
+    // FP32 factors: lane i first copies its row L(i, k < i) and its column
+    // L(k > i, i) from LDS into registers (zeros elsewhere), so the two
+    // substitutions below touch no memory: each step is the broadcast of
+    // y_k (x_k) and one FMA per lane
+    MT lrow[RP], lcol[RP];
+    const int base = lane < RP ? (lane * (lane + 1)) / 2 : 0;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      lrow[k] = Lp[(lane > k && lane < RP) ? base + k : P::ZERO];
+      lcol[k] = Lp[lane < k ? (k * (k + 1)) / 2 + lane : P::ZERO];
+    }
+    double bb = b;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      const double yk = readlane_d(bb * rdiag, k);
+      bb = fma(-(double)lrow[k], yk, bb);
+    }
+    bb *= rdiag;
+#pragma unroll
+    for (int k = RP - 1; k >= 0; --k) {
+      const double xk = readlane_d(bb * rdiag, k);
+      bb = fma(-(double)lcol[k], xk, bb);
+    }
+    x = bb * rdiag;
+  } else {
+    const double y = fwd_lds<RP, MT>(Lp, b, rdiag, lane);
+    x = bwd_lds<RP, MT>(Lp, y, rdiag, lane);
+  }
+  if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
+}
+
+// ---------------------------------------------------------------------------
+static inline int rp_for(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : 64); }
+
+// One workgroup per row, or a persistent grid of d.grid_max workgroups.
+static inline unsigned solve_grid(const SolveDev &d) {
+  return (unsigned)(d.grid_max > 0 ? std::min<int64_t>(d.nrow, d.grid_max) : d.nrow);
+}
+
+// One batch of the FP32 / BF16 forms: heavy tasks and light tasks of rows
+// with several tasks (Gram into the workspace), and the fused Gram + solve
+// of the rows whose only task is light (solo) or heavy (hsolo).
+struct GramLists {
+  const int32_t *heavy, *light, *solo, *hsolo;
+  int64_t nheavy, nlight, nsolo, nhsolo;
+  // heavy solo rows not fused with their solve: their tasks (Gram kernel)
+  const int32_t *hsolo_task;
+  int64_t nhsolo_task;
+  double light_bytes, light_flops, heavy_bytes, heavy_flops, solo_bytes, solo_flops,
+      hsolo_bytes, hsolo_flops;
+};
+
+// Rows whose only Gram task is heavy are fused with their solve up to this
+// padded rank.
+constexpr int kFuseHeavyMaxRP = 32;
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+static void launch_solo_rp(const GramDev &d, const SolveDev &sd, const GramLists &gl,
+                           hipStream_t s) {
+  if (gl.nsolo <= 0) return;
+  ProfScope ps(sd.factor_only ? "gram_factor_light" : "gram_solve_light", s, gl.solo_bytes,
+               gl.solo_flops);
+  SolveDev sd2 = sd;
+  sd2.rows = gl.solo;
+  sd2.nrow = gl.nsolo;
+  const dim3 grid(solve_grid(sd2)), block(64);
+  const bool pers = grid.x < (unsigned)gl.nsolo;
+#define TT_SOLO(FO)                                                                    \
+  do {                                                                                 \
+    if (pers) k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, true><<<grid, block, 0, s>>>(d, sd2); \
+    else k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, false><<<grid, block, 0, s>>>(d, sd2); \
+  } while (0)
+  if constexpr (RHS) {
+    // the fused right-hand side always comes with a solve
+    TT_SOLO(false);
+  } else {
+    if (sd.factor_only) TT_SOLO(true);
+    else TT_SOLO(false);
+  }
+#undef TT_SOLO
+}
+
+
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+static void launch_hsolo_rp(const GramDev &d, const SolveDev &sd, const GramLists &gl,
+                            hipStream_t s) {
+  if (gl.nhsolo <= 0) return;
+  ProfScope ps(sd.factor_only ? "gram_factor_heavy" : "gram_solve_heavy", s, gl.hsolo_bytes,
+               gl.hsolo_flops);
+  SolveDev sd2 = sd;
+  sd2.rows = gl.hsolo;
+  sd2.nrow = gl.nhsolo;
+  const dim3 grid((unsigned)gl.nhsolo), block(256);
+  if constexpr (RHS) {
+    // the fused right-hand side always comes with a solve
+    k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+  } else {
+    if (sd.factor_only)
+      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, true><<<grid, block, 0, s>>>(d, sd2);
+    else
+      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+  }
+}
+
+// Vector loads of VW = RP / 16 entries need R, ldA and the factor bases
+// aligned to VW elements.
+template <class TR, int RP>
+static inline bool gram_vec_ok(const GramDev &d) {
+  constexpr int VW = RP / 16;
+  constexpr size_t al = VW * sizeof(typename TR::T);
+  return d.R % VW == 0 && d.ldA % VW == 0 && reinterpret_cast<uintptr_t>(d.A0) % al == 0 &&
+         reinterpret_cast<uintptr_t>(d.A1) % al == 0 &&
+         reinterpret_cast<uintptr_t>(d.A_own) % al == 0;
+}
+
+// The Gram kernels' forms: weighted Grams (the Gauss-Newton
+// preconditioner) never carry a fused right-hand side; the Newton form of
+// alternating minimization (A_own set) has both, from the loss at the model
+// value.  F is called with the (VEC, WEIGHTED, RHS) of the launch.
+template <class TR, int RP, class F>
+static inline void gram_form(const GramDev &d, F &&f) {
+  const bool vec = gram_vec_ok<TR, RP>(d);
+  if (d.A_own) {
+    if (vec) f(std::true_type{}, std::true_type{}, std::true_type{});
+    else f(std::false_type{}, std::true_type{}, std::true_type{});
+  } else if (d.w) {
+    if (vec) f(std::true_type{}, std::true_type{}, std::false_type{});
+    else f(std::false_type{}, std::true_type{}, std::false_type{});
+  } else if (d.M) {
+    if (vec) f(std::true_type{}, std::false_type{}, std::true_type{});
+    else f(std::false_type{}, std::false_type{}, std::true_type{});
+  } else {
+    if (vec) f(std::true_type{}, std::false_type{}, std::false_type{});
+    else f(std::false_type{}, std::false_type{}, std::false_type{});
+  }
+}
+
+// The fused Gram + solve rows of one batch: solo rows (one light task, a
+// wave each) and heavy solo rows (one heavy task, a workgroup each).
+template <class TR>
+hipError_t launch_fused_rows(int RP, const GramDev &d, const SolveDev &sd, const GramLists &gl,
+                             hipStream_t s) {
+  auto run = [&](auto rp) {
+    constexpr int P = decltype(rp)::value;
+    gram_form<TR, P>(d, [&](auto v, auto w, auto h) {
+      constexpr bool V = decltype(v)::value, W = decltype(w)::value, H = decltype(h)::value;
+      launch_solo_rp<TR, P, V, W, H>(d, sd, gl, s);
+      launch_hsolo_rp<TR, P, V, W, H>(d, sd, gl, s);
+    });
+  };
+  switch (RP) {
+    case 16: run(std::integral_constant<int, 16>{}); break;
+    case 32: run(std::integral_constant<int, 32>{}); break;
+    default: run(std::integral_constant<int, 64>{}); break;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_fused_rows_f32(int RP, const GramDev &d, const SolveDev &sd,
+                                 const GramLists &gl, hipStream_t s);
+hipError_t launch_fused_rows_bf16(int RP, const GramDev &d, const SolveDev &sd,
+                                  const GramLists &gl, hipStream_t s);
+
+}  // namespace tt

@@ -82,7 +82,9 @@ __device__ double block_sum_d(double v) {
   return s;
 }
 
-__global__ void k_sum_doubles(const double *parts, int64_t n, double *out, int accumulate) {
+__global__ void k_sum_doubles(const double *parts, int64_t n, double *out, int accumulate,
+                              const double *skip) {
+  if (skip && *skip != 0.0) return;
   double v = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += parts[i];
   const double s = block_sum_d(v);
@@ -90,14 +92,15 @@ __global__ void k_sum_doubles(const double *parts, int64_t n, double *out, int a
 }
 
 hipError_t launch_sum_doubles(const double *parts, int64_t n, double *out, int accumulate,
-                              hipStream_t s) {
-  k_sum_doubles<<<1, VT_THREADS, 0, s>>>(parts, n, out, accumulate);
+                              hipStream_t s, const double *skip) {
+  k_sum_doubles<<<1, VT_THREADS, 0, s>>>(parts, n, out, accumulate, skip);
   return hipGetLastError();
 }
 
 template <class XT>
 __global__ void k_sumsq_rows(const XT *A, int64_t ldA, int64_t I, int R, double scale,
-                             double *parts) {
+                             double *parts, const double *skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t n = I * R;
   double v = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -113,15 +116,19 @@ __global__ void k_sumsq_rows(const XT *A, int64_t ldA, int64_t I, int R, double 
 int64_t sumsq_parts_needed(int64_t I, int R) { return grid_cap(I * (int64_t)R, RED_BLOCKS); }
 
 hipError_t launch_sumsq_rows(const void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
-                             double scale, double *parts, int64_t *nparts, hipStream_t s) {
+                             double scale, double *parts, int64_t *nparts, hipStream_t s,
+                             const double *skip) {
   const int g = grid_cap(I * (int64_t)R, RED_BLOCKS);
   *nparts = g;
   if (fdt == TT_F64)
-    k_sumsq_rows<double><<<g, VT_THREADS, 0, s>>>((const double *)A, ldA, I, R, scale, parts);
+    k_sumsq_rows<double><<<g, VT_THREADS, 0, s>>>((const double *)A, ldA, I, R, scale, parts,
+                                                  skip);
   else if (fdt == TT_F32)
-    k_sumsq_rows<float><<<g, VT_THREADS, 0, s>>>((const float *)A, ldA, I, R, scale, parts);
+    k_sumsq_rows<float><<<g, VT_THREADS, 0, s>>>((const float *)A, ldA, I, R, scale, parts,
+                                                 skip);
   else
-    k_sumsq_rows<uint16_t><<<g, VT_THREADS, 0, s>>>((const uint16_t *)A, ldA, I, R, scale, parts);
+    k_sumsq_rows<uint16_t><<<g, VT_THREADS, 0, s>>>((const uint16_t *)A, ldA, I, R, scale,
+                                                    parts, skip);
   return hipGetLastError();
 }
 
@@ -279,7 +286,9 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
 // A[i, r] += D[i, r] over I rows, both in the factor dtype with their own
 // leading dimensions; the sum is formed in FP64 and rounded once.
 template <class T>
-__global__ void k_add_rows(T *A, int64_t ldA, const T *D, int64_t ldD, int64_t I, int R) {
+__global__ void k_add_rows(T *A, int64_t ldA, const T *D, int64_t ldD, int64_t I, int R,
+                           const double *skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t n = I * R;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -291,17 +300,35 @@ __global__ void k_add_rows(T *A, int64_t ldA, const T *D, int64_t ldD, int64_t I
 }
 
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
-                           int64_t I, int R, hipStream_t s) {
+                           int64_t I, int R, hipStream_t s, const double *skip) {
   const int64_t n = I * R;
   if (n <= 0) return hipSuccess;
   const int g = grid_cap(n, 8192);
   if (fdt == TT_F64)
-    k_add_rows<double><<<g, VT_THREADS, 0, s>>>((double *)A, ldA, (const double *)D, ldD, I, R);
+    k_add_rows<double><<<g, VT_THREADS, 0, s>>>((double *)A, ldA, (const double *)D, ldD, I, R,
+                                                skip);
   else if (fdt == TT_F32)
-    k_add_rows<float><<<g, VT_THREADS, 0, s>>>((float *)A, ldA, (const float *)D, ldD, I, R);
+    k_add_rows<float><<<g, VT_THREADS, 0, s>>>((float *)A, ldA, (const float *)D, ldD, I, R,
+                                               skip);
   else
     k_add_rows<uint16_t><<<g, VT_THREADS, 0, s>>>((uint16_t *)A, ldA, (const uint16_t *)D, ldD,
-                                                  I, R);
+                                                  I, R, skip);
+  return hipGetLastError();
+}
+
+// Newton-iteration bookkeeping of alternating minimization, one mode at a
+// time: sc[0] = ||D||_F^2, sc[1] = ||A_n||_F^2, sc[2] = converged flag,
+// sc[count] = iterations run.  Unless the mode has converged, count the
+// iteration just run and, with `check`, set the flag when
+// ||D||_F <= tol ||A_n||_F.
+__global__ void k_gam_flag(double *sc, double tol, int count, int check) {
+  if (threadIdx.x != 0 || sc[2] != 0.0) return;
+  sc[count] += 1.0;
+  if (check && sqrt(sc[0]) <= tol * sqrt(sc[1])) sc[2] = 1.0;
+}
+
+hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s) {
+  k_gam_flag<<<1, 64, 0, s>>>(sc, tol, count, check);
   return hipGetLastError();
 }
 

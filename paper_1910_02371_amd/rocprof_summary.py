@@ -36,16 +36,21 @@ STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3, "gn_mttkrp":
 
 
 # fused Gram + Cholesky of rows with one light task:
-# k_solve_solo<traits, RP, vec, weighted, rhs, factor_only>
-SOLO_FO = {"gram_solve_light": "false", "gram_factor_light": "true"}
+# k_solve_solo<traits, RP, vec, weighted, rhs, factor_only, persist>; with one
+# heavy task: k_gram_solve_heavy<traits, RP, vec, weighted, rhs, factor_only>
+SOLO_FO = {"gram_solve_light": ("k_solve_solo<", "false"),
+           "gram_factor_light": ("k_solve_solo<", "true"),
+           "gram_solve_heavy": ("k_gram_solve_heavy<", "false"),
+           "gram_factor_heavy": ("k_gram_solve_heavy<", "true")}
 
 
 def matches(kernel, name):
     if kernel in SOLO_FO:
-        if "k_solve_solo<" not in name:
+        kname, fo = SOLO_FO[kernel]
+        if kname not in name:
             return False
-        args = name.split("k_solve_solo<", 1)[1].split(">")[0].split(",")
-        return len(args) >= 6 and args[5].strip() == SOLO_FO[kernel]
+        args = name.split(kname, 1)[1].split(">")[0].split(",")
+        return len(args) >= 6 and args[5].strip() == fo
     if kernel in STREAM_OP:
         # k_stream<traits, order, G, vec, op, chunk>: the op is the fifth argument
         if "k_stream<" not in name:

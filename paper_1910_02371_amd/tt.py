@@ -417,16 +417,18 @@ def ccd_sweep(ix, A, lam, info=None):
     return A
 
 
-def gam_sweep(ix, A, loss, lam, tol=1e-3, max_inner=5, info=None):
+def gam_sweep(ix, A, loss, lam, tol=1e-3, max_inner=5, info=None, counts=True):
     """One generalized alternating-minimization sweep (Section 2.2, general
     loss; Section 5.7 inner stop rule), factors updated in place.  Returns
-    the Newton iterations run per mode (host list)."""
+    the Newton iterations run per mode (host list), or None with
+    counts=False (then the FP32 and BF16 forms never synchronize, and the
+    call can be captured)."""
     fdt = fdt_of(A)
     R, ld = _rank_ld(A)
-    iters = (ctypes.c_int32 * len(A))()
+    iters = (ctypes.c_int32 * len(A))() if counts else None
     _check(lib().tt_gam_sweep(ix.handle, _ptrs(A), R, ld, fdt, LOSS[loss], float(lam),
                               float(tol), int(max_inner), _ptr(info), iters, _stream()))
-    return list(iters)
+    return list(iters) if counts else None
 
 
 class Graph:

@@ -329,6 +329,51 @@ def test_gam_sweep_low_precision_forms(gpu_lib, form, loss, case):
         assert err <= tau, f"{form} {loss} {case} mode {d}: relative error {err:.2e}"
 
 
+@pytest.mark.parametrize("loss", ["ls", "poisson"])
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_gam_sweep_device_stop_rule_and_capture(gpu_lib, form, loss):
+    """FP32 / BF16 forms with the relative-step stop rule (1e-3, at most 5):
+    the rule runs on the device; in FP32 the per-mode iteration counts are
+    within one of the oracle's (the norms are rounded differently near the
+    threshold), in BF16 they may run to the cap (a factor stored in bf16
+    moves by rounding steps of up to 2^-8 of its size, so relative steps
+    below 1e-3 are not resolved); the objective falls, and the sweep
+    recorded as a graph (no host counts) and replayed three times, with
+    eager work between the replays, equals the eager sweep bit for bit."""
+    tt = gpu_lib
+    wl, t, lam, mm = gam_problem("heavy", loss)
+    L = O.LOSS_LS if loss == "ls" else O.LOSS_POISSON_LOG
+    t = stored_values(t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 4, mm, 8, dtype=np.float64), form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    Ae = [dev_factor(a, form) for a in A0]
+    counts = tt.gam_sweep(ix, Ae, loss, lam, tol=1e-3, max_inner=5)
+    _, cr, _ = O.gam_sweep(wl.idx, t, A0, wl.dims, L, lam, 1e-3, 5)
+    if form == "f32":
+        assert all(abs(a - b) <= 1 for a, b in zip(counts, cr)), f"counts {counts} vs {cr}"
+    else:
+        assert all(max(1, b - 1) <= a <= 5 for a, b in zip(counts, cr)), f"counts {counts} vs {cr}"
+    assert tt.objective(ix, Ae, loss, lam).item() < O.objective(wl.idx, t, A0, L, lam)
+    # capture from the same start (the eager call above sized the workspaces)
+    Ag = [dev_factor(a, form) for a in A0]
+    Ae = [dev_factor(a, form) for a in A0]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g = tt.capture(lambda: tt.gam_sweep(ix, Ag, loss, lam, tol=1e-3, max_inner=5,
+                                            counts=False))
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        tt.gam_sweep(ix, Ae, loss, lam, tol=1e-3, max_inner=5)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            g.launch()
+        side.synchronize()
+        for d in range(3):
+            assert torch.equal(Ae[d], Ag[d]), f"replay {rep}, mode {d}"
+    g.close()
+
+
 @pytest.mark.parametrize("form", ["f64", "f32"])
 def test_gam_least_squares_one_iteration_is_als(gpu_lib, form):
     """Least squares: one Newton iteration per mode is the ALS update, so
