@@ -356,19 +356,21 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * CCD++ order (Section 2.3 and its Section 4 implementation): for each
  * column r, for each mode n in turn, every entry of column r of A_n is set
  * to its exact minimizer
- *     u_ir = sum_e rho_e h_e / (lambda + sum_e h_e^2),   e in row i,
- * h_e the product of the other modes' column-r entries and rho the
- * residual t - model without column r's rank-1 term.  Each column update
- * is mttkrp of rho at rank 1 followed by Solve Factor at rank 1 (the
- * column is a strided view: rank 1, leading dimension ldA).  rho is kept
- * incrementally (two rank-1 TTTP passes per column) in the sorted order of
- * the mode with the most rows, and the other modes read it through the
- * index's position map (built on first use, with one synchronization,
- * unless tt_index_reserve built it).  Factors are updated in place.
- * Requires t.
- *   d_info          optional int32[sum_n I_n]: Solve Factor info of the
- *                   last column's solves.
- * Workspaces (2 m values and I_max values) are allocated on first use.
+ *     u_ir = sum_e rhohat_e h_e / (lambda + sum_e h_e^2),   e in row i,
+ * h_e the product of the other modes' column-r entries (modes updated
+ * earlier in the column contribute their new values) and rhohat the
+ * residual t - model without column r's rank-1 term.  The residual is kept
+ * in every mode's sorted order (one TTTP pass per mode at the start of the
+ * sweep); per column, one pass per mode forms both sums (rhohat from the
+ * residual and the column's old entries, on the fly), a rank-1 solve per
+ * row (a non-positive pivot gives info 1 and 0, the potrf convention), and
+ * one pass per mode moves every residual copy from the old to the new
+ * rank-1 term.  Column r of each factor is read from contiguous copies.
+ * Factors are updated in place.  Requires t.
+ *   d_info          optional int32[sum_n I_n]: the rank-1 solves' info of
+ *                   the last column.
+ * Workspaces (N m values, 2 (sum_n I_n + N) values, 16 bytes per Gram task)
+ * are allocated on first use.
  * ------------------------------------------------------------------------- */
 tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
                        tt_dtype fdt, double lambda, int32_t *d_info,

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = [
     "solve.hip", "solve_fused_f32.hip", "solve_fused_bf16.hip",
     "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip",
-    "index.hip", "stream_host.hip", "vec.hip", "api.cpp", "noalloc.hip",
+    "index.hip", "stream_host.hip", "vec.hip", "ccd.hip", "api.cpp", "noalloc.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -892,64 +892,36 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   TT_CHECK(d_A != nullptr, "NULL argument");
   for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p], "factor %d is NULL", p);
   const int N = ix->N;
-  const tt_dtype dn = dense_of(fdt);
   const size_t vsz = value_size(fdt);
-  const size_t esz = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
   const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
-  // workspace: the residual rho and one rank-1 term (COO order), one column
-  // of right-hand sides
-  void *vrho = nullptr, *vterm = nullptr, *vm = nullptr;
-  TT_ST(ws_get(ix, "ccd_rho", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vrho));
-  TT_ST(ws_get(ix, "ccd_term", (size_t)std::max<int64_t>(ix->m, 1) * vsz, &vterm));
-  TT_ST(ws_get(ix, "ccd_m", (size_t)std::max<int64_t>(ix->max_I, 1) * vsz, &vm));
-  // rho = t - model, kept in the sorted order of the mode with the most rows
-  // (written and updated with unit stride); the other modes read it through
-  // the index's position map
-  const int zm = gn_zmode(ix);
-  const int32_t *zmap = nullptr;
-  if (ix->m > 0) {
-    TT_ST(zmap_get(ix, st, &zmap));
-    TT_ST(tttp_mode(ix, zm, ix->mode[zm].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID,
-                    TT_LOSS_LS, vrho, nullptr, nullptr, nullptr, st));
-  }
-  for (int r = 0; r < R; ++r) {
-    const void *cols[TT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr};
-    for (int p = 0; p < N; ++p) cols[p] = (const char *)d_A[p] + (size_t)r * esz;
-    // rho <- rho + u_r o v_r o w_r: the residual without column r
-    if (ix->m > 0) {
-      TT_ST(tttp_mode(ix, zm, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
-                      vterm, nullptr, nullptr, nullptr, st));
-      TT_LAUNCH(launch_axpy_values(vrho, vterm, 1.0, ix->m, dn, st), "ccd residual");
-    }
-    int64_t off = 0;
+  // workspace: the residual rho = t - model in every mode's sorted order,
+  // old and current copies of column r of every factor (dense dtype), and
+  // the per-task partial sums of a mode pass
+  void *rho[TT_MAX_ORDER] = {}, *old_v[TT_MAX_ORDER] = {}, *cur_v[TT_MAX_ORDER] = {};
+  void *vrho = nullptr, *vcol = nullptr, *vpart = nullptr;
+  const int64_t m1 = std::max<int64_t>(ix->m, 1);
+  int64_t max_task = 1;
+  for (int n = 0; n < N; ++n) max_task = std::max(max_task, ix->mode[n].ntask);
+  TT_ST(ws_get(ix, "ccd_rho", (size_t)N * m1 * vsz, &vrho));
+  TT_ST(ws_get(ix, "ccd_cols", (size_t)2 * (ix->sum_I + N) * vsz, &vcol));
+  TT_ST(ws_get(ix, "ccd_part", (size_t)2 * max_task * 8, &vpart));
+  {
+    char *c = (char *)vcol;
     for (int n = 0; n < N; ++n) {
-      // column r of A_n: (lambda + sum_e h_e^2) x_i = sum_e rho_e h_e, h_e the
-      // other modes' column-r entries (Solve Factor at rank 1)
-      const int32_t *rperm = (n == zm || ix->m == 0) ? nullptr : zmap + (int64_t)n * ix->m;
-      TT_ST(mttkrp_impl(ix, vrho, rperm, 1.0, cols, 1, ldA, fdt, n, vm, 0, st));
-      SolveCall c;
-      memset(&c, 0, sizeof(c));
-      c.ix = ix;
-      c.mode = n;
-      c.R = 1;
-      c.ldA = ldA;
-      c.fdt = fdt;
-      for (int p = 0; p < N; ++p) c.A[p] = cols[p];
-      c.w_scale = 1.0;
-      c.lambda = lambda;
-      c.rhs = vm;
-      c.X = const_cast<void *>(cols[n]);
-      c.info = d_info ? d_info + off : nullptr;
-      TT_ST(run_solve_factor(ix, c, st));
-      off += ix->mode[n].I;
-    }
-    // rho <- rho - (new rank-1 term)
-    if (ix->m > 0) {
-      TT_ST(tttp_mode(ix, zm, nullptr, nullptr, cols, 1, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
-                      vterm, nullptr, nullptr, nullptr, st));
-      TT_LAUNCH(launch_axpy_values(vrho, vterm, -1.0, ix->m, dn, st), "ccd residual");
+      rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
+      old_v[n] = c;
+      c += (size_t)(ix->mode[n].I + 1) * vsz;
+      cur_v[n] = c;
+      c += (size_t)(ix->mode[n].I + 1) * vsz;
     }
   }
+  for (int n = 0; n < N && ix->m > 0; ++n)
+    TT_ST(tttp_mode(ix, n, ix->mode[n].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID, TT_LOSS_LS,
+                    rho[n], nullptr, nullptr, nullptr, st));
+  for (int r = 0; r < R; ++r)
+    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, old_v, cur_v,
+                                (double *)vpart, d_info, st),
+              "ccd column");
   return TT_OK;
 }
 

@@ -359,12 +359,21 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
   md.h_rest_row.clear();
   md.h_light_task.clear();
   md.h_heavy_task.clear();
-  std::vector<int32_t> hsolo_task;
   md.h_solo_nnz.assign(1, 0);
   md.h_hsolo_nnz.assign(1, 0);
   md.h_heavy_nnz.assign(1, 0);
+  md.h_heavy_task_all.clear();
+  md.h_heavy_nnz_all.assign(1, 0);
+  md.h_rest_row_all.clear();
   for (int64_t i = 0; i < md.I; ++i) {
     const int32_t a = row_task[i], b = row_task[i + 1];
+    for (int32_t q = a; q < b; ++q) {
+      const int64_t nz = task[q + 1] - task[q];
+      if (nz > light) {
+        md.h_heavy_task_all.push_back(q);
+        md.h_heavy_nnz_all.push_back(md.h_heavy_nnz_all.back() + nz);
+      }
+    }
     if (b - a == 1) {
       const int64_t nz = task[a + 1] - task[a];
       if (nz <= light) {
@@ -372,12 +381,13 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
         md.h_solo_nnz.push_back(md.h_solo_nnz.back() + nz);
       } else {
         md.h_hsolo_row.push_back((int32_t)i);
-        hsolo_task.push_back(a);
+        md.h_rest_row_all.push_back((int32_t)i);
         md.h_hsolo_nnz.push_back(md.h_hsolo_nnz.back() + nz);
       }
       continue;
     }
     md.h_rest_row.push_back((int32_t)i);
+    md.h_rest_row_all.push_back((int32_t)i);
     for (int32_t q = a; q < b; ++q) {
       const int64_t nz = task[q + 1] - task[q];
       if (nz <= light) {
@@ -392,9 +402,10 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
   TT_ST(upload(L, &md.d_multi_row, md.h_multi_row, s));
   TT_ST(upload(L, &md.d_solo_row, md.h_solo_row, s));
   TT_ST(upload(L, &md.d_hsolo_row, md.h_hsolo_row, s));
-  TT_ST(upload(L, &md.d_hsolo_task, hsolo_task, s));
   TT_ST(upload(L, &md.d_rest_row, md.h_rest_row, s));
   TT_ST(upload(L, &md.d_light_task, md.h_light_task, s));
+  TT_ST(upload(L, &md.d_heavy_task_all, md.h_heavy_task_all, s));
+  TT_ST(upload(L, &md.d_rest_row_all, md.h_rest_row_all, s));
   // uploads are asynchronous from pageable vectors: wait before they go
   if ((he = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(he, "upload");
   ix->max_nchunk = ix->max_nslot = ix->max_nseg = 0;

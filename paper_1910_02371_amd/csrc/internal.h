@@ -72,11 +72,18 @@ struct ModeIndex {
   std::vector<int64_t> h_solo_nnz;  // prefix sums of the solo rows' nonzeros
   int32_t *d_rest_row = nullptr;
   std::vector<int32_t> h_rest_row;
-  // rows whose only Gram task is heavy, and that task of each (ascending)
+  // rows whose only Gram task is heavy (ascending)
   int32_t *d_hsolo_row = nullptr;
   std::vector<int32_t> h_hsolo_row;
-  int32_t *d_hsolo_task = nullptr;
   std::vector<int64_t> h_hsolo_nnz;  // prefix sums of the heavy solo rows' nonzeros
+  // the same partition without the heavy solo class (for ranks whose heavy
+  // solo rows are not fused with their solve): every heavy task, and every
+  // row that is not solo
+  int32_t *d_heavy_task_all = nullptr;
+  std::vector<int32_t> h_heavy_task_all;
+  std::vector<int64_t> h_heavy_nnz_all;
+  int32_t *d_rest_row_all = nullptr;
+  std::vector<int32_t> h_rest_row_all;
   int32_t *d_light_task = nullptr;
   std::vector<int32_t> h_light_task;
   double mean_row = 0.0;            // m / nrows
@@ -264,6 +271,13 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
 // A += D, both I x R in the factor dtype fdt with leading dimensions ldA, ldD.
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
                            int64_t I, int R, hipStream_t s, const double *skip = nullptr);
+// One CCD++ column update (ccd.hip): every mode's column r in turn, then
+// every residual copy; rho[n] = residual in mode n's order, old_v/cur_v[n]
+// = contiguous column vectors (dense dtype), part = 2 x max tasks doubles.
+hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
+                             tt_dtype fdt, double lambda, void *const *rho,
+                             void *const *old_v, void *const *cur_v, double *part,
+                             int32_t *d_info, hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.

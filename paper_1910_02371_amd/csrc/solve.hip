@@ -79,9 +79,6 @@ static void launch_gram_f32_rp(GramDev d, const GramLists &gl, hipStream_t s) {
   }
   launch_gram_heavy_rp<TR, RP, VEC, WEIGHTED, RHS>(d, gl.heavy, gl.nheavy, gl.heavy_bytes,
                                                    gl.heavy_flops, s);
-  // heavy solo rows that are not fused with their solve: their one task
-  launch_gram_heavy_rp<TR, RP, VEC, WEIGHTED, RHS>(d, gl.hsolo_task, gl.nhsolo_task,
-                                                   gl.hsolo_bytes, gl.hsolo_flops, s);
 }
 
 // The Gram kernels (workspace output) of one batch.
@@ -272,21 +269,30 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     const int64_t r1 = lo;
     gd.task_base = rt[r0];
     gd.task_end = rt[r1];
-    const std::vector<int32_t> &ht = md.h_heavy_task, &mr = md.h_multi_row;
+    const bool f64 = c.fdt == TT_F64;
+    // FP32 / BF16 forms up to kFuseHeavyMaxRP: rows with one heavy task are
+    // fused with their solve (their own class); otherwise they go with the
+    // heavy tasks to the Gram kernel and with the other rows to the solve
+    const bool fuse_heavy = !f64 && RP <= kFuseHeavyMaxRP;
+    // each host list with the device copy its indices address
+    const std::vector<int32_t> &ht = fuse_heavy ? md.h_heavy_task : md.h_heavy_task_all,
+                               &mr = md.h_multi_row,
+                               &re = fuse_heavy ? md.h_rest_row : md.h_rest_row_all;
+    const int32_t *d_ht = fuse_heavy ? md.d_heavy_task : md.d_heavy_task_all;
+    const int32_t *d_re = fuse_heavy ? md.d_rest_row : md.d_rest_row_all;
     const int64_t h0 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r0]) - ht.begin();
     const int64_t h1 = std::lower_bound(ht.begin(), ht.end(), (int32_t)rt[r1]) - ht.begin();
     const int64_t q0 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r0) - mr.begin();
     const int64_t q1 = std::lower_bound(mr.begin(), mr.end(), (int32_t)r1) - mr.begin();
-    const bool f64 = c.fdt == TT_F64;
     // FP32 / BF16 forms: rows whose only task is light are solved by the
     // fused kernel; the Gram kernels take the heavy tasks and the light tasks
     // of rows with several tasks; the solve kernel takes the other rows
     GramLists gl = {};
-    gl.heavy = md.d_heavy_task + h0;
+    gl.heavy = d_ht + h0;
     gl.nheavy = h1 - h0;
     int64_t p0 = 0, p1 = 0, hs0 = 0, hs1 = 0;
     GramWork wk;
-    const std::vector<int64_t> &hn = md.h_heavy_nnz;
+    const std::vector<int64_t> &hn = fuse_heavy ? md.h_heavy_nnz : md.h_heavy_nnz_all;
     wk.heavy_nnz = (double)(hn[h1] - hn[h0]);
     wk.reduce_tasks = 0;
     for (int64_t q = q0; q < q1; ++q) wk.reduce_tasks += rt[mr[q] + 1] - rt[mr[q]];
@@ -294,8 +300,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
       wk.light_nnz = (double)(md.h_task[rt[r1]] - md.h_task[rt[r0]]) - wk.heavy_nnz;
       wk.light_tasks = (double)(rt[r1] - rt[r0]) - (double)(h1 - h0);
     } else {
-      const std::vector<int32_t> &lt = md.h_light_task, &so = md.h_solo_row,
-                                 &re = md.h_rest_row;
+      const std::vector<int32_t> &lt = md.h_light_task, &so = md.h_solo_row;
       const int64_t l0 = std::lower_bound(lt.begin(), lt.end(), (int32_t)rt[r0]) - lt.begin();
       const int64_t l1 = std::lower_bound(lt.begin(), lt.end(), (int32_t)rt[r1]) - lt.begin();
       const int64_t s0 = std::lower_bound(so.begin(), so.end(), (int32_t)r0) - so.begin();
@@ -318,16 +323,13 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
                       (c.Lstore ? nsolo * RP * (RP + 1) / 2 * 4.0 : 0.0);
       gl.solo_flops = snnz * Rd * (Rd + 1) +
                       nsolo * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd));
-      // rows whose only task is heavy: fused with their solve up to RP 32;
-      // at RP 64 (where the factorization's registers would cut the Gram's
-      // occupancy) their task goes to the heavy Gram kernel and the row to
-      // the solve kernel
-      const std::vector<int32_t> &hs = md.h_hsolo_row;
-      hs0 = std::lower_bound(hs.begin(), hs.end(), (int32_t)r0) - hs.begin();
-      hs1 = std::lower_bound(hs.begin(), hs.end(), (int32_t)r1) - hs.begin();
-      const double hnnz = (double)(md.h_hsolo_nnz[hs1] - md.h_hsolo_nnz[hs0]);
-      const double nhs = (double)(hs1 - hs0);
-      if (RP <= kFuseHeavyMaxRP) {
+      // rows whose only task is heavy, fused with their solve
+      if (fuse_heavy) {
+        const std::vector<int32_t> &hs = md.h_hsolo_row;
+        hs0 = std::lower_bound(hs.begin(), hs.end(), (int32_t)r0) - hs.begin();
+        hs1 = std::lower_bound(hs.begin(), hs.end(), (int32_t)r1) - hs.begin();
+        const double hnnz = (double)(md.h_hsolo_nnz[hs1] - md.h_hsolo_nnz[hs0]);
+        const double nhs = (double)(hs1 - hs0);
         gl.hsolo = md.d_hsolo_row + hs0;
         gl.nhsolo = hs1 - hs0;
         gl.hsolo_bytes = hnnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + 2 * Rd * fb) +
@@ -335,12 +337,6 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
                          (c.Lstore ? nhs * RP * (RP + 1) / 2 * 4.0 : 0.0);
         gl.hsolo_flops = hnnz * Rd * (Rd + 1) +
                          nhs * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd));
-      } else {
-        gl.hsolo_task = md.d_hsolo_task + hs0;
-        gl.nhsolo_task = hs1 - hs0;
-        gl.hsolo_bytes = hnnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + 2 * Rd * fb) +
-                         nhs * gram_task_elems(RP) * 4.0;
-        gl.hsolo_flops = hnnz * Rd * (Rd + 1);
       }
     }
     hipError_t e = launch_gram(c.fdt, RP, gd, gl, md.d_multi_row + q0, q1 - q0,
@@ -349,7 +345,7 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
     sd.task_base = rt[r0];
     sd.r0 = r0;
     const int64_t nrest = f64 ? r1 - r0 : p1 - p0;
-    sd.rows = f64 ? nullptr : md.d_rest_row + p0;
+    sd.rows = f64 ? nullptr : d_re + p0;
     const double Rd = c.R, nrow = (double)nrest;
     {
       ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
@@ -367,21 +363,6 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
         e = launch_solve_rp<float, uint16_t, float>(RP, sd, nrest, s);
     }
     if (e != hipSuccess) return hip_fail(e, "solve kernel");
-    if (gl.nhsolo_task > 0) {
-      // heavy solo rows solved from the workspace
-      SolveDev sh = sd;
-      sh.rows = md.d_hsolo_row + hs0;
-      const double nh = (double)gl.nhsolo_task;
-      ProfScope ps(c.factor_only ? "cholesky_factor" : "cholesky_solve", s,
-                   nh * gram_task_elems(RP) * (double)gsz + nh * Rd * (double)(gsz + dtype_size(c.fdt)) +
-                       (c.Lstore ? nh * RP * (RP + 1) / 2 * (double)gsz : 0.0),
-                   nh * (Rd * Rd * Rd / 3.0 + (c.factor_only ? 0.0 : 2.0 * Rd * Rd)));
-      if (c.fdt == TT_F32)
-        e = launch_solve_rp<float, float, float>(RP, sh, gl.nhsolo_task, s);
-      else
-        e = launch_solve_rp<float, uint16_t, float>(RP, sh, gl.nhsolo_task, s);
-      if (e != hipSuccess) return hip_fail(e, "solve kernel");
-    }
     if (!f64) {
       e = launch_solo(c.fdt, RP, gd, sd, gl, s);
       if (e != hipSuccess) return hip_fail(e, "fused solve kernel");

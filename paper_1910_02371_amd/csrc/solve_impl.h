@@ -1186,16 +1186,16 @@ static inline unsigned solve_grid(const SolveDev &d) {
 struct GramLists {
   const int32_t *heavy, *light, *solo, *hsolo;
   int64_t nheavy, nlight, nsolo, nhsolo;
-  // heavy solo rows not fused with their solve: their tasks (Gram kernel)
-  const int32_t *hsolo_task;
-  int64_t nhsolo_task;
   double light_bytes, light_flops, heavy_bytes, heavy_flops, solo_bytes, solo_flops,
       hsolo_bytes, hsolo_flops;
 };
 
 // Rows whose only Gram task is heavy are fused with their solve up to this
 // padded rank.
-constexpr int kFuseHeavyMaxRP = 32;
+#ifndef TT_FUSE_HEAVY_MAX_RP
+#define TT_FUSE_HEAVY_MAX_RP 32
+#endif
+constexpr int kFuseHeavyMaxRP = TT_FUSE_HEAVY_MAX_RP;
 
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
 static void launch_solo_rp(const GramDev &d, const SolveDev &sd, const GramLists &gl,
