@@ -897,7 +897,7 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   // workspace: the residual rho = t - model in every mode's sorted order,
   // old and current copies of column r of every factor (dense dtype), and
   // the per-task partial sums of a mode pass
-  void *rho[TT_MAX_ORDER] = {}, *old_v[TT_MAX_ORDER] = {}, *cur_v[TT_MAX_ORDER] = {};
+  void *rho[TT_MAX_ORDER] = {}, *pairs[TT_MAX_ORDER] = {};
   void *vrho = nullptr, *vcol = nullptr, *vpart = nullptr;
   const int64_t m1 = std::max<int64_t>(ix->m, 1);
   int64_t max_task = 1;
@@ -906,21 +906,19 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   TT_ST(ws_get(ix, "ccd_cols", (size_t)2 * (ix->sum_I + N) * vsz, &vcol));
   TT_ST(ws_get(ix, "ccd_part", (size_t)2 * max_task * 8, &vpart));
   {
-    char *c = (char *)vcol;
+    char *c = (char *)vcol;  // each mode's (old, current) pairs, 2 vsz apart
     for (int n = 0; n < N; ++n) {
       rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
-      old_v[n] = c;
-      c += (size_t)(ix->mode[n].I + 1) * vsz;
-      cur_v[n] = c;
-      c += (size_t)(ix->mode[n].I + 1) * vsz;
+      pairs[n] = c;
+      c += (size_t)(ix->mode[n].I + 1) * 2 * vsz;
     }
   }
   for (int n = 0; n < N && ix->m > 0; ++n)
     TT_ST(tttp_mode(ix, n, ix->mode[n].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID, TT_LOSS_LS,
                     rho[n], nullptr, nullptr, nullptr, st));
   for (int r = 0; r < R; ++r)
-    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, old_v, cur_v,
-                                (double *)vpart, d_info, st),
+    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, pairs, (double *)vpart,
+                                d_info, st),
               "ccd column");
   return TT_OK;
 }

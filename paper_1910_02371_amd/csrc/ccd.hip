@@ -6,7 +6,7 @@
 // residual without column r's rank-1 term (old values of all modes).  The
 // residual rho = t - model is kept in every mode's sorted order, so each
 // pass streams its own copy; factor columns are read from contiguous
-// vectors (old and current), which stay in the caches.
+// vectors of (old, current) pairs, which stay in the caches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,15 +16,20 @@
 
 namespace tt {
 
-// Column r of an I x ldA factor into a contiguous vector (widened).
+// Old and current value of one factor column entry, kept side by side so
+// that a gather fetches both from one cache line.
+template <class AT> struct Pair2;
+template <> struct Pair2<float> { using type = float2; };
+template <> struct Pair2<double> { using type = double2; };
+
+// Column r of an I x ldA factor into its (old, current) pair vector.
 template <class T, class AT>
 __global__ void k_ccd_column(const T *__restrict__ A, int64_t ldA, int64_t I, int r,
-                             AT *__restrict__ a, AT *__restrict__ b) {
+                             typename Pair2<AT>::type *__restrict__ pr) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
        i += (int64_t)gridDim.x * blockDim.x) {
     const AT v = (AT)to_double<T>(A[i * ldA + r]);
-    a[i] = v;
-    b[i] = v;
+    pr[i] = {v, v};
   }
 }
 
@@ -35,19 +40,20 @@ template <class AT, class VT>
 __global__ __launch_bounds__(256) void k_ccd_tasks(
     const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ key,
     const int32_t *__restrict__ o0, const int32_t *__restrict__ o1,
-    const VT *__restrict__ rho, const AT *__restrict__ old_n, const AT *__restrict__ cur0,
-    const AT *__restrict__ old0, const AT *__restrict__ cur1, const AT *__restrict__ old1,
-    double *__restrict__ part) {
+    const VT *__restrict__ rho, const typename Pair2<AT>::type *__restrict__ pn,
+    const typename Pair2<AT>::type *__restrict__ p0,
+    const typename Pair2<AT>::type *__restrict__ p1, double *__restrict__ part) {
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= ntask) return;
   const int64_t nb = task[t], ne = task[t + 1];
+  const double own_old = (double)pn[key[nb]].x;  // one row per task
   double num = 0.0, den = 0.0;
   for (int64_t e = nb + lane; e < ne; e += 64) {
-    const int32_t i = key[e], j = o0[e], k = o1[e];
-    const double h = (double)cur0[j] * (double)cur1[k];
-    const double hold = (double)old0[j] * (double)old1[k];
-    const double rhat = (double)rho[e] + (double)old_n[i] * hold;
+    const auto a = p0[o0[e]];
+    const auto b = p1[o1[e]];
+    const double h = (double)a.y * (double)b.y;
+    const double rhat = (double)rho[e] + own_old * ((double)a.x * (double)b.x);
     num = fma(rhat, h, num);
     den = fma(h, h, den);
   }
@@ -65,11 +71,11 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
 // One thread per row: the row's task partials summed in task order, the
 // rank-1 solve (lambda + den) x = num (LAPACK convention: a non-positive
 // pivot gives info 1 and x = 0), x stored into column r of the factor
-// (storage dtype) and, as stored, into the current column vector.
+// (storage dtype) and, as stored, as the current value of the pair vector.
 template <class T, class AT>
 __global__ void k_ccd_rows(const int32_t *__restrict__ row_task, int64_t I,
                            const double *__restrict__ part, double lambda, T *A, int64_t ldA,
-                           int r, AT *__restrict__ cur, int32_t *info) {
+                           int r, typename Pair2<AT>::type *__restrict__ pr, int32_t *info) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
        i += (int64_t)gridDim.x * blockDim.x) {
     double num = 0.0, den = 0.0;
@@ -81,7 +87,7 @@ __global__ void k_ccd_rows(const int32_t *__restrict__ row_task, int64_t I,
     const bool ok = piv > 0.0;
     const T x = from_double<T>(ok ? num / piv : 0.0);
     A[i * ldA + r] = x;
-    cur[i] = (AT)to_double<T>(x);
+    pr[i].y = (AT)to_double<T>(x);
     if (info) info[i] = ok ? 0 : 1;
   }
 }
@@ -90,15 +96,16 @@ __global__ void k_ccd_rows(const int32_t *__restrict__ row_task, int64_t I,
 template <class AT, class VT>
 __global__ void k_ccd_update(int64_t m, const int32_t *__restrict__ key,
                              const int32_t *__restrict__ o0, const int32_t *__restrict__ o1,
-                             VT *__restrict__ rho, const AT *__restrict__ old_n,
-                             const AT *__restrict__ cur_n, const AT *__restrict__ old0,
-                             const AT *__restrict__ cur0, const AT *__restrict__ old1,
-                             const AT *__restrict__ cur1) {
+                             VT *__restrict__ rho, const typename Pair2<AT>::type *__restrict__ pn,
+                             const typename Pair2<AT>::type *__restrict__ p0,
+                             const typename Pair2<AT>::type *__restrict__ p1) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t i = key[e], j = o0[e], k = o1[e];
-    const double told = (double)old_n[i] * (double)old0[j] * (double)old1[k];
-    const double tnew = (double)cur_n[i] * (double)cur0[j] * (double)cur1[k];
+    const auto u = pn[key[e]];
+    const auto a = p0[o0[e]];
+    const auto b = p1[o1[e]];
+    const double told = (double)u.x * (double)a.x * (double)b.x;
+    const double tnew = (double)u.y * (double)a.y * (double)b.y;
     rho[e] = (VT)(((double)rho[e] + told) - tnew);
   }
 }
@@ -110,67 +117,64 @@ static unsigned grid_for_n(int64_t n, int64_t cap = 65536) {
 
 template <class T, class AT, class VT>
 static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                               double lambda, void *const *rho, void *const *old_v,
-                               void *const *cur_v, double *part, int32_t *d_info,
-                               hipStream_t s) {
+                               double lambda, void *const *rho, void *const *pairs,
+                               double *part, int32_t *d_info, hipStream_t s) {
+  using P2 = typename Pair2<AT>::type;
   const int N = ix->N;
   for (int n = 0; n < N; ++n) {
     const ModeIndex &md = ix->mode[n];
-    ProfScope ps("ccd_column", s, (double)md.I * (sizeof(T) + 2 * sizeof(AT)), 0.0);
+    ProfScope ps("ccd_column", s, (double)md.I * (sizeof(T) + sizeof(P2)), 0.0);
     if (md.I > 0)
-      k_ccd_column<T, AT><<<grid_for_n(md.I), 256, 0, s>>>(
-          (const T *)d_A[n], ldA, md.I, r, (AT *)old_v[n], (AT *)cur_v[n]);
+      k_ccd_column<T, AT><<<grid_for_n(md.I), 256, 0, s>>>((const T *)d_A[n], ldA, md.I, r,
+                                                           (P2 *)pairs[n]);
   }
   int64_t off = 0;
   for (int n = 0; n < N; ++n) {
     const ModeIndex &md = ix->mode[n];
-    int p0 = -1, p1 = -1;
+    int q0 = -1, q1 = -1;
     for (int p = 0; p < N; ++p)
-      if (p != n) (p0 < 0 ? p0 : p1) = p;
+      if (p != n) (q0 < 0 ? q0 : q1) = p;
     if (md.ntask > 0) {
-      ProfScope ps("ccd_mode_pass", s, (double)ix->m * (4.0 * 3 + sizeof(VT)),
+      ProfScope ps("ccd_mode_pass", s, (double)ix->m * (4.0 * 2 + sizeof(VT)),
                    (double)ix->m * 8.0);
       k_ccd_tasks<AT, VT><<<(unsigned)((md.ntask + 3) / 4), 256, 0, s>>>(
-          md.d_task, md.ntask, md.d_key, md.d_oidx[p0], md.d_oidx[p1], (const VT *)rho[n],
-          (const AT *)old_v[n], (const AT *)cur_v[p0], (const AT *)old_v[p0],
-          (const AT *)cur_v[p1], (const AT *)old_v[p1], part);
+          md.d_task, md.ntask, md.d_key, md.d_oidx[q0], md.d_oidx[q1], (const VT *)rho[n],
+          (const P2 *)pairs[n], (const P2 *)pairs[q0], (const P2 *)pairs[q1], part);
     }
     ProfScope ps("ccd_rows", s, (double)md.ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),
                  (double)md.ntask * 2);
     if (md.I > 0)
       k_ccd_rows<T, AT><<<grid_for_n(md.I), 256, 0, s>>>(
-          md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r, (AT *)cur_v[n],
+          md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r, (P2 *)pairs[n],
           d_info ? d_info + off : nullptr);
     off += md.I;
   }
   for (int n = 0; n < N; ++n) {
     const ModeIndex &md = ix->mode[n];
     if (ix->m <= 0) break;
-    int p0 = -1, p1 = -1;
+    int q0 = -1, q1 = -1;
     for (int p = 0; p < N; ++p)
-      if (p != n) (p0 < 0 ? p0 : p1) = p;
+      if (p != n) (q0 < 0 ? q0 : q1) = p;
     ProfScope ps("ccd_update", s, (double)ix->m * (4.0 * 3 + 2 * sizeof(VT)),
                  (double)ix->m * 6.0);
     k_ccd_update<AT, VT><<<grid_for_n(ix->m), 256, 0, s>>>(
-        ix->m, md.d_key, md.d_oidx[p0], md.d_oidx[p1], (VT *)rho[n], (const AT *)old_v[n],
-        (const AT *)cur_v[n], (const AT *)old_v[p0], (const AT *)cur_v[p0],
-        (const AT *)old_v[p1], (const AT *)cur_v[p1]);
+        ix->m, md.d_key, md.d_oidx[q0], md.d_oidx[q1], (VT *)rho[n], (const P2 *)pairs[n],
+        (const P2 *)pairs[q0], (const P2 *)pairs[q1]);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                             tt_dtype fdt, double lambda, void *const *rho,
-                             void *const *old_v, void *const *cur_v, double *part,
-                             int32_t *d_info, hipStream_t s) {
+                             tt_dtype fdt, double lambda, void *const *rho, void *const *pairs,
+                             double *part, int32_t *d_info, hipStream_t s) {
   if (fdt == TT_F64)
-    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, old_v, cur_v,
-                                                part, d_info, s);
+    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, pairs, part,
+                                                d_info, s);
   if (fdt == TT_F32)
-    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, old_v, cur_v, part,
-                                             d_info, s);
-  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, old_v, cur_v, part,
-                                              d_info, s);
+    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, pairs, part, d_info,
+                                             s);
+  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, pairs, part, d_info,
+                                              s);
 }
 
 }  // namespace tt

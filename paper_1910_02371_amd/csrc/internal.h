@@ -272,12 +272,12 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
                            int64_t I, int R, hipStream_t s, const double *skip = nullptr);
 // One CCD++ column update (ccd.hip): every mode's column r in turn, then
-// every residual copy; rho[n] = residual in mode n's order, old_v/cur_v[n]
-// = contiguous column vectors (dense dtype), part = 2 x max tasks doubles.
+// every residual copy; rho[n] = residual in mode n's order, pairs[n] =
+// I_n (old, current) pairs of column r (dense dtype, 16-byte aligned),
+// part = 2 x max tasks doubles.
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                             tt_dtype fdt, double lambda, void *const *rho,
-                             void *const *old_v, void *const *cur_v, double *part,
-                             int32_t *d_info, hipStream_t s);
+                             tt_dtype fdt, double lambda, void *const *rho, void *const *pairs,
+                             double *part, int32_t *d_info, hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.
