@@ -558,7 +558,67 @@ def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
     return {"ratings_step_ms": {"plain": plain, "graph": graph, "persistent": pers,
                                 "persistent_graph": pers_graph},
             "cube_als_sweep_ms": {"plain": plain_c, "graph": graph_c,
-                                  "workload": "200^3, 40,000 nonzeros, R = 10, FP64"}}
+                                  "workload": "200^3, 40,000 nonzeros, R = 10, FP64"},
+            "small_gn": small_problem_batching(tt, dev)}
+
+
+def small_problem_batching(tt, dev, reps=10):
+    """Launch-bound sizes: a 3 x 10^5-nonzero random tensor (1000^3, the
+    size of Section 5.6's GN-vs-ALS comparison), rank 10, FP32: one
+    Gauss-Newton step (least squares, lambda = 1e-3, PCG to 5e-3 or 30
+    iterations) and one ALS sweep, launched one by one and replayed as a
+    graph; plus, from the library profiler, the launches of one GN step and
+    the sum of their kernel times (HIP events around each launch)."""
+    import numpy as np
+    import torch
+    from paper_1910_02371_amd import workloads as W
+    wl = W.random_tensor((1000, 1000, 1000), 300_000, W.SEED_DATA + 6, rank=5,
+                         dtype=np.float32)
+    R = 10
+    ix = tt.build_index([torch.as_tensor(i).to(dev) for i in wl.idx], wl.dims,
+                        torch.as_tensor(wl.t).to(dev))
+    ix.reserve(R, tt.TT_F32, gn="ls")
+    A0 = W.init_factors(wl.dims, R, float(np.mean(wl.t)), W.SEED_INIT + 6, dtype=np.float32)
+    A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+    stats = torch.zeros(4, dtype=torch.float64, device=dev)
+    info = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
+
+    def timed_ms(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {"workload": "1000^3, 300,000 uniform nonzeros, R = 10, FP32",
+           "kmax": 30}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for name, fn in (("gn_step_ms", lambda: tt.gn_step(ix, A, "ls", 1e-3, tol=5e-3, kmax=30,
+                                                       stats=stats)),
+                     ("als_sweep_ms", lambda: tt.als_sweep(ix, A, 1e-5, info))):
+        with torch.cuda.stream(side):
+            fn()
+            plain = timed_ms(fn, reps)
+            g = tt.capture(fn)
+            g.launch()
+            graph = timed_ms(g.launch, reps)
+        torch.cuda.current_stream().wait_stream(side)
+        g.close()
+        out[name] = {"plain": plain, "graph": graph}
+    torch.cuda.synchronize()
+    tt.profile_enable(True)
+    tt.gn_step(ix, A, "ls", 1e-3, tol=5e-3, kmax=30, stats=stats)
+    torch.cuda.synchronize()
+    tt.profile_enable(False)
+    prof = tt.profile_report()
+    out["gn_step_launches"] = int(sum(v["launches"] for v in prof.values()))
+    out["gn_step_kernel_ms"] = float(sum(v["ms"] for v in prof.values()))
+    out["pcg_iterations"] = float(stats[0].item())
+    ix.close()
+    return out
 
 
 def compare_forms(tt, ix, A0, wl, R, lam, sweeps, dev, gn_steps=0, lam_gn=1e-3, kmax=30):
