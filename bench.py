@@ -89,6 +89,11 @@ def parse(argv=None):
                         "comparison (0: skip)")
     p.add_argument("--gn-steps", type=int, default=3,
                    help="Gauss-Newton steps after the ALS sweeps of the forms comparison")
+    p.add_argument("--launch-bound", default=None, metavar="CASE:FORM",
+                   help="only time the launch-bound GN step of CASE (small_gn or cube_gn) "
+                        "in FORM (kernel_by_kernel, persistent_wgs1, persistent_wgs2, "
+                        "automatic), launched one by one, and print its JSON (for a kernel "
+                        "trace)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run a plain device copy of this size first (counter calibration)")
     return p.parse_args(argv)
@@ -361,6 +366,12 @@ def main(argv=None):
         torch.cuda.synchronize()
         del xa, xb
 
+    if args.launch_bound:
+        case, form = args.launch_bound.split(":")
+        print(json.dumps(launch_bound_gn(tt, dev, reps=args.steps, cases=(case,),
+                                         forms=(form,), graph=False)), flush=True)
+        return
+
     leg = Leg(tt, W, args.workload, args, R=args.R, form=args.form, tune=args.tune,
               nnz=args.nnz)
     res = leg.measure(args.steps, args.warmup)
@@ -559,29 +570,26 @@ def compare_batching(tt, ix, A, M, R, lam, lam_gn, cg, stats, dev, reps=3):
                                 "persistent_graph": pers_graph},
             "cube_als_sweep_ms": {"plain": plain_c, "graph": graph_c,
                                   "workload": "200^3, 40,000 nonzeros, R = 10, FP64"},
-            "small_gn": small_problem_batching(tt, dev)}
+            "gn_step_ms": launch_bound_gn(tt, dev)}
 
 
-def small_problem_batching(tt, dev, reps=10):
-    """Launch-bound sizes: a 3 x 10^5-nonzero random tensor (1000^3, the
-    size of Section 5.6's GN-vs-ALS comparison), rank 10, FP32: one
-    Gauss-Newton step (least squares, lambda = 1e-3, PCG to 5e-3 or 30
-    iterations) and one ALS sweep, launched one by one and replayed as a
-    graph; plus, from the library profiler, the launches of one GN step and
-    the sum of their kernel times (HIP events around each launch)."""
+LB_FORMS = {"kernel_by_kernel": 0, "persistent_wgs1": 1, "persistent_wgs2": 2, "automatic": -1}
+
+
+def launch_bound_gn(tt, dev, reps=10, kmax=30, cases=("small_gn", "cube_gn"),
+                    forms=tuple(LB_FORMS), graph=True):
+    """Launch-bound sizes: one Gauss-Newton step with kmax CG iterations
+    (tolerance 0, so every step runs all of them) on (a) a 3 x 10^5-nonzero
+    random tensor (1000^3, the size of Section 5.6's GN-vs-ALS comparison),
+    R = 10, FP32, and (b) the 200^3 cube (40,000 nonzeros), R = 10, FP64;
+    launched kernel by kernel, replayed as a graph, and with the CG
+    iterations as one persistent kernel (pcg_wgs = 1 and 2 workgroups per
+    compute unit, and the library's automatic choice; each launched and
+    replayed as a graph); plus one ALS sweep of (a) launched and replayed.
+    Milliseconds per call (HIP events)."""
     import numpy as np
     import torch
     from paper_1910_02371_amd import workloads as W
-    wl = W.random_tensor((1000, 1000, 1000), 300_000, W.SEED_DATA + 6, rank=5,
-                         dtype=np.float32)
-    R = 10
-    ix = tt.build_index([torch.as_tensor(i).to(dev) for i in wl.idx], wl.dims,
-                        torch.as_tensor(wl.t).to(dev))
-    ix.reserve(R, tt.TT_F32, gn="ls")
-    A0 = W.init_factors(wl.dims, R, float(np.mean(wl.t)), W.SEED_INIT + 6, dtype=np.float32)
-    A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
-    stats = torch.zeros(4, dtype=torch.float64, device=dev)
-    info = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
 
     def timed_ms(fn, n):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -592,32 +600,55 @@ def small_problem_batching(tt, dev, reps=10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
-    out = {"workload": "1000^3, 300,000 uniform nonzeros, R = 10, FP32",
-           "kmax": 30}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
-    for name, fn in (("gn_step_ms", lambda: tt.gn_step(ix, A, "ls", 1e-3, tol=5e-3, kmax=30,
-                                                       stats=stats)),
-                     ("als_sweep_ms", lambda: tt.als_sweep(ix, A, 1e-5, info))):
+
+    def plain_and_graph(fn):
         with torch.cuda.stream(side):
             fn()
             plain = timed_ms(fn, reps)
-            g = tt.capture(fn)
-            g.launch()
-            graph = timed_ms(g.launch, reps)
+            if graph:
+                g = tt.capture(fn)
+                g.launch()
+                replay = timed_ms(g.launch, reps)
         torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        if not graph:
+            return plain, None
         g.close()
-        out[name] = {"plain": plain, "graph": graph}
-    torch.cuda.synchronize()
-    tt.profile_enable(True)
-    tt.gn_step(ix, A, "ls", 1e-3, tol=5e-3, kmax=30, stats=stats)
-    torch.cuda.synchronize()
-    tt.profile_enable(False)
-    prof = tt.profile_report()
-    out["gn_step_launches"] = int(sum(v["launches"] for v in prof.values()))
-    out["gn_step_kernel_ms"] = float(sum(v["ms"] for v in prof.values()))
-    out["pcg_iterations"] = float(stats[0].item())
-    ix.close()
+        return plain, replay
+
+    out = {}
+    make = {"small_gn": lambda: ("1000^3, 300,000 uniform nonzeros, R = 10, FP32",
+                                 W.random_tensor((1000, 1000, 1000), 300_000, W.SEED_DATA + 6,
+                                                 rank=5, dtype=np.float32), np.float32,
+                                 tt.TT_F32),
+            "cube_gn": lambda: ("200^3 cube, 40,000 nonzeros, R = 10, FP64", W.cube(),
+                                np.float64, tt.TT_F64)}
+    for name in cases:
+        desc, wl, npdt, fdt = make[name]()
+        R = 10
+        ix = tt.build_index([torch.as_tensor(i).to(dev) for i in wl.idx], wl.dims,
+                            torch.as_tensor(wl.t).to(dev))
+        A0 = W.init_factors(wl.dims, R, float(np.mean(wl.t)), W.SEED_INIT + 6, dtype=npdt)
+        A = [torch.as_tensor(a).to(dev).contiguous() for a in A0]
+        stats = torch.zeros(4, dtype=torch.float64, device=dev)
+        res = {"workload": desc, "kmax": kmax, "tol": 0.0}
+        step = lambda: tt.gn_step(ix, A, "ls", 1e-3, tol=0.0, kmax=kmax, stats=stats)
+        for key in forms:
+            ix.tune(pcg_wgs=LB_FORMS[key])
+            ix.reserve(R, fdt, gn="ls")
+            plain, replay = plain_and_graph(step)
+            res[key] = {"plain": plain, "graph": replay}
+        res["pcg_iterations"] = float(stats[0].item())
+        ix.tune(pcg_wgs=0)
+        if name == "small_gn" and graph:
+            info = torch.empty(sum(wl.dims), dtype=torch.int32, device=dev)
+            ix.reserve(R, fdt)
+            plain, graph = plain_and_graph(lambda: tt.als_sweep(ix, A, 1e-5, info))
+            res["als_sweep_ms"] = {"plain": plain, "graph": graph}
+        ix.close()
+        out[name] = res
     return out
 
 

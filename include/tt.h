@@ -138,10 +138,24 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
  *               1 .. 64: they run as persistent kernels, solve_wgs
  *               workgroups per compute unit, each taking every grid-th row
  *               of the batch in order
+ *   pcg_wgs     0: the conjugate-gradient iterations of tt_gn_step run
+ *               kernel by kernel; 1 .. 16: at ranks up to 16 they run as
+ *               one persistent kernel of pcg_wgs workgroups per compute
+ *               unit (capped so that all are resident at once), the phases
+ *               of an iteration separated by grid-wide barriers, with
+ *               results bit-identical to the kernel-by-kernel loop; -1:
+ *               persistent (two workgroups per compute unit) when each
+ *               streaming phase of the loop fits in one round of that grid
+ *               (launch-bound sizes), kernel by kernel otherwise.  Two
+ *               persistent loops running at the same time on one device may
+ *               not fit together: a loop whose barrier wait exceeds its
+ *               spin bound stops, leaves the factors unchanged and reports
+ *               iterations = -1 and a NaN residual in tt_gn_step's
+ *               statistics
  * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
  * is not capturable, and fails with TT_ERR_INVALID_ARG while an instantiated
  * graph is alive); call tt_index_reserve again afterwards if the
- * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0.
+ * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0, -1.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t chunk;
@@ -149,6 +163,7 @@ typedef struct {
   int32_t gram_light;
   int32_t gram_waves;
   int32_t solve_wgs;
+  int32_t pcg_wgs;
 } tt_tuning;
 tt_status tt_index_tune(tt_index *ix, const tt_tuning *tuning, hipStream_t stream);
 tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out);
@@ -361,15 +376,16 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * earlier in the column contribute their new values) and rhohat the
  * residual t - model without column r's rank-1 term.  The residual is kept
  * in every mode's sorted order (one TTTP pass per mode at the start of the
- * sweep); per column, one pass per mode forms both sums (rhohat from the
- * residual and the column's old entries, on the fly), a rank-1 solve per
- * row (a non-positive pivot gives info 1 and 0, the potrf convention), and
- * one pass per mode moves every residual copy from the old to the new
- * rank-1 term.  Column r of each factor is read from contiguous copies.
- * Factors are updated in place.  Requires t.
+ * sweep); per column, one pass per mode first moves that mode's residual
+ * copy from column r - 1's old to its new rank-1 term and then forms both
+ * sums (rhohat from the residual and the column's old entries, on the
+ * fly), followed by a rank-1 solve per row (a non-positive pivot gives
+ * info 1 and 0, the potrf convention).  Columns r - 1 and r of each factor
+ * are read from contiguous copies.  Factors are updated in place.
+ * Requires t.
  *   d_info          optional int32[sum_n I_n]: the rank-1 solves' info of
  *                   the last column.
- * Workspaces (N m values, 2 (sum_n I_n + N) values, 16 bytes per Gram task)
+ * Workspaces (N m values, 4 (sum_n I_n + N) values, 16 bytes per Gram task)
  * are allocated on first use.
  * ------------------------------------------------------------------------- */
 tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,

@@ -19,6 +19,7 @@ SOURCES = [
     "solve.hip", "solve_fused_f32.hip", "solve_fused_bf16.hip",
     "stream_f32.hip", "stream_bf16.hip", "stream_f64.hip",
     "index.hip", "stream_host.hip", "vec.hip", "ccd.hip", "api.cpp", "noalloc.hip",
+    "pcg_loop_f32.hip", "pcg_loop_bf16.hip", "pcg_loop_f64.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

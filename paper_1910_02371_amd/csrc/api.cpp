@@ -226,6 +226,42 @@ static tt_status mttkrp_impl(tt_index *ix, const void *s, const int32_t *s_perm,
 // the caches when gathered): that pass also accumulates its own block and
 // stores w_e z_e; the other blocks are MTTKRPs of those scalars, read through
 // the index's position map, which gather no direction rows at all.
+// The streaming passes of one Gauss-Newton product Y += J^T diag(w) J X:
+// c[0] the OP_GN pass in zmode's order (it also stores w_e z_e per nonzero
+// in zbuf), c[1..N-1] OP_MTTKRP passes of the other modes reading those
+// scalars through the position map.
+static void gn_passes(tt_index *ix, const void *const *w, double w_const,
+                      const int32_t *const *w_perm, const void *const *d_A,
+                      const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
+                      void *const *d_Y, double *carry, int zm, const int32_t *zmap, void *zbuf,
+                      StreamCall *c) {
+  c[0] = base_call(ix, zm, R, ldA, fdt);
+  for (int p = 0; p < ix->N; ++p) {
+    c[0].A[p] = d_A[p];
+    c[0].X[p] = d_X[p];
+  }
+  c[0].s = w ? w[zm] : nullptr;
+  c[0].s_perm = w_perm ? w_perm[zm] : nullptr;
+  c[0].w_const = w_const;
+  c[0].out = d_Y[zm];
+  c[0].accumulate = 1;
+  c[0].carry = carry;
+  c[0].zout = zbuf;
+  int i = 1;
+  for (int d = 0; d < ix->N; ++d) {
+    if (d == zm) continue;
+    c[i] = base_call(ix, d, R, ldA, fdt);
+    for (int p = 0; p < ix->N; ++p) c[i].A[p] = d_A[p];
+    c[i].s = zbuf;
+    c[i].s_perm = zmap + (int64_t)d * ix->m;
+    c[i].out = d_Y[d];
+    c[i].accumulate = 1;
+    c[i].carry = carry;
+    c[i].prof_name = "gn_mttkrp";
+    ++i;
+  }
+}
+
 static tt_status gn_matvec_impl(tt_index *ix, const void *const *w, double w_const,
                                 const int32_t *const *w_perm, const void *const *d_A,
                                 const void *const *d_X, int R, int64_t ldA, tt_dtype fdt,
@@ -244,34 +280,12 @@ static tt_status gn_matvec_impl(tt_index *ix, const void *const *w, double w_con
                                 dense_of(fdt), st),
               "gn prefill");
   }
-  {
-    StreamCall c = base_call(ix, zm, R, ldA, fdt);
-    for (int p = 0; p < ix->N; ++p) {
-      c.A[p] = d_A[p];
-      c.X[p] = d_X[p];
-    }
-    c.s = w ? w[zm] : nullptr;
-    c.s_perm = w_perm ? w_perm[zm] : nullptr;
-    c.w_const = w_const;
-    c.out = d_Y[zm];
-    c.accumulate = 1;
-    c.carry = carry;
-    c.skip = skip;
-    c.zout = zbuf;
-    TT_LAUNCH(launch_stream(OP_GN, c, st), "gn kernel");
-  }
-  for (int d = 0; d < ix->N; ++d) {
-    if (d == zm) continue;
-    StreamCall c = base_call(ix, d, R, ldA, fdt);
-    for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
-    c.s = zbuf;
-    c.s_perm = zmap + (int64_t)d * ix->m;
-    c.out = d_Y[d];
-    c.accumulate = 1;
-    c.carry = carry;
-    c.skip = skip;
-    c.prof_name = "gn_mttkrp";
-    TT_LAUNCH(launch_stream(OP_MTTKRP, c, st), "gn mttkrp kernel");
+  StreamCall c[TT_MAX_ORDER];
+  gn_passes(ix, w, w_const, w_perm, d_A, d_X, R, ldA, fdt, d_Y, carry, zm, zmap, zbuf, c);
+  for (int i = 0; i < ix->N; ++i) {
+    c[i].skip = skip;
+    TT_LAUNCH(launch_stream(i == 0 ? OP_GN : OP_MTTKRP, c[i], st),
+              i == 0 ? "gn kernel" : "gn mttkrp kernel");
   }
   return TT_OK;
 }
@@ -386,6 +400,7 @@ tt_status tt_index_destroy(tt_index *ix) {
 // Cholesky factors (dense dtype) and, for the Poisson loss, phi'' per mode.
 struct GnWs {
   void *x, *r, *z, *p, *q, *sc, *parts, *w, *L;
+  void *loop_carry, *loop_bar;  // persistent loop only (else NULL)
 };
 
 static tt_status gn_workspace(tt_index *ix, int R, tt_dtype fdt, tt_loss loss, GnWs *ws) {
@@ -403,10 +418,16 @@ static tt_status gn_workspace(tt_index *ix, int R, tt_dtype fdt, tt_loss loss, G
   TT_ST(ws_get(ix, "pcg_p", ntot * dsz, &ws->p));
   TT_ST(ws_get(ix, "pcg_q", ntot * dsz, &ws->q));
   TT_ST(ws_get(ix, "pcg_sc", 32 * 8, &ws->sc));
-  TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 8, &ws->parts));
+  // three sets of dot-product partials (the persistent loop alternates them)
+  TT_ST(ws_get(ix, "pcg_parts", (size_t)dot_parts_needed(ntot) * 3 * 8, &ws->parts));
   TT_ST(ws_get(ix, "pcg_L", (size_t)Ltot * (fdt == TT_F64 ? 8 : 4), &ws->L));
   ws->w = nullptr;
   if (loss == TT_LOSS_POISSON_LOG) TT_ST(ws_get(ix, "pcg_w", (size_t)N * ix->m * dsz, &ws->w));
+  ws->loop_carry = ws->loop_bar = nullptr;
+  if (ix->tune.pcg_wgs != 0 && R <= kPcgMaxRank) {
+    TT_ST(ws_get(ix, "pcg_loop_carry", (size_t)pcg_loop_carry_doubles(ix) * 8, &ws->loop_carry));
+    TT_ST(ws_get(ix, "pcg_loop_bar", (size_t)pcg_loop_bar_words() * 4, &ws->loop_bar));
+  }
   return TT_OK;
 }
 
@@ -459,6 +480,7 @@ tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
            "gram_waves %d is not 2, 4 or 8", t->gram_waves);
   TT_CHECK(t->solve_wgs >= 0 && t->solve_wgs <= 64, "solve_wgs %d outside [0, 64]",
            t->solve_wgs);
+  TT_CHECK(t->pcg_wgs >= -1 && t->pcg_wgs <= 16, "pcg_wgs %d outside [-1, 16]", t->pcg_wgs);
   TT_CHECK(live_graphs() == 0,
            "%d instantiated graph(s) are alive: retuning rebuilds the work partitions "
            "their kernels read; destroy the graphs first", live_graphs());
@@ -864,7 +886,38 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
     Pc[d] = Pb[d];
     Qb[d] = blk(Q, d);
   }
-  for (int k = 0; k < kmax; ++k) {
+  // all iterations in one persistent kernel (same arithmetic), if chosen
+  bool persist = ws.loop_bar != nullptr && kmax > 0 &&
+                 kmax <= pcg_loop_max_iters(ix, ix->tune.pcg_wgs);
+  PcgLoopCall pc;
+  memset(&pc, 0, sizeof(pc));
+  if (persist) {
+    const int32_t *zmap = nullptr;
+    TT_ST(zmap_get(ix, st, &zmap));
+    void *zbuf = nullptr;
+    TT_ST(ws_get(ix, "gn_z", (size_t)std::max<int64_t>(ix->m, 1) * value_size(fdt), &zbuf));
+    gn_passes(ix, loss == TT_LOSS_POISSON_LOG ? w : nullptr, w_const, nullptr, A, Pc, R, ldA,
+              fdt, Qb, nullptr, gn_zmode(ix), zmap, zbuf, pc.pass);
+    pc.wgs_per_cu = ix->tune.pcg_wgs > 0 ? ix->tune.pcg_wgs : 2;
+    if (ix->tune.pcg_wgs < 0) persist = pcg_loop_fits(pc);
+  }
+  if (persist) {
+    pc.carry = (double *)ws.loop_carry;
+    for (int d = 0; d < N; ++d) pc.L[d] = Lb[d];
+    pc.x = X;
+    pc.r = Rv;
+    pc.z = Z;
+    pc.p = P;
+    pc.q = Q;
+    pc.lambda2 = 2.0 * lambda;
+    pc.parts = parts;
+    pc.sc = sc;
+    pc.tol = tol;
+    pc.kmax = kmax;
+    pc.bar = (unsigned *)ws.loop_bar;
+    TT_LAUNCH(launch_pcg_loop(pc, st), "pcg loop");
+  }
+  for (int k = 0; k < (persist ? 0 : kmax); ++k) {
     TT_ST(gn_matvec_impl(ix, loss == TT_LOSS_POISSON_LOG ? w : nullptr, w_const, nullptr, A, Pc,
                          R, ldA, fdt, 2.0 * lambda, Qb, done, st));
     TT_ST(dot(P, Q, 1));
@@ -878,7 +931,9 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dtyp
     TT_LAUNCH(launch_xpby(P, Z, ntot, dn, sc, 0, st), "xpby");
   }
   for (int d = 0; d < N; ++d)
-    TT_LAUNCH(launch_add_to_factor(d_A[d], fdt, ldA, ix->mode[d].I, R, blk(X, d), st), "step");
+    TT_LAUNCH(launch_add_to_factor(d_A[d], fdt, ldA, ix->mode[d].I, R, blk(X, d), st,
+                                   persist ? sc + kPcgAbortSlot : nullptr),
+              "step");
   if (d_stats) TT_LAUNCH(launch_pcg_stats(sc, sc + 10, d_stats, st), "stats");
   return TT_OK;
 }
@@ -895,30 +950,33 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   const size_t vsz = value_size(fdt);
   const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
   // workspace: the residual rho = t - model in every mode's sorted order,
-  // old and current copies of column r of every factor (dense dtype), and
-  // the per-task partial sums of a mode pass
-  void *rho[TT_MAX_ORDER] = {}, *pairs[TT_MAX_ORDER] = {};
+  // old and current copies of columns r - 1 and r of every factor (dense
+  // dtype, two sets used in turn), and the per-task partial sums of a mode
+  // pass
+  void *rho[TT_MAX_ORDER] = {}, *pairs[2][TT_MAX_ORDER] = {};
   void *vrho = nullptr, *vcol = nullptr, *vpart = nullptr;
   const int64_t m1 = std::max<int64_t>(ix->m, 1);
   int64_t max_task = 1;
   for (int n = 0; n < N; ++n) max_task = std::max(max_task, ix->mode[n].ntask);
   TT_ST(ws_get(ix, "ccd_rho", (size_t)N * m1 * vsz, &vrho));
-  TT_ST(ws_get(ix, "ccd_cols", (size_t)2 * (ix->sum_I + N) * vsz, &vcol));
+  TT_ST(ws_get(ix, "ccd_cols", (size_t)2 * 2 * (ix->sum_I + N) * vsz, &vcol));
   TT_ST(ws_get(ix, "ccd_part", (size_t)2 * max_task * 8, &vpart));
   {
     char *c = (char *)vcol;  // each mode's (old, current) pairs, 2 vsz apart
-    for (int n = 0; n < N; ++n) {
-      rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
-      pairs[n] = c;
-      c += (size_t)(ix->mode[n].I + 1) * 2 * vsz;
-    }
+    for (int n = 0; n < N; ++n) rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
+    for (int k = 0; k < 2; ++k)
+      for (int n = 0; n < N; ++n) {
+        pairs[k][n] = c;
+        c += (size_t)(ix->mode[n].I + 1) * 2 * vsz;
+      }
   }
   for (int n = 0; n < N && ix->m > 0; ++n)
     TT_ST(tttp_mode(ix, n, ix->mode[n].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID, TT_LOSS_LS,
                     rho[n], nullptr, nullptr, nullptr, st));
   for (int r = 0; r < R; ++r)
-    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, pairs, (double *)vpart,
-                                d_info, st),
+    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, pairs[r & 1],
+                                r > 0 ? pairs[(r - 1) & 1] : nullptr, (double *)vpart, d_info,
+                                st),
               "ccd column");
   return TT_OK;
 }

@@ -21,6 +21,7 @@ constexpr int kGramPieceDefault = 4096;
 constexpr int kGramLightDefault = 512;
 constexpr int kGramWavesDefault = 4;
 constexpr int kSolveWgsDefault = 0;
+constexpr int kPcgWgsDefault = -1;
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
@@ -107,7 +108,7 @@ struct tt_index {
   std::map<std::string, tt::Buf> ws;         // named workspace buffers
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
   tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
-                    tt::kGramWavesDefault, tt::kSolveWgsDefault};
+                    tt::kGramWavesDefault, tt::kSolveWgsDefault, tt::kPcgWgsDefault};
   int cu_count = 0;  // compute units of the device the index was built on
   // Gauss-Newton position map (built on first use, N x m): slot n != zmode
   // maps mode-n sorted positions to mode-zmode sorted positions
@@ -197,6 +198,38 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s);
 int stream_group_width(tt_dtype fdt, int R);
 int stream_rp(tt_dtype fdt, int R);
 
+// The conjugate-gradient loop of tt_gn_step as one persistent kernel
+// (pcg_loop_impl.h), for R <= kPcgMaxRank.  pass[0] is the OP_GN pass of
+// the Gauss-Newton product and pass[1], pass[2] its OP_MTTKRP passes, set
+// up as gn_matvec sets them up (their carry and skip fields are replaced).
+constexpr int kPcgMaxRank = 16;
+// PCG scalar slot that the persistent loop sets to 1 when a barrier wait
+// gave up (the step is then not applied), 0 otherwise
+constexpr int kPcgAbortSlot = 11;
+struct PcgLoopCall {
+  StreamCall pass[3];
+  double *carry;            // pcg_loop_carry_doubles(ix) doubles
+  const void *L[TT_MAX_ORDER];   // preconditioner factors per mode
+  void *x, *r, *z, *p, *q;  // PCG vectors, dense dtype, modes' blocks in order
+  double lambda2;
+  double *parts;            // 3 x dot_parts_needed(sum_n I_n R) doubles
+  double *sc;               // PCG scalar slots after stage 0
+  double tol;
+  int kmax;
+  unsigned *bar;            // pcg_loop_bar_words() barrier words
+  int wgs_per_cu;
+};
+int64_t pcg_loop_carry_doubles(const tt_index *ix);
+int pcg_loop_bar_words();
+// Largest iteration count one launch can take with wgs_per_cu workgroups
+// per compute unit (its barrier counter must not wrap).
+int64_t pcg_loop_max_iters(const tt_index *ix, int wgs_per_cu);
+hipError_t launch_pcg_loop(const PcgLoopCall &c, hipStream_t s);
+// Automatic choice (pcg_wgs = -1): the persistent loop when every streaming
+// phase fits in one round of a grid of two resident workgroups per compute
+// unit, i.e. the launch-bound sizes where it pays.
+bool pcg_loop_fits(const PcgLoopCall &c);
+
 // MTTKRP after argument checks (api.cpp).  `carry` = NULL takes the carry
 // slots from the index workspace; otherwise `carry` holds this mode's slots
 // (nslot x stream_rp) followed by its heavy-row partials (nseg x stream_rp).
@@ -267,17 +300,18 @@ hipError_t launch_pcg_scalar(double *sc, int stage, double tol, hipStream_t s);
 // stats[0..3] = iterations, final relative residual, initial residual norm, *f0
 hipError_t launch_pcg_stats(const double *sc, const double *f0, double *stats, hipStream_t s);
 hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
-                                const void *dx, hipStream_t s);
+                                const void *dx, hipStream_t s, const double *skip = nullptr);
 // A += D, both I x R in the factor dtype fdt with leading dimensions ldA, ldD.
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
                            int64_t I, int R, hipStream_t s, const double *skip = nullptr);
-// One CCD++ column update (ccd.hip): every mode's column r in turn, then
-// every residual copy; rho[n] = residual in mode n's order, pairs[n] =
-// I_n (old, current) pairs of column r (dense dtype, 16-byte aligned),
-// part = 2 x max tasks doubles.
+// One CCD++ column update (ccd.hip): every mode's column r in turn; rho[n]
+// = residual in mode n's order, pairs[n] = I_n (old, current) pairs of
+// column r (dense dtype), prev[n] = those of column r - 1 (or prev = NULL
+// for the first column): mode n's pass first moves its residual copy from
+// column r - 1's old to its new rank-1 term.  part = 2 x max tasks doubles.
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
                              tt_dtype fdt, double lambda, void *const *rho, void *const *pairs,
-                             double *part, int32_t *d_info, hipStream_t s);
+                             void *const *prev, double *part, int32_t *d_info, hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.

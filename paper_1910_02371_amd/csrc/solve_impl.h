@@ -1111,15 +1111,16 @@ __attribute__((amdgpu_waves_per_eu(RP == 64 ? 2 : 4))) void k_gram_solve_heavy(G
 // dtype MT (FP64 for the FP64 form, FP32 otherwise: they only precondition);
 // they are copied into LDS in that dtype with coalesced loads and both
 // triangular solves run in FP64 from there.
+//
+// apply_row solves one row with one wave (lane = threadIdx.x mod 64) and
+// the wave's own LDS block Lp; a single wave orders its LDS accesses by
+// program order, so only the compiler has to be kept from moving the reads
+// of the copy above its writes.
 template <class MT, int RP>
-__global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore,
-                                                   const void *rhs, void *X, int R,
-                                                   const double *skip) {
+__device__ __forceinline__ void apply_row(const MT *__restrict__ Lstore, const void *rhs,
+                                          void *X, int R, int64_t row, MT *Lp) {
   using P = Packed<RP>;
-  __shared__ MT Lp[P::LDS];
-  if (skip && *skip != 0.0) return;
-  const int lane = threadIdx.x;
-  const int64_t row = blockIdx.x;
+  const int lane = threadIdx.x & 63;
   const MT *L = Lstore + row * (int64_t)P::PS;
   // all loads of the row's factor are issued before the first LDS write
   constexpr int NIT = (P::PS + 63) / 64;
@@ -1135,7 +1136,9 @@ __global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore
     if (q < P::PS) Lp[q] = v[it];
   }
   if (lane == 0) Lp[P::ZERO] = MT(0);
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   const double b = lane < R ? (double)reinterpret_cast<const MT *>(rhs)[row * R + lane] : 0.0;
   const double dg = lane < RP ? (double)Lp[(lane * (lane + 3)) / 2] : 1.0;  // L(i, i)
   const double rdiag = 1.0 / dg;
@@ -1170,6 +1173,15 @@ __global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore
     x = bwd_lds<RP, MT>(Lp, y, rdiag, lane);
   }
   if (lane < R) reinterpret_cast<MT *>(X)[row * R + lane] = (MT)x;
+}
+
+template <class MT, int RP>
+__global__ __launch_bounds__(64) void k_apply_rows(const MT *__restrict__ Lstore,
+                                                   const void *rhs, void *X, int R,
+                                                   const double *skip) {
+  __shared__ MT Lp[Packed<RP>::LDS];
+  if (skip && *skip != 0.0) return;
+  apply_row<MT, RP>(Lstore, rhs, X, R, blockIdx.x, Lp);
 }
 
 // ---------------------------------------------------------------------------

@@ -3,8 +3,10 @@
 // and runs the heavy-row carry reduction after segmented operations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
+#include "pcg_loop.h"
 #include "stream_impl.h"
 
 namespace tt {
@@ -38,11 +40,10 @@ static bool frag_aligned(const void *p, tt_dtype fdt) {
   return ((uintptr_t)p & (fdt == TT_BF16 ? 7u : 15u)) == 0;
 }
 
-hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
+StreamDev stream_dev(StreamOp op, const StreamCall &c, int *vm_out) {
   const tt_index *ix = c.ix;
   const ModeIndex &md = ix->mode[c.mode];
   const int V = frag_elems(c.fdt);
-  const int G = stream_group_width(c.fdt, c.R);
   StreamDev d = {};
   d.chunk = md.d_chunk;
   d.chunk_slot = md.d_chunk_slot;
@@ -82,6 +83,17 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
   d.carry = c.carry;
   d.skip = c.skip;
   d.zout = (op == OP_GN || op == OP_GRAD) ? c.zout : nullptr;
+  *vm_out = vm;
+  return d;
+}
+
+hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
+  const tt_index *ix = c.ix;
+  const ModeIndex &md = ix->mode[c.mode];
+  const int V = frag_elems(c.fdt);
+  const int G = stream_group_width(c.fdt, c.R);
+  int vm = 0;
+  const StreamDev d = stream_dev(op, c, &vm);
   hipError_t e;
   {
     // algorithmic work of this launch (per-nonzero byte model: index
@@ -150,6 +162,109 @@ hipError_t launch_stream(StreamOp op, const StreamCall &c, hipStream_t s) {
     e = hipGetLastError();
   }
   return e;
+}
+
+// Carry slots and heavy-row partials of the three passes side by side (the
+// two MTTKRP passes run in the same phase).
+int64_t pcg_loop_carry_doubles(const tt_index *ix) {
+  int64_t n = 0;
+  for (int d = 0; d < ix->N; ++d) n += (ix->mode[d].nslot + ix->mode[d].nseg) * 64;
+  return std::max<int64_t>(n, 64);
+}
+
+int pcg_loop_bar_words() { return kBarWords; }
+
+// A barrier counter reaches (barriers so far) x (its group size or group
+// count, at most kPcgMaxGrid / kBarGroup): at most 1 + 11 barriers per
+// iteration, kept below 2^31.
+int64_t pcg_loop_max_iters(const tt_index *ix, int wgs_per_cu) {
+  (void)ix;
+  (void)wgs_per_cu;
+  return ((int64_t)1 << 31) / (12 * (kPcgMaxGrid / kBarGroup)) - 1;
+}
+
+// Load mode of the loop: the most general one any of the three passes
+// needs (the loads differ between load modes, the arithmetic does not).
+static int pcg_loop_vm(const PcgLoopCall &c, StreamDev *dev) {
+  int vm = 2;
+  for (int i = 0; i < 3; ++i) {
+    int v = 0;
+    const StreamDev d = stream_dev(i == 0 ? OP_GN : OP_MTTKRP, c.pass[i], &v);
+    if (dev) dev[i] = d;
+    vm = std::min(vm, v);
+  }
+  return vm;
+}
+
+static int pcg_loop_occupancy(const PcgLoopCall &c, int vm) {
+  const tt_dtype fdt = c.pass[0].fdt;
+  const int G = stream_group_width(fdt, c.pass[0].R);
+  if (fdt == TT_F32) return pcg_loop_occupancy_f32(G, vm);
+  if (fdt == TT_BF16) return pcg_loop_occupancy_bf16(G, vm);
+  return pcg_loop_occupancy_f64(G, vm);
+}
+
+bool pcg_loop_fits(const PcgLoopCall &c) {
+  const tt_index *ix = c.pass[0].ix;
+  if (ix->N != 3 || c.pass[0].R > kPcgMaxRank) return false;
+  const int occ = pcg_loop_occupancy(c, pcg_loop_vm(c, nullptr));
+  if (occ < 1) return false;
+  const int64_t grid = (int64_t)std::min(occ, 2) * ix->cu_count;
+  const int64_t gn = ix->mode[c.pass[0].mode].nchunk;
+  const int64_t mt = ix->mode[c.pass[1].mode].nchunk + ix->mode[c.pass[2].mode].nchunk;
+  return gn <= grid && mt <= grid;
+}
+
+hipError_t launch_pcg_loop(const PcgLoopCall &c, hipStream_t s) {
+  const tt_index *ix = c.pass[0].ix;
+  const tt_dtype fdt = c.pass[0].fdt;
+  const int R = c.pass[0].R;
+  if (ix->N != 3 || R > kPcgMaxRank || c.wgs_per_cu < 1) return hipErrorInvalidValue;
+  PcgLoopDev a = {};
+  const int vm = pcg_loop_vm(c, a.pass);
+  double *cb = c.carry;
+  for (int i = 0; i < 3; ++i) {
+    a.pass[i].skip = nullptr;
+    const ModeIndex &md = ix->mode[c.pass[i].mode];
+    a.nchunk[i] = md.nchunk;
+    a.pass[i].carry = cb;
+    cb += md.nslot * 64;
+    a.partial[i] = cb;
+    cb += md.nseg * 64;
+    a.seg[i] = md.d_seg;
+    a.hrow[i] = md.d_heavy_row;
+    a.hseg[i] = md.d_heavy_seg;
+    a.nseg[i] = md.nseg;
+    a.nheavy[i] = md.nheavy;
+  }
+  a.srp = stream_rp(fdt, R);
+  a.rowoff[0] = 0;
+  for (int d = 0; d < 3; ++d) {
+    a.L[d] = c.L[d];
+    a.rowoff[d + 1] = a.rowoff[d] + ix->mode[d].I;
+  }
+  a.x = c.x;
+  a.r = c.r;
+  a.z = c.z;
+  a.p = c.p;
+  a.q = c.q;
+  a.ntot = a.rowoff[3] * R;
+  a.R = R;
+  a.lambda2 = c.lambda2;
+  a.parts = c.parts;
+  a.np = dot_parts_needed(a.ntot);
+  a.sc = c.sc;
+  a.tol = c.tol;
+  a.kmax = c.kmax;
+  a.bar = c.bar;
+  if (c.kmax > pcg_loop_max_iters(ix, c.wgs_per_cu)) return hipErrorInvalidValue;
+  hipError_t e = launch_fill(c.bar, kBarWords, TT_F32, 0.0, s);  // zero words
+  if (e != hipSuccess) return e;
+  const int G = stream_group_width(fdt, R);
+  ProfScope ps("pcg_loop", s, 0.0, 0.0);
+  if (fdt == TT_F32) return launch_pcg_loop_f32(a, G, vm, c.wgs_per_cu, ix->cu_count, s);
+  if (fdt == TT_BF16) return launch_pcg_loop_bf16(a, G, vm, c.wgs_per_cu, ix->cu_count, s);
+  return launch_pcg_loop_f64(a, G, vm, c.wgs_per_cu, ix->cu_count, s);
 }
 
 }  // namespace tt

@@ -65,6 +65,10 @@ struct StreamDev {
                             // OP_GRAD phi''(t_e, m_e)
 };
 
+// Device arguments of a streaming pass and its load mode (the VM parameter
+// of k_stream), as launch_stream sets them up.
+StreamDev stream_dev(StreamOp op, const StreamCall &c, int *vm);
+
 template <class TR, int G, int CHUNK>
 struct StreamSmem {
   using VT = typename TR::VT;
@@ -135,8 +139,13 @@ __device__ __forceinline__ typename TR::VT load_value(const StreamDev &a, int64_
 // fragments masked per element (R not a multiple of V, leading dimension
 // padded to one) with element loads of the dense blocks (row stride R);
 // 2 vector fragments everywhere (R a multiple of V).
+//
+// stream_chunk processes chunk k with the calling workgroup (256 threads)
+// and its LDS block sm; the caller separates two calls on one block with a
+// workgroup barrier.
 template <class TR, int N, int G, int VM, int OP, int CHUNK>
-__global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
+__device__ __forceinline__ void stream_chunk(const StreamDev &a, int64_t k,
+                                             StreamSmem<TR, G, CHUNK> &sm) {
   using T = typename TR::T;
   using VT = typename TR::VT;
   using AT = typename TR::AT;
@@ -147,11 +156,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   constexpr int NO = N - 1;
   constexpr int NG = ST_THREADS / G;
   static_assert(NO <= 2, "order 3 streams");
-  __shared__ StreamSmem<TR, G, CHUNK> sm;
-  if (a.skip && *a.skip != 0.0) return;
 
   const int tid = threadIdx.x;
-  const int64_t k = blockIdx.x;
   const int64_t b = a.chunk[k];
   const int len = (int)(a.chunk[k + 1] - b);
   const int slot = a.chunk_slot[k];
@@ -300,6 +306,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
               reinterpret_cast<VT *>(a.zout)[b + e] =
                   (VT)loss_eval<AT>(EPI_D2PHI, a.loss, (AT)sm.val[e], mval);
           } else if constexpr (OP == OP_GN) {
+            // sums of two products are written as explicit fused
+            // multiply-adds: left to contraction, the compiler may fuse
+            // either product, and differently in different load modes
             AT zz = AT(0);
 #pragma unroll
             for (int j = 0; j < V; ++j) {
@@ -307,9 +316,9 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
               if constexpr (NO == 1) {
                 dh = fx[0][j];
               } else {
-                dh = fx[0][j] * fa[1][j] + fa[0][j] * fx[1][j];
+                dh = fma(fx[0][j], fa[1][j], fa[0][j] * fx[1][j]);
               }
-              zz += xown[j] * h[j] + own[j] * dh;
+              zz += fma(own[j], dh, xown[j] * h[j]);
             }
             const AT z = group_sum<G>(zz);
             const AT wz = (AT)sm.val[e] * z;
@@ -324,7 +333,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
               if constexpr (NO == 1) {
                 dh = fx[0][j];
               } else {
-                dh = fx[0][j] * fa[1][j] + fa[0][j] * fx[1][j];
+                dh = fma(fx[0][j], fa[1][j], fa[0][j] * fx[1][j]);
               }
               acc[j] += sv * dh;
             }
@@ -415,16 +424,20 @@ __global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
   }
 }
 
+template <class TR, int N, int G, int VM, int OP, int CHUNK>
+__global__ __launch_bounds__(ST_THREADS) void k_stream(StreamDev a) {
+  __shared__ StreamSmem<TR, G, CHUNK> sm;
+  if (a.skip && *a.skip != 0.0) return;
+  stream_chunk<TR, N, G, VM, OP, CHUNK>(a, blockIdx.x, sm);
+}
+
 // Heavy rows, first level: each block sums one segment of <= kSegSlots
 // consecutive carry slots (strided over 256/RP partial lanes, then a fixed
 // tree) into an FP64 partial.
-static __global__ __launch_bounds__(256) void k_carry_partial(const int32_t *__restrict__ seg,
-                                                       const double *__restrict__ carry,
-                                                       int RP, double *__restrict__ partial,
-                                                       const double *skip) {
-  __shared__ double part[256];
-  if (skip && *skip != 0.0) return;
-  const int g = blockIdx.x;
+__device__ __forceinline__ void carry_partial_seg(const int32_t *__restrict__ seg,
+                                                  const double *__restrict__ carry, int RP,
+                                                  double *__restrict__ partial, int g,
+                                                  double (&part)[256]) {
   const int tid = threadIdx.x;
   const int lanes = 256 / RP;
   const int r = tid % RP, q = tid / RP;
@@ -440,17 +453,23 @@ static __global__ __launch_bounds__(256) void k_carry_partial(const int32_t *__r
   if (q == 0) partial[(int64_t)g * RP + r] = part[tid];
 }
 
+static __global__ __launch_bounds__(256) void k_carry_partial(const int32_t *__restrict__ seg,
+                                                       const double *__restrict__ carry,
+                                                       int RP, double *__restrict__ partial,
+                                                       const double *skip) {
+  __shared__ double part[256];
+  if (skip && *skip != 0.0) return;
+  carry_partial_seg(seg, carry, RP, partial, blockIdx.x, part);
+}
+
 // Heavy rows, second level: sum the FP64 partials of each heavy row in order
 // (strided over 256/RP partial lanes, then a fixed tree) and store.
 template <class AT>
-__global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__ hrow,
-                                                     const int32_t *__restrict__ hslot,
-                                                     const double *__restrict__ carry,
-                                                     int RP, int R, void *out,
-                                                     int accumulate, const double *skip) {
-  __shared__ double part[256];
-  if (skip && *skip != 0.0) return;
-  const int h = blockIdx.x;
+__device__ __forceinline__ void heavy_fixup_row(const int32_t *__restrict__ hrow,
+                                                const int32_t *__restrict__ hslot,
+                                                const double *__restrict__ carry, int RP, int R,
+                                                void *out, int accumulate, int h,
+                                                double (&part)[256]) {
   const int tid = threadIdx.x;
   const int lanes = 256 / RP;
   const int r = tid % RP, q = tid / RP;
@@ -469,6 +488,17 @@ __global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__
     double v = part[tid];
     *o = accumulate ? (AT)((double)*o + v) : (AT)v;
   }
+}
+
+template <class AT>
+__global__ __launch_bounds__(256) void k_heavy_fixup(const int32_t *__restrict__ hrow,
+                                                     const int32_t *__restrict__ hslot,
+                                                     const double *__restrict__ carry,
+                                                     int RP, int R, void *out,
+                                                     int accumulate, const double *skip) {
+  __shared__ double part[256];
+  if (skip && *skip != 0.0) return;
+  heavy_fixup_row<AT>(hrow, hslot, carry, RP, R, out, accumulate, blockIdx.x, part);
 }
 
 template <class TR, int N, int G, int VM, int CHUNK>

@@ -7,11 +7,9 @@
 
 #include "common.h"
 #include "internal.h"
+#include "vec_impl.h"
 
 namespace tt {
-
-constexpr int VT_THREADS = 256;
-constexpr int RED_BLOCKS = 1024;  // max partials of a two-level reduction
 
 static int grid_cap(int64_t n, int cap) {
   int64_t g = (n + VT_THREADS - 1) / VT_THREADS;
@@ -43,7 +41,7 @@ __global__ void k_scale_rows(YT *y, const XT *x, int64_t ldx, int64_t I, int R, 
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = i / R;
     const int r = (int)(i - row * R);
-    y[i] = (YT)(a * to_double<XT>(x[row * ldx + r]));
+    y[i] = scaled<YT>(a, to_double<XT>(x[row * ldx + r]));
   }
 }
 
@@ -68,26 +66,11 @@ hipError_t launch_scale_rows(void *y, const void *x, tt_dtype xdt, int64_t ldx,
   return hipGetLastError();
 }
 
-// Block-level FP64 sum in a fixed order (wave butterfly, then waves in order).
-__device__ double block_sum_d(double v) {
-  __shared__ double part[VT_THREADS / 64];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < VT_THREADS / 64; ++w) s += part[w];
-  __syncthreads();
-  return s;
-}
-
-__global__ void k_sum_doubles(const double *parts, int64_t n, double *out, int accumulate,
-                              const double *skip) {
+__global__ __launch_bounds__(VT_THREADS) void k_sum_doubles(const double *parts, int64_t n,
+                                                             double *out, int accumulate,
+                                                             const double *skip) {
   if (skip && *skip != 0.0) return;
-  double v = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v += parts[i];
-  const double s = block_sum_d(v);
+  const double s = sum_parts_block(parts, n);
   if (threadIdx.x == 0) *out = accumulate ? *out + s : s;
 }
 
@@ -133,12 +116,9 @@ hipError_t launch_sumsq_rows(const void *A, tt_dtype fdt, int64_t ldA, int64_t I
 }
 
 template <class X>
-__global__ void k_dot_parts(const X *x, const X *y, int64_t n, double *parts) {
-  double v = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    v += (double)x[i] * (double)y[i];
-  const double s = block_sum_d(v);
+__global__ __launch_bounds__(VT_THREADS) void k_dot_parts(const X *x, const X *y, int64_t n,
+                                                          double *parts) {
+  const double s = dot_part_block(x, y, n, blockIdx.x, gridDim.x);
   if (threadIdx.x == 0) parts[blockIdx.x] = s;
 }
 
@@ -155,22 +135,14 @@ hipError_t launch_dot_parts(const void *x, const void *y, int64_t n, tt_dtype de
   return hipGetLastError();
 }
 
-// PCG scalar slots (device doubles).
-enum {
-  SC_RZ = 0, SC_PHP = 1, SC_RR = 2, SC_R0 = 3, SC_RZNEW = 4, SC_DONE = 5,
-  SC_ITERS = 6, SC_ALPHA = 7, SC_BETA = 8, SC_REL = 9
-};
-
 // x += alpha p; r -= alpha q   (skipped once converged)
 template <class X>
 __global__ void k_axpy2(X *x, const X *p, X *r, const X *q, int64_t n, const double *sc) {
   if (sc[SC_DONE] != 0.0) return;
   const double a = sc[SC_ALPHA];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] = (X)((double)x[i] + a * (double)p[i]);
-    r[i] = (X)((double)r[i] - a * (double)q[i]);
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    axpy2_at(x, p, r, q, i, a);
 }
 
 hipError_t launch_axpy2(void *x, const void *p, void *r, const void *q, int64_t n,
@@ -193,7 +165,7 @@ __global__ void k_xpby(X *p, const X *z, int64_t n, const double *sc) {
   const double b = sc[SC_BETA];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = (X)((double)z[i] + b * (double)p[i]);
+    p[i] = xpby_at(p, z, i, b);
 }
 
 hipError_t launch_xpby(void *p, const void *z, int64_t n, tt_dtype dense, const double *sc,
@@ -207,33 +179,9 @@ hipError_t launch_xpby(void *p, const void *z, int64_t n, tt_dtype dense, const 
   return hipGetLastError();
 }
 
-// Scalar steps of PCG.
-//  stage 0 (after z0 = P^{-1} r0, rz = r.z, rr = r.r): r0 = sqrt(rr); done if r0 == 0
-//  stage 1 (after pHp = p.Hp): alpha = rz / pHp
-//  stage 2 (after rr = r.r): rel = sqrt(rr) / r0; iters += 1; done if rel <= tol
-//  stage 3 (after rznew = r.z): beta = rznew / rz; rz = rznew
 __global__ void k_pcg_scalar(double *sc, int stage, double tol) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (stage == 0) {
-    sc[SC_R0] = sqrt(sc[SC_RR]);
-    sc[SC_ITERS] = 0.0;
-    sc[SC_REL] = 1.0;
-    sc[SC_DONE] = (sc[SC_R0] == 0.0) ? 1.0 : 0.0;
-    if (sc[SC_R0] == 0.0) sc[SC_REL] = 0.0;
-    return;
-  }
-  if (sc[SC_DONE] != 0.0) return;
-  if (stage == 1) {
-    sc[SC_ALPHA] = sc[SC_RZ] / sc[SC_PHP];
-  } else if (stage == 2) {
-    const double rel = sqrt(sc[SC_RR]) / sc[SC_R0];
-    sc[SC_REL] = rel;
-    sc[SC_ITERS] += 1.0;
-    if (rel <= tol) sc[SC_DONE] = 1.0;
-  } else if (stage == 3) {
-    sc[SC_BETA] = sc[SC_RZNEW] / sc[SC_RZ];
-    sc[SC_RZ] = sc[SC_RZNEW];
-  }
+  pcg_stage(sc, stage, tol);
 }
 
 hipError_t launch_pcg_scalar(double *sc, int stage, double tol, hipStream_t s) {
@@ -256,7 +204,9 @@ hipError_t launch_pcg_stats(const double *sc, const double *f0, double *stats, h
 
 // A[i, r] += dx[i * R + r]  (storage dtype; bfloat16 rounded to nearest even)
 template <class T, class D>
-__global__ void k_add_to_factor(T *A, int64_t ldA, int64_t I, int R, const D *dx) {
+__global__ void k_add_to_factor(T *A, int64_t ldA, int64_t I, int R, const D *dx,
+                                const double *skip) {
+  if (skip && *skip != 0.0) return;
   const int64_t n = I * R;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -267,19 +217,19 @@ __global__ void k_add_to_factor(T *A, int64_t ldA, int64_t I, int R, const D *dx
 }
 
 hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, int R,
-                                const void *dx, hipStream_t s) {
+                                const void *dx, hipStream_t s, const double *skip) {
   const int64_t n = I * R;
   if (n <= 0) return hipSuccess;
   const int g = grid_cap(n, 8192);
   if (fdt == TT_F64)
     k_add_to_factor<double, double><<<g, VT_THREADS, 0, s>>>((double *)A, ldA, I, R,
-                                                             (const double *)dx);
+                                                             (const double *)dx, skip);
   else if (fdt == TT_F32)
     k_add_to_factor<float, float><<<g, VT_THREADS, 0, s>>>((float *)A, ldA, I, R,
-                                                           (const float *)dx);
+                                                           (const float *)dx, skip);
   else
     k_add_to_factor<uint16_t, float><<<g, VT_THREADS, 0, s>>>((uint16_t *)A, ldA, I, R,
-                                                              (const float *)dx);
+                                                              (const float *)dx, skip);
   return hipGetLastError();
 }
 

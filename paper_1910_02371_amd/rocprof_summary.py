@@ -5,6 +5,12 @@
         <kernel> <workload> <src_hash> <copy_bytes> <out.md> <cmd>
 
 ``stats`` renders the per-kernel table of a ``--kernel-trace --stats`` run.
+``trace`` (``trace <kernel_trace.csv> <last_kernel> <skip> <out.md> <cmd>``)
+cuts a ``--kernel-trace`` run into calls, each ending with a dispatch whose
+name contains ``last_kernel``, drops the first ``skip`` calls (warm-up) and
+reports per call the dispatches, the span from the first start to the last
+end, the summed kernel time, the gaps between consecutive dispatches and
+the dispatches and mean duration of each kernel.
 ``counters`` (``counters <kernel> <workload> <src_hash> <out.md> <cmd> <pmc_dir>...``)
 averages every counter of ``kernel``'s dispatches over one or more ``--pmc``
 runs and records derived utilisation and request-size figures in
@@ -202,6 +208,43 @@ def counters(kernel, workload, src_hash, out_md, cmd, *pmc_dirs):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def trace(csv_path, last_kernel, skip, out_md, cmd):
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    calls, cur = [], []
+    for r in rows:
+        cur.append(r)
+        if last_kernel in r["Kernel_Name"]:
+            calls.append(cur)
+            cur = []
+    calls = calls[int(skip):]
+    if not calls:
+        raise SystemExit(f"no call ends with {last_kernel}")
+    t = lambda r, k: int(r[k])
+    per = []
+    by_name = {}
+    for c in calls:
+        span = t(c[-1], "End_Timestamp") - t(c[0], "Start_Timestamp")
+        busy = sum(t(r, "End_Timestamp") - t(r, "Start_Timestamp") for r in c)
+        gaps = sorted(t(c[i + 1], "Start_Timestamp") - t(c[i], "End_Timestamp")
+                      for i in range(len(c) - 1)) or [0]
+        per.append((len(c), span / 1e3, busy / 1e3, gaps[len(gaps) // 2] / 1e3))
+        for r in c:
+            name = r["Kernel_Name"].split("(")[0]
+            n, d = by_name.get(name, (0, 0))
+            by_name[name] = (n + 1, d + t(r, "End_Timestamp") - t(r, "Start_Timestamp"))
+    k = len(calls)
+    lines = [f"# Kernel trace: {k} calls ending with `{last_kernel}`\n", f"Command: `{cmd}`\n",
+             "| call | dispatches | span us | summed kernel us | median gap us |",
+             "|---|---|---|---|---|"]
+    for i, (n, span, busy, gap) in enumerate(per):
+        lines.append(f"| {i} | {n} | {span:.1f} | {busy:.1f} | {gap:.2f} |")
+    lines += ["", "| kernel | dispatches per call | mean us |", "|---|---|---|"]
+    for name, (n, d) in sorted(by_name.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{name[:90]}` | {n / k:.1f} | {d / n / 1e3:.2f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
@@ -209,5 +252,7 @@ if __name__ == "__main__":
         traffic(*sys.argv[2:10])
     elif sys.argv[1] == "counters":
         counters(*sys.argv[2:])
+    elif sys.argv[1] == "trace":
+        trace(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)

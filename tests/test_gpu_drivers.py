@@ -70,8 +70,10 @@ def test_als_sweep_low_precision_forms(gpu_lib, form):
         del tt_before
 
 
+@pytest.mark.parametrize("pcg", [0, 1])
 @pytest.mark.parametrize("loss", ["ls", "poisson"])
-def test_gn_step_f64_matches_oracle(gpu_lib, loss):
+def test_gn_step_f64_matches_oracle(gpu_lib, loss, pcg):
+    """pcg = 1: the CG iterations run as one persistent kernel."""
     tt = gpu_lib
     wl = W.random_tensor((12, 10, 14), 500, 21, rank=3, noise=0.0)
     R = 4
@@ -81,6 +83,7 @@ def test_gn_step_f64_matches_oracle(gpu_lib, loss):
     mean_model = float(np.mean(t)) if loss == "ls" else float(np.log(np.mean(t) + 1))
     A0 = W.init_factors(wl.dims, R, mean_model, 8, dtype=np.float64)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f64"))
+    ix.tune(pcg_wgs=pcg)
     A = [dev_factor(a, "f64") for a in A0]
     kmax = 30 if loss == "ls" else R
     stats = tt.gn_step(ix, A, loss, lam, tol=5e-3, kmax=kmax)
@@ -169,12 +172,14 @@ def test_cp_loss_autograd(gpu_lib, form):
         assert_close_abs(gd, g[d], gabs, tau, f"CPLoss gradient mode {d}")
 
 
+@pytest.mark.parametrize("pcg", [0, 2])
 @pytest.mark.parametrize("form,loss", [("f64", "ls"), ("f32", "ls"), ("bf16", "poisson")])
-def test_graph_replay_matches_eager(gpu_lib, form, loss):
+def test_graph_replay_matches_eager(gpu_lib, form, loss, pcg):
     """An ALS sweep followed by a Gauss-Newton step, recorded once with
     tt_graph_begin/end and replayed three times (with eager library work and
     host synchronizations between the replays), gives bit-for-bit the
-    factors, PCG statistics and solve info of the same calls run eagerly."""
+    factors, PCG statistics and solve info of the same calls run eagerly;
+    pcg = 2: with the CG iterations as one persistent kernel."""
     tt = gpu_lib
     wl = W.random_tensor((40, 33, 29), 4000, 31, rank=3)
     t = wl.t if loss == "ls" else np.rint(np.asarray(wl.t) * 2.0)
@@ -182,6 +187,7 @@ def test_graph_replay_matches_eager(gpu_lib, form, loss):
     lam = 0.05
     A0 = W.init_factors(wl.dims, R, float(np.mean(t)) + 0.5, W.SEED_INIT + 7, dtype=np.float64)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    ix.tune(pcg_wgs=pcg)
     dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[form]
     ix.reserve(R, tt.fdt_of([torch.empty(1, 1, dtype=dt)]), gn=loss)
 
@@ -215,6 +221,123 @@ def test_graph_replay_matches_eager(gpu_lib, form, loss):
         assert torch.equal(info_e, info_g)
     assert np.isfinite(host(Ag[0])).all()
     g.close()
+
+
+def _skew_tensor(seed):
+    """500 x 80 x 60, 20,000 distinct coordinates, 3,000 of them in mode-0
+    row 7: mode 0 has the most rows, so the Gauss-Newton pass runs in its
+    order and row 7 is cut into streaming pieces whose carries are reduced
+    inside that pass."""
+    rng = np.random.default_rng(seed)
+    dims = (500, 80, 60)
+    plane = 80 * 60
+    k7 = 7 * plane + rng.choice(plane, size=3000, replace=False)
+    rest = rng.choice(500 * plane, size=20000, replace=False)
+    rest = rest[rest // plane != 7][:17000]
+    keys = np.concatenate([k7, rest])
+    idx = [a.astype(np.int32) for a in (keys // plane, (keys // 60) % 80, keys % 60)]
+    return W.Workload("skew", dims, idx, rng.random(keys.size) + 0.5, None)
+
+
+# (tensor, form, loss, R, padded leading dimension or None)
+PCG_CASES = {
+    "cube_f64_ls_R10": ("cube", "f64", "ls", 10, None),
+    "uniform_f32_ls_R10_ld12": ("uniform", "f32", "ls", 10, 12),
+    "skew_f32_poisson_R7": ("skew", "f32", "poisson", 7, None),
+    "skew_f64_ls_R3": ("skew", "f64", "ls", 3, None),
+    "heavy_f32_ls_R4": ("heavy", "f32", "ls", 4, None),
+    "uniform_bf16_poisson_R16": ("uniform", "bf16", "poisson", 16, None),
+}
+
+
+def _pcg_tensor(kind):
+    if kind == "cube":
+        return W.cube()
+    if kind == "skew":
+        return _skew_tensor(44)
+    if kind == "heavy":  # three mode-0 rows of ~5,000 nonzeros (an MTTKRP pass's carries)
+        return W.random_tensor((3, 300, 200), 15000, 2, rank=2, noise=0.0)
+    return W.random_tensor((60, 50, 40), 6000, 43, rank=3)
+
+
+@pytest.mark.parametrize("wgs", [1, 2, -1])
+@pytest.mark.parametrize("case", list(PCG_CASES))
+def test_pcg_loop_matches_launch_by_launch(gpu_lib, case, wgs):
+    """The CG iterations as one persistent kernel (pcg_wgs workgroups per
+    compute unit) give bit-for-bit the factors and PCG statistics of the
+    kernel-by-kernel loop: two Gauss-Newton steps in a row, the first
+    running all its iterations (tolerance not reached), the second stopping
+    at a loose tolerance; heavy rows exercise the carry phases of the GN
+    pass and of the MTTKRP passes, and a padded leading dimension the
+    fragment loads.  wgs = -1 is the automatic choice (persistent at these
+    sizes)."""
+    tt = gpu_lib
+    kind, form, loss, R, ld = PCG_CASES[case]
+    wl = _pcg_tensor(kind)
+    t = np.asarray(wl.t, dtype=np.float64)
+    if loss == "poisson":
+        t = np.rint(2.0 * t)
+    lam = 1e-3 if loss == "ls" else 0.1
+    mean_model = float(np.mean(t)) if loss == "ls" else float(np.log(np.mean(t) + 1))
+    A0 = W.init_factors(wl.dims, R, mean_model, 9, dtype=np.float64)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+
+    def fresh():
+        F = [dev_factor(a, form) for a in A0]
+        if ld is None:
+            return F
+        out = []
+        for a in F:
+            buf = torch.full((a.shape[0], ld), 3.0e4, dtype=a.dtype, device=a.device)
+            buf[:, :R] = a
+            out.append(buf[:, :R])
+        return out
+
+    runs = {}
+    for w in (0, wgs):
+        ix.tune(pcg_wgs=w)
+        F = fresh()
+        st = []
+        for tol, kmax in ((1e-12, 6), (0.3, 30)):
+            st.append(tt.gn_step(ix, F, loss, lam, tol=tol, kmax=kmax).clone())
+            torch.cuda.synchronize()
+        runs[w] = (F, st)
+    (Fp, sp), (Fq, sq) = runs[0], runs[wgs]
+    assert int(sp[0][0].item()) == 6, "first step must run every iteration"
+    assert 1 <= int(sp[1][0].item()) < 30
+    for k in range(2):
+        assert torch.equal(sp[k], sq[k]), f"step {k}: stats {sp[k]} vs {sq[k]}"
+    for d in range(3):
+        assert torch.equal(Fp[d], Fq[d]), f"mode {d}"
+    assert np.isfinite(host(Fq[0])).all()
+
+
+def test_pcg_loop_automatic_choice(gpu_lib):
+    """pcg_wgs = -1 runs the CG loop as one persistent kernel when every
+    streaming phase fits in one round of two workgroups per compute unit
+    (a 6,000-nonzero tensor), and kernel by kernel when the MTTKRP phase has
+    more chunks than that (600,000 nonzeros in 512-nonzero chunks); both
+    runs are bit-identical to the explicit choices."""
+    tt = gpu_lib
+    for m, dims, persistent in ((6000, (60, 50, 40), True), (600_000, (2000, 2000, 2000), False)):
+        wl = W.random_tensor(dims, m, 47, rank=3, dtype=np.float32)
+        ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(wl.t, "f32"))
+        A0 = W.init_factors(wl.dims, 10, float(np.mean(wl.t)), 5, dtype=np.float64)
+        res = {}
+        for w in (-1, 0, 2):
+            ix.tune(pcg_wgs=w, chunk=512)
+            F = [dev_factor(a, "f32") for a in A0]
+            tt.profile_enable(True)
+            st = tt.gn_step(ix, F, "ls", 1e-3, tol=1e-9, kmax=4)
+            torch.cuda.synchronize()
+            tt.profile_enable(False)
+            res[w] = (F, st.clone(), "pcg_loop" in tt.profile_report())
+        assert res[-1][2] == persistent and res[2][2] and not res[0][2]
+        for w in (0, 2):
+            assert torch.equal(res[-1][1], res[w][1])
+            for d in range(3):
+                assert torch.equal(res[-1][0][d], res[w][0][d])
+        ix.close()
 
 
 def test_graph_blocks_workspace_growth_and_retuning(gpu_lib):
