@@ -381,7 +381,7 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * sums (rhohat from the residual and the column's old entries, on the
  * fly), followed by a rank-1 solve per row (a non-positive pivot gives
  * info 1 and 0, the potrf convention).  Columns r - 1 and r of each factor
- * are read from contiguous copies.  Factors are updated in place.
+ * are read from one record per row.  Factors are updated in place.
  * Requires t.
  *   d_info          optional int32[sum_n I_n]: the rank-1 solves' info of
  *                   the last column.

@@ -950,33 +950,30 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   const size_t vsz = value_size(fdt);
   const void *A[TT_MAX_ORDER] = {d_A[0], d_A[1], d_A[2], nullptr};
   // workspace: the residual rho = t - model in every mode's sorted order,
-  // old and current copies of columns r - 1 and r of every factor (dense
-  // dtype, two sets used in turn), and the per-task partial sums of a mode
-  // pass
-  void *rho[TT_MAX_ORDER] = {}, *pairs[2][TT_MAX_ORDER] = {};
-  void *vrho = nullptr, *vcol = nullptr, *vpart = nullptr;
+  // one record per factor row (columns r - 1 and r, dense dtype), and the
+  // per-task partial sums of a mode pass
+  void *rho[TT_MAX_ORDER] = {}, *recs[TT_MAX_ORDER] = {};
+  void *vrho = nullptr, *vrec = nullptr, *vpart = nullptr;
   const int64_t m1 = std::max<int64_t>(ix->m, 1);
   int64_t max_task = 1;
   for (int n = 0; n < N; ++n) max_task = std::max(max_task, ix->mode[n].ntask);
   TT_ST(ws_get(ix, "ccd_rho", (size_t)N * m1 * vsz, &vrho));
-  TT_ST(ws_get(ix, "ccd_cols", (size_t)2 * 2 * (ix->sum_I + N) * vsz, &vcol));
+  TT_ST(ws_get(ix, "ccd_recs", (size_t)4 * (ix->sum_I + N) * vsz, &vrec));
   TT_ST(ws_get(ix, "ccd_part", (size_t)2 * max_task * 8, &vpart));
   {
-    char *c = (char *)vcol;  // each mode's (old, current) pairs, 2 vsz apart
-    for (int n = 0; n < N; ++n) rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
-    for (int k = 0; k < 2; ++k)
-      for (int n = 0; n < N; ++n) {
-        pairs[k][n] = c;
-        c += (size_t)(ix->mode[n].I + 1) * 2 * vsz;
-      }
+    char *c = (char *)vrec;  // each mode's records, 4 vsz each
+    for (int n = 0; n < N; ++n) {
+      rho[n] = (char *)vrho + (size_t)n * m1 * vsz;
+      recs[n] = c;
+      c += (size_t)(ix->mode[n].I + 1) * 4 * vsz;
+    }
   }
   for (int n = 0; n < N && ix->m > 0; ++n)
     TT_ST(tttp_mode(ix, n, ix->mode[n].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID, TT_LOSS_LS,
                     rho[n], nullptr, nullptr, nullptr, st));
   for (int r = 0; r < R; ++r)
-    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, pairs[r & 1],
-                                r > 0 ? pairs[(r - 1) & 1] : nullptr, (double *)vpart, d_info,
-                                st),
+    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, recs, (double *)vpart,
+                                d_info, st),
               "ccd column");
   return TT_OK;
 }

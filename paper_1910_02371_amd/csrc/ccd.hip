@@ -5,13 +5,18 @@
 // values: modes updated earlier in the column are new) and rhohat the
 // residual without column r's rank-1 term (old values of all modes).  The
 // residual rho = t - model is kept in every mode's sorted order, so each
-// pass streams its own copy; factor columns are read from contiguous
-// vectors of (old, current) pairs, which stay in the caches.  Column r - 1
-// leaves every copy to be moved from its old to its new rank-1 term; mode
-// n's pass of column r applies that move to its own copy as it streams it
-// (two sets of pair vectors, columns r - 1 and r), so each column costs one
+// pass streams its own copy.  Column r - 1 leaves every copy to be moved
+// from its old to its new rank-1 term; mode n's pass of column r applies
+// that move to its own copy as it streams it, so each column costs one
 // read-modify-write pass per mode.  After the sweep's last column the
 // copies are stale: the next sweep recomputes them.
+//
+// Factor entries are gathered from one record per row holding column
+// r - 1's old and new value and column r's old and current value: the
+// gathers of a pass hit random rows of the other factors, so each costs a
+// whole cache line, and one record per row fetches the four values with
+// one line (the largest mode's records, 7.7 MB at 480K rows, do not stay
+// in L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,64 +26,79 @@
 
 namespace tt {
 
-// Old and current value of one factor column entry, kept side by side so
-// that a gather fetches both from one cache line.
-template <class AT> struct Pair2;
-template <> struct Pair2<float> { using type = float2; };
-template <> struct Pair2<double> { using type = double2; };
+// (column r - 1 old, column r - 1 new, column r old, column r current)
+template <class AT> struct Rec4;
+template <> struct Rec4<float> { using type = float4; };
+template <> struct Rec4<double> { using type = double4; };
 
-// Column r of an I x ldA factor into its (old, current) pair vector.
+// Start of column r: every record moves its column-r values into the
+// column r - 1 slots and takes column r of the I x ldA factor.
 template <class T, class AT>
 __global__ void k_ccd_column(const T *__restrict__ A, int64_t ldA, int64_t I, int r,
-                             typename Pair2<AT>::type *__restrict__ pr) {
+                             typename Rec4<AT>::type *__restrict__ rec) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I;
        i += (int64_t)gridDim.x * blockDim.x) {
     const AT v = (AT)to_double<T>(A[i * ldA + r]);
-    pr[i] = {v, v};
+    const auto q = rec[i];
+    rec[i] = {q.z, q.w, v, v};
   }
 }
 
 // One wave per Gram task (a piece of <= gram_piece nonzeros of one row):
 // FP64 partial sums of rhohat_e h_e and h_e^2 over the task, lanes striding
-// over its nonzeros, then a fixed butterfly.  With the previous column's
-// pairs (qn, q0, q1 non-NULL) each residual is first moved from that
-// column's old to its new rank-1 term and stored back.
+// over its nonzeros, then a fixed butterfly.  With `move` each residual is
+// first moved from column r - 1's old to its new rank-1 term and stored
+// back.
 template <class AT, class VT>
 __global__ __launch_bounds__(256) void k_ccd_tasks(
     const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ key,
     const int32_t *__restrict__ o0, const int32_t *__restrict__ o1, VT *__restrict__ rho,
-    const typename Pair2<AT>::type *__restrict__ pn,
-    const typename Pair2<AT>::type *__restrict__ p0,
-    const typename Pair2<AT>::type *__restrict__ p1,
-    const typename Pair2<AT>::type *__restrict__ qn,
-    const typename Pair2<AT>::type *__restrict__ q0,
-    const typename Pair2<AT>::type *__restrict__ q1, double *__restrict__ part) {
+    const typename Rec4<AT>::type *__restrict__ rn,
+    const typename Rec4<AT>::type *__restrict__ r0,
+    const typename Rec4<AT>::type *__restrict__ r1, int move, double *__restrict__ part) {
   const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= ntask) return;
   const int64_t nb = task[t], ne = task[t + 1];
-  const int32_t row = key[nb];  // one row per task
-  const double own_old = (double)pn[row].x;
-  const bool move = qn != nullptr;
-  const auto un = move ? qn[row] : typename Pair2<AT>::type{};
+  const auto un = rn[key[nb]];  // one row per task
+  const double own_old = (double)un.z;
+  // each lane takes nonzeros lane, lane + 64, ... in order, U at a time:
+  // all their loads and gathers are issued before the first is used
+  constexpr int U = 4;
+  using R4 = typename Rec4<AT>::type;
   double num = 0.0, den = 0.0;
-  for (int64_t e = nb + lane; e < ne; e += 64) {
-    const int32_t i0 = o0[e], i1 = o1[e];
-    VT r = rho[e];
-    if (move) {
-      const auto a = q0[i0];
-      const auto b = q1[i1];
-      const double told = (double)un.x * (double)a.x * (double)b.x;
-      const double tnew = (double)un.y * (double)a.y * (double)b.y;
-      r = (VT)(((double)r + told) - tnew);
-      rho[e] = r;
+  for (int64_t e0 = nb + lane; e0 < ne; e0 += 64 * U) {
+    int32_t i0[U], i1[U];
+    VT r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + 64 * u < ne ? e0 + 64 * u : nb;  // in range
+      i0[u] = o0[e];
+      i1[u] = o1[e];
+      r[u] = rho[e];
     }
-    const auto a = p0[i0];
-    const auto b = p1[i1];
-    const double h = (double)a.y * (double)b.y;
-    const double rhat = (double)r + own_old * ((double)a.x * (double)b.x);
-    num = fma(rhat, h, num);
-    den = fma(h, h, den);
+    R4 a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      a[u] = r0[i0[u]];
+      b[u] = r1[i1[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + 64 * u;
+      if (e < ne) {
+        if (move) {
+          const double told = (double)un.x * (double)a[u].x * (double)b[u].x;
+          const double tnew = (double)un.y * (double)a[u].y * (double)b[u].y;
+          r[u] = (VT)(((double)r[u] + told) - tnew);
+          rho[e] = r[u];
+        }
+        const double h = (double)a[u].w * (double)b[u].w;
+        const double rhat = (double)r[u] + own_old * ((double)a[u].z * (double)b[u].z);
+        num = fma(rhat, h, num);
+        den = fma(h, h, den);
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -95,12 +115,12 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
 // over the tasks, then a fixed butterfly), the rank-1 solve
 // (lambda + den) x = num (LAPACK convention: a non-positive pivot gives
 // info 1 and x = 0), x stored into column r of the factor (storage dtype)
-// and, as stored, as the current value of the pair vector.
+// and, as stored, as the current value of the record.
 template <class T, class AT>
 __global__ __launch_bounds__(256) void k_ccd_rows(const int32_t *__restrict__ row_task,
                                                   int64_t I, const double *__restrict__ part,
                                                   double lambda, T *A, int64_t ldA, int r,
-                                                  typename Pair2<AT>::type *__restrict__ pr,
+                                                  typename Rec4<AT>::type *__restrict__ rec,
                                                   int32_t *info) {
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < I;
@@ -120,7 +140,7 @@ __global__ __launch_bounds__(256) void k_ccd_rows(const int32_t *__restrict__ ro
       const bool ok = piv > 0.0;
       const T x = from_double<T>(ok ? num / piv : 0.0);
       A[i * ldA + r] = x;
-      pr[i].y = (AT)to_double<T>(x);
+      rec[i].w = (AT)to_double<T>(x);
       if (info) info[i] = ok ? 0 : 1;
     }
   }
@@ -133,17 +153,16 @@ static unsigned grid_for_n(int64_t n, int64_t cap = 65536) {
 
 template <class T, class AT, class VT>
 static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                               double lambda, void *const *rho, void *const *pairs,
-                               void *const *prev, double *part, int32_t *d_info,
-                               hipStream_t s) {
-  using P2 = typename Pair2<AT>::type;
+                               double lambda, void *const *rho, void *const *recs,
+                               double *part, int32_t *d_info, hipStream_t s) {
+  using R4 = typename Rec4<AT>::type;
   const int N = ix->N;
   for (int n = 0; n < N; ++n) {
     const ModeIndex &md = ix->mode[n];
-    ProfScope ps("ccd_column", s, (double)md.I * (sizeof(T) + sizeof(P2)), 0.0);
+    ProfScope ps("ccd_column", s, (double)md.I * (sizeof(T) + 2 * sizeof(R4)), 0.0);
     if (md.I > 0)
       k_ccd_column<T, AT><<<grid_for_n(md.I), 256, 0, s>>>((const T *)d_A[n], ldA, md.I, r,
-                                                           (P2 *)pairs[n]);
+                                                           (R4 *)recs[n]);
   }
   int64_t off = 0;
   for (int n = 0; n < N; ++n) {
@@ -152,20 +171,18 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
     for (int p = 0; p < N; ++p)
       if (p != n) (q0 < 0 ? q0 : q1) = p;
     if (md.ntask > 0) {
-      ProfScope ps("ccd_mode_pass", s,
-                   (double)ix->m * (4.0 * 2 + sizeof(VT) * (prev ? 2 : 1)),
-                   (double)ix->m * (prev ? 14.0 : 8.0));
+      ProfScope ps("ccd_mode_pass", s, (double)ix->m * (4.0 * 2 + sizeof(VT) * (r > 0 ? 2 : 1)),
+                   (double)ix->m * (r > 0 ? 14.0 : 8.0));
       k_ccd_tasks<AT, VT><<<(unsigned)((md.ntask + 3) / 4), 256, 0, s>>>(
           md.d_task, md.ntask, md.d_key, md.d_oidx[q0], md.d_oidx[q1], (VT *)rho[n],
-          (const P2 *)pairs[n], (const P2 *)pairs[q0], (const P2 *)pairs[q1],
-          prev ? (const P2 *)prev[n] : nullptr, prev ? (const P2 *)prev[q0] : nullptr,
-          prev ? (const P2 *)prev[q1] : nullptr, part);
+          (const R4 *)recs[n], (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0,
+          part);
     }
     ProfScope ps("ccd_rows", s, (double)md.ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),
                  (double)md.ntask * 2);
     if (md.I > 0)
       k_ccd_rows<T, AT><<<grid_for_n(64 * md.I, 262144), 256, 0, s>>>(
-          md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r, (P2 *)pairs[n],
+          md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r, (R4 *)recs[n],
           d_info ? d_info + off : nullptr);
     off += md.I;
   }
@@ -173,16 +190,16 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
 }
 
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                             tt_dtype fdt, double lambda, void *const *rho, void *const *pairs,
-                             void *const *prev, double *part, int32_t *d_info, hipStream_t s) {
+                             tt_dtype fdt, double lambda, void *const *rho, void *const *recs,
+                             double *part, int32_t *d_info, hipStream_t s) {
   if (fdt == TT_F64)
-    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, pairs, prev,
-                                                part, d_info, s);
+    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, recs, part,
+                                                d_info, s);
   if (fdt == TT_F32)
-    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, pairs, prev, part,
-                                             d_info, s);
-  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, pairs, prev, part,
-                                              d_info, s);
+    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, recs, part, d_info,
+                                             s);
+  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, recs, part, d_info,
+                                              s);
 }
 
 }  // namespace tt

@@ -305,13 +305,14 @@ hipError_t launch_add_to_factor(void *A, tt_dtype fdt, int64_t ldA, int64_t I, i
 hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_dtype fdt,
                            int64_t I, int R, hipStream_t s, const double *skip = nullptr);
 // One CCD++ column update (ccd.hip): every mode's column r in turn; rho[n]
-// = residual in mode n's order, pairs[n] = I_n (old, current) pairs of
-// column r (dense dtype), prev[n] = those of column r - 1 (or prev = NULL
-// for the first column): mode n's pass first moves its residual copy from
-// column r - 1's old to its new rank-1 term.  part = 2 x max tasks doubles.
+// = residual in mode n's order, recs[n] = I_n records (column r - 1 old,
+// new; column r old, current; dense dtype, aligned to 4 values), carried
+// from column to column: mode n's pass of column r > 0 first moves its
+// residual copy from column r - 1's old to its new rank-1 term.  part =
+// 2 x max tasks doubles.
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
-                             tt_dtype fdt, double lambda, void *const *rho, void *const *pairs,
-                             void *const *prev, double *part, int32_t *d_info, hipStream_t s);
+                             tt_dtype fdt, double lambda, void *const *rho, void *const *recs,
+                             double *part, int32_t *d_info, hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.
