@@ -356,6 +356,8 @@ tt_status tt_als_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * iterations; then A <- A + dx (full step).  Dot products in FP64.  The
  * iteration count runs on the device: convergence sets a device flag that
  * turns the remaining iterations into no-ops, so no host sync is needed.
+ * Depending on the index's tuning (pcg_wgs) the CG iterations run kernel
+ * by kernel or as one persistent kernel; both give the same bits.
  *   d_stats         optional device double[4]: iterations, final relative
  *                   residual, initial residual norm, objective before step.
  * The products use gn_matvec's position map: built on first use (one
