@@ -1008,10 +1008,127 @@ __device__ __forceinline__ void solve_from_acc(const GramDev &g, const SolveDev 
   }
 }
 
+// Rows of the fused least-squares update with k <= KP nonzeros (KP = 16 or
+// 32) at ranks above 32.  With H the k x R matrix of the rows h_e and c the
+// constant weight, (c H^T H + lambda I)^{-1} H^T t = H^T (c H H^T +
+// lambda I)^{-1} t for lambda > 0 (push-through identity), so the row's R x
+// R system reduces to a k x k one.  K = H H^T is formed on the matrix cores
+// from the same exact bf16 splits as the Gram (the contraction now runs
+// over the R columns: lane 16 g + i holds columns 8 g .. 8 g + 7 of h_e,
+// e = 16 I + i, which is its operand K-run for the tiles of row block I),
+// stored in the tile layout, factored and solved by chol_tiles at padded
+// size KP (rows e >= k are the identity), and x = H^T y is summed in FP64
+// from an LDS copy of H.  LDS: K's tiles and then L, the panel buffer and H
+// one after the other inside the RP = 64 solve's Lp.
+template <class TR, int KP, bool VEC>
+__device__ __forceinline__ void solve_pushthrough(const GramDev &g, const SolveDev &d,
+                                                  int64_t row, int64_t nb, int k, int lane,
+                                                  double *lds) {
+  using T = typename TR::T;
+  using XT = typename TR::T;
+  constexpr bool F32 = std::is_same<TR, TrF32>::value;
+  constexpr int PA = F32 ? 3 : 2;
+  using PP = PartPairs<PA, PA>;
+  constexpr int NB = KP / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int kPnOff = Packed<KP>::LDS;
+  constexpr int kHOff = kPnOff + PanelBuf<KP>::SIZE;
+  static_assert(NT * 256 <= 2 * Packed<KP>::PS, "K's tiles fit below Lp[ZERO]");
+  static_assert(kHOff + KP * 32 <= Packed<64>::LDS, "fits the RP = 64 solve's Lp");
+  double *Lp = lds, *Pn = lds + kPnOff;
+  float *Kl = reinterpret_cast<float *>(lds);
+  float *Hl = reinterpret_cast<float *>(lds + kHOff);
+  const T *A0 = reinterpret_cast<const T *>(g.A0);
+  const T *A1 = reinterpret_cast<const T *>(g.A1);
+  const int R = d.R;
+  const uint32_t ldA = (uint32_t)g.ldA;
+  const int gq = lane >> 4, i = lane & 15;
+  // earlier LDS reads (a previous row's, one wave, program order) stay before
+  // these writes
+  asm volatile("" ::: "memory");
+  uint32_t op[NB][2][PA][4];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) {
+    const int e = 16 * I + i;
+    const bool ok = e < k;
+    const int64_t ec = nb + (ok ? e : 0);
+    const uint32_t r0 = (uint32_t)g.oidx0[ec] * ldA, r1 = (uint32_t)g.oidx1[ec] * ldA;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int cb = 32 * s + 8 * gq;
+      float a0[8], a1[8];
+      load_cols<TR, 4, VEC>(A0, r0, cb, R, *reinterpret_cast<float(*)[4]>(a0));
+      load_cols<TR, 4, VEC>(A0, r0, cb + 4, R, *reinterpret_cast<float(*)[4]>(a0 + 4));
+      load_cols<TR, 4, VEC>(A1, r1, cb, R, *reinterpret_cast<float(*)[4]>(a1));
+      load_cols<TR, 4, VEC>(A1, r1, cb + 4, R, *reinterpret_cast<float(*)[4]>(a1 + 4));
+      uint32_t pt[8][PA];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float h = (ok && cb + j < R) ? a0[j] * a1[j] : 0.f;
+        Hl[e * 64 + cb + j] = h;
+        split_bf16<PA>(h, pt[j]);
+      }
+#pragma unroll
+      for (int ii = 0; ii < PA; ++ii)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) op[I][s][ii][w] = pack_bf16(pt[2 * w][ii], pt[2 * w + 1][ii]);
+    }
+  }
+  f32x4 acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int kk = 0; kk < PP::N; ++kk) {
+          const int ia = PP::a(kk), ib = PP::b(kk);
+          const u32x4 wa = {op[I][s][ia][0], op[I][s][ia][1], op[I][s][ia][2], op[I][s][ia][3]};
+          const u32x4 wb = {op[J][s][ib][0], op[J][s][ib][1], op[J][s][ib][2], op[J][s][ib][3]};
+          const int q = I * (I + 1) / 2 + J;
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf16x8, wa), __builtin_bit_cast(bf16x8, wb), acc[q], 0, 0, 0);
+        }
+  // tile (I, J), register v of lane l: K[16 I + 4 (l / 16) + v][16 J + l % 16],
+  // stored row-major in its tile
+  const float c = g.w ? 1.f : (float)g.w_scale;
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Kl[256 * q + 16 * (4 * gq + v) + i] = acc[q][v] * c;
+  asm volatile("" ::: "memory");
+  SolveDev dk = d;
+  dk.R = k;  // rows and columns k .. KP - 1 become the identity
+  double b = lane < k ? (double)g.rhs_t[nb + lane] : 0.0;
+  double rdiag = 1.0;
+  if (lane == 0) Lp[Packed<KP>::ZERO] = 0.0;
+  const int info = chol_tiles<float, KP, true>(dk, Kl, 1, lane, Lp, Pn, rdiag, b);
+  if (d.info && lane == 0) d.info[row] = info;
+  const double y = info == 0 ? bwd_regs<KP>(Lp, b, rdiag, lane) : 0.0;
+  double x = 0.0;
+  for (int e = 0; e < k; ++e) x = fma((double)Hl[e * 64 + lane], readlane_d(y, e), x);
+  if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+}
+
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
 __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev &d, int64_t row,
                                                int lane, double *Lp, double *Pn) {
   const int32_t t = d.row_task[row];
+  if constexpr (RP == 64 && RHS && !WEIGHTED && !FO) {
+    // the least-squares update of a row with at most 32 nonzeros: its k x k
+    // system (uniform over the wave)
+    const int64_t nb = g.task[t], n = g.task[t + 1] - nb;
+    if (d.lambda > 0.0 && d.own == nullptr && n <= 32) {
+      if (n <= 16)
+        solve_pushthrough<TR, 16, VEC>(g, d, row, nb, (int)n, lane, Lp);
+      else
+        solve_pushthrough<TR, 32, VEC>(g, d, row, nb, (int)n, lane, Lp);
+      return;
+    }
+  }
   GramAcc<RP> acc;
   acc.zero();
   gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, g.task[t], g.task[t + 1], acc);

@@ -297,9 +297,10 @@ def solve_factor(ix, w, A, mode, rhs, lam, X=None, info=None, w_order=ORDER_COO,
     fdt = fdt_of(A)
     R, ld = _rank_ld([a for n, a in enumerate(A) if n != mode])
     if X is None:
+        # the library writes X with the factors' leading dimension
         dt = {TT_F64: torch.float64, TT_F32: torch.float32, TT_BF16: torch.bfloat16}[fdt]
-        X = torch.empty((ix.dims[mode], R), dtype=dt, device="cuda")
-        ldx = R
+        X = torch.empty((ix.dims[mode], ld), dtype=dt, device="cuda")[:, :R]
+        ldx = ld
     else:
         ldx = X.stride(0)
         if ldx != ld:

@@ -321,6 +321,53 @@ def test_solve_factor_fused_rhs(gpu_lib, form, R, kind):
             np.testing.assert_allclose(host(X), Xr, rtol=1e-8, atol=1e-10)
 
 
+def _short_rows_tensor(R_counts, seed):
+    """Mode-0 row i holds exactly R_counts[i] nonzeros (distinct coordinates
+    in a 300 x 200 plane); every mode-0 row is one light Gram task."""
+    rng = np.random.default_rng(seed)
+    plane = 300 * 200
+    keys = np.concatenate([i * plane + rng.choice(plane, size=k, replace=False)
+                           for i, k in enumerate(R_counts)])
+    idx = [a.astype(np.int32) for a in (keys // plane, (keys // 200) % 300, keys % 200)]
+    return W.Workload("short_rows", (len(R_counts), 300, 200), idx,
+                      rng.random(keys.size) * 4.0 + 1.0, None)
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("R,ld", [(64, 64), (40, 40), (50, 52)])
+@pytest.mark.parametrize("lam", [0.05, 1e-5])
+def test_solve_factor_short_rows(gpu_lib, form, R, ld, lam):
+    """The fused least-squares update of rows with k <= 32 nonzeros at ranks
+    above 32 solves the k x k system (c H H^T + lambda I) y = t and returns
+    x = H^T y: every row count from 1 to 40 (both sides of 16 and 32),
+    aligned, unaligned and padded factors; x meets the oracle's R x R
+    normal equations (G + lambda I) x = MTTKRP(t) at the FP32 backward
+    error, and (at lambda = 0.05) agrees with the oracle's solution."""
+    tt = gpu_lib
+    counts = list(range(1, 41)) * 2
+    wl = _short_rows_tensor(counts, 71)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(wl.t, form))
+    A64 = factors(wl.dims, R, 900 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    if ld != R:
+        A = [_padded(a, ld) for a in A]
+    s = stored_values(wl.t, form)
+    X, info = tt.solve_factor(ix, None, A, 0, tt.RHS_MTTKRP, lam)
+    assert (info.cpu().numpy() == 0).all()
+    G = O.gram(wl.idx, None, As, 0, wl.dims[0])
+    M = O.mttkrp(wl.idx, s, As, 0, wl.dims[0])
+    tau = {"f32": 1e-5, "bf16": 2e-2}[form]
+    be = backward_error(G, lam, host(X), M)
+    assert be <= tau, f"backward error {be:.3e}"
+    if lam > 1e-3:  # well conditioned: the solutions agree too
+        Xr, _ = O.solve_rows(G, M, lam)
+        err = np.linalg.norm(host(X) - Xr, axis=1) / np.maximum(np.linalg.norm(Xr, axis=1),
+                                                                1e-30)
+        bound = {"f32": 1e-3, "bf16": 5e-2}[form]
+        assert err.max() <= bound, f"forward error {err.max():.3e} (row {err.argmax()})"
+
+
 def test_solve_factor_weights_and_info(gpu_lib):
     tt = gpu_lib
     form = "f64"
