@@ -152,10 +152,20 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
  *               spin bound stops, leaves the factors unchanged and reports
  *               iterations = -1 and a NaN residual in tt_gn_step's
  *               statistics
+ *   ccd_xcd     tt_ccd_sweep's stream layout: 1: each mode's nonzeros are
+ *               regrouped per row by the bucket (8 row ranges of balanced
+ *               nonzero count) of their index in the largest other mode,
+ *               and bucket b's tasks run on workgroups b, b + 8, ...
+ *               (workgroups go to the 8 XCDs in turn, so each XCD's L2
+ *               holds one bucket's column records); 0: the sorted stream;
+ *               -1: the regrouped layout for modes whose largest other
+ *               mode's column records exceed 2 MiB.  Built on first use
+ *               (allocation, synchronization; 16 bytes per nonzero per
+ *               mode); results do not depend on it
  * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
  * is not capturable, and fails with TT_ERR_INVALID_ARG while an instantiated
  * graph is alive); call tt_index_reserve again afterwards if the
- * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0, -1.
+ * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0, -1, -1.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t chunk;
@@ -164,6 +174,7 @@ typedef struct {
   int32_t gram_waves;
   int32_t solve_wgs;
   int32_t pcg_wgs;
+  int32_t ccd_xcd;
 } tt_tuning;
 tt_status tt_index_tune(tt_index *ix, const tt_tuning *tuning, hipStream_t stream);
 tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out);
@@ -383,8 +394,9 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * sums (rhohat from the residual and the column's old entries, on the
  * fly), followed by a rank-1 solve per row (a non-positive pivot gives
  * info 1 and 0, the potrf convention).  Columns r - 1 and r of each factor
- * are read from one record per row.  Factors are updated in place.
- * Requires t.
+ * are read from one record per row.  Depending on the tuning (ccd_xcd) a
+ * mode's pass streams its nonzeros regrouped per XCD bucket (the layout is
+ * built on the first call).  Factors are updated in place.  Requires t.
  *   d_info          optional int32[sum_n I_n]: the rank-1 solves' info of
  *                   the last column.
  * Workspaces (N m values, 4 (sum_n I_n + N) values, 16 bytes per Gram task)

@@ -481,6 +481,7 @@ tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
   TT_CHECK(t->solve_wgs >= 0 && t->solve_wgs <= 64, "solve_wgs %d outside [0, 64]",
            t->solve_wgs);
   TT_CHECK(t->pcg_wgs >= -1 && t->pcg_wgs <= 16, "pcg_wgs %d outside [-1, 16]", t->pcg_wgs);
+  TT_CHECK(t->ccd_xcd >= -1 && t->ccd_xcd <= 1, "ccd_xcd %d outside [-1, 1]", t->ccd_xcd);
   TT_CHECK(live_graphs() == 0,
            "%d instantiated graph(s) are alive: retuning rebuilds the work partitions "
            "their kernels read; destroy the graphs first", live_graphs());
@@ -955,8 +956,12 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   void *rho[TT_MAX_ORDER] = {}, *recs[TT_MAX_ORDER] = {};
   void *vrho = nullptr, *vrec = nullptr, *vpart = nullptr;
   const int64_t m1 = std::max<int64_t>(ix->m, 1);
+  // each mode's stream layout (regrouped per XCD bucket, or the sorted one)
+  const CcdLayout *lay[TT_MAX_ORDER] = {};
+  for (int n = 0; n < N; ++n) TT_ST(ccd_layout_get(ix, n, vsz, st, &lay[n]));
   int64_t max_task = 1;
-  for (int n = 0; n < N; ++n) max_task = std::max(max_task, ix->mode[n].ntask);
+  for (int n = 0; n < N; ++n)
+    max_task = std::max(max_task, lay[n] ? lay[n]->ntask : ix->mode[n].ntask);
   TT_ST(ws_get(ix, "ccd_rho", (size_t)N * m1 * vsz, &vrho));
   TT_ST(ws_get(ix, "ccd_recs", (size_t)4 * (ix->sum_I + N) * vsz, &vrec));
   TT_ST(ws_get(ix, "ccd_part", (size_t)2 * max_task * 8, &vpart));
@@ -970,9 +975,9 @@ tt_status tt_ccd_sweep(tt_index *ix, void *const *d_A, int R, int64_t ldA, tt_dt
   }
   for (int n = 0; n < N && ix->m > 0; ++n)
     TT_ST(tttp_mode(ix, n, ix->mode[n].d_t, nullptr, A, R, ldA, fdt, TT_EPI_RESID, TT_LOSS_LS,
-                    rho[n], nullptr, nullptr, nullptr, st));
+                    rho[n], lay[n] ? lay[n]->d_inv : nullptr, nullptr, nullptr, st));
   for (int r = 0; r < R; ++r)
-    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, recs, (double *)vpart,
+    TT_LAUNCH(launch_ccd_column(ix, r, d_A, ldA, fdt, lambda, rho, recs, lay, (double *)vpart,
                                 d_info, st),
               "ccd column");
   return TT_OK;

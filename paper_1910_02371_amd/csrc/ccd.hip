@@ -16,7 +16,10 @@
 // gathers of a pass hit random rows of the other factors, so each costs a
 // whole cache line, and one record per row fetches the four values with
 // one line (the largest mode's records, 7.7 MB at 480K rows, do not stay
-// in L2).
+// in L2).  With the CCD++ layout of a mode (tuning ccd_xcd) its pass runs
+// over the stream regrouped by bucket of the largest other mode's index,
+// and each XCD only gathers the records of its bucket's rows, which fit its
+// L2; the residual copy of that mode follows the layout's order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,35 +47,42 @@ __global__ void k_ccd_column(const T *__restrict__ A, int64_t ldA, int64_t I, in
   }
 }
 
-// One wave per Gram task (a piece of <= gram_piece nonzeros of one row):
-// FP64 partial sums of rhohat_e h_e and h_e^2 over the task, lanes striding
-// over its nonzeros, then a fixed butterfly.  With `move` each residual is
-// first moved from column r - 1's old to its new rank-1 term and stored
-// back.
-template <class AT, class VT>
+// One group of GL lanes (GL = 64: a wave) per Gram task (a piece of <=
+// gram_piece nonzeros of one row): FP64 partial sums of rhohat_e h_e and
+// h_e^2 over the task, lanes striding over its nonzeros, then a fixed
+// butterfly.  With `move` each residual is first moved from column r - 1's
+// old to its new rank-1 term and stored back.  (A task per quarter wave was
+// measured slower on short rows: the passes are bound by the gathers'
+// cache-line transfers, not by the number of waves.)
+template <class AT, class VT, int GL>
 __global__ __launch_bounds__(256) void k_ccd_tasks(
-    const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ key,
-    const int32_t *__restrict__ o0, const int32_t *__restrict__ o1, VT *__restrict__ rho,
+    const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ sched,
+    const int32_t *__restrict__ key, const int32_t *__restrict__ o0,
+    const int32_t *__restrict__ o1, VT *__restrict__ rho,
     const typename Rec4<AT>::type *__restrict__ rn,
     const typename Rec4<AT>::type *__restrict__ r0,
     const typename Rec4<AT>::type *__restrict__ r1, int move, double *__restrict__ part) {
-  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (t >= ntask) return;
-  const int64_t nb = task[t], ne = task[t + 1];
-  const auto un = rn[key[nb]];  // one row per task
+  // group q of workgroup j takes task (256 / GL) j + q, or the one the
+  // schedule gives
+  const int64_t slot = (int64_t)blockIdx.x * (256 / GL) + (threadIdx.x / GL);
+  const int64_t t = sched ? (int64_t)sched[slot] : slot;
+  const int lane = threadIdx.x % GL;
+  // (no early return: every lane of the wave takes part in the butterfly)
+  const bool live = t >= 0 && t < ntask;
+  const int64_t nb = live ? task[t] : 0, ne = live ? task[t + 1] : 0;
+  const auto un = live ? rn[key[nb]] : typename Rec4<AT>::type{};  // one row per task
   const double own_old = (double)un.z;
-  // each lane takes nonzeros lane, lane + 64, ... in order, U at a time:
+  // each lane takes nonzeros lane, lane + GL, ... in order, U at a time:
   // all their loads and gathers are issued before the first is used
   constexpr int U = 4;
   using R4 = typename Rec4<AT>::type;
   double num = 0.0, den = 0.0;
-  for (int64_t e0 = nb + lane; e0 < ne; e0 += 64 * U) {
+  for (int64_t e0 = nb + lane; e0 < ne; e0 += GL * U) {
     int32_t i0[U], i1[U];
     VT r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + 64 * u < ne ? e0 + 64 * u : nb;  // in range
+      const int64_t e = e0 + GL * u < ne ? e0 + GL * u : nb;  // in range
       i0[u] = o0[e];
       i1[u] = o1[e];
       r[u] = rho[e];
@@ -85,7 +95,7 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t e = e0 + 64 * u;
+      const int64_t e = e0 + GL * u;
       if (e < ne) {
         if (move) {
           const double told = (double)un.x * (double)a[u].x * (double)b[u].x;
@@ -101,11 +111,11 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
     }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int o = GL / 2; o > 0; o >>= 1) {
     num += __shfl_xor(num, o);
     den += __shfl_xor(den, o);
   }
-  if (lane == 0) {
+  if (live && lane == 0) {
     part[2 * t] = num;
     part[2 * t + 1] = den;
   }
@@ -154,7 +164,8 @@ static unsigned grid_for_n(int64_t n, int64_t cap = 65536) {
 template <class T, class AT, class VT>
 static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
                                double lambda, void *const *rho, void *const *recs,
-                               double *part, int32_t *d_info, hipStream_t s) {
+                               const CcdLayout *const *lay, double *part, int32_t *d_info,
+                               hipStream_t s) {
   using R4 = typename Rec4<AT>::type;
   const int N = ix->N;
   for (int n = 0; n < N; ++n) {
@@ -170,20 +181,31 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
     int q0 = -1, q1 = -1;
     for (int p = 0; p < N; ++p)
       if (p != n) (q0 < 0 ? q0 : q1) = p;
-    if (md.ntask > 0) {
+    // the mode's own stream and tasks, or its CCD++ layout
+    const CcdLayout *L = lay ? lay[n] : nullptr;
+    const int64_t ntask = L ? L->ntask : md.ntask;
+    if (ntask > 0) {
       ProfScope ps("ccd_mode_pass", s, (double)ix->m * (4.0 * 2 + sizeof(VT) * (r > 0 ? 2 : 1)),
                    (double)ix->m * (r > 0 ? 14.0 : 8.0));
-      k_ccd_tasks<AT, VT><<<(unsigned)((md.ntask + 3) / 4), 256, 0, s>>>(
-          md.d_task, md.ntask, md.d_key, md.d_oidx[q0], md.d_oidx[q1], (VT *)rho[n],
-          (const R4 *)recs[n], (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0,
-          part);
+      const int32_t *key = L ? L->d_key : md.d_key;
+      const int32_t *a0 = L ? L->d_oidx[q0] : md.d_oidx[q0];
+      const int32_t *a1 = L ? L->d_oidx[q1] : md.d_oidx[q1];
+      if (L) {  // the layout's schedule: one wave per task, four per workgroup
+        k_ccd_tasks<AT, VT, 64><<<(unsigned)L->nsched, 256, 0, s>>>(
+            L->d_task, ntask, L->d_sched, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n],
+            (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0, part);
+      } else {
+        k_ccd_tasks<AT, VT, 64><<<(unsigned)((ntask + 3) / 4), 256, 0, s>>>(
+            md.d_task, ntask, nullptr, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n],
+            (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0, part);
+      }
     }
-    ProfScope ps("ccd_rows", s, (double)md.ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),
-                 (double)md.ntask * 2);
+    ProfScope ps("ccd_rows", s, (double)ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),
+                 (double)ntask * 2);
     if (md.I > 0)
       k_ccd_rows<T, AT><<<grid_for_n(64 * md.I, 262144), 256, 0, s>>>(
-          md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r, (R4 *)recs[n],
-          d_info ? d_info + off : nullptr);
+          L ? L->d_row_task : md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r,
+          (R4 *)recs[n], d_info ? d_info + off : nullptr);
     off += md.I;
   }
   return hipGetLastError();
@@ -191,15 +213,16 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
 
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
                              tt_dtype fdt, double lambda, void *const *rho, void *const *recs,
-                             double *part, int32_t *d_info, hipStream_t s) {
+                             const CcdLayout *const *lay, double *part, int32_t *d_info,
+                             hipStream_t s) {
   if (fdt == TT_F64)
-    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, recs, part,
+    return ccd_column_t<double, double, double>(ix, r, d_A, ldA, lambda, rho, recs, lay, part,
                                                 d_info, s);
   if (fdt == TT_F32)
-    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, recs, part, d_info,
-                                             s);
-  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, recs, part, d_info,
-                                              s);
+    return ccd_column_t<float, float, float>(ix, r, d_A, ldA, lambda, rho, recs, lay, part,
+                                             d_info, s);
+  return ccd_column_t<uint16_t, float, float>(ix, r, d_A, ldA, lambda, rho, recs, lay, part,
+                                              d_info, s);
 }
 
 }  // namespace tt

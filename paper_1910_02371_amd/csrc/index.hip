@@ -261,7 +261,40 @@ __global__ void k_inv_perm(const int32_t *__restrict__ perm, int64_t m,
 }
 
 // ---------------------------------------------------------------------------
-static int grid_for(int64_t n, int threads, int cap = 65536) {
+static int grid_for(int64_t n, int threads, int cap = 65536);
+
+// Stable LSD radix sort of the m keys in kA (all below `range`) with their
+// input positions: on return *kout / *vout point at the sorted keys and the
+// input position of each (each is one of kA/kB, vA/vB; all four hold m
+// words).  hist and offs hold ceil(m / RS_TILE) * RS_BINS words, tmp
+// scan_tmp_words of that.
+static hipError_t radix_sort_positions(uint32_t *kA, uint32_t *kB, uint32_t *vA, uint32_t *vB,
+                                       int64_t m, int64_t range, uint32_t *hist,
+                                       uint32_t *offs, uint32_t *tmp, hipStream_t s,
+                                       uint32_t **kout, uint32_t **vout) {
+  const int64_t nblocks = std::max<int64_t>(1, (m + RS_TILE - 1) / RS_TILE);
+  const int64_t hn = nblocks * RS_BINS;
+  int bits = 0;
+  while (bits < 31 && ((int64_t)1 << bits) < range) ++bits;
+  const int passes = (bits + RS_BITS - 1) / RS_BITS;
+  uint32_t *kc = kA, *vc = vA, *kn = kB, *vn = vB;
+  hipError_t he = hipSuccess;
+  if (passes == 0) k_iota_u32<<<grid_for(m, 256), 256, 0, s>>>(vc, m);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * RS_BITS;
+    k_rs_hist<<<nblocks, RS_THREADS, 0, s>>>(kc, m, shift, nblocks, hist);
+    if ((he = exscan_u32(hist, offs, hn, tmp, s)) != hipSuccess) return he;
+    k_rs_scatter<<<nblocks, RS_THREADS, 0, s>>>(kc, vc, kn, vn, m, shift, nblocks, offs,
+                                                p == 0);
+    std::swap(kc, kn);
+    std::swap(vc, vn);
+  }
+  *kout = kc;
+  *vout = vc;
+  return hipGetLastError();
+}
+
+static int grid_for(int64_t n, int threads, int cap) {
   int64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
   if (g > cap) g = cap;
@@ -306,6 +339,21 @@ static tt_status upload(std::vector<void *> &list, X **p, const std::vector<X> &
   return TT_OK;
 }
 
+// Device array of `count` elements recorded in `list` (freed by the caller).
+template <class X>
+static tt_status dev_alloc_list(std::vector<void *> &list, X **p, int64_t count) {
+  void *q = nullptr;
+  const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(X);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return TT_ERR_OOM;
+  }
+  list.push_back(q);
+  *p = (X *)q;
+  return TT_OK;
+}
+
 static void partitions(const std::vector<int64_t> &ptr, ModeIndex &md, int64_t kChunk,
                        int64_t kGramPiece, std::vector<int64_t> &chunk,
                        std::vector<int32_t> &slot, std::vector<int32_t> &heavy_row,
@@ -323,6 +371,7 @@ tt_status build_partitions(tt_index *ix, int n, hipStream_t s) {
     for (void *q : md.part) hipFree(q);
     md.part.clear();
   }
+  md.ccd = CcdLayout{};  // its arrays were in `part`; rebuilt on next use
   std::vector<int64_t> chunk, task;
   std::vector<int32_t> slot, hrow, hslot, rows, row_task;
   partitions(md.h_ptr, md, ix->tune.chunk, ix->tune.gram_piece, chunk, slot, hrow, hslot, rows,
@@ -543,23 +592,10 @@ tt_status build_index_impl(int N, const int64_t *dims, int64_t m,
   for (int n = 0; n < N && st == TT_OK; ++n) {
     ModeIndex &md = ix->mode[n];
     md.I = dims[n];
-    int bits = 0;
-    while (bits < 31 && ((int64_t)1 << bits) < dims[n]) ++bits;
-    int passes = (bits + RS_BITS - 1) / RS_BITS;
-    uint32_t *kc = kA, *vc = vA, *kn = kB, *vn = vB;
+    uint32_t *kc = kA, *vc = vA;
     if (m > 0) {
-      k_copy_u32<<<grid_for(m, 256), 256, 0, s>>>(d_idx[n], m, kc);
-      if (passes == 0) k_iota_u32<<<grid_for(m, 256), 256, 0, s>>>(vc, m);
-      for (int p = 0; p < passes; ++p) {
-        int shift = p * RS_BITS;
-        k_rs_hist<<<nblocks, RS_THREADS, 0, s>>>(kc, m, shift, nblocks, hist);
-        if ((he = exscan_u32(hist, offs, hn, tmp, s)) != hipSuccess) break;
-        k_rs_scatter<<<nblocks, RS_THREADS, 0, s>>>(kc, vc, kn, vn, m, shift, nblocks,
-                                                    offs, p == 0);
-        std::swap(kc, kn);
-        std::swap(vc, vn);
-      }
-      if (he == hipSuccess) he = hipGetLastError();
+      k_copy_u32<<<grid_for(m, 256), 256, 0, s>>>(d_idx[n], m, kA);
+      he = radix_sort_positions(kA, kB, vA, vB, m, dims[n], hist, offs, tmp, s, &kc, &vc);
       if (he != hipSuccess) { st = hip_fail(he, "radix sort"); break; }
     }
     // persistent per-mode arrays
@@ -630,6 +666,149 @@ int gn_zmode(const tt_index *ix) {
   for (int n = 1; n < ix->N; ++n)
     if (ix->mode[n].I > ix->mode[b].I) b = n;
   return b;
+}
+
+// Composite sort key of the CCD++ layout: row * kCcdBuckets + the bucket of
+// the nonzero's index in the bucketed mode (bucket b holds rows
+// [b[b], b[b + 1])).
+struct CcdBounds {
+  int32_t b[kCcdBuckets + 1];
+};
+__global__ void k_ccd_composite(const int32_t *__restrict__ key, const int32_t *__restrict__ big,
+                                int64_t m, CcdBounds bnd, uint32_t *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < m; i += stride) {
+    const int32_t v = big[i];
+    uint32_t b = 0;
+#pragma unroll
+    for (int q = 1; q < kCcdBuckets; ++q) b += v >= bnd.b[q] ? 1u : 0u;
+    out[i] = (uint32_t)key[i] * kCcdBuckets + b;
+  }
+}
+
+tt_status ccd_layout_get(tt_index *ix, int n, size_t vsz, hipStream_t s,
+                         const CcdLayout **out) {
+  *out = nullptr;
+  ModeIndex &md = ix->mode[n];
+  int big = -1;
+  for (int p = 0; p < ix->N; ++p)
+    if (p != n && (big < 0 || ix->mode[p].I > ix->mode[big].I)) big = p;
+  const int mode = ix->tune.ccd_xcd;
+  const int64_t IB = big < 0 ? 0 : ix->mode[big].I;
+  const bool want = mode == 1 ? IB >= kCcdBuckets
+                              : (mode < 0 && (double)IB * 4.0 * (double)vsz > 2.0 * (1 << 20));
+  if (!want || ix->m <= 0 || (double)md.I * kCcdBuckets >= 2147483647.0) return TT_OK;
+  if (md.ccd.built) {
+    *out = &md.ccd;
+    return TT_OK;
+  }
+  const int64_t m = ix->m;
+  // bucket boundaries: row ranges of mode `big` with balanced nonzero counts
+  CcdLayout L;
+  L.big = big;
+  {
+    const std::vector<int64_t> &hp = ix->mode[big].h_ptr;
+    L.bnd[0] = 0;
+    int64_t r = 0;
+    for (int b = 1; b < kCcdBuckets; ++b) {
+      const int64_t target = m * b / kCcdBuckets;
+      while (r < IB && hp[r] < target) ++r;
+      L.bnd[b] = (int32_t)r;
+    }
+    L.bnd[kCcdBuckets] = (int32_t)IB;
+  }
+  CcdBounds cb;
+  for (int b = 0; b <= kCcdBuckets; ++b) cb.b[b] = L.bnd[b];
+  // stable sort of the sorted stream by (row, bucket)
+  const int64_t nblocks = std::max<int64_t>(1, (m + RS_TILE - 1) / RS_TILE);
+  const int64_t hn = nblocks * RS_BINS;
+  const int64_t nseg = md.I * kCcdBuckets;
+  uint32_t *kA = nullptr, *kB = nullptr, *vA = nullptr, *vB = nullptr, *hist = nullptr,
+           *offs = nullptr, *tmp = nullptr;
+  int64_t *segptr = nullptr;
+  hipError_t he = hipSuccess;
+  auto alloc_tmp = [&](void **p, size_t bytes) -> bool {
+    he = hipMalloc(p, bytes);
+    return he == hipSuccess;
+  };
+  auto free_tmp = [&]() {
+    hipFree(kA); hipFree(kB); hipFree(vA); hipFree(vB);
+    hipFree(hist); hipFree(offs); hipFree(tmp); hipFree(segptr);
+  };
+  if (!(alloc_tmp((void **)&kA, m * 4) && alloc_tmp((void **)&kB, m * 4) &&
+        alloc_tmp((void **)&vA, m * 4) && alloc_tmp((void **)&vB, m * 4) &&
+        alloc_tmp((void **)&hist, hn * 4) && alloc_tmp((void **)&offs, hn * 4) &&
+        alloc_tmp((void **)&tmp, scan_tmp_words(hn) * 4) &&
+        alloc_tmp((void **)&segptr, (nseg + 1) * 8))) {
+    free_tmp();
+    set_error("CCD++ layout: temporary allocation failed: %s", hipGetErrorString(he));
+    return TT_ERR_OOM;
+  }
+  uint32_t *kc = nullptr, *vc = nullptr;
+  k_ccd_composite<<<grid_for(m, 256), 256, 0, s>>>(md.d_key, md.d_oidx[big], m, cb, kA);
+  he = radix_sort_positions(kA, kB, vA, vB, m, nseg, hist, offs, tmp, s, &kc, &vc);
+  if (he == hipSuccess) {
+    k_row_ptr<<<grid_for(nseg + 1, 256, 1 << 30), 256, 0, s>>>(kc, m, nseg, segptr);
+    he = hipGetLastError();
+  }
+  std::vector<int64_t> hseg(nseg + 1);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(hseg.data(), segptr, (nseg + 1) * 8, hipMemcpyDeviceToHost, s);
+  tt_status st = he == hipSuccess ? TT_OK : hip_fail(he, "CCD++ layout sort");
+  // the streams in the new order (vc: new position -> sorted position)
+  std::vector<void *> &P = md.part;
+  if (st == TT_OK) st = dev_alloc_list(P, &L.d_key, m);
+  if (st == TT_OK) st = dev_alloc_list(P, &L.d_inv, m);
+  for (int p = 0; p < ix->N && st == TT_OK; ++p)
+    if (p != n) st = dev_alloc_list(P, &L.d_oidx[p], m);
+  if (st == TT_OK) {
+    k_gather_i32<<<grid_for(m, 256), 256, 0, s>>>(md.d_key, vc, m, L.d_key);
+    for (int p = 0; p < ix->N; ++p)
+      if (p != n)
+        k_gather_i32<<<grid_for(m, 256), 256, 0, s>>>(md.d_oidx[p], vc, m, L.d_oidx[p]);
+    k_inv_perm<<<grid_for(m, 256), 256, 0, s>>>(reinterpret_cast<const int32_t *>(vc), m,
+                                                 L.d_inv);
+    he = hipGetLastError();
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) st = hip_fail(he, "CCD++ layout streams");
+  }
+  if (st != TT_OK) hipStreamSynchronize(s);
+  free_tmp();
+  if (st != TT_OK) return st;
+  // tasks: every (row, bucket) segment cut into pieces of <= gram_piece;
+  // bucket b's tasks go to workgroups b, b + kCcdBuckets, ... (4 each)
+  const int64_t piece = ix->tune.gram_piece;
+  std::vector<int64_t> task{0};
+  std::vector<int32_t> row_task(md.I + 1, 0);
+  std::vector<std::vector<int32_t>> per(kCcdBuckets);
+  for (int64_t r = 0; r < md.I; ++r) {
+    row_task[r] = (int32_t)(task.size() - 1);
+    for (int b = 0; b < kCcdBuckets; ++b) {
+      const int64_t lo = hseg[r * kCcdBuckets + b], hi = hseg[r * kCcdBuckets + b + 1];
+      for (int64_t e = lo; e < hi; e += piece) {
+        per[b].push_back((int32_t)(task.size() - 1));
+        task.push_back(std::min(hi, e + piece));
+      }
+    }
+  }
+  row_task[md.I] = (int32_t)(task.size() - 1);
+  size_t rounds = 0;
+  for (auto &v : per) rounds = std::max(rounds, (v.size() + 3) / 4);
+  std::vector<int32_t> sched(rounds * kCcdBuckets * 4, -1);
+  for (int b = 0; b < kCcdBuckets; ++b)
+    for (size_t j = 0; j < per[b].size(); ++j)
+      sched[((j / 4) * kCcdBuckets + b) * 4 + (j % 4)] = per[b][j];
+  L.ntask = (int64_t)task.size() - 1;
+  L.nsched = (int64_t)rounds * kCcdBuckets;
+  TT_ST(upload(P, &L.d_task, task, s));
+  TT_ST(upload(P, &L.d_row_task, row_task, s));
+  TT_ST(upload(P, &L.d_sched, sched, s));
+  TT_HIP(hipStreamSynchronize(s));
+  L.built = true;
+  md.ccd = L;
+  *out = &md.ccd;
+  return TT_OK;
 }
 
 tt_status zmap_get(tt_index *ix, hipStream_t s, const int32_t **out) {

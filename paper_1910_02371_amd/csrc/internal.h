@@ -22,6 +22,7 @@ constexpr int kGramLightDefault = 512;
 constexpr int kGramWavesDefault = 4;
 constexpr int kSolveWgsDefault = 0;
 constexpr int kPcgWgsDefault = -1;
+constexpr int kCcdXcdDefault = -1;
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
@@ -29,6 +30,28 @@ constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
 // Elements of one Gram task's matrix in the lower-tile layout (the
 // NB (NB + 1) / 2 lower 16 x 16 tiles of the RP x RP matrix, NB = RP / 16).
 __host__ __device__ constexpr int gram_task_elems(int RP) { return 128 * (RP / 16) * (RP / 16 + 1); }
+
+// CCD++ layout of one mode's stream (index.hip, built on first use): the
+// nonzeros of each row grouped by the bucket of their index in the mode
+// with the most rows among the others (kCcdBuckets row ranges of balanced
+// nonzero count), tasks cut at bucket boundaries and at gram_piece
+// nonzeros, and a schedule that gives bucket b's tasks to workgroups b,
+// b + kCcdBuckets, ...: workgroups are dispatched to the XCDs in turn, so
+// each XCD's L2 sees the column records of one bucket's rows only.
+constexpr int kCcdBuckets = 8;
+struct CcdLayout {
+  bool built = false;
+  int big = -1;                          // the bucketed mode (-1: no layout)
+  int32_t bnd[kCcdBuckets + 1] = {};     // bucket row boundaries in mode `big`
+  int32_t *d_key = nullptr;              // new order: row of each nonzero
+  int32_t *d_oidx[TT_MAX_ORDER] = {};    // new order: the other modes' indices
+  int32_t *d_inv = nullptr;              // sorted position -> new position
+  int64_t ntask = 0;
+  int64_t *d_task = nullptr;             // ntask + 1 boundaries in the new order
+  int32_t *d_row_task = nullptr;         // I + 1: tasks of row i
+  int64_t nsched = 0;                    // workgroups of a pass (4 tasks each)
+  int32_t *d_sched = nullptr;            // nsched * 4 task ids, -1 = none
+};
 
 struct ModeIndex {
   int64_t I = 0;
@@ -88,6 +111,7 @@ struct ModeIndex {
   int32_t *d_light_task = nullptr;
   std::vector<int32_t> h_light_task;
   double mean_row = 0.0;            // m / nrows
+  CcdLayout ccd;                    // arrays in `part` (rebuilt with the partitions)
 };
 
 struct Buf {
@@ -108,7 +132,8 @@ struct tt_index {
   std::map<std::string, tt::Buf> ws;         // named workspace buffers
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
   tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
-                    tt::kGramWavesDefault, tt::kSolveWgsDefault, tt::kPcgWgsDefault};
+                    tt::kGramWavesDefault, tt::kSolveWgsDefault, tt::kPcgWgsDefault,
+                    tt::kCcdXcdDefault};
   int cu_count = 0;  // compute units of the device the index was built on
   // Gauss-Newton position map (built on first use, N x m): slot n != zmode
   // maps mode-n sorted positions to mode-zmode sorted positions
@@ -125,6 +150,11 @@ int gn_zmode(const tt_index *ix);
 // The index's Gauss-Newton position map, built (allocated, filled on stream s
 // and synchronized) on first use; fails while s is capturing a graph.
 tt_status zmap_get(tt_index *ix, hipStream_t s, const int32_t **out);
+// The CCD++ layout of mode n (built on first use: allocates and
+// synchronizes s), or *out = NULL when the tuning (ccd_xcd) or the shape
+// does not call for one; vsz = bytes of one dense value.
+tt_status ccd_layout_get(tt_index *ix, int n, size_t vsz, hipStream_t s,
+                         const CcdLayout **out);
 
 // ----- error handling ------------------------------------------------------
 void set_error(const char *fmt, ...);
@@ -308,11 +338,13 @@ hipError_t launch_add_rows(void *A, int64_t ldA, const void *D, int64_t ldD, tt_
 // = residual in mode n's order, recs[n] = I_n records (column r - 1 old,
 // new; column r old, current; dense dtype, aligned to 4 values), carried
 // from column to column: mode n's pass of column r > 0 first moves its
-// residual copy from column r - 1's old to its new rank-1 term.  part =
-// 2 x max tasks doubles.
+// residual copy from column r - 1's old to its new rank-1 term.  lay[n]:
+// mode n's CCD++ layout or NULL (lay may be NULL).  part = 2 x max tasks
+// doubles.
 hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_t ldA,
                              tt_dtype fdt, double lambda, void *const *rho, void *const *recs,
-                             double *part, int32_t *d_info, hipStream_t s);
+                             const CcdLayout *const *lay, double *part, int32_t *d_info,
+                             hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
 // y += a x over n values of the dense dtype.

@@ -521,16 +521,19 @@ def test_gam_least_squares_one_iteration_is_als(gpu_lib, form):
 
 
 # ------------------------------------------------------------------ CCD++ ----
+@pytest.mark.parametrize("xcd", [0, 1])
 @pytest.mark.parametrize("case", list(GAM_CASES))
 @pytest.mark.parametrize("R", [1, 4, 7])
-def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R):
+def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R, xcd):
     """FP64 form: two CCD++ sweeps equal the oracle's (column views of rank
     1 with the factors' leading dimension; ragged R; empty rows), and the
-    objective does not increase."""
+    objective does not increase; xcd = 1: every mode's stream regrouped by
+    bucket of its largest other mode, tasks scheduled per bucket."""
     tt = gpu_lib
     wl, t, lam, mm = gam_problem(case, "ls")
     A0 = W.init_factors(wl.dims, R, mm, 8, dtype=np.float64)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f64"))
+    ix.tune(ccd_xcd=xcd)
     A = [dev_factor(a, "f64") for a in A0]
     info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
     Ar = A0
@@ -546,17 +549,20 @@ def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R):
         f_prev = f
 
 
+@pytest.mark.parametrize("xcd", [0, 1])
 @pytest.mark.parametrize("form", ["f32", "bf16"])
 @pytest.mark.parametrize("case", ["small", "heavy"])
-def test_ccd_sweep_low_precision_forms(gpu_lib, form, case):
+def test_ccd_sweep_low_precision_forms(gpu_lib, form, case, xcd):
     """FP32 / BF16 storage: one CCD++ sweep at R = 8 within the form's
     tolerance of the oracle run from the same stored inputs (relative
-    Frobenius error per factor)."""
+    Frobenius error per factor), with the sorted and the regrouped stream
+    layouts."""
     tt = gpu_lib
     wl, t, lam, mm = gam_problem(case, "ls")
     t = stored_values(t, form)
     A0 = stored_factors(W.init_factors(wl.dims, 8, mm, 8, dtype=np.float64), form)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    ix.tune(ccd_xcd=xcd)
     A = [dev_factor(a, form) for a in A0]
     tt.ccd_sweep(ix, A, lam)
     Ar, _ = O.ccd_sweep(wl.idx, t, A0, wl.dims, lam)
@@ -564,6 +570,34 @@ def test_ccd_sweep_low_precision_forms(gpu_lib, form, case):
     for d in range(3):
         err = np.linalg.norm(host(A[d]) - Ar[d]) / np.linalg.norm(Ar[d])
         assert err <= tau, f"{form} {case} mode {d}: relative error {err:.2e}"
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_ccd_layout_matches_sorted_stream(gpu_lib, form):
+    """The regrouped stream layout changes only the order of each row's
+    FP64 partial sums: on a 20,000-nonzero tensor whose largest mode spans
+    all eight buckets, two sweeps with ccd_xcd = 1 agree with the sorted
+    layout to FP64 summation order (and to the form's rounding), with equal
+    solve info."""
+    tt = gpu_lib
+    wl = W.random_tensor((60, 900, 40), 20000, 12, rank=3, noise=0.01)
+    t = stored_values(wl.t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 6, float(np.mean(t)), 4, dtype=np.float64),
+                        form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    out = {}
+    for xcd in (0, 1):
+        ix.tune(ccd_xcd=xcd)
+        A = [dev_factor(a, form) for a in A0]
+        info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            tt.ccd_sweep(ix, A, 1e-3, info)
+        out[xcd] = ([host(a) for a in A], info.cpu().numpy())
+    tol = 1e-12 if form == "f64" else 1e-5
+    assert np.array_equal(out[0][1], out[1][1])
+    for d in range(3):
+        a, b = out[0][0][d], out[1][0][d]
+        assert np.linalg.norm(a - b) <= tol * np.linalg.norm(a), f"mode {d}"
 
 
 def test_ccd_rank1_is_als_f32(gpu_lib):
