@@ -347,8 +347,5 @@ hipError_t launch_ccd_column(const tt_index *ix, int r, void *const *d_A, int64_
                              hipStream_t s);
 // Alternating-minimization Newton bookkeeping on the device (see vec.hip).
 hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStream_t s);
-// y += a x over n values of the dense dtype.
-hipError_t launch_axpy_values(void *y, const void *x, double a, int64_t n, tt_dtype dense,
-                              hipStream_t s);
 
 }  // namespace tt

@@ -282,23 +282,4 @@ hipError_t launch_gam_flag(double *sc, double tol, int count, int check, hipStre
   return hipGetLastError();
 }
 
-// y[i] += a * x[i] over n values of the dense dtype.
-template <class X>
-__global__ void k_axpy_values(X *y, const X *x, double a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (X)((double)y[i] + a * (double)x[i]);
-}
-
-hipError_t launch_axpy_values(void *y, const void *x, double a, int64_t n, tt_dtype dense,
-                              hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const int g = grid_cap(n, 8192);
-  if (dense == TT_F64)
-    k_axpy_values<double><<<g, VT_THREADS, 0, s>>>((double *)y, (const double *)x, a, n);
-  else
-    k_axpy_values<float><<<g, VT_THREADS, 0, s>>>((float *)y, (const float *)x, a, n);
-  return hipGetLastError();
-}
-
 }  // namespace tt
