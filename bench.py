@@ -303,16 +303,19 @@ class Leg:
             e1.record(stream)
             self.calls.setdefault(name, []).append((e0, e1))
 
-        if not self.ratings:
-            # model values for every nonzero, written in the index's mode-0
-            # order (the library's sparse layout; the caller's COO order would
-            # add a random scatter of m values)
-            run("tttp", lambda: tt.tttp(ix, None, A, out=self.out_m, out_order=0))
         for n in range(3):
             # ALS update of mode n: Solve Factor with the MTTKRP(t) right-hand
             # side formed in the same pass over the nonzeros as the Gram
-            run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP,
-                                                       self.lam, X=A[n]))
+            if n == 0 and not self.ratings:
+                # ... and, in mode 0's pass, the TTTP: the model value of every
+                # nonzero for the factors at the start of the step, written in
+                # the index's mode-0 order (the library's sparse layout; the
+                # caller's COO order would add a random scatter of m values)
+                run("tttp_als0", lambda: tt.solve_factor_model(ix, A, 0, self.lam, X=A[0],
+                                                               model=self.out_m))
+            else:
+                run(f"als{n}", lambda n=n: tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP,
+                                                           self.lam, X=A[n]))
         if self.ratings:
             run("gn_step", lambda: tt.gn_step(ix, A, "ls", self.lam_gn, tol=5e-3,
                                               kmax=self.args.cg, stats=self.stats))
@@ -476,7 +479,8 @@ def step_desc(leg):
         return ("ALS sweep (3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed "
                 f"in the Gram pass) + Gauss-Newton step ({leg.args.cg} CG iterations)")
     return ("TTTP (model values in the index's mode-0 order) + ALS sweep (3 x [MTTKRP + "
-            "Solve Factor], the MTTKRP right-hand side formed in the Gram pass)")
+            "Solve Factor], the MTTKRP right-hand side formed in the Gram pass; the TTTP "
+            "formed in mode 0's pass from the same gathered rows)")
 
 
 def ratings_extras(tt, leg, args, dev):

@@ -279,6 +279,23 @@ tt_status solve_factor(const tt_index *ix, const void *d_w, int w_order,
                        uint32_t flags, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * solve_factor_model -- the ALS update of mode `mode` (solve_factor with
+ * d_rhs = TT_RHS_MTTKRP and no weights) that also evaluates the model at
+ * every nonzero (TTTP, Section 3.3, of the factors as they are before the
+ * update): d_model[e] = sum_r prod_n A_n[i_n(e), r] for the nonzeros in the
+ * index's mode-`mode` sorted order (value dtype, m values).  The FP32 and
+ * BF16 forms compute the model values in the Gram pass from the factor rows
+ * it gathers anyway (one pass over the nonzeros for both results); the
+ * FP64 form runs a TTTP pass first.  Every d_A[p] must be given; d_X may
+ * alias d_A[mode]; d_info as in solve_factor.  The model values are those
+ * of tttp with d_s NULL up to FP32 summation order.
+ * ------------------------------------------------------------------------- */
+tt_status solve_factor_model(tt_index *ix, const void *const *d_A, int R,
+                             int64_t ldA, tt_dtype fdt, int mode,
+                             double lambda, void *d_X, int32_t *d_info,
+                             void *d_model, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * gn_matvec -- implicit Gauss-Newton matrix-vector product (Section 2.5
  * without the phi' terms; the TTTP -> MTTKRP decomposition of Section 2.5;
  * Appendix A first Hessian term):

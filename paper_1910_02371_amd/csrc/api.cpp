@@ -663,6 +663,41 @@ tt_status solve_factor(const tt_index *cix, const void *d_w, int w_order, const 
   return TT_OK;
 }
 
+tt_status solve_factor_model(tt_index *ix, const void *const *d_A, int R, int64_t ldA,
+                             tt_dtype fdt, int mode, double lambda, void *d_X, int32_t *d_info,
+                             void *d_model, hipStream_t stream) {
+  g_err.clear();
+  TT_ST(check_common(ix, R, ldA, fdt));
+  TT_CHECK(mode >= 0 && mode < ix->N, "bad mode %d", mode);
+  TT_CHECK(d_A != nullptr && d_X != nullptr && d_model != nullptr, "NULL argument");
+  for (int p = 0; p < ix->N; ++p) TT_CHECK(d_A[p] != nullptr, "factor %d is NULL", p);
+  TT_CHECK(ix->has_t, "the index holds no observed values");
+  TT_CHECK((ix->vdt == TT_F64) == (fdt == TT_F64), "value dtype does not match factor dtype");
+  SolveCall c;
+  memset(&c, 0, sizeof(c));
+  c.ix = ix;
+  c.mode = mode;
+  c.R = R;
+  c.ldA = ldA;
+  c.fdt = fdt;
+  for (int p = 0; p < ix->N; ++p) c.A[p] = d_A[p];
+  c.w_scale = 1.0;
+  c.lambda = lambda;
+  c.rhs = TT_RHS_MTTKRP;
+  if (fdt == TT_F64) {
+    // the FP64 form forms its right-hand side by a separate MTTKRP pass, so
+    // the model values come from a TTTP pass of their own
+    TT_ST(tttp_mode(ix, mode, nullptr, nullptr, d_A, R, ldA, fdt, TT_EPI_NONE, TT_LOSS_LS,
+                    d_model, nullptr, nullptr, nullptr, stream));
+  } else {
+    c.model = d_model;
+  }
+  TT_ST(als_rhs(ix, c.A, R, ldA, fdt, mode, &c, stream));
+  c.X = d_X;
+  c.info = d_info;
+  return run_solve_factor(ix, c, stream);
+}
+
 tt_status gn_matvec(const tt_index *cix, const void *d_w, int w_order, double w_const,
                     const void *const *d_A, const void *const *d_X, int R, int64_t ldA,
                     tt_dtype fdt, double lambda2, void *const *d_Y, hipStream_t stream) {

@@ -294,6 +294,10 @@ struct SolveCall {
   int loss;
   double own_coef;
   const double *skip;       // optional device flag: every launch becomes a no-op
+  // FP32 / BF16 least-squares form with fused_rhs: also write the model value
+  // <A[mode][i], h_e> of every nonzero (factors before the update) to model[e]
+  // in this mode's sorted order (value dtype), from the Gram pass's gathers
+  void *model;
 };
 tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s);
 // The Gram (and fused right-hand-side) workspaces of one row batch of

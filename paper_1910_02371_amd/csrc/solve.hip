@@ -106,7 +106,7 @@ static hipError_t launch_gram(tt_dtype fdt, int RP, const GramDev &d, const Gram
   dim3 g((unsigned)((n + 3) / 4)), b(256);
   const double R = d.R, fb = fdt == TT_F64 ? 8 : (fdt == TT_F32 ? 4 : 2);
   const double gs = fdt == TT_F64 ? 8 : 4,
-               pernz = 8 + (d.w ? gs : 0) + (d.M ? 4 : 0) + 2 * R * fb;
+               pernz = 8 + (d.w ? gs : 0) + (d.M ? 4 : 0) + (d.model ? 4 : 0) + 2 * R * fb;
   const double tile = (double)gram_task_elems(RP) * gs;
   if (fdt == TT_F64) {
     ProfScope ps("gram_light", s, (wk.light_nnz + wk.heavy_nnz) * pernz + wk.light_tasks * tile,
@@ -235,6 +235,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
   gd.key = md.d_key;
   gd.loss = c.loss;
   gd.skip = c.skip;
+  gd.A_model = c.model ? c.A[c.mode] : nullptr;
+  gd.model = reinterpret_cast<float *>(c.model);
 
   SolveDev sd;
   memset(&sd, 0, sizeof(sd));
@@ -318,7 +320,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
       // fused solo rows: gathers of their nonzeros, the solve's own traffic
       const double Rd = c.R, fb = (double)dtype_size(c.fdt), nsolo = (double)gl.nsolo;
       const double snnz = (double)(md.h_solo_nnz[s1] - md.h_solo_nnz[s0]);
-      gl.solo_bytes = snnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + 2 * Rd * fb) +
+      gl.solo_bytes = snnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + (c.model ? 4 : 0) +
+                              2 * Rd * fb) +
                       nsolo * Rd * (4 + fb) +
                       (c.Lstore ? nsolo * RP * (RP + 1) / 2 * 4.0 : 0.0);
       gl.solo_flops = snnz * Rd * (Rd + 1) +
@@ -332,7 +335,8 @@ tt_status run_solve_factor(tt_index *ix, const SolveCall &c, hipStream_t s) {
         const double nhs = (double)(hs1 - hs0);
         gl.hsolo = md.d_hsolo_row + hs0;
         gl.nhsolo = hs1 - hs0;
-        gl.hsolo_bytes = hnnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + 2 * Rd * fb) +
+        gl.hsolo_bytes = hnnz * (8 + (c.w ? 4 : 0) + (c.fused_rhs ? 4 : 0) + (c.model ? 4 : 0) +
+                                 2 * Rd * fb) +
                          nhs * Rd * (4 + fb) +
                          (c.Lstore ? nhs * RP * (RP + 1) / 2 * 4.0 : 0.0);
         gl.hsolo_flops = hnnz * Rd * (Rd + 1) +

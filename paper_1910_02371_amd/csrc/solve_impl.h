@@ -43,6 +43,11 @@ struct GramDev {
   const int32_t *key;         // sorted mode index of each nonzero
   int loss;
   const double *skip;         // when set and *skip != 0 the launch is a no-op
+  // least-squares form with a model output (RHS without weights): the model
+  // value <A_model[i], h_e> of every nonzero, written to model[e] in stream
+  // order (TTTP of the factors as they are before the update)
+  const void *A_model;
+  float *model;
 };
 
 // Slot of the lower element (r, c), r >= c, in the lower-tile layout.
@@ -224,13 +229,19 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   const int cb = VW * (lane & 15);
   const int64_t n = ne - nb;
   if (n <= 0) return;
-  // NEWTON: this lane's columns of the row's own factor row (0 beyond R)
+  // NEWTON, or the model output: this lane's columns of the row's own
+  // factor row (0 beyond R)
+  constexpr bool MODEL = RHS && !WEIGHTED;  // a model output is possible
+  const bool model = MODEL && d.model != nullptr;  // uniform
   float own[VW];
-  if constexpr (NEWTON) {
-    const uint32_t row = (uint32_t)d.key[nb];
-    load_cols<TR, VW, VEC>(reinterpret_cast<const T *>(d.A_own), row * ldA, cb, R, own);
+  if constexpr (NEWTON || MODEL) {
+    if (NEWTON || model) {
+      const uint32_t row = (uint32_t)d.key[nb];
+      load_cols<TR, VW, VEC>(reinterpret_cast<const T *>(NEWTON ? d.A_own : d.A_model),
+                             row * ldA, cb, R, own);
 #pragma unroll
-    for (int v = 0; v < VW; ++v) own[v] = cb + v < R ? own[v] : 0.f;
+      for (int v = 0; v < VW; ++v) own[v] = cb + v < R ? own[v] : 0.f;
+    }
   }
   const int64_t nblk = (n + 63) / 64;
   const int64_t nst = (n + 31) / 32;
@@ -280,6 +291,21 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
       load_cols<TR, VW, VEC>(A1, r1[u], cb, R, a1[u]);
     }
     __builtin_amdgcn_sched_barrier(0);
+    // the model output: each substep's nonzero (the 16 lanes of a DPP row
+    // hold its columns) gets <own, h_e>; lane 16 k of the row stores it
+    if constexpr (MODEL) {
+      if (model) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          float dsum = 0.f;
+#pragma unroll
+          for (int v = 0; v < VW; ++v) dsum = fmaf(own[v], a0[u][v] * a1[u][v], dsum);
+          const float m = group_sum<16>(dsum);
+          const int64_t e = nb + cblk * 64 + sb + 4 * u;
+          if ((lane & 15) == 0 && e < ne) d.model[e] = m;
+        }
+      }
+    }
     // NEWTON: model value of each substep's nonzero (the 16 lanes of a DPP
     // row hold its columns), then phi'' as the weight and phi' as the
     // right-hand-side value; both vanish past the end of the range
@@ -1072,6 +1098,18 @@ __device__ __forceinline__ void solve_pushthrough(const GramDev &g, const SolveD
       for (int ii = 0; ii < PA; ++ii)
 #pragma unroll
         for (int w = 0; w < 4; ++w) op[I][s][ii][w] = pack_bf16(pt[2 * w][ii], pt[2 * w + 1][ii]);
+    }
+  }
+  // the model output: lane e < k forms <own row, h_e> from the LDS copy of H
+  // (FP64 sum, rounded once; the own row is read before this row's update)
+  if (g.model != nullptr) {
+    asm volatile("" ::: "memory");
+    if (lane < k) {
+      const T *own = reinterpret_cast<const T *>(g.A_model) + row * (int64_t)ldA;
+      double mm = 0.0;
+      for (int c = 0; c < R; ++c)
+        mm = fma((double)Hl[lane * 64 + c], (double)elem_f<TR>(own, c), mm);
+      g.model[nb + lane] = (float)mm;
     }
   }
   f32x4 acc[NT];

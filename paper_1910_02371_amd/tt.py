@@ -49,6 +49,7 @@ SIGNATURES = {
     "mttkrp": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _I, _P]),
     "mttkrp_noalloc": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _I, _P]),
     "solve_factor": (_I, [_P, _P, _I, _PP, _I, _I64, _I, _I, _P, _D, _P, _P, _U32, _P]),
+    "solve_factor_model": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _P, _P, _P, _P]),
     "gn_matvec": (_I, [_P, _P, _I, _D, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
     "newton_matvec": (_I, [_P, _P, _I, _D, _P, _I, _PP, _PP, _I, _I64, _I, _D, _PP, _P]),
     "tt_gradient": (_I, [_P, _PP, _I, _I64, _I, _I, _D, _PP, _P]),
@@ -320,6 +321,27 @@ def solve_factor(ix, w, A, mode, rhs, lam, X=None, info=None, w_order=ORDER_COO,
                               float(lam), _ptr(X), _ptr(info), TT_SYNC if sync else 0,
                               _stream()))
     return X, info
+
+
+def solve_factor_model(ix, A, mode, lam, X=None, info=None, model=None):
+    """The ALS update of ``mode`` (solve_factor with RHS_MTTKRP) that also
+    returns the model value of every nonzero for the factors before the
+    update, in the index's mode-``mode`` sorted order; returns (X, info,
+    model)."""
+    fdt = fdt_of(A)
+    R, ld = _rank_ld(A)
+    if X is None:
+        dt = {TT_F64: torch.float64, TT_F32: torch.float32, TT_BF16: torch.bfloat16}[fdt]
+        X = torch.empty((ix.dims[mode], ld), dtype=dt, device="cuda")[:, :R]
+    elif X.stride(0) != ld:
+        raise ValueError("X must share the factors' leading dimension")
+    if info is None:
+        info = torch.empty(ix.dims[mode], dtype=torch.int32, device="cuda")
+    if model is None:
+        model = torch.empty(ix.nnz, dtype=value_dtype(fdt), device="cuda")
+    _check(lib().solve_factor_model(ix.handle, _ptrs(A), R, ld, fdt, mode, float(lam), _ptr(X),
+                                    _ptr(info), _ptr(model), _stream()))
+    return X, info, model
 
 
 def gn_matvec(ix, w, A, X, lam2, Y=None, w_order=ORDER_PER_MODE, w_const=2.0):

@@ -368,6 +368,35 @@ def test_solve_factor_short_rows(gpu_lib, form, R, ld, lam):
         assert err.max() <= bound, f"forward error {err.max():.3e} (row {err.argmax()})"
 
 
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [10, 32, 64])
+@pytest.mark.parametrize("kind", ["heavy", "zipf"])
+def test_solve_factor_model(gpu_lib, form, R, kind):
+    """solve_factor_model: the ALS update equals solve_factor(RHS_MTTKRP) bit
+    for bit (X and info, also in place), and the model values it returns
+    (factors before the update, the mode's sorted order) equal the oracle's
+    TTTP elementwise at tau (absolute form: the model on |A|)."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, kind, form)
+    A64 = factors(wl.dims, R, 700 + R)
+    As = stored_factors(A64, form)
+    ref = O.tttp(wl.idx, None, As)
+    ref_abs = O.tttp(wl.idx, None, [np.abs(a) for a in As])
+    lam = 0.05
+    for n in range(3):
+        A = [dev_factor(a, form) for a in A64]
+        X0, info0 = tt.solve_factor(ix, None, A, n, tt.RHS_MTTKRP, lam)
+        X1, info1, model = tt.solve_factor_model(ix, A, n, lam)
+        assert torch.equal(X0, X1) and torch.equal(info0, info1), f"mode {n}"
+        perm = ix.view(n)[1].cpu().numpy()
+        m_coo = np.empty(wl.nnz)
+        m_coo[perm] = host(model)
+        assert_close_abs(m_coo, ref, ref_abs, TAU[form], f"model values, mode {n}")
+        # in place (X = A[n]): the same update and model values
+        Xp, _, mp = tt.solve_factor_model(ix, A, n, lam, X=A[n])
+        assert torch.equal(Xp, X1) and torch.equal(mp, model), f"in place, mode {n}"
+
+
 def test_solve_factor_weights_and_info(gpu_lib):
     tt = gpu_lib
     form = "f64"
