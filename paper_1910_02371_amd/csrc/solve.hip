@@ -63,19 +63,34 @@ static void launch_gram_heavy_rp(const GramDev &d, const int32_t *heavy, int64_t
   if (nheavy <= 0) return;
   ProfScope ps("gram_heavy", s, bytes, flops);
   const dim3 g((unsigned)nheavy);
-  switch (d.waves) {
-    case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 2><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
-    case 8: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 8><<<g, dim3(512), 0, s>>>(d, heavy, nheavy); break;
-    default: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 4><<<g, dim3(256), 0, s>>>(d, heavy, nheavy); break;
+  auto launch = [&](auto mod) {
+    constexpr bool MOD = decltype(mod)::value;
+    switch (d.waves) {
+      case 2: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 2, MOD><<<g, dim3(128), 0, s>>>(d, heavy, nheavy); break;
+      case 8: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 8, MOD><<<g, dim3(512), 0, s>>>(d, heavy, nheavy); break;
+      default: k_gram_f32_heavy<TR, RP, VEC, WEIGHTED, RHS, 4, MOD><<<g, dim3(256), 0, s>>>(d, heavy, nheavy); break;
+    }
+  };
+  if constexpr (RHS && !WEIGHTED) {
+    if (d.model != nullptr) {
+      launch(std::true_type{});
+      return;
+    }
   }
+  launch(std::false_type{});
 }
 
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
 static void launch_gram_f32_rp(GramDev d, const GramLists &gl, hipStream_t s) {
   if (gl.nlight > 0) {
     ProfScope ps("gram_light", s, gl.light_bytes, gl.light_flops);
-    k_gram_f32<TR, RP, VEC, WEIGHTED, RHS><<<dim3((unsigned)((gl.nlight + 3) / 4)), dim3(256), 0, s>>>(
-        d, gl.light, gl.nlight);
+    const dim3 g((unsigned)((gl.nlight + 3) / 4));
+    bool mod = false;
+    if constexpr (RHS && !WEIGHTED) {
+      mod = d.model != nullptr;
+      if (mod) k_gram_f32<TR, RP, VEC, WEIGHTED, RHS, true><<<g, dim3(256), 0, s>>>(d, gl.light, gl.nlight);
+    }
+    if (!mod) k_gram_f32<TR, RP, VEC, WEIGHTED, RHS, false><<<g, dim3(256), 0, s>>>(d, gl.light, gl.nlight);
   }
   launch_gram_heavy_rp<TR, RP, VEC, WEIGHTED, RHS>(d, gl.heavy, gl.nheavy, gl.heavy_bytes,
                                                    gl.heavy_flops, s);

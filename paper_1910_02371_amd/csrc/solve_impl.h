@@ -167,6 +167,8 @@ __device__ __forceinline__ uint32_t pack_bf16(uint32_t a, uint32_t b) {
 // bits): x = sum of the parts, largest first.
 template <int NP>
 __device__ __forceinline__ void split_bf16(float x, uint32_t (&p)[NP]) {
+  // no contraction of the caller's product into the subtractions
+#pragma clang fp contract(off)
   float r = x;
 #pragma unroll
   for (int i = 0; i + 1 < NP; ++i) {
@@ -209,9 +211,13 @@ struct PartPairs {
 // that only reach padding entries of G, which the solve replaces by the
 // identity.  Nonzeros past the end of the range (only in the last step)
 // read row 0 and are zeroed by their weight or validity.
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+// MOD = false compiles the model output out (callers that never ask for it).
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool MOD = true>
 __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t ne,
                                            GramAcc<RP> &acc) {
+  // every instantiation (load mode, model output) rounds the same operations
+  // the same way: products are not contracted into later additions
+#pragma clang fp contract(off)
   using T = typename TR::T;
   constexpr int VW = RP / 16;
   constexpr bool F32 = std::is_same<TR, TrF32>::value;
@@ -231,7 +237,7 @@ __device__ __forceinline__ void gram_accum(const GramDev &d, int64_t nb, int64_t
   if (n <= 0) return;
   // NEWTON, or the model output: this lane's columns of the row's own
   // factor row (0 beyond R)
-  constexpr bool MODEL = RHS && !WEIGHTED;  // a model output is possible
+  constexpr bool MODEL = MOD && RHS && !WEIGHTED;  // a model output is possible
   const bool model = MODEL && d.model != nullptr;  // uniform
   float own[VW];
   if constexpr (NEWTON || MODEL) {
@@ -434,7 +440,10 @@ __device__ __forceinline__ void rhs_store(double *M, const GramAcc<RP> &acc, int
   }
 }
 
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS>
+// MOD (the Gram kernels and k_gram_solve_heavy): compiled with the model
+// output; the launches take the variant without it when none is asked for,
+// which keeps its registers free for the gathers.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool MOD>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32(
     GramDev d, const int32_t *tasks, int64_t ntasks) {
@@ -445,7 +454,7 @@ __attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f
   const int64_t nb = d.task[t], ne = d.task[t + 1];
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, nb, ne, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS, MOD>(d, nb, ne, acc);
   gram_store<RP>(reinterpret_cast<float *>(d.G) + (t - d.task_base) * (int64_t)gram_task_elems(RP), acc,
                  d.w ? 1.f : (float)d.w_scale);
   if constexpr (RHS) rhs_store<RP>(d.M + (t - d.task_base) * (int64_t)RP, acc, threadIdx.x & 63);
@@ -453,7 +462,7 @@ __attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f
 
 // Heavy tasks: the waves of a workgroup split the task's nonzeros and add
 // their accumulators through LDS in wave order (deterministic).
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, int NW>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, int NW, bool MOD>
 __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f32_heavy(
     GramDev d, const int32_t *heavy, int64_t nheavy) {
@@ -469,7 +478,7 @@ __attribute__((amdgpu_waves_per_eu(GramOcc<RP, WEIGHTED>::value))) void k_gram_f
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(d, b0, b1, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS, MOD>(d, b0, b1, acc);
   for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
@@ -789,15 +798,24 @@ __device__ __forceinline__ double bwd_regs(const double *Lp, double b, double rd
 // holds y on return.
 // The row's Gram is the sum of `ntask` consecutive tile-layout matrices at
 // gbase (task workspace, or the LDS copy of a Gram formed in the kernel).
-template <class GT, int RP, bool FWD>
-__device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, int ntask,
-                                          int lane, double *Lp, double *Pn,
-                                          double &rdiag, double &b) {
+// REGL: no LDS copy of L; after each panel's trailing update the factored
+// columns are written back from the panel buffer into the tiles of column
+// block J (replacing what the update left there), so on return tile (I, J)
+// holds L in the accumulator layout, zero above the diagonal (bwd_acc,
+// store_acc read it from there).
+template <int RP>
+constexpr int chol_nt() {
+  return (RP / 16) * (RP / 16 + 1) / 2;
+}
+
+// S = sum of the task Grams + lambda I in the accumulator tiles (identity on
+// the padding rows and columns, zero above the diagonal).
+template <class GT, int RP>
+__device__ __forceinline__ void chol_load(f64x4 (&acc)[chol_nt<RP>()], const GT *gbase,
+                                          int ntask, int R, double lambda, int lane) {
   constexpr int NB = RP / 16;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int SZ = 256 * NT;
-  const int R = d.R;
-  f64x4 acc[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
   for (int t = 0; t < ntask; ++t) {
@@ -824,7 +842,7 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
       for (int v = 0; v < 4; ++v) {
         double x = acc[I * (I + 1) / 2 + I][v];
         x = (4 * v + rr < cc) ? 0.0 : x;
-        x += (4 * v + rr == cc) ? d.lambda : 0.0;
+        x += (4 * v + rr == cc) ? lambda : 0.0;
         acc[I * (I + 1) / 2 + I][v] = x;
       }
     if (R < RP) {  // uniform: padding rows and columns become the identity
@@ -840,6 +858,12 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
           }
     }
   }
+}
+
+template <int RP, bool FWD, bool REGL>
+__device__ __forceinline__ int chol_core(f64x4 (&acc)[chol_nt<RP>()], int lane, double *Lp,
+                                         double *Pn, double &rdiag, double &b) {
+  constexpr int NB = RP / 16;
   using P = Packed<RP>;
   using PB = PanelBuf<RP>;
   // every lane of the wave is a row when RP = 64: the lane < RP tests fold
@@ -884,7 +908,7 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
         b = lane == k ? yk : fma(-lik, yk, b);
       }
 #pragma unroll
-      for (int c2 = c + 1; c2 < 4; ++c2) x[c2] -= lik * readlane_d(lik, k0 + c2);
+      for (int c2 = c + 1; c2 < 4; ++c2) x[c2] = fma(-lik, readlane_d(lik, k0 + c2), x[c2]);
     }
     // 3. the factored panel to Pn and to the row-packed copy of L
     {
@@ -892,7 +916,8 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         Pn[(FULL || ln < RP) ? c * PB::PP + ln : PB::SCR + ln] = x[c];
-        Lp[(k0 + c <= ln && (FULL || ln < RP)) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
+        if constexpr (!REGL)
+          Lp[(k0 + c <= ln && (FULL || ln < RP)) ? base + k0 + c : P::ZERO + 1 + ln] = x[c];
       }
     }
     // 4. trailing update on the matrix cores
@@ -907,8 +932,121 @@ __device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, in
           acc[I * (I + 1) / 2 + J2] = __builtin_amdgcn_mfma_f64_16x16x4f64(
               -a[I], a[J2], acc[I * (I + 1) / 2 + J2], 0, 0, 0);
     }
+    if constexpr (REGL) {
+      // 5. the factored panel into the tiles of column block J (lanes whose
+      // column is outside the panel read their scratch slot and keep theirs)
+      const int ln = opaque_lane(lane);
+      const int cc = ln & 15, rr = ln >> 4;
+      const bool mine = (unsigned)(cc - c0) < 4u;
+#pragma unroll
+      for (int I = J; I < NB; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double y = Pn[mine ? (cc - c0) * PB::PP + 16 * I + 4 * v + rr : PB::SCR + ln];
+          acc[I * (I + 1) / 2 + J][v] = mine ? y : acc[I * (I + 1) / 2 + J][v];
+        }
+    }
   }
   return 0;
+}
+
+template <class GT, int RP, bool FWD>
+__device__ __forceinline__ int chol_tiles(const SolveDev &d, const GT *gbase, int ntask,
+                                          int lane, double *Lp, double *Pn,
+                                          double &rdiag, double &b) {
+  f64x4 acc[chol_nt<RP>()];
+  chol_load<GT, RP>(acc, gbase, ntask, d.R, d.lambda, lane);
+  return chol_core<RP, FWD, false>(acc, lane, Lp, Pn, rdiag, b);
+}
+
+// Buffer of bwd_acc: a diagonal tile row-major (256), a zero, the block's x.
+struct BwdBuf {
+  static constexpr int ZERO = 256;
+  static constexpr int X = 264;
+  static constexpr int SIZE = 280;
+};
+
+// Backward substitution L^T x = y with L in the accumulator tiles (lane l,
+// register v of tile (I, J): L(16 I + 4 v + l / 16, 16 J + l % 16)); lane i
+// holds y_i in b and 1 / L(i, i) in rdiag.  Column blocks from the last:
+// the diagonal tile goes to the LDS buffer T row-major and the block's 16
+// unknowns are solved one after the other (x_k broadcast, lanes c < k of
+// the block subtract L(k, c) x_k, the other lanes a zero); then the block's
+// x goes to T, and for every block G above it the lanes form their part of
+// sum_r L(r, c) x_r over the rows r of block J in tile (J, G), the four
+// lane groups add theirs (two butterfly steps) and the lanes of block G
+// subtract it.  Returns x_i on lane i.
+template <int RP>
+__device__ __forceinline__ double bwd_acc(const f64x4 (&acc)[chol_nt<RP>()], double *T,
+                                          double b, double rdiag, int lane) {
+  constexpr int NB = RP / 16;
+  using BB = BwdBuf;
+  const int ln = opaque_lane(lane);
+  const int rr = ln >> 4, cc = ln & 15;
+  // earlier LDS reads (the factorization's) stay before these writes
+  asm volatile("" ::: "memory");
+  if (lane == 0) T[BB::ZERO] = 0.0;
+#pragma unroll
+  for (int J = NB - 1; J >= 0; --J) {
+    const int dq = J * (J + 1) / 2 + J;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[(4 * v + rr) * 16 + cc] = acc[dq][v];
+    asm volatile("" ::: "memory");
+    const bool inblk = rr == J;
+#pragma unroll 4
+    for (int k = 15; k >= 0; --k) {
+      const double xk = readlane_d(b * rdiag, 16 * J + k);
+      const double lkc = T[(inblk && cc < k) ? k * 16 + cc : BB::ZERO];
+      b = fma(-lkc, xk, b);
+    }
+    if (J > 0) {
+      asm volatile("" ::: "memory");
+      T[inblk ? BB::X + cc : BB::ZERO + 1 + (ln & 3)] = b * rdiag;
+      asm volatile("" ::: "memory");
+      double xs[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xs[v] = T[BB::X + 4 * v + rr];
+#pragma unroll
+      for (int G = 0; G < J; ++G) {
+        const int q = J * (J + 1) / 2 + G;
+        double p = acc[q][0] * xs[0];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) p = fma(acc[q][v], xs[v], p);
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        b = rr == G ? b - p : b;
+      }
+      // the next block's tile overwrites T: these reads stay before it
+      asm volatile("" ::: "memory");
+    }
+  }
+  return b * rdiag;
+}
+
+// L from the tiles to the row-packed factor store (RP (RP + 1) / 2 floats
+// per row), staged in LDS (Lf: PS + 64 floats) so that the global stores
+// are coalesced; info != 0 stores the identity.
+template <int RP>
+__device__ __forceinline__ void store_acc(const f64x4 (&acc)[chol_nt<RP>()], float *Lf,
+                                          float *L, int info, int lane) {
+  constexpr int NB = RP / 16;
+  constexpr int PS = Packed<RP>::PS;
+  const int ln = opaque_lane(lane);
+  const int rr = ln >> 4, cc = ln & 15;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = 0; J <= I; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * I + 4 * v + rr, c = 16 * J + cc;
+        const bool diag = r == c;
+        const float y = info ? (diag ? 1.f : 0.f) : (float)acc[I * (I + 1) / 2 + J][v];
+        Lf[c <= r ? (r * (r + 1)) / 2 + c : PS + ln] = y;
+      }
+  asm volatile("" ::: "memory");
+  for (int q = lane; q < PS; q += 64) L[q] = Lf[q];
 }
 
 // One row of k_solve_rows.
@@ -1034,6 +1172,77 @@ __device__ __forceinline__ void solve_from_acc(const GramDev &g, const SolveDev 
   }
 }
 
+// LDS of the push-through solve at padded size KP (doubles): K's tiles,
+// then (same place) the panel buffer and the backward-solve buffer, then H
+// (KP rows of 64 floats).
+template <int KP>
+struct PushLds {
+  static constexpr int K = chol_nt<KP>() * 128;
+  static constexpr int PB = PanelBuf<KP>::SIZE > BwdBuf::SIZE ? PanelBuf<KP>::SIZE : BwdBuf::SIZE;
+  static constexpr int H = K > PB ? K : PB;
+  static constexpr int SIZE = H + KP * 32;
+};
+
+// LDS of a k_solve_solo workgroup (doubles): the largest of the Gram in the
+// tile layout, the panel buffer, the backward-solve buffer, the factor
+// staging (PS + 64 floats) and, at RP = 64, the push-through solves.
+template <int RP>
+struct SoloLds {
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int FAC = cmax(cmax(gram_task_elems(RP) / 2, PanelBuf<RP>::SIZE),
+                                  cmax(BwdBuf::SIZE, (Packed<RP>::PS + 64 + 1) / 2));
+  static constexpr int DOUBLES =
+      RP == 64 ? cmax(FAC, cmax(PushLds<16>::SIZE, PushLds<32>::SIZE)) : FAC;
+};
+
+// solve_from_acc with L kept in the accumulator tiles (chol_core REGL) and
+// one LDS block `lds` that holds in turn the right-hand side reduction, the
+// Gram in the tile layout, the panel buffer, the factor staging and the
+// backward-solve buffer (one wave: its LDS accesses complete in program
+// order; the empty asm statements keep the compiler from moving them).
+template <class TR, int RP, bool RHS, bool FO>
+__device__ __forceinline__ void solve_from_acc_regl(const GramDev &g, const SolveDev &d,
+                                                    int64_t row, int lane, double *lds,
+                                                    const GramAcc<RP> &acc) {
+  using XT = typename TR::T;
+  constexpr int VW = RP / 16;
+  const int R = d.R;
+  // earlier LDS reads (a previous row's) stay before these writes
+  asm volatile("" ::: "memory");
+  double b = 0.0;
+  if constexpr (RHS) {
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+      double x = acc.m[v];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      if (lane < 16) lds[VW * lane + v] = x;
+    }
+    const double bv = lds[lane < RP ? lane : 0];
+    b = lane < R ? bv : 0.0;
+    if (d.own && lane < R) b = newton_rhs<XT>(d, row, lane, b);
+  } else if (!FO && lane < R) {
+    b = (double)reinterpret_cast<const float *>(d.rhs)[row * R + lane];
+  }
+  // the Gram overwrites the right-hand side buffer
+  asm volatile("" ::: "memory");
+  float *Gl = reinterpret_cast<float *>(lds);
+  gram_store<RP>(Gl, acc, g.w ? 1.f : (float)g.w_scale);
+  asm volatile("" ::: "memory");
+  f64x4 L[chol_nt<RP>()];
+  chol_load<float, RP>(L, Gl, 1, R, d.lambda, lane);
+  double rdiag = 1.0;
+  const int info = chol_core<RP, !FO, true>(L, lane, nullptr, lds, rdiag, b);
+  if (d.info && lane == 0) d.info[row] = info;
+  if (d.Lstore)
+    store_acc<RP>(L, reinterpret_cast<float *>(lds),
+                  reinterpret_cast<float *>(d.Lstore) + row * (int64_t)Packed<RP>::PS, info, lane);
+  if constexpr (!FO) {
+    const double x = info == 0 ? bwd_acc<RP>(L, lds, b, rdiag, lane) : 0.0;
+    if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
+  }
+}
+
 // Rows of the fused least-squares update with k <= KP nonzeros (KP = 16 or
 // 32) at ranks above 32.  With H the k x R matrix of the rows h_e and c the
 // constant weight, (c H^T H + lambda I)^{-1} H^T t = H^T (c H H^T +
@@ -1042,10 +1251,11 @@ __device__ __forceinline__ void solve_from_acc(const GramDev &g, const SolveDev 
 // from the same exact bf16 splits as the Gram (the contraction now runs
 // over the R columns: lane 16 g + i holds columns 8 g .. 8 g + 7 of h_e,
 // e = 16 I + i, which is its operand K-run for the tiles of row block I),
-// stored in the tile layout, factored and solved by chol_tiles at padded
-// size KP (rows e >= k are the identity), and x = H^T y is summed in FP64
-// from an LDS copy of H.  LDS: K's tiles and then L, the panel buffer and H
-// one after the other inside the RP = 64 solve's Lp.
+// stored in the tile layout, factored (L kept in the accumulator tiles) and
+// solved at padded size KP (rows e >= k are the identity), and x = H^T y is
+// summed in FP64 from an LDS copy of H.  LDS (`lds`, PushLds<KP>): K's
+// tiles, then the panel buffer and the backward-solve buffer in the same
+// place, and H after them.
 template <class TR, int KP, bool VEC>
 __device__ __forceinline__ void solve_pushthrough(const GramDev &g, const SolveDev &d,
                                                   int64_t row, int64_t nb, int k, int lane,
@@ -1057,13 +1267,8 @@ __device__ __forceinline__ void solve_pushthrough(const GramDev &g, const SolveD
   using PP = PartPairs<PA, PA>;
   constexpr int NB = KP / 16;
   constexpr int NT = NB * (NB + 1) / 2;
-  constexpr int kPnOff = Packed<KP>::LDS;
-  constexpr int kHOff = kPnOff + PanelBuf<KP>::SIZE;
-  static_assert(NT * 256 <= 2 * Packed<KP>::PS, "K's tiles fit below Lp[ZERO]");
-  static_assert(kHOff + KP * 32 <= Packed<64>::LDS, "fits the RP = 64 solve's Lp");
-  double *Lp = lds, *Pn = lds + kPnOff;
   float *Kl = reinterpret_cast<float *>(lds);
-  float *Hl = reinterpret_cast<float *>(lds + kHOff);
+  float *Hl = reinterpret_cast<float *>(lds + PushLds<KP>::H);
   const T *A0 = reinterpret_cast<const T *>(g.A0);
   const T *A1 = reinterpret_cast<const T *>(g.A1);
   const int R = d.R;
@@ -1138,22 +1343,22 @@ __device__ __forceinline__ void solve_pushthrough(const GramDev &g, const SolveD
 #pragma unroll
     for (int v = 0; v < 4; ++v) Kl[256 * q + 16 * (4 * gq + v) + i] = acc[q][v] * c;
   asm volatile("" ::: "memory");
-  SolveDev dk = d;
-  dk.R = k;  // rows and columns k .. KP - 1 become the identity
   double b = lane < k ? (double)g.rhs_t[nb + lane] : 0.0;
   double rdiag = 1.0;
-  if (lane == 0) Lp[Packed<KP>::ZERO] = 0.0;
-  const int info = chol_tiles<float, KP, true>(dk, Kl, 1, lane, Lp, Pn, rdiag, b);
+  f64x4 L[NT];
+  // rows and columns k .. KP - 1 become the identity
+  chol_load<float, KP>(L, Kl, 1, k, d.lambda, lane);
+  const int info = chol_core<KP, true, true>(L, lane, nullptr, lds, rdiag, b);
   if (d.info && lane == 0) d.info[row] = info;
-  const double y = info == 0 ? bwd_regs<KP>(Lp, b, rdiag, lane) : 0.0;
+  const double y = info == 0 ? bwd_acc<KP>(L, lds, b, rdiag, lane) : 0.0;
   double x = 0.0;
   for (int e = 0; e < k; ++e) x = fma((double)Hl[e * 64 + lane], readlane_d(y, e), x);
   if (lane < R) reinterpret_cast<XT *>(d.X)[row * d.ldX + lane] = from_double<XT>(x);
 }
 
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool MOD>
 __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev &d, int64_t row,
-                                               int lane, double *Lp, double *Pn) {
+                                               int lane, double *lds) {
   const int32_t t = d.row_task[row];
   if constexpr (RP == 64 && RHS && !WEIGHTED && !FO) {
     // the least-squares update of a row with at most 32 nonzeros: its k x k
@@ -1161,16 +1366,16 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
     const int64_t nb = g.task[t], n = g.task[t + 1] - nb;
     if (d.lambda > 0.0 && d.own == nullptr && n <= 32) {
       if (n <= 16)
-        solve_pushthrough<TR, 16, VEC>(g, d, row, nb, (int)n, lane, Lp);
+        solve_pushthrough<TR, 16, VEC>(g, d, row, nb, (int)n, lane, lds);
       else
-        solve_pushthrough<TR, 32, VEC>(g, d, row, nb, (int)n, lane, Lp);
+        solve_pushthrough<TR, 32, VEC>(g, d, row, nb, (int)n, lane, lds);
       return;
     }
   }
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, g.task[t], g.task[t + 1], acc);
-  solve_from_acc<TR, RP, RHS, FO>(g, d, row, lane, Lp, Pn, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS, MOD>(g, g.task[t], g.task[t + 1], acc);
+  solve_from_acc_regl<TR, RP, RHS, FO>(g, d, row, lane, lds, acc);
 }
 
 // Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
@@ -1179,21 +1384,23 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
 // factors and solves it there, so the Gram never goes to the workspace.
 // The fused right-hand side is reduced over the four nonzero groups with
 // the butterfly of rhs_store.  PERSIST as in k_solve_rows.
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_solve_solo(
+// MOD: the fused update also writes the model values.  The variants with a
+// model output, per-nonzero weights or the persistent loop need more
+// registers and are compiled for two waves per SIMD, the others for three.
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST, bool MOD>
+__global__ __launch_bounds__(64) __attribute__((
+    amdgpu_waves_per_eu((PERSIST || MOD || WEIGHTED) ? 2 : 3))) void k_solve_solo(
     GramDev g, SolveDev d) {
-  using P = Packed<RP>;
-  __shared__ double Lp[P::LDS];
-  __shared__ double Pn[PanelBuf<RP>::SIZE];
+  __shared__ double lds[SoloLds<RP>::DOUBLES];
   if (d.skip && *d.skip != 0.0) return;
   if constexpr (PERSIST) {
     for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
       const int lane = opaque_lane(threadIdx.x);  // per row (see k_solve_rows)
-      solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[idx], lane, Lp, Pn);
+      solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO, MOD>(g, d, d.rows[idx], lane, lds);
       asm volatile("" ::: "memory");
     }
   } else {
-    solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO>(g, d, d.rows[blockIdx.x], threadIdx.x, Lp, Pn);
+    solve_solo_row<TR, RP, VEC, WEIGHTED, RHS, FO, MOD>(g, d, d.rows[blockIdx.x], threadIdx.x, lds);
   }
 }
 
@@ -1213,7 +1420,7 @@ struct HeavySoloLds {
   static constexpr int DOUBLES = ((RED > FAC ? RED : FAC) + 7) / 8;
 };
 
-template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO>
+template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool MOD>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RP == 64 ? 2 : 4))) void k_gram_solve_heavy(GramDev g,
                                                                                SolveDev d) {
@@ -1233,7 +1440,7 @@ __attribute__((amdgpu_waves_per_eu(RP == 64 ? 2 : 4))) void k_gram_solve_heavy(G
   const int64_t b0 = min(ne, nb + w * per), b1 = min(ne, b0 + per);
   GramAcc<RP> acc;
   acc.zero();
-  gram_accum<TR, RP, VEC, WEIGHTED, RHS>(g, b0, b1, acc);
+  gram_accum<TR, RP, VEC, WEIGHTED, RHS, MOD>(g, b0, b1, acc);
   for (int q = 0; q < NW; ++q) {
     if (w == q) {
 #pragma unroll
@@ -1375,17 +1582,22 @@ static void launch_solo_rp(const GramDev &d, const SolveDev &sd, const GramLists
   sd2.nrow = gl.nsolo;
   const dim3 grid(solve_grid(sd2)), block(64);
   const bool pers = grid.x < (unsigned)gl.nsolo;
-#define TT_SOLO(FO)                                                                    \
+#define TT_SOLO(FO, MOD)                                                               \
   do {                                                                                 \
-    if (pers) k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, true><<<grid, block, 0, s>>>(d, sd2); \
-    else k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, false><<<grid, block, 0, s>>>(d, sd2); \
+    if (pers) k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, true, MOD><<<grid, block, 0, s>>>(d, sd2); \
+    else k_solve_solo<TR, RP, VEC, WEIGHTED, RHS, FO, false, MOD><<<grid, block, 0, s>>>(d, sd2); \
   } while (0)
   if constexpr (RHS) {
     // the fused right-hand side always comes with a solve
-    TT_SOLO(false);
+    bool mod = false;
+    if constexpr (!WEIGHTED) {
+      mod = d.model != nullptr;
+      if (mod) TT_SOLO(false, true);
+    }
+    if (!mod) TT_SOLO(false, false);
   } else {
-    if (sd.factor_only) TT_SOLO(true);
-    else TT_SOLO(false);
+    if (sd.factor_only) TT_SOLO(true, false);
+    else TT_SOLO(false, false);
   }
 #undef TT_SOLO
 }
@@ -1403,12 +1615,17 @@ static void launch_hsolo_rp(const GramDev &d, const SolveDev &sd, const GramList
   const dim3 grid((unsigned)gl.nhsolo), block(256);
   if constexpr (RHS) {
     // the fused right-hand side always comes with a solve
-    k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+    bool mod = false;
+    if constexpr (!WEIGHTED) {
+      mod = d.model != nullptr;
+      if (mod) k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false, true><<<grid, block, 0, s>>>(d, sd2);
+    }
+    if (!mod) k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false, false><<<grid, block, 0, s>>>(d, sd2);
   } else {
     if (sd.factor_only)
-      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, true><<<grid, block, 0, s>>>(d, sd2);
+      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, true, false><<<grid, block, 0, s>>>(d, sd2);
     else
-      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false><<<grid, block, 0, s>>>(d, sd2);
+      k_gram_solve_heavy<TR, RP, VEC, WEIGHTED, RHS, false, false><<<grid, block, 0, s>>>(d, sd2);
   }
 }
 
