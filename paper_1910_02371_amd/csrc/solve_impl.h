@@ -688,8 +688,10 @@ __device__ __forceinline__ double rsqrt_newton(double d) {
   return y;
 }
 __device__ __forceinline__ double rsqrt_pivot(double d) {
-  if (__builtin_expect(d < 0x1p-900, 0)) return rsqrt_newton(d * 0x1p960) * 0x1p480;
-  return rsqrt_newton(d);
+  // selects rather than a branch: one estimate and refinement per pivot
+  const bool tiny = d < 0x1p-900;
+  const double y = rsqrt_newton(tiny ? d * 0x1p960 : d);
+  return tiny ? y * 0x1p480 : y;
 }
 
 // A copy of the lane index that the compiler cannot identify with the
@@ -1185,15 +1187,22 @@ struct PushLds {
 
 // LDS of a k_solve_solo workgroup (doubles): the largest of the Gram in the
 // tile layout, the panel buffer, the backward-solve buffer, the factor
-// staging (PS + 64 floats) and, at RP = 64, the push-through solves.
-template <int RP>
+// staging (PS + 64 floats) and, for the push-through solves (PUSH), their
+// buffers.
+template <int RP, bool PUSH>
 struct SoloLds {
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int FAC = cmax(cmax(gram_task_elems(RP) / 2, PanelBuf<RP>::SIZE),
                                   cmax(BwdBuf::SIZE, (Packed<RP>::PS + 64 + 1) / 2));
-  static constexpr int DOUBLES =
-      RP == 64 ? cmax(FAC, cmax(PushLds<16>::SIZE, PushLds<32>::SIZE)) : FAC;
+  static constexpr int DOUBLES = PUSH ? cmax(FAC, cmax(PushLds<16>::SIZE, PushLds<32>::SIZE)) : FAC;
 };
+
+// Rows of at most 32 nonzeros take the push-through solve in the unweighted
+// fused least-squares update at padded rank 64.
+template <int RP, bool WEIGHTED, bool RHS, bool FO>
+constexpr bool solo_push() {
+  return RP == 64 && RHS && !WEIGHTED && !FO;
+}
 
 // solve_from_acc with L kept in the accumulator tiles (chol_core REGL) and
 // one LDS block `lds` that holds in turn the right-hand side reduction, the
@@ -1360,7 +1369,7 @@ template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool MOD
 __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev &d, int64_t row,
                                                int lane, double *lds) {
   const int32_t t = d.row_task[row];
-  if constexpr (RP == 64 && RHS && !WEIGHTED && !FO) {
+  if constexpr (solo_push<RP, WEIGHTED, RHS, FO>()) {
     // the least-squares update of a row with at most 32 nonzeros: its k x k
     // system (uniform over the wave)
     const int64_t nb = g.task[t], n = g.task[t + 1] - nb;
@@ -1384,14 +1393,22 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
 // factors and solves it there, so the Gram never goes to the workspace.
 // The fused right-hand side is reduced over the four nonzero groups with
 // the butterfly of rhs_store.  PERSIST as in k_solve_rows.
-// MOD: the fused update also writes the model values.  The variants with a
-// model output, per-nonzero weights or the persistent loop need more
-// registers and are compiled for two waves per SIMD, the others for three.
+// MOD: the fused update also writes the model values.  Waves per SIMD the
+// kernel is compiled for: the variants with a model output, per-nonzero
+// weights or the persistent loop need more registers (two), the factor-only
+// one fits four (10 KB of LDS at RP = 64), the others three.
+#ifndef TT_SOLO_FO_WAVES
+#define TT_SOLO_FO_WAVES 4
+#endif
+template <bool WEIGHTED, bool RHS, bool FO, bool PERSIST, bool MOD>
+constexpr int solo_waves() {
+  return (PERSIST || MOD || WEIGHTED) ? 2 : (FO && !RHS) ? TT_SOLO_FO_WAVES : 3;
+}
+
 template <class TR, int RP, bool VEC, bool WEIGHTED, bool RHS, bool FO, bool PERSIST, bool MOD>
-__global__ __launch_bounds__(64) __attribute__((
-    amdgpu_waves_per_eu((PERSIST || MOD || WEIGHTED) ? 2 : 3))) void k_solve_solo(
-    GramDev g, SolveDev d) {
-  __shared__ double lds[SoloLds<RP>::DOUBLES];
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
+    solo_waves<WEIGHTED, RHS, FO, PERSIST, MOD>()))) void k_solve_solo(GramDev g, SolveDev d) {
+  __shared__ double lds[SoloLds<RP, solo_push<RP, WEIGHTED, RHS, FO>()>::DOUBLES];
   if (d.skip && *d.skip != 0.0) return;
   if constexpr (PERSIST) {
     for (int64_t idx = blockIdx.x; idx < d.nrow; idx += gridDim.x) {
