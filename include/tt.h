@@ -162,10 +162,16 @@ tt_status tt_index_reserve(tt_index *ix, int R, tt_dtype fdt, uint32_t flags);
  *               mode's column records exceed 2 MiB.  Built on first use
  *               (allocation, synchronization; 16 bytes per nonzero per
  *               mode); results do not depend on it
+ *   ccd_lds     tt_ccd_sweep's record gathers: -1: in each mode's pass the
+ *               column records of the smaller other mode are copied into
+ *               LDS by every workgroup first when they fit in 48 KiB (the
+ *               workgroups then loop over the pass's tasks), so only the
+ *               other mode's records are gathered from memory; 0: both
+ *               from memory.  Results do not depend on it
  * tt_index_tune rebuilds the partitions on `stream` and synchronizes it (it
  * is not capturable, and fails with TT_ERR_INVALID_ARG while an instantiated
  * graph is alive); call tt_index_reserve again afterwards if the
- * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0, -1, -1.
+ * workspace was reserved.  Defaults: 1024, 4096, 512, 4, 0, -1, -1, -1.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t chunk;
@@ -175,6 +181,7 @@ typedef struct {
   int32_t solve_wgs;
   int32_t pcg_wgs;
   int32_t ccd_xcd;
+  int32_t ccd_lds;
 } tt_tuning;
 tt_status tt_index_tune(tt_index *ix, const tt_tuning *tuning, hipStream_t stream);
 tt_status tt_index_get_tuning(const tt_index *ix, tt_tuning *out);
@@ -413,7 +420,8 @@ tt_status tt_gn_step(tt_index *ix, void *const *d_A, int R, int64_t ldA,
  * info 1 and 0, the potrf convention).  Columns r - 1 and r of each factor
  * are read from one record per row.  Depending on the tuning (ccd_xcd) a
  * mode's pass streams its nonzeros regrouped per XCD bucket (the layout is
- * built on the first call).  Factors are updated in place.  Requires t.
+ * built on the first call), and (ccd_lds) reads the records of a small
+ * other mode from an LDS copy.  Factors are updated in place.  Requires t.
  *   d_info          optional int32[sum_n I_n]: the rank-1 solves' info of
  *                   the last column.
  * Workspaces (N m values, 4 (sum_n I_n + N) values, 16 bytes per Gram task)

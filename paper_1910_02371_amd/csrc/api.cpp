@@ -482,6 +482,7 @@ tt_status tt_index_tune(tt_index *ix, const tt_tuning *t, hipStream_t stream) {
            t->solve_wgs);
   TT_CHECK(t->pcg_wgs >= -1 && t->pcg_wgs <= 16, "pcg_wgs %d outside [-1, 16]", t->pcg_wgs);
   TT_CHECK(t->ccd_xcd >= -1 && t->ccd_xcd <= 1, "ccd_xcd %d outside [-1, 1]", t->ccd_xcd);
+  TT_CHECK(t->ccd_lds == -1 || t->ccd_lds == 0, "ccd_lds %d is not -1 or 0", t->ccd_lds);
   TT_CHECK(live_graphs() == 0,
            "%d instantiated graph(s) are alive: retuning rebuilds the work partitions "
            "their kernels read; destroy the graphs first", live_graphs());

@@ -54,18 +54,16 @@ __global__ void k_ccd_column(const T *__restrict__ A, int64_t ldA, int64_t I, in
 // old to its new rank-1 term and stored back.  (A task per quarter wave was
 // measured slower on short rows: the passes are bound by the gathers'
 // cache-line transfers, not by the number of waves.)
-template <class AT, class VT, int GL>
-__global__ __launch_bounds__(256) void k_ccd_tasks(
-    const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ sched,
-    const int32_t *__restrict__ key, const int32_t *__restrict__ o0,
-    const int32_t *__restrict__ o1, VT *__restrict__ rho,
-    const typename Rec4<AT>::type *__restrict__ rn,
-    const typename Rec4<AT>::type *__restrict__ r0,
-    const typename Rec4<AT>::type *__restrict__ r1, int move, double *__restrict__ part) {
-  // group q of workgroup j takes task (256 / GL) j + q, or the one the
-  // schedule gives
-  const int64_t slot = (int64_t)blockIdx.x * (256 / GL) + (threadIdx.x / GL);
-  const int64_t t = sched ? (int64_t)sched[slot] : slot;
+template <class AT, class VT, int GL, int LS>
+__device__ __forceinline__ void ccd_task(int64_t t, int64_t ntask, const int64_t *__restrict__ task,
+                                         const int32_t *__restrict__ key,
+                                         const int32_t *__restrict__ o0,
+                                         const int32_t *__restrict__ o1, VT *__restrict__ rho,
+                                         const typename Rec4<AT>::type *__restrict__ rn,
+                                         const typename Rec4<AT>::type *__restrict__ r0,
+                                         const typename Rec4<AT>::type *__restrict__ r1,
+                                         const typename Rec4<AT>::type *st, int move,
+                                         double *__restrict__ part) {
   const int lane = threadIdx.x % GL;
   // (no early return: every lane of the wave takes part in the butterfly)
   const bool live = t >= 0 && t < ntask;
@@ -90,8 +88,9 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
     R4 a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      a[u] = r0[i0[u]];
-      b[u] = r1[i1[u]];
+      // LS: that side's records come from the workgroup's LDS copy
+      a[u] = LS == 0 ? st[i0[u]] : r0[i0[u]];
+      b[u] = LS == 1 ? st[i1[u]] : r1[i1[u]];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -118,6 +117,40 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
   if (live && lane == 0) {
     part[2 * t] = num;
     part[2 * t + 1] = den;
+  }
+}
+
+extern __shared__ double4 ccd_lds[];
+
+// Wave q of workgroup j takes slot 4 j + q (task = the slot, or the one the
+// schedule gives).  LS = 0 or 1: the workgroup first copies the nstage
+// records of that side (r0 or r1) into LDS, then its waves loop over slots
+// 4 (j + k gridDim.x) + q; with a schedule the grid is a multiple of 8, so
+// the workgroup stays on the XCD the schedule meant for those slots.  (The
+// records staged are the small side's, which mostly hit the L1 cache
+// otherwise: the copy saves ~7 % of such a pass; the other side's gathers
+// from L2 remain the bound.)
+template <class AT, class VT, int GL, int LS>
+__global__ __launch_bounds__(256) void k_ccd_tasks(
+    const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ sched,
+    int64_t nslot, const int32_t *__restrict__ key, const int32_t *__restrict__ o0,
+    const int32_t *__restrict__ o1, VT *__restrict__ rho,
+    const typename Rec4<AT>::type *__restrict__ rn,
+    const typename Rec4<AT>::type *__restrict__ r0,
+    const typename Rec4<AT>::type *__restrict__ r1, int64_t nstage, int move,
+    double *__restrict__ part) {
+  static_assert(GL == 64, "one-wave slots, four per workgroup");
+  using R4 = typename Rec4<AT>::type;
+  R4 *st = reinterpret_cast<R4 *>(ccd_lds);
+  if constexpr (LS >= 0) {
+    const R4 *src = LS == 0 ? r0 : r1;
+    for (int64_t i = threadIdx.x; i < nstage; i += blockDim.x) st[i] = src[i];
+    __syncthreads();
+  }
+  const int64_t stride = LS >= 0 ? 4 * (int64_t)gridDim.x : nslot;
+  for (int64_t slot = (int64_t)blockIdx.x * 4 + threadIdx.x / GL; slot < nslot; slot += stride) {
+    const int64_t t = sched ? (int64_t)sched[slot] : slot;
+    ccd_task<AT, VT, GL, LS>(t, ntask, task, key, o0, o1, rho, rn, r0, r1, st, move, part);
   }
 }
 
@@ -190,14 +223,36 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
       const int32_t *key = L ? L->d_key : md.d_key;
       const int32_t *a0 = L ? L->d_oidx[q0] : md.d_oidx[q0];
       const int32_t *a1 = L ? L->d_oidx[q1] : md.d_oidx[q1];
-      if (L) {  // the layout's schedule: one wave per task, four per workgroup
-        k_ccd_tasks<AT, VT, 64><<<(unsigned)L->nsched, 256, 0, s>>>(
-            L->d_task, ntask, L->d_sched, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n],
-            (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0, part);
+      const int64_t *tk = L ? L->d_task : md.d_task;
+      const int32_t *sched = L ? L->d_sched : nullptr;
+      // slots: with the layout's schedule four per scheduled workgroup (one
+      // wave per task), else one per task
+      const int64_t nslot = L ? 4 * L->nsched : ntask;
+      // the smaller other mode's records in LDS when they fit
+      const int qs = ix->mode[q0].I <= ix->mode[q1].I ? q0 : q1;
+      const int64_t nstage = ix->mode[qs].I;
+      const int64_t stage_bytes = nstage * (int64_t)sizeof(R4);
+      const bool lds = ix->tune.ccd_lds != 0 && stage_bytes <= kCcdLdsBytes;
+      const R4 *rq0 = (const R4 *)recs[q0], *rq1 = (const R4 *)recs[q1];
+      const int mv = r > 0 ? 1 : 0;
+      if (lds) {
+        // as many workgroups as are resident at once (registers and LDS
+        // copies), a multiple of 8 in all: the workgroups loop over the
+        // slots, so a second round would only lengthen the pass
+        const size_t shm = (size_t)std::max<int64_t>(stage_bytes, 16);
+        auto kern = qs == q0 ? &k_ccd_tasks<AT, VT, 64, 0> : &k_ccd_tasks<AT, VT, 64, 1>;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, shm) != hipSuccess ||
+            per_cu < 1)
+          per_cu = 1;
+        int64_t grid = std::min<int64_t>((nslot + 3) / 4, (int64_t)per_cu * std::max(ix->cu_count, 8));
+        grid = std::max<int64_t>(8, grid / 8 * 8);
+        kern<<<(unsigned)grid, 256, shm, s>>>(tk, ntask, sched, nslot, key, a0, a1, (VT *)rho[n],
+                                              (const R4 *)recs[n], rq0, rq1, nstage, mv, part);
       } else {
-        k_ccd_tasks<AT, VT, 64><<<(unsigned)((ntask + 3) / 4), 256, 0, s>>>(
-            md.d_task, ntask, nullptr, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n],
-            (const R4 *)recs[q0], (const R4 *)recs[q1], r > 0 ? 1 : 0, part);
+        k_ccd_tasks<AT, VT, 64, -1><<<(unsigned)((nslot + 3) / 4), 256, 0, s>>>(
+            tk, ntask, sched, nslot, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n], rq0, rq1, 0,
+            mv, part);
       }
     }
     ProfScope ps("ccd_rows", s, (double)ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),

@@ -23,6 +23,9 @@ constexpr int kGramWavesDefault = 4;
 constexpr int kSolveWgsDefault = 0;
 constexpr int kPcgWgsDefault = -1;
 constexpr int kCcdXcdDefault = -1;
+constexpr int kCcdLdsDefault = -1;
+// Largest record set a CCD++ pass copies into LDS (tuning ccd_lds).
+constexpr int64_t kCcdLdsBytes = 48 * 1024;
 constexpr int kReduceMin = 4;      // rows with more tasks are pre-reduced
 constexpr int kSegSlots = 16;      // carry slots summed per first-level block
 constexpr int64_t kGramBatchBytes = 256ll << 20;  // Gram workspace per batch
@@ -133,7 +136,7 @@ struct tt_index {
   int64_t max_I = 0, sum_I = 0, max_nchunk = 0, max_nslot = 0, max_nseg = 0;
   tt_tuning tune = {tt::kChunkDefault, tt::kGramPieceDefault, tt::kGramLightDefault,
                     tt::kGramWavesDefault, tt::kSolveWgsDefault, tt::kPcgWgsDefault,
-                    tt::kCcdXcdDefault};
+                    tt::kCcdXcdDefault, tt::kCcdLdsDefault};
   int cu_count = 0;  // compute units of the device the index was built on
   // Gauss-Newton position map (built on first use, N x m): slot n != zmode
   // maps mode-n sorted positions to mode-zmode sorted positions

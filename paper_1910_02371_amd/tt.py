@@ -76,7 +76,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("gram_piece", ctypes.c_int32),
                 ("gram_light", ctypes.c_int32), ("gram_waves", ctypes.c_int32),
                 ("solve_wgs", ctypes.c_int32), ("pcg_wgs", ctypes.c_int32),
-                ("ccd_xcd", ctypes.c_int32)]
+                ("ccd_xcd", ctypes.c_int32), ("ccd_lds", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -188,7 +188,7 @@ class Index:
 
     def tune(self, **kw):
         """Set work-partition parameters (chunk, gram_piece, gram_light,
-        gram_waves, solve_wgs, pcg_wgs, ccd_xcd; unspecified ones keep their value) and rebuild
+        gram_waves, solve_wgs, pcg_wgs, ccd_xcd, ccd_lds; unspecified ones keep their value) and rebuild
         the partitions; reserve the workspace again afterwards."""
         cur = self.tuning()
         unknown = set(kw) - set(cur)

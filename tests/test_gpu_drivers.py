@@ -521,19 +521,21 @@ def test_gam_least_squares_one_iteration_is_als(gpu_lib, form):
 
 
 # ------------------------------------------------------------------ CCD++ ----
+@pytest.mark.parametrize("lds", [-1, 0])
 @pytest.mark.parametrize("xcd", [0, 1])
 @pytest.mark.parametrize("case", list(GAM_CASES))
 @pytest.mark.parametrize("R", [1, 4, 7])
-def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R, xcd):
+def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R, xcd, lds):
     """FP64 form: two CCD++ sweeps equal the oracle's (column views of rank
     1 with the factors' leading dimension; ragged R; empty rows), and the
     objective does not increase; xcd = 1: every mode's stream regrouped by
-    bucket of its largest other mode, tasks scheduled per bucket."""
+    bucket of its largest other mode, tasks scheduled per bucket; lds = -1:
+    the smaller other mode's records read from an LDS copy."""
     tt = gpu_lib
     wl, t, lam, mm = gam_problem(case, "ls")
     A0 = W.init_factors(wl.dims, R, mm, 8, dtype=np.float64)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, "f64"))
-    ix.tune(ccd_xcd=xcd)
+    ix.tune(ccd_xcd=xcd, ccd_lds=lds)
     A = [dev_factor(a, "f64") for a in A0]
     info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
     Ar = A0
@@ -549,20 +551,21 @@ def test_ccd_sweep_f64_matches_oracle(gpu_lib, case, R, xcd):
         f_prev = f
 
 
+@pytest.mark.parametrize("lds", [-1, 0])
 @pytest.mark.parametrize("xcd", [0, 1])
 @pytest.mark.parametrize("form", ["f32", "bf16"])
 @pytest.mark.parametrize("case", ["small", "heavy"])
-def test_ccd_sweep_low_precision_forms(gpu_lib, form, case, xcd):
+def test_ccd_sweep_low_precision_forms(gpu_lib, form, case, xcd, lds):
     """FP32 / BF16 storage: one CCD++ sweep at R = 8 within the form's
     tolerance of the oracle run from the same stored inputs (relative
     Frobenius error per factor), with the sorted and the regrouped stream
-    layouts."""
+    layouts, records gathered from memory or from an LDS copy."""
     tt = gpu_lib
     wl, t, lam, mm = gam_problem(case, "ls")
     t = stored_values(t, form)
     A0 = stored_factors(W.init_factors(wl.dims, 8, mm, 8, dtype=np.float64), form)
     ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
-    ix.tune(ccd_xcd=xcd)
+    ix.tune(ccd_xcd=xcd, ccd_lds=lds)
     A = [dev_factor(a, form) for a in A0]
     tt.ccd_sweep(ix, A, lam)
     Ar, _ = O.ccd_sweep(wl.idx, t, A0, wl.dims, lam)
@@ -598,6 +601,35 @@ def test_ccd_layout_matches_sorted_stream(gpu_lib, form):
     for d in range(3):
         a, b = out[0][0][d], out[1][0][d]
         assert np.linalg.norm(a - b) <= tol * np.linalg.norm(a), f"mode {d}"
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
+def test_ccd_lds_records_bit_exact(gpu_lib, form, xcd):
+    """Reading the smaller other mode's records from an LDS copy changes
+    only where they are read from: two sweeps with ccd_lds = -1 equal those
+    with ccd_lds = 0 bit for bit (factors and info).  On the 60 x 900 x 40
+    tensor every pass stages one side (mode 2 for the passes of modes 0 and
+    1, mode 0 for that of mode 2: both gather sides), with the sorted and
+    the bucketed layouts (the workgroups loop over the scheduled slots)."""
+    tt = gpu_lib
+    wl = W.random_tensor((60, 900, 40), 20000, 13, rank=3, noise=0.01)
+    t = stored_values(wl.t, form)
+    A0 = stored_factors(W.init_factors(wl.dims, 5, float(np.mean(t)), 4, dtype=np.float64),
+                        form)
+    ix = tt.build_index(dev_idx(wl.idx), wl.dims, dev_vals(t, form))
+    out = {}
+    for lds in (0, -1):
+        ix.tune(ccd_xcd=xcd, ccd_lds=lds)
+        A = [dev_factor(a, form) for a in A0]
+        info = torch.full((sum(wl.dims),), -7, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            tt.ccd_sweep(ix, A, 1e-3, info)
+        torch.cuda.synchronize()
+        out[lds] = ([a.clone() for a in A], info.clone())
+    assert torch.equal(out[0][1], out[-1][1])
+    for d in range(3):
+        assert torch.equal(out[0][0][d], out[-1][0][d]), f"mode {d}"
 
 
 def test_ccd_rank1_is_als_f32(gpu_lib):

@@ -662,11 +662,11 @@ def test_padded_ld_vector_path(gpu_lib, form, R, kind):
 # --------------------------------------------------------------- tuning ----
 TUNINGS = [
     dict(chunk=512, gram_piece=2048, gram_light=256, gram_waves=2, solve_wgs=0, pcg_wgs=0,
-         ccd_xcd=0),
+         ccd_xcd=0, ccd_lds=0),
     dict(chunk=2048, gram_piece=8192, gram_light=1024, gram_waves=8, solve_wgs=1, pcg_wgs=2,
-         ccd_xcd=1),
+         ccd_xcd=1, ccd_lds=-1),
     dict(chunk=1024, gram_piece=1024, gram_light=0, gram_waves=4, solve_wgs=4, pcg_wgs=-1,
-         ccd_xcd=-1),
+         ccd_xcd=-1, ccd_lds=-1),
 ]
 
 
