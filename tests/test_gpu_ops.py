@@ -294,6 +294,38 @@ def test_solve_factor_weighted_lowp(gpu_lib, form, R):
         assert be <= {"f32": 1e-5, "bf16": 2e-2}[form], f"backward error {be:.3e} (mode {n})"
 
 
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+@pytest.mark.parametrize("R", [16, 40, 64])
+def test_solve_factor_not_spd_lowp(gpu_lib, form, R):
+    """FP32/BF16 forms, whose one-task rows are factored in the solo-row
+    kernels with L kept in the accumulator tiles: all-negative weights and
+    lambda = 0 make every row's matrix negative semidefinite, so the first
+    pivot fails: info equals the oracle's (LAPACK convention, 1 on every
+    row), those rows of X are 0, and a synchronous call reports
+    TT_ERR_NOT_SPD."""
+    tt = gpu_lib
+    wl, ix = get_index(tt, "uniform", form)
+    A64 = factors(wl.dims, R, 900 + R)
+    As = stored_factors(A64, form)
+    A = [dev_factor(a, form) for a in A64]
+    wneg = -np.ones(wl.nnz)
+    rng = np.random.default_rng(R)
+    for n in range(3):
+        M = stored_values(rng.standard_normal((wl.dims[n], R)), form)
+        X, info = tt.solve_factor(ix, dev_vals(wneg, form), A, n, dev_vals(M, form), 0.0,
+                                  w_order=-1)
+        G = O.gram(wl.idx, wneg, As, n, wl.dims[n])
+        _, ir = O.solve_rows(G, M, 0.0)
+        assert (ir != 0).all()
+        assert np.array_equal(info.cpu().numpy(), ir), f"mode {n}"
+        assert (host(X) == 0).all(), f"mode {n}"
+    M0 = stored_values(np.ones((wl.dims[0], R)), form)
+    with pytest.raises(tt.TTError) as e:
+        tt.solve_factor(ix, dev_vals(wneg, form), A, 0, dev_vals(M0, form), 0.0, w_order=-1,
+                        sync=True)
+    assert e.value.status == -5
+
+
 @pytest.mark.parametrize("form", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("R", [10, 21, 64])
 @pytest.mark.parametrize("kind", ["heavy", "zipf"])
