@@ -84,6 +84,9 @@ def parse(argv=None):
                    help="ALS sweeps per storage form in the BF16-vs-FP32 comparison (0: skip)")
     p.add_argument("--no-ccd", dest="ccd", action="store_false",
                    help="ratings: skip the ALS-vs-CCD++ sweep comparison")
+    p.add_argument("--ccd-lds", type=int, choices=[-1, 0], default=-1,
+                   help="ratings: the CCD++ sweep's ccd_lds tuning (LDS copies of small "
+                        "record sets: -1 automatic, 0 off)")
     p.add_argument("--poisson-iters", type=int, default=3,
                    help="ratings: GAM sweeps and GN steps of the Poisson log-link "
                         "comparison (0: skip)")
@@ -495,7 +498,7 @@ def ratings_extras(tt, leg, args, dev):
         out["poisson"] = compare_poisson(tt, leg.ix, leg.wl, dev, args.poisson_iters)
         log("poisson leg done")
     if args.ccd:
-        out["ccd"] = compare_ccd(tt, leg.ix, leg.A0, leg.wl, leg.lam, dev)
+        out["ccd"] = compare_ccd(tt, leg.ix, leg.A0, leg.wl, leg.lam, dev, args.ccd_lds)
         log("ccd leg done")
     return out
 
@@ -805,13 +808,18 @@ def compare_poisson(tt, ix, wl, dev, iters, R=10, lam=0.1, tol=1e-3, max_inner=5
     return out
 
 
-def compare_ccd(tt, ix, A0, wl, lam, dev):
+def compare_ccd(tt, ix, A0, wl, lam, dev, ccd_lds=-1):
     """One ALS sweep and one CCD++ sweep (Section 2.3: column-wise exact
     coordinate minimization, rank-1 MTTKRP + Solve Factor per column and
     mode) from the same FP32 start: time (HIP events) and training RMSE
     after the sweep.  A first untimed CCD++ sweep on a copy allocates its
-    workspaces."""
+    workspaces.  ccd_lds: the index's tuning for the CCD++ sweeps (restored
+    afterwards)."""
     import torch
+
+    before = ix.tuning()["ccd_lds"]
+    if ccd_lds != before:
+        ix.tune(ccd_lds=ccd_lds)
 
     def fresh():
         return [torch.as_tensor(a).to(dev).contiguous() for a in A0]
@@ -829,11 +837,13 @@ def compare_ccd(tt, ix, A0, wl, lam, dev):
         return e0.elapsed_time(e1)
 
     tt.ccd_sweep(ix, fresh(), lam)
-    out = {"rmse_start": rmse(fresh())}
+    out = {"rmse_start": rmse(fresh()), "ccd_lds": ccd_lds}
     for name, fn in (("als", tt.als_sweep), ("ccd", tt.ccd_sweep)):
         A = fresh()
         out[f"{name}_ms"] = timed(lambda: fn(ix, A, lam))
         out[f"{name}_rmse"] = rmse(A)
+    if ccd_lds != before:
+        ix.tune(ccd_lds=before)
     return out
 
 

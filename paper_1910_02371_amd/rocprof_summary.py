@@ -5,6 +5,9 @@
         <kernel> <workload> <src_hash> <copy_bytes> <out.md> <cmd>
 
 ``stats`` renders the per-kernel table of a ``--kernel-trace --stats`` run.
+``ccd`` (``ccd <out.md> <cmd> <kernel_trace.csv> ...``) gives the per-mode
+pass times of the timed CCD++ sweep of the bench's CCD++ leg, one column
+per trace (one trace per setting).
 ``trace`` (``trace <kernel_trace.csv> <last_kernel> <skip> <out.md> <cmd>``)
 cuts a ``--kernel-trace`` run into calls, each ending with a dispatch whose
 name contains ``last_kernel``, drops the first ``skip`` calls (warm-up) and
@@ -245,6 +248,47 @@ def trace(csv_path, last_kernel, skip, out_md, cmd):
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def ccd(out_md, cmd, *csvs):
+    """Per-mode pass times of the last CCD++ sweep in each kernel trace
+    (one trace per setting, in the order given by `cmd`'s settings): the
+    k_ccd_tasks dispatches of a sweep run column by column, modes 0, 1, 2
+    in turn, so dispatch i of the sweep is mode i mod 3."""
+    cols = []
+    for path in csvs:
+        rows = [r for r in csv.DictReader(open(path)) if "k_ccd_" in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        tasks = [r for r in rows if "k_ccd_tasks" in r["Kernel_Name"]]
+        rws = [r for r in rows if "k_ccd_rows" in r["Kernel_Name"]]
+        colk = [r for r in rows if "k_ccd_column" in r["Kernel_Name"]]
+        # the bench's CCD++ leg runs one untimed and one timed sweep: the
+        # timed one is the second half of the dispatches
+        last = tasks[-(len(tasks) // 2):]
+        per_mode = {}
+        for i, r in enumerate(last):
+            per_mode.setdefault(i % 3, []).append(dur(r))
+        names = sorted({r["Kernel_Name"].split("(")[0] for r in last})
+        cols.append({"mode_us": {m: sum(v) / len(v) for m, v in per_mode.items()},
+                     "rows_us": sum(dur(r) for r in rws[-len(last):]) / max(1, len(last)),
+                     "column_us": sum(dur(r) for r in colk[-len(last):]) / max(1, len(last)),
+                     "columns": len(last) // 3, "kernels": names})
+    lines = [f"# CCD++ sweep: kernel times per mode pass\n", f"Commands: `{cmd}`\n",
+             "| | " + " | ".join(f"setting {i}" for i in range(len(cols))) + " |",
+             "|---" * (len(cols) + 1) + "|"]
+    for m in range(3):
+        lines.append(f"| mode-{m} pass (k_ccd_tasks) us | " +
+                     " | ".join(f"{c['mode_us'][m]:.1f}" for c in cols) + " |")
+    lines.append("| per-row solves (k_ccd_rows) us | " +
+                 " | ".join(f"{c['rows_us']:.1f}" for c in cols) + " |")
+    lines.append("| column start (k_ccd_column) us | " +
+                 " | ".join(f"{c['column_us']:.1f}" for c in cols) + " |")
+    lines.append("| columns in the sweep | " + " | ".join(str(c["columns"]) for c in cols) + " |")
+    lines.append("")
+    for i, c in enumerate(cols):
+        lines.append(f"* setting {i} pass kernels: " + ", ".join(f"`{n}`" for n in c["kernels"]))
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
@@ -254,5 +298,7 @@ if __name__ == "__main__":
         counters(*sys.argv[2:])
     elif sys.argv[1] == "trace":
         trace(*sys.argv[2:7])
+    elif sys.argv[1] == "ccd":
+        ccd(*sys.argv[2:])
     else:
         raise SystemExit(__doc__)

@@ -80,14 +80,36 @@ def test_poisson_leg_reports_divergence_as_null(fake, monkeypatch):
     assert out["gn"]["loss"] == [None, None]
 
 
-def test_ccd_leg(fake):
+class _TunedIndex:
+    """Stand-in for an index's tuning calls."""
+
+    def __init__(self):
+        self.cur = {"ccd_lds": -1}
+        self.log = []
+
+    def tuning(self):
+        return dict(self.cur)
+
+    def tune(self, **kw):
+        self.log.append(kw)
+        self.cur.update(kw)
+
+
+@pytest.mark.parametrize("lds", [-1, 0])
+def test_ccd_leg(fake, lds):
+    """The CCD++ leg: keys, call counts, and the ccd_lds setting applied for
+    the leg only (restored afterwards; no retuning when it is the index's)."""
     tt, calls = fake
     wl = W.random_tensor((20, 15, 10), 300, 3)
     A0 = W.init_factors(wl.dims, 4, 1.0, 3)
-    out = bench.compare_ccd(tt, None, A0, wl, 1e-5, "cpu")
+    ix = _TunedIndex()
+    out = bench.compare_ccd(tt, ix, A0, wl, 1e-5, "cpu", lds)
     json.loads(json.dumps(out, allow_nan=False))
-    assert set(out) == {"rmse_start", "als_ms", "als_rmse", "ccd_ms", "ccd_rmse"}
+    assert set(out) == {"rmse_start", "als_ms", "als_rmse", "ccd_ms", "ccd_rmse", "ccd_lds"}
+    assert out["ccd_lds"] == lds
     assert calls.count("ccd_sweep") == 2 and calls.count("als_sweep") == 1
+    assert ix.log == ([] if lds == -1 else [{"ccd_lds": 0}, {"ccd_lds": -1}])
+    assert ix.cur["ccd_lds"] == -1
 
 
 def _rec(ms, launches, nbytes, flops):
