@@ -1388,11 +1388,12 @@ __device__ __forceinline__ void solve_solo_row(const GramDev &g, const SolveDev 
 }
 
 // Rows whose only Gram task is light (FP32 and BF16 forms): the wave forms
-// the row's Gram on the matrix cores (gram_accum), stores it in the tile
-// layout into the LDS that the factorization later reuses for L, and
-// factors and solves it there, so the Gram never goes to the workspace.
-// The fused right-hand side is reduced over the four nonzero groups with
-// the butterfly of rhs_store.  PERSIST as in k_solve_rows.
+// the row's Gram on the matrix cores (gram_accum), stages it in the tile
+// layout in LDS, loads it into the FP64 accumulator tiles and factors and
+// solves it there (solve_from_acc_regl: L stays in the tiles), so the Gram
+// never goes to the workspace.  The fused right-hand side is reduced over
+// the four nonzero groups with the butterfly of rhs_store.  PERSIST as in
+// k_solve_rows.
 // MOD: the fused update also writes the model values.  Waves per SIMD the
 // kernel is compiled for: the variants with a model output, per-nonzero
 // weights or the persistent loop need more registers (two), the factor-only
