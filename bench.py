@@ -446,7 +446,8 @@ def main(argv=None):
             "step": (step_desc(cfg_leg) if cfg_leg is not None else
                      "TTTP (model values in the index's mode-0 order) + ALS sweep "
                      "(3 x [MTTKRP + Solve Factor], the MTTKRP right-hand side formed in "
-                     "the Gram pass)"),
+                     "the Gram pass; the TTTP formed in mode 0's pass from the same "
+                     "gathered rows)"),
             "R": R, "factor_storage": args.form, "lambda": 1e-5,
             "lambda_gn": 1e-3 if args.workload == "ratings" else None,
             "loss": "least squares",
