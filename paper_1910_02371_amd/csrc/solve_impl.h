@@ -672,25 +672,29 @@ __device__ __forceinline__ double newton_rhs(const SolveDev &d, int64_t row, int
 }
 
 // Pivot of step k: 1 / sqrt(d) for d > 0 (d is the broadcast pivot, the
-// same on every lane, so the branch below is uniform).  The hardware
-// reciprocal square root estimate is refined by two Newton steps
-// y <- y + y (1 - d y^2) / 2 (each squares the relative error, so the result
-// is within a few ulp).  Pivots below 2^-900 are scaled by 2^960 first and
-// the result by 2^480 (both exact), so d y^2 neither underflows nor
-// overflows.
+// same on every lane).  The hardware reciprocal square root estimate is
+// refined by NIT Newton steps y <- y + y (1 - d y^2) / 2, each of which
+// squares the relative error: two give a result within a few ulp; one, from
+// the estimate's ~2^-22, leaves ~2^-43, which is what the FP32 and BF16
+// forms' solves use (a relative error below 1e-12 in each column of L is a
+// backward error of the same size, far below their tolerance).  Pivots
+// below 2^-900 are scaled by 2^960 first and the result by 2^480 (both
+// exact), so d y^2 neither underflows nor overflows.
+template <int NIT>
 __device__ __forceinline__ double rsqrt_newton(double d) {
   double y = __builtin_amdgcn_rsq(d);
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < NIT; ++it) {
     const double e = fma(-d, y * y, 1.0);
     y = fma(0.5 * y, e, y);
   }
   return y;
 }
+template <int NIT>
 __device__ __forceinline__ double rsqrt_pivot(double d) {
   // selects rather than a branch: one estimate and refinement per pivot
   const bool tiny = d < 0x1p-900;
-  const double y = rsqrt_newton(tiny ? d * 0x1p960 : d);
+  const double y = rsqrt_newton<NIT>(tiny ? d * 0x1p960 : d);
   return tiny ? y * 0x1p480 : y;
 }
 
@@ -800,9 +804,11 @@ __device__ __forceinline__ double bwd_regs(const double *Lp, double b, double rd
 // holds y on return.
 // The row's Gram is the sum of `ntask` consecutive tile-layout matrices at
 // gbase (task workspace, or the LDS copy of a Gram formed in the kernel).
-// REGL: no LDS copy of L; after each panel's trailing update the factored
-// columns are written back from the panel buffer into the tiles of column
-// block J (replacing what the update left there), so on return tile (I, J)
+// REGL (the FP32 and BF16 forms' solo-row kernels): one Newton step per
+// pivot (rsqrt_pivot); no LDS copy of L; after each panel's trailing update
+// the factored columns are written back from the panel buffer into the
+// tiles of column block J (replacing what the update left there), so on
+// return tile (I, J)
 // holds L in the accumulator layout, zero above the diagonal (bwd_acc,
 // store_acc read it from there).
 template <int RP>
@@ -900,7 +906,7 @@ __device__ __forceinline__ int chol_core(f64x4 (&acc)[chol_nt<RP>()], int lane, 
       const int k = k0 + c;
       const double dkk = readlane_d(x[c], k);
       if (!(dkk > 0.0)) return k + 1;
-      const double inv = rsqrt_pivot(dkk);
+      const double inv = rsqrt_pivot<REGL ? 1 : 2>(dkk);
       if (lane == k) rdiag = inv;
       const double lik = lane >= k ? x[c] * inv : 0.0;
       x[c] = lik;
