@@ -45,8 +45,9 @@ STREAM_OP = {"tttp": 0, "mttkrp": 1, "gradient": 2, "gn_matvec": 3, "gn_mttkrp":
 
 
 # fused Gram + Cholesky of rows with one light task:
-# k_solve_solo<traits, RP, vec, weighted, rhs, factor_only, persist>; with one
-# heavy task: k_gram_solve_heavy<traits, RP, vec, weighted, rhs, factor_only>
+# k_solve_solo<traits, RP, vec, weighted, rhs, factor_only, persist, model>;
+# with one heavy task:
+# k_gram_solve_heavy<traits, RP, vec, weighted, rhs, factor_only, model>
 SOLO_FO = {"gram_solve_light": ("k_solve_solo<", "false"),
            "gram_factor_light": ("k_solve_solo<", "true"),
            "gram_solve_heavy": ("k_gram_solve_heavy<", "false"),
