@@ -54,21 +54,50 @@ __global__ void k_ccd_column(const T *__restrict__ A, int64_t ldA, int64_t I, in
 // old to its new rank-1 term and stored back.  (A task per quarter wave was
 // measured slower on short rows: the passes are bound by the gathers'
 // cache-line transfers, not by the number of waves.)
-template <class AT, class VT, int GL, int LS>
+// Rows with a single task (row_task[i + 1] - row_task[i] == 1) are solved by
+// that task's wave right away (RowSolve), exactly as k_ccd_rows would from
+// the one partial; k_ccd_rows skips them.
+template <class T, class AT>
+struct RowSolve {
+  const int32_t *row_task;
+  double lambda;
+  T *A;
+  int64_t ldA;
+  int r;
+  typename Rec4<AT>::type *rec;  // the pass's own mode's records
+  int32_t *info;
+};
+
+// The rank-1 solve of row i from its sums (LAPACK convention: a non-positive
+// pivot gives info 1 and x = 0); x goes to column r of the factor (storage
+// dtype) and, as stored, to the current value of the record.
+template <class T, class AT>
+__device__ __forceinline__ void ccd_solve_row(const RowSolve<T, AT> &rs, int64_t i, double num,
+                                              double den) {
+  const double piv = rs.lambda + den;
+  const bool ok = piv > 0.0;
+  const T x = from_double<T>(ok ? num / piv : 0.0);
+  rs.A[i * rs.ldA + rs.r] = x;
+  rs.rec[i].w = (AT)to_double<T>(x);
+  if (rs.info) rs.info[i] = ok ? 0 : 1;
+}
+
+template <class T, class AT, class VT, int GL, int LS>
 __device__ __forceinline__ void ccd_task(int64_t t, int64_t ntask, const int64_t *__restrict__ task,
                                          const int32_t *__restrict__ key,
                                          const int32_t *__restrict__ o0,
                                          const int32_t *__restrict__ o1, VT *__restrict__ rho,
-                                         const typename Rec4<AT>::type *__restrict__ rn,
+                                         const typename Rec4<AT>::type *rn,
                                          const typename Rec4<AT>::type *__restrict__ r0,
                                          const typename Rec4<AT>::type *__restrict__ r1,
                                          const typename Rec4<AT>::type *st, int move,
-                                         double *__restrict__ part) {
+                                         double *__restrict__ part, const RowSolve<T, AT> &rs) {
   const int lane = threadIdx.x % GL;
   // (no early return: every lane of the wave takes part in the butterfly)
   const bool live = t >= 0 && t < ntask;
   const int64_t nb = live ? task[t] : 0, ne = live ? task[t + 1] : 0;
-  const auto un = live ? rn[key[nb]] : typename Rec4<AT>::type{};  // one row per task
+  const int32_t own_row = live ? key[nb] : 0;  // one row per task
+  const auto un = live ? rn[own_row] : typename Rec4<AT>::type{};
   const double own_old = (double)un.z;
   // each lane takes nonzeros lane, lane + GL, ... in order, U at a time:
   // all their loads and gathers are issued before the first is used
@@ -115,8 +144,12 @@ __device__ __forceinline__ void ccd_task(int64_t t, int64_t ntask, const int64_t
     den += __shfl_xor(den, o);
   }
   if (live && lane == 0) {
-    part[2 * t] = num;
-    part[2 * t + 1] = den;
+    if (rs.row_task[own_row + 1] - rs.row_task[own_row] == 1) {
+      ccd_solve_row<T, AT>(rs, own_row, num, den);
+    } else {
+      part[2 * t] = num;
+      part[2 * t + 1] = den;
+    }
   }
 }
 
@@ -130,15 +163,15 @@ extern __shared__ double4 ccd_lds[];
 // records staged are the small side's, which mostly hit the L1 cache
 // otherwise: the copy saves ~7 % of such a pass; the other side's gathers
 // from L2 remain the bound.)
-template <class AT, class VT, int GL, int LS>
+template <class T, class AT, class VT, int GL, int LS>
 __global__ __launch_bounds__(256) void k_ccd_tasks(
     const int64_t *__restrict__ task, int64_t ntask, const int32_t *__restrict__ sched,
     int64_t nslot, const int32_t *__restrict__ key, const int32_t *__restrict__ o0,
     const int32_t *__restrict__ o1, VT *__restrict__ rho,
-    const typename Rec4<AT>::type *__restrict__ rn,
+    const typename Rec4<AT>::type *rn,  // the own mode's records (rs.rec)
     const typename Rec4<AT>::type *__restrict__ r0,
     const typename Rec4<AT>::type *__restrict__ r1, int64_t nstage, int move,
-    double *__restrict__ part) {
+    double *__restrict__ part, RowSolve<T, AT> rs) {
   static_assert(GL == 64, "one-wave slots, four per workgroup");
   using R4 = typename Rec4<AT>::type;
   R4 *st = reinterpret_cast<R4 *>(ccd_lds);
@@ -150,26 +183,25 @@ __global__ __launch_bounds__(256) void k_ccd_tasks(
   const int64_t stride = LS >= 0 ? 4 * (int64_t)gridDim.x : nslot;
   for (int64_t slot = (int64_t)blockIdx.x * 4 + threadIdx.x / GL; slot < nslot; slot += stride) {
     const int64_t t = sched ? (int64_t)sched[slot] : slot;
-    ccd_task<AT, VT, GL, LS>(t, ntask, task, key, o0, o1, rho, rn, r0, r1, st, move, part);
+    ccd_task<T, AT, VT, GL, LS>(t, ntask, task, key, o0, o1, rho, rn, r0, r1, st, move, part,
+                                rs);
   }
 }
 
-// One wave per row: the row's task partials summed in FP64 (lanes stride
-// over the tasks, then a fixed butterfly), the rank-1 solve
-// (lambda + den) x = num (LAPACK convention: a non-positive pivot gives
-// info 1 and x = 0), x stored into column r of the factor (storage dtype)
-// and, as stored, as the current value of the record.
+// One wave per row with several tasks or none (single-task rows were solved
+// by their task's wave): the row's task partials summed in FP64 (lanes
+// stride over the tasks, then a fixed butterfly) and the rank-1 solve
+// (lambda + den) x = num (ccd_solve_row).
 template <class T, class AT>
-__global__ __launch_bounds__(256) void k_ccd_rows(const int32_t *__restrict__ row_task,
-                                                  int64_t I, const double *__restrict__ part,
-                                                  double lambda, T *A, int64_t ldA, int r,
-                                                  typename Rec4<AT>::type *__restrict__ rec,
-                                                  int32_t *info) {
+__global__ __launch_bounds__(256) void k_ccd_rows(int64_t I, const double *__restrict__ part,
+                                                  RowSolve<T, AT> rs) {
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < I;
        i += (int64_t)gridDim.x * 4) {
+    const int32_t t0 = rs.row_task[i], t1 = rs.row_task[i + 1];
+    if (t1 - t0 == 1) continue;  // uniform over the wave
     double num = 0.0, den = 0.0;
-    for (int32_t t = row_task[i] + lane; t < row_task[i + 1]; t += 64) {
+    for (int32_t t = t0 + lane; t < t1; t += 64) {
       num += part[2 * t];
       den += part[2 * t + 1];
     }
@@ -178,14 +210,7 @@ __global__ __launch_bounds__(256) void k_ccd_rows(const int32_t *__restrict__ ro
       num += __shfl_xor(num, o);
       den += __shfl_xor(den, o);
     }
-    if (lane == 0) {
-      const double piv = lambda + den;
-      const bool ok = piv > 0.0;
-      const T x = from_double<T>(ok ? num / piv : 0.0);
-      A[i * ldA + r] = x;
-      rec[i].w = (AT)to_double<T>(x);
-      if (info) info[i] = ok ? 0 : 1;
-    }
+    if (lane == 0) ccd_solve_row<T, AT>(rs, i, num, den);
   }
 }
 
@@ -235,12 +260,14 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
       const bool lds = ix->tune.ccd_lds != 0 && stage_bytes <= kCcdLdsBytes;
       const R4 *rq0 = (const R4 *)recs[q0], *rq1 = (const R4 *)recs[q1];
       const int mv = r > 0 ? 1 : 0;
+      const RowSolve<T, AT> rs{L ? L->d_row_task : md.d_row_task, lambda, (T *)d_A[n], ldA, r,
+                               (R4 *)recs[n], d_info ? d_info + off : nullptr};
       if (lds) {
         // as many workgroups as are resident at once (registers and LDS
         // copies), a multiple of 8 in all: the workgroups loop over the
         // slots, so a second round would only lengthen the pass
         const size_t shm = (size_t)std::max<int64_t>(stage_bytes, 16);
-        auto kern = qs == q0 ? &k_ccd_tasks<AT, VT, 64, 0> : &k_ccd_tasks<AT, VT, 64, 1>;
+        auto kern = qs == q0 ? &k_ccd_tasks<T, AT, VT, 64, 0> : &k_ccd_tasks<T, AT, VT, 64, 1>;
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, shm) != hipSuccess ||
             per_cu < 1)
@@ -248,19 +275,22 @@ static hipError_t ccd_column_t(const tt_index *ix, int r, void *const *d_A, int6
         int64_t grid = std::min<int64_t>((nslot + 3) / 4, (int64_t)per_cu * std::max(ix->cu_count, 8));
         grid = std::max<int64_t>(8, grid / 8 * 8);
         kern<<<(unsigned)grid, 256, shm, s>>>(tk, ntask, sched, nslot, key, a0, a1, (VT *)rho[n],
-                                              (const R4 *)recs[n], rq0, rq1, nstage, mv, part);
+                                              (const R4 *)recs[n], rq0, rq1, nstage, mv, part,
+                                              rs);
       } else {
-        k_ccd_tasks<AT, VT, 64, -1><<<(unsigned)((nslot + 3) / 4), 256, 0, s>>>(
+        k_ccd_tasks<T, AT, VT, 64, -1><<<(unsigned)((nslot + 3) / 4), 256, 0, s>>>(
             tk, ntask, sched, nslot, key, a0, a1, (VT *)rho[n], (const R4 *)recs[n], rq0, rq1, 0,
-            mv, part);
+            mv, part, rs);
       }
     }
     ProfScope ps("ccd_rows", s, (double)ntask * 16 + (double)md.I * (sizeof(T) + sizeof(AT)),
                  (double)ntask * 2);
-    if (md.I > 0)
-      k_ccd_rows<T, AT><<<grid_for_n(64 * md.I, 262144), 256, 0, s>>>(
-          L ? L->d_row_task : md.d_row_task, md.I, part, lambda, (T *)d_A[n], ldA, r,
-          (R4 *)recs[n], d_info ? d_info + off : nullptr);
+    if (md.I > 0) {
+      // rows with several tasks or none (the others were solved in the pass)
+      const RowSolve<T, AT> rs{L ? L->d_row_task : md.d_row_task, lambda, (T *)d_A[n], ldA, r,
+                               (R4 *)recs[n], d_info ? d_info + off : nullptr};
+      k_ccd_rows<T, AT><<<grid_for_n(64 * md.I, 262144), 256, 0, s>>>(md.I, part, rs);
+    }
     off += md.I;
   }
   return hipGetLastError();
