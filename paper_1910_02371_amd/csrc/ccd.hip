@@ -19,7 +19,11 @@
 // in L2).  With the CCD++ layout of a mode (tuning ccd_xcd) its pass runs
 // over the stream regrouped by bucket of the largest other mode's index,
 // and each XCD only gathers the records of its bucket's rows, which fit its
-// L2; the residual copy of that mode follows the layout's order.
+// L2; the residual copy of that mode follows the layout's order.  When the
+// smaller other mode's records fit in 48 KiB (tuning ccd_lds) every
+// workgroup of the pass reads them from an LDS copy.  A row's rank-1 solve
+// is done by its task's wave when the row has a single task, else by
+// k_ccd_rows from the tasks' partial sums.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
