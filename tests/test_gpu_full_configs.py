@@ -446,8 +446,9 @@ def test_counts_poisson_gn(gpu_lib):
 # ----------------------------------------------------------- uniform ----
 def test_uniform_1p5b(gpu_lib):
     """1.5B uniform nonzeros on 2^20 cubed, R = 32, FP32: TTTP on sampled
-    nonzeros, MTTKRP and Solve Factor on sampled rows, and the identity
-    sum TTTP = <A_n, MTTKRP_n>."""
+    nonzeros, MTTKRP and Solve Factor on sampled rows, the identity
+    sum TTTP = <A_n, MTTKRP_n>, and the fused update with model values of
+    the benchmarked step (solve_factor_model, mode 0)."""
     tt = gpu_lib
     t0 = time.time()
     wl = W.uniform()
@@ -483,6 +484,22 @@ def test_uniform_1p5b(gpu_lib):
             be = backward_error(G, lam, host(X)[rows], ref)
             assert be <= 1e-5, f"solve 1.5B mode {n}: {be:.2e}"
             del M, X, info
+        # the benchmarked step's call: mode 0's ALS update that also writes the
+        # model values (mode-0 sorted order) equals solve_factor with the fused
+        # right-hand side bit for bit, and its model values at sampled sorted
+        # positions are the oracle's TTTP of the factors before the update
+        X0, info0 = tt.solve_factor(c.ix, None, c.A, 0, tt.RHS_MTTKRP, lam)
+        X1, info1, model = tt.solve_factor_model(c.ix, c.A, 0, lam)
+        assert torch.equal(X0, X1) and torch.equal(info0, info1), "fused model update 1.5B"
+        del X0, X1, info0, info1
+        js = torch.as_tensor(rng.choice(wl.nnz, 20000, replace=False)).cuda()
+        cpos = c.ix.view(0)[1][js].long().cpu().numpy()
+        ms = model[js].double().cpu().numpy()
+        del model
+        sidx = [i[cpos] for i in wl.idx]
+        assert_close_abs(ms, O.tttp(sidx, None, c.As),
+                         O.tttp(sidx, None, [np.abs(a) for a in c.As]), TAU["f32"],
+                         "model values 1.5B")
         # BF16 factor storage on the same index: TTTP on sampled nonzeros,
         # MTTKRP on sampled rows (FP32 accumulation: tau against the oracle on
         # the RNE-rounded factors) and the fused ALS update (Gram and
